@@ -1,0 +1,284 @@
+"""Pins of the FP64 oracle against facts that do not depend on it.
+
+Each test fixes the oracle to something other than itself: brute-force
+enumeration of supports and signs, the LASSO optimality conditions (the natural
+stopping condition, Eq. (9)), the dual of Eq. (5), closed forms (orthonormal
+dictionaries; noiseless sign-consistent recovery), the OMP reduction
+(lambda = 0, rho = 1, end of Section II-A), the per-iteration decrease bound of
+Lemma 1 with the monotone objective of Section II-B, an independent
+full-problem coordinate descent, and exact invariances of the problem.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import bmpl_inputs as bi
+import oracle
+
+
+def lam_rel(At, Bt, c):
+    return c * np.abs(At.astype(np.float64) @ Bt.astype(np.float64).T).max(axis=0)
+
+
+def kkt_residuals(At, b, x, lam):
+    """(max off-support excess, max on-support deviation) of the LASSO conditions."""
+    A = At.astype(np.float64).T
+    r = b.astype(np.float64) - A @ x
+    g = A.T @ r
+    on = x != 0
+    off_ex = np.max(np.abs(g[~on]) - lam) if (~on).any() else -np.inf
+    on_dev = np.max(np.abs(g[on] - lam * np.sign(x[on]))) if on.any() else 0.0
+    return off_ex, on_dev
+
+
+def brute_force_lasso(At, b, lam):
+    """Enumerate every sign vector s in {-1,0,1}^m; keep the ones whose sign-fixed
+    normal-equation solution is sign-consistent and dual feasible."""
+    A = At.astype(np.float64).T
+    b = b.astype(np.float64)
+    n, m = A.shape
+    sols = []
+    for s in itertools.product((-1.0, 0.0, 1.0), repeat=m):
+        s = np.array(s)
+        S = np.nonzero(s)[0]
+        if len(S) > n:
+            continue
+        x = np.zeros(m)
+        if len(S):
+            AS = A[:, S]
+            xs = np.linalg.solve(AS.T @ AS, AS.T @ b - lam * s[S])
+            if np.any(np.sign(xs) != s[S]):
+                continue
+            x[S] = xs
+        g = A.T @ (b - A @ x)
+        off = np.setdiff1d(np.arange(m), S)
+        if len(off) and np.max(np.abs(g[off])) > lam * (1 + 1e-12):
+            continue
+        sols.append(x)
+    return sols
+
+
+@pytest.mark.parametrize("seed,lrel", [(1, 0.05), (2, 0.15), (3, 0.01), (4, 0.3)])
+def test_brute_force_enumeration(seed, lrel):
+    P = bi.tiny_gaussian(n=6, m=10, p=1, k=3, sigma=0.05, seed=seed)
+    lam = lam_rel(P.At, P.Bt, lrel)
+    sols = brute_force_lasso(P.At, P.Bt[0], lam[0])
+    assert len(sols) == 1, "general position gives exactly one LASSO solution"
+    r = oracle.solve(P.At, P.Bt, lam, rho=2)
+    assert r["status"][0] & oracle.ST_CONVERGED
+    np.testing.assert_allclose(r["X"][0], sols[0], rtol=0, atol=1e-10)
+
+
+def test_kkt_on_every_output():
+    P = bi.small_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho)
+    assert np.all(r["status"] == oracle.ST_CONVERGED)
+    for i in range(P.p):
+        off_ex, on_dev = kkt_residuals(P.At, P.Bt[i], r["X"][i], lam[i])
+        assert off_ex <= 1e-9 * lam[i]
+        assert on_dev <= 1e-9 * lam[i]
+        assert r["kkt"][i] <= 1e-9
+
+
+def test_duality_gap_of_eq5():
+    P = bi.small_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho)
+    A = P.At.astype(np.float64).T
+    for i in range(P.p):
+        b = P.Bt[i].astype(np.float64)
+        x = r["X"][i]
+        res = b - A @ x
+        F = 0.5 * res @ res + lam[i] * np.abs(x).sum()
+        alpha = res * min(1.0, lam[i] / np.abs(A.T @ res).max())
+        D = -0.5 * alpha @ alpha + alpha @ b
+        assert F - D <= 1e-12 * F
+        assert abs(F - r["objective"][i]) <= 1e-12 * F
+
+
+def test_orthonormal_dictionary_closed_form_and_iteration_count():
+    # A with orthonormal columns: x = soft(A^T b, lambda) and MPL needs ceil(|S|/rho) additions,
+    # each adding the next rho largest |a_j^T b| (g_j = a_j^T b off I for every iterate).
+    rng = np.random.default_rng(7)
+    n, m = 64, 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    At = np.ascontiguousarray(Q.T.astype(np.float32))
+    b = (Q[:, :25] @ (rng.uniform(0.5, 2.0, 25) * rng.choice([-1, 1], 25))
+         + 0.2 * rng.standard_normal(n)).astype(np.float32)
+    A64 = At.astype(np.float64).T
+    z = A64.T @ b.astype(np.float64)
+    order = np.argsort(-np.abs(z), kind="stable")
+    # choose lambda in a wide gap of |z| so float32 non-orthogonality cannot reorder anything
+    az = np.abs(z)[order]
+    gaps = az[:-1] - az[1:]
+    q = int(np.argmax(gaps[:30])) if gaps[:30].max() > 1e-3 else 20
+    lam = 0.5 * (az[q] + az[q + 1])
+    expect = np.sign(z) * np.maximum(np.abs(z) - lam, 0)
+    for rho in (1, 3, 4):
+        t = oracle.trace(At, b, lam, rho)
+        np.testing.assert_allclose(t["x"], expect, atol=2e-5)
+        nS = int((expect != 0).sum())
+        assert t["iters"] == -(-nS // rho)
+        added = np.concatenate([a for a, _ in t["steps"]])
+        np.testing.assert_array_equal(added, order[:nS])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_noiseless_sign_consistent_closed_form(seed):
+    # b = A x, k-sparse.  If the sign-fixed solution x_S - lambda G_SS^{-1} s is sign consistent
+    # and strictly dual feasible off S, it is the LASSO solution (primal-dual witness), and it
+    # tends to x as lambda -> 0.
+    P = bi.tiny_gaussian(n=128, m=512, p=1, k=5, sigma=0.0, seed=10 + seed)
+    S = P.supports[0]
+    A = P.At.astype(np.float64).T
+    b = P.Bt[0].astype(np.float64)
+    AS = A[:, S]
+    G = AS.T @ AS
+    s = np.sign(P.amplitudes[0])
+    errs = []
+    for lam in (1e-1, 1e-2, 1e-3):
+        xs = np.linalg.solve(G, AS.T @ b - lam * s)
+        assert np.all(np.sign(xs) == s)
+        xw = np.zeros(512)
+        xw[S] = xs
+        g = A.T @ (b - A @ xw)
+        off = np.setdiff1d(np.arange(512), S)
+        assert np.abs(g[off]).max() < lam     # witness certifies uniqueness
+        r = oracle.solve(P.At, P.Bt, np.array([lam]), rho=2)
+        np.testing.assert_allclose(r["X"][0], xw, rtol=0, atol=1e-10)
+        errs.append(np.linalg.norm(r["X"][0][S] - P.amplitudes[0]))
+    # exact recovery in the limit: error shrinks linearly with lambda (b is float32-rounded)
+    assert errs[2] < 2e-2 * errs[0] + 1e-5
+
+
+def omp_textbook(A, b, steps):
+    r = b.copy()
+    I = []
+    for _ in range(steps):
+        c = np.abs(A.T @ r)
+        c[I] = -1
+        j = int(np.argmax(c))
+        I.append(j)
+        xs, *_ = np.linalg.lstsq(A[:, I], b, rcond=None)
+        r = b - A[:, I] @ xs
+    x = np.zeros(A.shape[1])
+    x[I] = xs
+    return I, x
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_omp_reduction_lambda0_rho1(seed):
+    P = bi.tiny_gaussian(n=64, m=200, p=1, k=8, sigma=0.01, seed=20 + seed)
+    steps = 12
+    t = oracle.trace(P.At, P.Bt[0], 0.0, 1, max_outer=steps)
+    I_or = [int(a[0]) for a, _ in t["steps"]]
+    A = P.At.astype(np.float64).T
+    I_omp, x_omp = omp_textbook(A, P.Bt[0].astype(np.float64), steps)
+    assert I_or == I_omp
+    np.testing.assert_allclose(t["x"], x_omp, atol=1e-9)
+
+
+@pytest.mark.parametrize("rho", [1, 2, 5])
+def test_monotone_objective_and_lemma1_bound(rho):
+    P = bi.small_gaussian(indices=[0, 3, 7])
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    A = P.At.astype(np.float64).T
+    for i in range(P.p):
+        t = oracle.trace(P.At, P.Bt[i], lam[i], rho)
+        F = t["obj_trace"]
+        assert np.all(np.diff(F) <= 1e-12 * F[0])
+        I = []
+        for step, (added, gsel) in enumerate(t["steps"]):
+            I.extend(int(a) for a in added)
+            L = np.linalg.eigvalsh(A[:, I].T @ A[:, I]).max()
+            bound = ((np.abs(gsel) - lam[i]) ** 2).sum() / (2 * L)
+            assert np.all(np.abs(gsel) > lam[i])
+            assert F[step] - F[step + 1] >= bound * (1 - 1e-9)
+
+
+def full_cd(A, b, lam, tol=1e-13, max_rounds=200):
+    """Independent full-problem FP64 coordinate descent (covariance updates, active-set inner loops)."""
+    n, m = A.shape
+    G = A.T @ A
+    c = A.T @ b
+    x = np.zeros(m)
+    grad = c.copy()
+
+    def sweep(idx):
+        for j in idx:
+            old = x[j]
+            z = grad[j] + G[j, j] * old
+            nw = np.sign(z) * max(abs(z) - lam, 0.0) / G[j, j]
+            if nw != old:
+                grad[:] -= G[:, j] * (nw - old)
+                x[j] = nw
+
+    for _ in range(max_rounds):
+        sweep(range(m))
+        for _ in range(100000):
+            act = np.nonzero(x)[0]
+            before = x.copy()
+            sweep(act)
+            if np.max(np.abs(x - before)) <= tol:
+                break
+        g = c - G @ x
+        on = x != 0
+        viol = max(np.max(np.abs(g[~on]) - lam, initial=0.0),
+                   np.max(np.abs(g[on] - lam * np.sign(x[on])), initial=0.0))
+        if viol <= 1e-11 * lam:
+            break
+    return x
+
+
+def test_cross_solver_full_cd():
+    P = bi.small_gaussian(indices=[1, 5, 11])
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho)
+    A = P.At.astype(np.float64).T
+    for i in range(P.p):
+        xcd = full_cd(A, P.Bt[i].astype(np.float64), lam[i])
+        np.testing.assert_allclose(r["X"][i], xcd, atol=1e-9)
+
+
+def test_invariances():
+    P = bi.small_gaussian(indices=[2, 9])
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    base = oracle.solve(P.At, P.Bt, lam, P.rho)
+    rng = np.random.default_rng(3)
+    # permuting atoms permutes the solution
+    perm = rng.permutation(P.m)
+    r = oracle.solve(P.At[perm], P.Bt, lam, P.rho)
+    np.testing.assert_allclose(r["X"], base["X"][:, perm], atol=1e-10)
+    # permuting signals permutes the results
+    r = oracle.solve(P.At, P.Bt[::-1], lam[::-1], P.rho)
+    np.testing.assert_allclose(r["X"], base["X"][::-1], atol=1e-12)
+    # b -> 2b, lambda -> 2 lambda gives x -> 2x (powers of two keep float32 exact)
+    r = oracle.solve(P.At, 2 * P.Bt, 2 * lam, P.rho)
+    np.testing.assert_allclose(r["X"], 2 * base["X"], atol=1e-10)
+    # flipping atom j flips x_j
+    At2 = P.At.copy()
+    flip = np.nonzero(base["X"][0])[0][:3]
+    At2[flip] *= -1
+    r = oracle.solve(At2, P.Bt, lam, P.rho)
+    expect = base["X"].copy()
+    expect[:, flip] *= -1
+    np.testing.assert_allclose(r["X"], expect, atol=1e-10)
+    # lambda >= ||A^T b||_inf gives x = 0 after zero iterations
+    r = oracle.solve(P.At, P.Bt, lam / P.lambda_rel * 1.0001, P.rho)
+    assert np.all(r["X"] == 0) and np.all(r["iters"] == 0) and np.all(r["status"] == oracle.ST_CONVERGED)
+
+
+def test_caps_and_nonfinite():
+    P = bi.small_gaussian(indices=[0, 1])
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho, max_outer=1)
+    assert np.all(r["status"] & oracle.ST_CAP_ITERS) and np.all(r["iters"] == 1)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho, max_active=3)
+    assert np.all(r["status"] & oracle.ST_CAP_ACTIVE)
+    assert np.all((r["X"] != 0).sum(axis=1) <= 3)
+    Bt = P.Bt.copy()
+    Bt[1, 5] = np.nan
+    r = oracle.solve(P.At, Bt, lam, P.rho)
+    assert r["status"][1] == oracle.ST_NONFINITE and r["status"][0] == oracle.ST_CONVERGED
