@@ -1,0 +1,163 @@
+"""Benchmark: signals solved per second by batched BMPL on one MI355X.
+
+A step is one bmpl_solve over the whole batch: lambda from the relative rule,
+then the outer iterations (correlation product, selection, master problem,
+residual, certificate) until every signal stops.  Default workload: the
+compressive-sensing shape, A 2048 x 16384 Gaussian with unit columns, 1024
+signals with 100-sparse +-U[1,2] codes and sigma = 0.005 noise,
+lambda_i = 0.02 ||A^T b_i||_inf, rho = 10, KKT tolerance 1e-4, float32
+correlation product.  Inputs are seeded and synthetic and resident in HBM
+before timing starts.
+
+Printed: one JSON line with the throughput, the correlation kernel's
+roofline (HIP-event times of every launch in the timed steps, algorithmic
+flops 2 m n p_running per launch), and the FP64 CPU oracle timed on a sample
+of the same workload (with its parity against the GPU on that sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def load_traffic(path: str, kernel_src: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
+    try:
+        import hashlib
+        with open(path) as f:
+            rec = json.load(f)
+        with open(kernel_src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        if rec.get("kernel_sha256_16") != h:
+            return None
+        return rec
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cs2048x16384")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="signals the oracle solves for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (signals shard with no "
+              "per-iteration exchange, so N GPUs run N independent batches)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import bmpl_inputs as bi
+    import paper_1302_5010_amd as pk
+
+    gen = bi.WORKLOADS[args.workload]
+    P = gen()
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(P.At).to(dev)
+    Bt = torch.from_numpy(P.Bt).to(dev)
+    solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        out = solver.solve(Bt)
+    torch.cuda.synchronize()
+    solver.reset_timing()
+    solved = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = solver.solve(Bt)
+        solved.append(out["status"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    conv = [int(((s & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for s in solved]
+    kkt = out["kkt"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    supp = out["supp_len"].cpu().numpy()
+    tm = solver.timing()
+    corr_avg_s = tm["corr_ms"] / max(1, tm["corr_launches"]) * 1e-3
+    achieved = tm["corr_flops"] / (tm["corr_ms"] * 1e-3) / 1e12 if tm["corr_ms"] > 0 else 0.0
+    traffic = None
+    rec = load_traffic(os.path.join(ROOT, "profiles", f"corr_gemm_f32_{args.workload}_pmc.json"),
+                       os.path.join(ROOT, "paper_1302_5010_amd", "csrc", "corr_gemm.hip"))
+    if rec is not None:
+        traffic = rec.get("hbm_bytes_per_launch")
+
+    result = {
+        "metric": "signals solved/sec at KKT tol 1e-4 (plain FP32 BMPL)",
+        "value": sum(conv) / elapsed,
+        "unit": "signals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": P.name, "n": P.n, "m": P.m, "p": P.p, "rho": P.rho,
+                   "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": "fp32"},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "corr_gemm_f32",
+            "achieved": achieved,
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": traffic,
+            "avg_launch_ms": corr_avg_s * 1e3,
+            "launches": tm["corr_launches"],
+            "algorithmic_gflop_per_step": tm["corr_flops"] / args.steps / 1e9,
+        },
+        "kernel_ms_per_step": {k: tm[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms", "other_ms",
+                                                                "wall_ms")},
+        "outer_iters_per_step": tm["outer_iters"] / args.steps,
+        "signals": {"converged_per_step": conv, "kkt_max": float(np.max(kkt)),
+                    "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
+                    "support_mean": float(np.mean(supp))},
+    }
+
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle
+        from tests.parity import check_batch
+        q = min(args.cpu_sample, P.p)
+        rows = list(range(q))
+        lam_gpu = out["lambda"].cpu().numpy()
+        A64 = P.At.astype(np.float64)
+        lam_or = P.lambda_rel * np.abs(A64 @ P.Bt[rows].astype(np.float64).T).max(axis=0)
+        threads = min(oracle.max_threads(), q)
+        c0 = time.perf_counter()
+        ref = oracle.solve(P.At, P.Bt[rows], lam_or, P.rho, nthreads=threads)
+        c1 = time.perf_counter()
+        errs = check_batch(P.At, P.Bt, lam_or, out, ref, rows=range(q), gpu_rows=rows)
+        result["cpu_baseline"] = {
+            "value": q / (c1 - c0), "unit": "signals/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {q} signals of the same workload, FP64 C oracle, OpenMP one signal per thread",
+        }
+        result["parity_on_sample"] = {
+            "signals": q, "max_rel_obj": float(max(e["rel_obj"] for e in errs)),
+            "max_rel_x": float(max(e["rel_x"] for e in errs)),
+            "max_rel_lambda": float(np.max(np.abs(lam_gpu[rows] - lam_or) / lam_or)),
+        }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * bmpl.h - C ABI of the batch-mode Matching Pursuit LASSO library for
+ * AMD MI355X (gfx950).
+ *
+ * Problem (the batch sparse-recovery problem, Eq. (3), read with one half per
+ * signal and a per-signal lambda_i, which makes it separable over signals and
+ * equal to p copies of the LASSO, Eq. (2)):
+ *
+ *     for every column b_i of B:   min_x  lambda_i ||x||_1 + 1/2 ||b_i - A x||^2
+ *
+ * solved by Matching Pursuit LASSO (Algorithm 1) run on all p signals at once:
+ * each outer iteration computes the correlations G = A^T (B - A X) of every
+ * still-running signal as one matrix product (the full matrix-vector products
+ * of the "Implementation Concerns" subsection, batched), adds to each signal's
+ * active set I the rho atoms outside I with the largest |g_j| > lambda_i
+ * (the worst-case analysis), solves the master problem Eq. (7) restricted to I
+ * exactly, and stops a signal once ||A^T xi||_inf <= lambda_i, the natural
+ * stopping condition of the "Stopping Conditions" subsection.  Without early
+ * stopping the result is the LASSO solution.
+ *
+ * Conventions shared by every entry point
+ *  - All pointers named *_dev are device pointers (hipMalloc'd memory or
+ *    PyTorch CUDA tensors) on the device that is current when the context is
+ *    created.  Host pointers are named without the suffix.
+ *  - A is column-major n x m: element (r, j) is A_dev[r + j*lda], lda >= n, so
+ *    atom a_j is contiguous (the atom-by-atom storage of "Implementation
+ *    Concerns").  B is column-major n x p with leading dimension ldb >= n.
+ *  - Calls that take a `hip_stream` enqueue their work on that stream
+ *    (NULL = the null stream) and may return before it finishes; outputs are
+ *    valid once the stream is synchronised.  bmpl_solve synchronises the stream
+ *    once per outer iteration to read back how many signals are still running.
+ *  - Every call returns a bmpl_status; on failure bmpl_last_error() describes
+ *    it.  A context is not re-entrant: one call in flight per context.
+ */
+#ifndef BMPL_H
+#define BMPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bmpl_ctx bmpl_ctx;
+
+typedef enum {
+    BMPL_OK = 0,
+    BMPL_E_INVALID = -1,      /* bad shape, pointer or option */
+    BMPL_E_NOMEM = -2,        /* device allocation failed */
+    BMPL_E_HIP = -3,          /* a HIP runtime call failed */
+    BMPL_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+} bmpl_status;
+
+typedef enum {
+    BMPL_LAMBDA_ABS = 0,          /* lambda_i = value, or lambda_dev[i] when given to bmpl_solve */
+    BMPL_LAMBDA_REL_MAX_ATB = 1   /* lambda_i = value * ||A^T b_i||_inf (Section IV-A's rule) */
+} bmpl_lambda_mode;
+
+typedef enum {
+    BMPL_PREC_FP32 = 0,   /* correlation product in float32 (MFMA, float32 accumulation) */
+    BMPL_PREC_BF16 = 1,   /* bfloat16 screening product, float32 re-score before admission */
+    BMPL_PREC_FP8 = 2     /* fp8 e4m3 screening product, float32 re-score before admission */
+} bmpl_precision;
+
+/* Per-signal status bits (bmpl_result.sig_status). */
+#define BMPL_SIG_CONVERGED   1   /* natural stop reached: kkt <= kkt_tol */
+#define BMPL_SIG_CAP_ITERS   2   /* max_outer outer iterations done, not converged */
+#define BMPL_SIG_CAP_ACTIVE  4   /* |I| reached max_active, not converged */
+#define BMPL_SIG_NONFINITE   8   /* b_i or lambda_i not finite: x_i = 0 */
+#define BMPL_SIG_FALLBACK   16   /* a warm-start proposal failed the certificate */
+#define BMPL_SIG_INEXACT    32   /* a restricted solve hit its step cap */
+
+/* bmpl_options.flags bits. */
+#define BMPL_FLAG_TIMING 1   /* time every kernel launch with HIP events (see bmpl_get_timing) */
+
+typedef struct {
+    int32_t rho;            /* atoms added per outer iteration (Algorithm 1, step 3); default 10 */
+    int32_t max_outer;      /* outer-iteration cap; <= 0 selects ceil(m / rho) */
+    int32_t max_active;     /* cap on |I|; <= 0 selects min(m, 2n) */
+    double kkt_tol;         /* certificate tolerance relative to lambda_i; default 1e-4 */
+    bmpl_precision screen;  /* precision of the correlation product; default FP32 */
+    int32_t flags;          /* BMPL_FLAG_* bits; default 0 */
+} bmpl_options;
+
+/*
+ * Caller-owned device result buffers, filled by bmpl_solve.  For signal i:
+ * x_idx[i*ld_x + s], x_val[i*ld_x + s] for s < supp_len[i] hold the nonzero
+ * coefficients sorted by atom index; ld_x >= min(max_active, n).
+ * kkt[i] = max( max_{j not in S}(|a_j^T xi| - lambda)_+ , max_{j in S}|a_j^T xi - lambda sign x_j| ) / lambda,
+ * computed in float64 on I and from the float32 correlation product outside I.
+ * objective[i] = lambda ||x||_1 + 1/2 ||b - A x||^2 in float64.
+ * lambda[i] = the lambda_i actually used.  iters[i] = outer iterations that added atoms.
+ * Any pointer except x_idx/x_val/supp_len may be NULL to skip that output.
+ */
+typedef struct {
+    float* x_val_dev;
+    int32_t* x_idx_dev;
+    int32_t* supp_len_dev;
+    int32_t* iters_dev;
+    double* kkt_dev;
+    double* lambda_dev;
+    double* objective_dev;
+    int32_t* sig_status_dev;
+    int32_t ld_x;
+} bmpl_result;
+
+/* Fill `o` with the defaults listed in bmpl_options.  Returns BMPL_E_INVALID for NULL. */
+bmpl_status bmpl_options_default(bmpl_options* o);
+
+/*
+ * Create a context for dictionary A (n x m, see conventions) and the lambda rule.
+ * The library copies A into its own device memory (float32, rows padded to a
+ * multiple of 32 with zeros), so the caller may free A_dev after the call.
+ * `o` may be NULL for the defaults.  Work is enqueued on `hip_stream` and the
+ * stream is synchronised before returning.  Errors: BMPL_E_INVALID for n <= 0,
+ * m <= 0, lda < n, NULL pointers, lambda < 0 or a non-finite lambda, rho <= 0;
+ * BMPL_E_NOMEM / BMPL_E_HIP on runtime failures.  *out is NULL on failure.
+ */
+bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m,
+                        bmpl_lambda_mode mode, double lambda, const bmpl_options* o,
+                        void* hip_stream, bmpl_ctx** out);
+
+/*
+ * Solve the p signals in B (n x p, leading dimension ldb) with the context's
+ * dictionary, lambda rule and options (Algorithm 1 batched over signals, see
+ * the top of this file).  lambda_dev (p float64 values) overrides the context's
+ * lambda with per-signal absolute values when non-NULL.  warm_idx_dev (p x
+ * warm_k atom indices, -1 = unused entry) seeds each active set: the master
+ * problem is solved on the proposal first and the pursuit continues from there,
+ * so the result is the same LASSO solution; NULL / warm_k = 0 for none.
+ * Workspace grows on demand and is kept in the context.  Per-signal outcomes
+ * never fail the call; they are reported in sig_status.  Errors:
+ * BMPL_E_INVALID (bad pointers, ldb < n, p < 0, ld_x too small),
+ * BMPL_E_NOMEM, BMPL_E_HIP.
+ */
+bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p,
+                       const double* lambda_dev, const int32_t* warm_idx_dev, int32_t warm_k,
+                       const bmpl_result* out, void* hip_stream);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+bmpl_status bmpl_destroy(bmpl_ctx* c);
+
+/* Message describing the last failure on this thread; valid until the next call. */
+const char* bmpl_last_error(void);
+
+/*
+ * Diagnostic entry points (one step of the pursuit each, used by the kernel
+ * parity tests and the benchmark's per-kernel timing).
+ */
+
+/*
+ * The batched correlation step: G[i*ldg + j] = a_j^T r_i for j < m, i < p,
+ * where r_i = R_dev + i*ldr (n float32 values, ldr >= n), in the context's
+ * screening precision with float32 accumulation.  This is the full
+ * matrix-vector product g = A^T xi of Algorithm 1, step 3, for p residuals at
+ * once.  ldg >= m.  Errors: BMPL_E_INVALID.
+ */
+bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t p,
+                           float* G_dev, int64_t ldg, void* hip_stream);
+
+/*
+ * The worst-case analysis of Algorithm 1, step 3, on given correlations:
+ * for each row i of G (p rows, leading dimension ldg >= m) pick up to k atoms j
+ * with |G[i,j]| > lambda_dev[i] and mask bit j of excl_dev clear, largest
+ * |G[i,j]| first, ties to the lower index.  excl_dev holds p bitmaps of
+ * ceil(m/32) uint32 words (bit j of word j/32), or NULL for none.  Writes
+ * sel_dev[i*k + q] (atom, -1 past the end) and nsel_dev[i]; also
+ * vmax_dev[i] = max over unmasked j of |G[i,j]| (0 if none).  1 <= k <= 64.
+ */
+bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
+                        const double* lambda_dev, const uint32_t* excl_dev, int32_t k,
+                        int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev, void* hip_stream);
+
+/*
+ * Kernel timing accumulated over the solves run since the last reset, recorded
+ * with HIP events on the solve's stream when the context was created with
+ * BMPL_FLAG_TIMING (all zero otherwise).  corr_flops counts the algorithmic
+ * 2 * m * n * p_running flops of every correlation launch (no padding);
+ * corr_bytes the algorithmic bytes 4 * (m * n + n * p_running + m * p_running)
+ * (dictionary and residuals read once, correlations written once).  Times are
+ * milliseconds.  With timing on, bmpl_solve synchronises its stream before
+ * returning.
+ */
+typedef struct {
+    double corr_ms; int64_t corr_launches; double corr_flops; double corr_bytes;
+    double select_ms; int64_t select_launches;
+    double solve_ms; int64_t solve_launches;
+    double other_ms;        /* set-up, compaction, packing */
+    double wall_ms;         /* first to last event of each solve, summed */
+    int64_t solves;
+    int64_t outer_iters;
+} bmpl_timing;
+
+/* Copy the accumulated timing into *t.  Errors: BMPL_E_INVALID for NULL. */
+bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t);
+
+/* Zero the accumulated timing.  Errors: BMPL_E_INVALID for NULL. */
+bmpl_status bmpl_reset_timing(bmpl_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMPL_H */

@@ -1,0 +1,219 @@
+"""ctypes marshalling for libbmpl (argument conversion only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbmpl.so")
+
+BMPL_SIG_CONVERGED = 1
+BMPL_SIG_CAP_ITERS = 2
+BMPL_SIG_CAP_ACTIVE = 4
+BMPL_SIG_NONFINITE = 8
+BMPL_SIG_FALLBACK = 16
+BMPL_SIG_INEXACT = 32
+
+_PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+_MODE = {"abs": 0, "rel": 1}
+
+
+class BmplError(RuntimeError):
+    pass
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("kkt_tol", ctypes.c_double), ("screen", ctypes.c_int), ("flags", ctypes.c_int32)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("corr_ms", ctypes.c_double), ("corr_launches", ctypes.c_int64), ("corr_flops", ctypes.c_double),
+                ("corr_bytes", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("select_launches", ctypes.c_int64), ("solve_ms", ctypes.c_double),
+                ("solve_launches", ctypes.c_int64), ("other_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+BMPL_FLAG_TIMING = 1
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("x_val_dev", ctypes.c_void_p), ("x_idx_dev", ctypes.c_void_p),
+                ("supp_len_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
+                ("kkt_dev", ctypes.c_void_p), ("lambda_dev", ctypes.c_void_p),
+                ("objective_dev", ctypes.c_void_p), ("sig_status_dev", ctypes.c_void_p),
+                ("ld_x", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libbmpl.so not found at {_LIB_PATH}; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.bmpl_options_default.argtypes = [ctypes.POINTER(_Options)]
+    lib.bmpl_create.argtypes = [vp, i64, i32, i32, ctypes.c_int, dbl, ctypes.POINTER(_Options), vp,
+                                ctypes.POINTER(vp)]
+    lib.bmpl_solve.argtypes = [vp, vp, i64, i32, vp, vp, i32, ctypes.POINTER(_Result), vp]
+    lib.bmpl_destroy.argtypes = [vp]
+    lib.bmpl_last_error.restype = ctypes.c_char_p
+    lib.bmpl_last_error.argtypes = []
+    lib.bmpl_correlate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    lib.bmpl_select.argtypes = [vp, vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.bmpl_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.bmpl_reset_timing.argtypes = [vp]
+    for f in ("bmpl_options_default", "bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_correlate",
+              "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = _lib.bmpl_last_error().decode(errors="replace")
+        raise BmplError(f"{what} failed ({rc}): {msg}")
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise BmplError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise BmplError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise BmplError(f"{name} must be contiguous")
+    return t
+
+
+class Solver:
+    """A BMPL context: the dictionary on the device plus the lambda rule and options.
+
+    ``At``: (m, n) float32 CUDA tensor, atom j in row j.  ``lam``: lambda
+    (``mode='abs'``) or the factor c of lambda_i = c ||A^T b_i||_inf
+    (``mode='rel'``).
+    """
+
+    def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
+                 max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
+                 stream=None):
+        At = _dev(At, torch.float32, "At")
+        self.m, self.n = At.shape
+        self.device = At.device
+        o = _Options()
+        _lib.bmpl_options_default(ctypes.byref(o))
+        o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
+        o.screen = _PREC[screen]
+        o.flags = BMPL_FLAG_TIMING if timing else 0
+        self.options = o
+        self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_create(At.data_ptr(), self.n, self.n, self.m, _MODE[mode], float(lam), ctypes.byref(o),
+                                    _stream_ptr(stream), ctypes.byref(h)), "bmpl_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.bmpl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, Bt: torch.Tensor, lam: torch.Tensor | None = None, warm: torch.Tensor | None = None,
+              stream=None, ld_x: int | None = None) -> dict:
+        """Solve every row of ``Bt`` ((p, n) float32).  Returns device tensors:
+        x_idx/x_val (p, ld_x) sorted by atom, supp_len, iters, kkt, lambda,
+        objective, status.  ``lam``: optional (p,) float64 absolute lambdas.
+        ``warm``: optional (p, k) int32 proposed atoms (-1 = unused)."""
+        Bt = _dev(Bt, torch.float32, "Bt")
+        p, n = Bt.shape
+        if n != self.n:
+            raise BmplError(f"signals have length {n}, dictionary expects {self.n}")
+        ld = ld_x if ld_x is not None else min(self.max_active, self.n)
+        dev = Bt.device
+        out = {
+            "x_val": torch.zeros((p, ld), dtype=torch.float32, device=dev),
+            "x_idx": torch.full((p, ld), -1, dtype=torch.int32, device=dev),
+            "supp_len": torch.zeros(p, dtype=torch.int32, device=dev),
+            "iters": torch.zeros(p, dtype=torch.int32, device=dev),
+            "kkt": torch.zeros(p, dtype=torch.float64, device=dev),
+            "lambda": torch.zeros(p, dtype=torch.float64, device=dev),
+            "objective": torch.zeros(p, dtype=torch.float64, device=dev),
+            "status": torch.zeros(p, dtype=torch.int32, device=dev),
+        }
+        r = _Result(out["x_val"].data_ptr(), out["x_idx"].data_ptr(), out["supp_len"].data_ptr(),
+                    out["iters"].data_ptr(), out["kkt"].data_ptr(), out["lambda"].data_ptr(),
+                    out["objective"].data_ptr(), out["status"].data_ptr(), ld)
+        lam_ptr = 0
+        if lam is not None:
+            lam = _dev(lam, torch.float64, "lam")
+            if lam.numel() != p:
+                raise BmplError("lam must hold one value per signal")
+            lam_ptr = lam.data_ptr()
+        warm_ptr, warm_k = 0, 0
+        if warm is not None:
+            warm = _dev(warm, torch.int32, "warm")
+            if warm.dim() != 2 or warm.shape[0] != p:
+                raise BmplError("warm must be (p, k) int32")
+            warm_ptr, warm_k = warm.data_ptr(), warm.shape[1]
+        with torch.cuda.device(dev):
+            _check(_lib.bmpl_solve(self._h, Bt.data_ptr(), n, p, lam_ptr or None, warm_ptr or None, warm_k,
+                                   ctypes.byref(r), _stream_ptr(stream)), "bmpl_solve")
+        out["_keep"] = (Bt, lam, warm)
+        return out
+
+    def timing(self) -> dict:
+        """Kernel times accumulated since the last reset (needs ``timing=True``)."""
+        t = Timing()
+        _check(_lib.bmpl_get_timing(self._h, ctypes.byref(t)), "bmpl_get_timing")
+        return t.as_dict()
+
+    def reset_timing(self):
+        _check(_lib.bmpl_reset_timing(self._h), "bmpl_reset_timing")
+
+    def correlate(self, Rt: torch.Tensor, stream=None) -> torch.Tensor:
+        """G (p, m) with G[i, j] = a_j^T r_i for the rows r_i of ``Rt`` ((p, n) float32)."""
+        Rt = _dev(Rt, torch.float32, "Rt")
+        p = Rt.shape[0]
+        G = torch.empty((p, self.m), dtype=torch.float32, device=Rt.device)
+        with torch.cuda.device(Rt.device):
+            _check(_lib.bmpl_correlate(self._h, Rt.data_ptr(), self.n, p, G.data_ptr(), self.m,
+                                       _stream_ptr(stream)), "bmpl_correlate")
+        return G
+
+    def select(self, G: torch.Tensor, lam: torch.Tensor, k: int, excl: torch.Tensor | None = None, stream=None):
+        """Top-k violators per row of G; returns (sel (p, k) int32, nsel (p,), vmax (p,))."""
+        G = _dev(G, torch.float32, "G")
+        lam = _dev(lam, torch.float64, "lam")
+        p = G.shape[0]
+        sel = torch.full((p, k), -1, dtype=torch.int32, device=G.device)
+        nsel = torch.zeros(p, dtype=torch.int32, device=G.device)
+        vmax = torch.zeros(p, dtype=torch.float32, device=G.device)
+        ex = 0
+        if excl is not None:
+            ex = _dev(excl, torch.int32, "excl").data_ptr()
+        with torch.cuda.device(G.device):
+            _check(_lib.bmpl_select(self._h, G.data_ptr(), G.shape[1], p, lam.data_ptr(), ex or None, k,
+                                    sel.data_ptr(), nsel.data_ptr(), vmax.data_ptr(), _stream_ptr(stream)),
+                   "bmpl_select")
+        return sel, nsel, vmax

@@ -1,0 +1,514 @@
+// Host side of the C ABI (include/bmpl.h): context, workspace management and
+// the outer loop of the batched pursuit (Algorithm 1 run over all signals).
+//
+// Per outer iteration, on the caller's stream:
+//   corr_gemm   G = A^T Xi for the running signals (worst-case analysis, step 3)
+//   select      J_t per signal: top-rho violators of |g_j| <= lambda outside I
+//   status      stop test (natural stop, Eq. (9); caps) and compaction of the running list
+//   solve       master problem Eq. (7) on I_t = I_{t-1} u J_t, residual xi^t (steps 4-8)
+// The running count is read back once per iteration to size the next grids.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bmpl.h"
+#include "bmpl_internal.h"
+#include "pursuit.h"
+
+using namespace bmpl;
+
+namespace {
+
+thread_local std::string g_err;
+
+bmpl_status fail(bmpl_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPC(call)                                                                      \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP,          \
+                        "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                      \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct bmpl_ctx {
+    int device = 0;
+    int n = 0, m = 0, kpad = 0;
+    float* At = nullptr;          // [m][kpad] float32 dictionary, atom-major
+    bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
+    double lambda = 0.0;
+    bmpl_options opt{};
+
+    // per-signal workspace
+    Workspace w{};
+    int p_cap = 0;
+    int K_cap = 0;
+    int selcap = 0;
+    float* Bw = nullptr;          // [p_cap][kpad]
+    float* Gc = nullptr;          // [p_cap][ldg] correlations
+    int64_t ldg = 0;
+    int* act[2] = {nullptr, nullptr};
+    int* n_act_dev = nullptr;     // [2]
+    int* h_count = nullptr;       // pinned host int
+
+    // diagnostic correlate staging
+    float* diagR = nullptr;
+    int diag_cap = 0;
+
+    // kernel timing (BMPL_FLAG_TIMING)
+    bmpl_timing timing{};
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Span { size_t a, b; int kind; double flops, bytes; };
+    std::vector<Span> spans;
+};
+
+namespace {
+
+enum { K_CORR = 0, K_SELECT = 1, K_SOLVE = 2, K_OTHER = 3 };
+
+bool timing_on(const bmpl_ctx* c) { return (c->opt.flags & BMPL_FLAG_TIMING) != 0; }
+
+// Record an event on `s` (timing mode only); returns its pool index.
+size_t mark(bmpl_ctx* c, hipStream_t s)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+        c->ev_pool.push_back(e);
+    }
+    size_t i = c->ev_used++;
+    if (hipEventRecord(c->ev_pool[i], s) != hipSuccess) return (size_t)-1;
+    return i;
+}
+
+void span(bmpl_ctx* c, size_t a, size_t b, int kind, double flops = 0.0, double bytes = 0.0)
+{
+    if (a != (size_t)-1 && b != (size_t)-1) c->spans.push_back({a, b, kind, flops, bytes});
+}
+
+// Fold the recorded spans of one solve into the totals (the stream must be idle).
+void fold_timing(bmpl_ctx* c, size_t first, size_t last)
+{
+    for (const auto& sp : c->spans) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[sp.a], c->ev_pool[sp.b]) != hipSuccess) continue;
+        switch (sp.kind) {
+        case K_CORR:
+            c->timing.corr_ms += ms; c->timing.corr_launches++;
+            c->timing.corr_flops += sp.flops; c->timing.corr_bytes += sp.bytes;
+            break;
+        case K_SELECT: c->timing.select_ms += ms; c->timing.select_launches++; break;
+        case K_SOLVE: c->timing.solve_ms += ms; c->timing.solve_launches++; break;
+        default: c->timing.other_ms += ms; break;
+        }
+    }
+    float wall = 0.f;
+    if (first != (size_t)-1 && last != (size_t)-1 &&
+        hipEventElapsedTime(&wall, c->ev_pool[first], c->ev_pool[last]) == hipSuccess)
+        c->timing.wall_ms += wall;
+    c->timing.solves++;
+    c->spans.clear();
+    c->ev_used = 0;
+}
+
+}  // namespace
+
+namespace {
+
+SlotArrays slots_of(const Workspace& w)
+{
+    return SlotArrays{w.slot_atom, w.x, w.c, w.theta, w.excl, w.sord, w.G, w.Rinv};
+}
+
+void free_slots(Workspace& w)
+{
+    dfree(w.slot_atom); dfree(w.x); dfree(w.c); dfree(w.theta); dfree(w.excl);
+    dfree(w.sord); dfree(w.G); dfree(w.Rinv); dfree(w.vscratch);
+}
+
+hipError_t alloc_slots(Workspace& w, int p, int K)
+{
+    const size_t pk = (size_t)p * K, pt = (size_t)p * (size_t)tri(K);
+    hipError_t e;
+    if ((e = dalloc(&w.slot_atom, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.x, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.c, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.theta, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.excl, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.sord, pk)) != hipSuccess) return e;
+    if ((e = dalloc(&w.G, pt)) != hipSuccess) return e;
+    if ((e = dalloc(&w.Rinv, pt)) != hipSuccess) return e;
+    if ((e = dalloc(&w.vscratch, pk * 6)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void free_signals(bmpl_ctx* c)
+{
+    Workspace& w = c->w;
+    dfree(w.R); dfree(w.bnorm2); dfree(w.lam); dfree(w.status); dfree(w.iters); dfree(w.nI);
+    dfree(w.nS); dfree(w.nsel); dfree(w.sel); dfree(w.vmax); dfree(w.kkt_on); dfree(w.obj);
+    dfree(w.kkt); dfree(w.inI);
+    free_slots(w);
+    dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
+    c->p_cap = 0;
+    c->K_cap = 0;
+}
+
+// Size the per-signal workspace for p signals, slot capacity K, selection capacity selcap.
+bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
+{
+    if (p <= c->p_cap && K <= c->K_cap && selcap <= c->selcap) return BMPL_OK;
+    free_signals(c);
+    Workspace& w = c->w;
+    const size_t P = p;
+    HIPC(dalloc(&w.R, P * c->kpad));
+    HIPC(dalloc(&w.bnorm2, P));
+    HIPC(dalloc(&w.lam, P));
+    HIPC(dalloc(&w.status, P));
+    HIPC(dalloc(&w.iters, P));
+    HIPC(dalloc(&w.nI, P));
+    HIPC(dalloc(&w.nS, P));
+    HIPC(dalloc(&w.nsel, P));
+    HIPC(dalloc(&w.sel, P * selcap));
+    HIPC(dalloc(&w.vmax, P));
+    HIPC(dalloc(&w.kkt_on, P));
+    HIPC(dalloc(&w.obj, P));
+    HIPC(dalloc(&w.kkt, P));
+    HIPC(dalloc(&w.inI, P * w.words));
+    HIPC(alloc_slots(w, p, K));
+    HIPC(dalloc(&c->Bw, P * c->kpad));
+    HIPC(dalloc(&c->Gc, P * (size_t)c->ldg));
+    HIPC(dalloc(&c->act[0], P));
+    HIPC(dalloc(&c->act[1], P));
+    c->p_cap = p;
+    c->K_cap = K;
+    c->selcap = selcap;
+    w.K = K;
+    w.selcap = selcap;
+    return BMPL_OK;
+}
+
+// Grow the slot capacity in the middle of a solve, keeping every signal's state.
+bmpl_status grow_slots(bmpl_ctx* c, int K_new, hipStream_t s)
+{
+    Workspace& w = c->w;
+    Workspace nw = w;
+    nw.slot_atom = nullptr; nw.x = nullptr; nw.c = nullptr; nw.theta = nullptr; nw.excl = nullptr;
+    nw.sord = nullptr; nw.G = nullptr; nw.Rinv = nullptr; nw.vscratch = nullptr;
+    hipError_t e = alloc_slots(nw, c->p_cap, K_new);
+    if (e != hipSuccess) {
+        free_slots(nw);
+        return fail(e == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP,
+                    "growing the active-set capacity to %d failed: %s", K_new, hipGetErrorString(e));
+    }
+    RestrideArgs ra{slots_of(w), slots_of(nw), w.nI, w.nS, c->K_cap, K_new};
+    hipLaunchKernelGGL(restride_kernel, dim3(w.p), dim3(256), 0, s, ra);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+    free_slots(w);
+    w.slot_atom = nw.slot_atom; w.x = nw.x; w.c = nw.c; w.theta = nw.theta; w.excl = nw.excl;
+    w.sord = nw.sord; w.G = nw.G; w.Rinv = nw.Rinv; w.vscratch = nw.vscratch;
+    w.K = K_new;
+    c->K_cap = K_new;
+    return BMPL_OK;
+}
+
+int default_max_active(const bmpl_ctx* c)
+{
+    return std::min(c->m, 2 * c->n);
+}
+
+}  // namespace
+
+extern "C" {
+
+bmpl_status bmpl_options_default(bmpl_options* o)
+{
+    if (!o) return fail(BMPL_E_INVALID, "bmpl_options_default: NULL options");
+    o->rho = 10;
+    o->max_outer = 0;
+    o->max_active = 0;
+    o->kkt_tol = 1e-4;
+    o->screen = BMPL_PREC_FP32;
+    o->flags = 0;
+    return BMPL_OK;
+}
+
+const char* bmpl_last_error(void) { return g_err.c_str(); }
+
+bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, bmpl_lambda_mode mode,
+                        double lambda, const bmpl_options* o, void* hip_stream, bmpl_ctx** out)
+{
+    if (!out) return fail(BMPL_E_INVALID, "bmpl_create: NULL out");
+    *out = nullptr;
+    if (!A_dev) return fail(BMPL_E_INVALID, "bmpl_create: NULL A");
+    if (n <= 0 || m <= 0 || lda < n)
+        return fail(BMPL_E_INVALID, "bmpl_create: bad shape n=%d m=%d lda=%lld", n, m, (long long)lda);
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(BMPL_E_INVALID, "bmpl_create: lambda must be finite and >= 0");
+    if (mode != BMPL_LAMBDA_ABS && mode != BMPL_LAMBDA_REL_MAX_ATB)
+        return fail(BMPL_E_INVALID, "bmpl_create: unknown lambda mode %d", (int)mode);
+    bmpl_options opt;
+    bmpl_options_default(&opt);
+    if (o) opt = *o;
+    if (opt.rho <= 0 || opt.rho > 64) return fail(BMPL_E_INVALID, "bmpl_create: rho must be in [1, 64]");
+    if (!(opt.kkt_tol >= 0.0)) return fail(BMPL_E_INVALID, "bmpl_create: kkt_tol must be >= 0");
+    if (opt.screen != BMPL_PREC_FP32)
+        return fail(BMPL_E_UNSUPPORTED, "bmpl_create: screening precision %d not available", (int)opt.screen);
+    if (opt.max_active > m) opt.max_active = m;
+
+    bmpl_ctx* c = new bmpl_ctx();
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { delete c; return fail(BMPL_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)); }
+    c->n = n;
+    c->m = m;
+    c->kpad = round_up(n, 32);
+    c->mode = mode;
+    c->lambda = lambda;
+    c->opt = opt;
+    c->ldg = round_up(m, 64);
+    c->w.n = n;
+    c->w.kpad = c->kpad;
+    c->w.m = m;
+    c->w.words = (m + 31) / 32;
+    e = dalloc(&c->At, (size_t)m * c->kpad);
+    if (e == hipSuccess) e = dalloc(&c->n_act_dev, 2);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_count), sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemsetAsync(c->At, 0, (size_t)m * c->kpad * sizeof(float), s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
+                             hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        bmpl_status st = fail(e == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP, "bmpl_create: %s",
+                              hipGetErrorString(e));
+        bmpl_destroy(c);
+        return st;
+    }
+    *out = c;
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_destroy(bmpl_ctx* c)
+{
+    if (!c) return BMPL_OK;
+    free_signals(c);
+    dfree(c->At);
+    dfree(c->n_act_dev);
+    dfree(c->diagR);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->h_count) (void)hipHostFree(c->h_count);
+    delete c;
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t p, float* G_dev, int64_t ldg,
+                           void* hip_stream)
+{
+    if (!c || !R_dev || !G_dev) return fail(BMPL_E_INVALID, "bmpl_correlate: NULL argument");
+    if (p < 0 || ldr < c->n || ldg < c->m) return fail(BMPL_E_INVALID, "bmpl_correlate: bad shape");
+    if (p == 0) return BMPL_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (p > c->diag_cap) {
+        dfree(c->diagR);
+        HIPC(dalloc(&c->diagR, (size_t)p * c->kpad));
+        c->diag_cap = p;
+    }
+    HIPC(hipMemsetAsync(c->diagR, 0, (size_t)p * c->kpad * sizeof(float), s));
+    HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
+                          hipMemcpyDeviceToDevice, s));
+    HIPC(launch_corr_gemm_f32(c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, s));
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p, const double* lambda_dev,
+                        const uint32_t* excl_dev, int32_t k, int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev,
+                        void* hip_stream)
+{
+    if (!c || !G_dev || !lambda_dev || !sel_dev || !nsel_dev || !vmax_dev)
+        return fail(BMPL_E_INVALID, "bmpl_select: NULL argument");
+    if (p < 0 || ldg < c->m || k < 1 || k > 64) return fail(BMPL_E_INVALID, "bmpl_select: bad shape or k");
+    if (p == 0) return BMPL_OK;
+    SelectArgs a{};
+    a.G = G_dev; a.ldg = ldg; a.m = c->m;
+    a.act = nullptr; a.n_act_dev = nullptr; a.p_grid = p;
+    a.lam = const_cast<double*>(lambda_dev); a.lam_rel = 0.0;
+    a.excl = excl_dev; a.words = (c->m + 31) / 32;
+    a.k = k; a.sel = sel_dev; a.selcap = k; a.nsel = nsel_dev; a.vmax = vmax_dev;
+    a.nI = nullptr; a.max_active = 0;
+    HIPC(launch_select(a, reinterpret_cast<hipStream_t>(hip_stream)));
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, const double* lambda_dev,
+                       const int32_t* warm_idx_dev, int32_t warm_k, const bmpl_result* out, void* hip_stream)
+{
+    if (!c || !out) return fail(BMPL_E_INVALID, "bmpl_solve: NULL context or result");
+    if (p < 0 || ldb < c->n) return fail(BMPL_E_INVALID, "bmpl_solve: bad p=%d or ldb=%lld", p, (long long)ldb);
+    if (p == 0) return BMPL_OK;
+    if (!B_dev) return fail(BMPL_E_INVALID, "bmpl_solve: NULL B");
+    if (!out->x_val_dev || !out->x_idx_dev || !out->supp_len_dev)
+        return fail(BMPL_E_INVALID, "bmpl_solve: x_val, x_idx and supp_len are required");
+    const int max_active = c->opt.max_active > 0 ? c->opt.max_active : default_max_active(c);
+    const int need_ld = std::min(max_active, c->n);
+    if (out->ld_x < need_ld)
+        return fail(BMPL_E_INVALID, "bmpl_solve: ld_x=%d < min(max_active, n)=%d", out->ld_x, need_ld);
+    if (warm_k < 0 || warm_k > 256 || (warm_k > 0 && !warm_idx_dev))
+        return fail(BMPL_E_INVALID, "bmpl_solve: warm_k must be in [0, 256] with a proposal array");
+    const bool warm = warm_idx_dev && warm_k > 0;
+    const int rho = c->opt.rho;
+    const int max_outer = c->opt.max_outer > 0 ? c->opt.max_outer : (c->m + rho - 1) / rho;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+
+    const int first_add = warm ? std::max(warm_k, rho) : rho;
+    int K0 = std::min(max_active, std::max(64, round_up(2 * first_add, 32)));
+    K0 = std::max(K0, std::min(max_active, c->K_cap));
+    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), K0, std::max(rho, warm ? warm_k : 0));
+    if (st != BMPL_OK) return st;
+    Workspace& w = c->w;
+    w.p = p;
+
+    const bool rel = c->mode == BMPL_LAMBDA_REL_MAX_ATB && !lambda_dev;
+    const bool tm = timing_on(c);
+    c->spans.clear();
+    c->ev_used = 0;
+    const size_t ev_first = tm ? mark(c, s) : (size_t)-1;
+    PrepArgs pa{w, B_dev, ldb, c->Bw, lambda_dev, c->lambda, rel ? 1 : 0};
+    hipLaunchKernelGGL(prep_kernel, dim3(p), dim3(256), 0, s, pa);
+    HIPC(hipGetLastError());
+
+    StatusArgs sa{};
+    sa.w = w; sa.act_in = nullptr; sa.n_in_dev = nullptr; sa.n_in = p;
+    sa.act_out = c->act[0]; sa.n_out_dev = c->n_act_dev; sa.initial = 1;
+    sa.max_outer = max_outer; sa.kkt_tol = c->opt.kkt_tol; sa.warm_check = 0;
+    hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    int n_act = *c->h_count;
+
+    int cur = 0;
+    int imax = 0;
+    if (tm) span(c, ev_first, mark(c, s), K_OTHER);
+    for (int it = 0; n_act > 0; ++it) {
+        const int nxt = 1 - cur;
+        c->timing.outer_iters += tm ? 1 : 0;
+        size_t e0 = tm ? mark(c, s) : 0;
+        HIPC(launch_corr_gemm_f32(c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur], c->n_act_dev + cur,
+                                  n_act, c->Gc, c->ldg, s));
+        if (tm) {
+            const double mm = c->m, nn = c->n, pp = n_act;
+            span(c, e0, mark(c, s), K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
+            e0 = mark(c, s);
+        }
+        SelectArgs a{};
+        a.G = c->Gc; a.ldg = c->ldg; a.m = c->m;
+        a.act = c->act[cur]; a.n_act_dev = c->n_act_dev + cur; a.p_grid = n_act;
+        a.lam = w.lam; a.lam_rel = (rel && it == 0) ? c->lambda : 0.0;
+        a.excl = w.inI; a.words = w.words;
+        a.k = rho; a.sel = w.sel; a.selcap = w.selcap; a.nsel = w.nsel; a.vmax = w.vmax;
+        a.nI = w.nI; a.max_active = max_active;
+        HIPC(launch_select(a, s));
+        if (tm) { span(c, e0, mark(c, s), K_SELECT); e0 = mark(c, s); }
+        if (it == 0 && warm) {
+            WarmArgs wa{w, c->act[cur], c->n_act_dev + cur, warm_idx_dev, warm_k, max_active};
+            hipLaunchKernelGGL(warm_select_kernel, dim3(n_act), dim3(64), 0, s, wa);
+            HIPC(hipGetLastError());
+        }
+        sa.initial = 0;
+        sa.act_in = c->act[cur]; sa.n_in_dev = c->n_act_dev + cur; sa.n_in = n_act;
+        sa.act_out = c->act[nxt]; sa.n_out_dev = c->n_act_dev + nxt;
+        sa.warm_check = (warm && it == 1) ? 1 : 0;
+        hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
+        HIPC(hipGetLastError());
+        if (tm) span(c, e0, mark(c, s), K_OTHER);
+        HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev + nxt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        n_act = *c->h_count;
+        if (n_act == 0) break;
+
+        const int add = (it == 0 && warm) ? std::max(warm_k, rho) : rho;
+        imax = std::min(max_active, imax + add);
+        if (imax > c->K_cap) {
+            int K_new = std::min(max_active, std::max(2 * c->K_cap, round_up(imax, 32)));
+            st = grow_slots(c, K_new, s);
+            if (st != BMPL_OK) return st;
+        }
+        SolveArgs so{};
+        so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
+        so.act = c->act[nxt]; so.n_act_dev = c->n_act_dev + nxt;
+        so.max_steps = 16 * w.K + 256;
+        const size_t lds = (size_t)w.K * (4 * sizeof(double) + sizeof(int));
+        so.use_lds = lds + 20000 <= 65536 ? 1 : 0;
+        e0 = tm ? mark(c, s) : 0;
+        hipLaunchKernelGGL(solve_kernel, dim3(n_act), dim3(256), so.use_lds ? lds : 0, s, so);
+        HIPC(hipGetLastError());
+        if (tm) span(c, e0, mark(c, s), K_SOLVE);
+        cur = nxt;
+    }
+    const size_t e_pack = tm ? mark(c, s) : 0;
+    PackArgs pk{w, out->x_val_dev, out->x_idx_dev, out->supp_len_dev, out->iters_dev, out->kkt_dev,
+                out->lambda_dev, out->objective_dev, out->sig_status_dev, out->ld_x};
+    hipLaunchKernelGGL(pack_kernel, dim3(p), dim3(256), 0, s, pk);
+    HIPC(hipGetLastError());
+    if (tm) {
+        const size_t e_last = mark(c, s);
+        span(c, e_pack, e_last, K_OTHER);
+        HIPC(hipStreamSynchronize(s));
+        fold_timing(c, ev_first, e_last);
+    }
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t)
+{
+    if (!c || !t) return fail(BMPL_E_INVALID, "bmpl_get_timing: NULL argument");
+    *t = c->timing;
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_reset_timing(bmpl_ctx* c)
+{
+    if (!c) return fail(BMPL_E_INVALID, "bmpl_reset_timing: NULL context");
+    c->timing = bmpl_timing{};
+    return BMPL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the HIP translation units of libbmpl.
+// Not part of the public ABI (include/bmpl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmpl {
+
+// Packed lower-triangular row-major storage: row i starts at tri(i) and holds
+// columns 0..i.  A matrix of order s occupies the prefix tri(s).
+__host__ __device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
+
+// Symmetric lookup in a packed lower triangle.
+__device__ inline double sym_at(const double* P, int u, int v)
+{
+    return u >= v ? P[tri(u) + v] : P[tri(v) + u];
+}
+
+// Per-signal state of the batched pursuit.  Arrays indexed [signal * stride + ...].
+// "slot" = position in the active set I (insertion order, never removed);
+// "position" = position in the support S (order of entry into S).
+struct Workspace {
+    int n;          // signal length
+    int kpad;       // n rounded up to a multiple of 32 (rows of the residual buffer)
+    int m;          // atoms
+    int words;      // ceil(m / 32): bitmap words per signal
+    int K;          // slot capacity per signal
+    int p;          // signals in the current solve
+
+    float* R;           // [p][kpad] float32 residuals xi_i (zero rows past n)
+    double* bnorm2;     // [p] ||b_i||^2
+    double* lam;        // [p] lambda_i
+    int* status;        // [p] BMPL_SIG_* bits
+    int* iters;         // [p] outer iterations that added atoms
+    int* nI;            // [p] |I|
+    int* nS;            // [p] |S|
+    int* nsel;          // [p] atoms selected in this iteration
+    int* sel;           // [p][selcap] atoms selected in this iteration
+    int selcap;         // capacity of sel per signal
+    float* vmax;        // [p] max |g_j| outside I in the last correlation pass
+    double* kkt_on;     // [p] restricted optimality residual on I (absolute)
+    double* obj;        // [p] objective after the last master solve
+    double* kkt;        // [p] final certificate (relative to lambda_i)
+    uint32_t* inI;      // [p][words] membership bitmap of I
+    int* slot_atom;     // [p][K]
+    double* x;          // [p][K] coefficient per slot
+    double* c;          // [p][K] a_u^T b per slot
+    signed char* theta; // [p][K] sign per slot (0 = not in S)
+    unsigned char* excl;// [p][K] slot excluded from S (linearly dependent)
+    int* sord;          // [p][K] slot of each support position
+    double* G;          // [p][tri(K)] Gram of I, packed by slot
+    double* Rinv;       // [p][tri(K)] inverse Cholesky factor of G_SS, packed by position
+    double* vscratch;   // [p][6K] vectors when they do not fit LDS
+};
+
+// Launchers (all asynchronous on `stream`).
+
+// G[a*ldg + j] = a_j^T r_{act[a]} for a < n_active, j < m, float32 MFMA.
+// At: atom-major [m][lda] float32 with lda % 4 == 0, zero-padded to kpad.
+// Rbuf: [*][ldr] float32, ldr % 4 == 0, columns zero-padded to kpad.
+// act == nullptr means the identity map.  If n_act_dev != nullptr the active count is
+// read on the device and `p_grid` only sizes the grid.
+hipError_t launch_corr_gemm_f32(const float* At, int64_t lda, int m, int kpad,
+                                const float* Rbuf, int64_t ldr, const int* act,
+                                const int* n_act_dev, int p_grid, float* G, int64_t ldg,
+                                hipStream_t stream);
+
+// Top-k selection per row (worst-case analysis).  See bmpl_select in bmpl.h; here
+// `lam_rel` > 0 computes lambda[sig] = lam_rel * max_j |G| first (first pass).
+struct SelectArgs {
+    const float* G; int64_t ldg; int m;
+    const int* act; const int* n_act_dev; int p_grid;
+    double* lam; double lam_rel;
+    const uint32_t* excl; int words;
+    int k;                 // atoms per row requested
+    int* sel; int selcap; int* nsel; float* vmax;
+    // pursuit bookkeeping (may be null in the diagnostic entry point)
+    const int* nI; int max_active;
+};
+hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
+
+}  // namespace bmpl

@@ -1,0 +1,68 @@
+// Argument blocks of the per-signal pursuit kernels (pursuit.hip).
+#pragma once
+
+#include "bmpl_internal.h"
+
+namespace bmpl {
+
+struct PrepArgs {
+    Workspace w;
+    const float* B; int64_t ldb;   // caller's signals
+    float* Bw;                     // [p][kpad] padded float32 copy
+    const double* lambda_dev;      // per-signal lambda or null
+    double lambda_abs;
+    int lam_rel_mode;              // lambda set later from the first correlation pass
+};
+
+struct StatusArgs {
+    Workspace w;
+    const int* act_in; const int* n_in_dev; int n_in;
+    int* act_out; int* n_out_dev;
+    int initial;        // first call: keep every finite signal
+    int max_outer;
+    double kkt_tol;
+    int warm_check;     // pass right after a warm-started master solve
+};
+
+struct WarmArgs {
+    Workspace w;
+    const int* act; const int* n_act_dev;
+    const int32_t* warm; int warm_k;
+    int max_active;
+};
+
+struct SolveArgs {
+    Workspace w;
+    const float* At; int64_t lda;
+    const float* Bw;
+    const int* act; const int* n_act_dev;
+    int max_steps;
+    int use_lds;
+};
+
+struct PackArgs {
+    Workspace w;
+    float* x_val; int32_t* x_idx; int32_t* supp_len; int32_t* iters;
+    double* kkt; double* lambda; double* objective; int32_t* status;
+    int ld_x;
+};
+
+struct SlotArrays {
+    int* slot_atom; double* x; double* c; signed char* theta; unsigned char* excl;
+    int* sord; double* G; double* Rinv;
+};
+
+struct RestrideArgs {
+    SlotArrays src, dst;
+    const int* nI; const int* nS;
+    int K_old, K_new;
+};
+
+__global__ void prep_kernel(PrepArgs a);
+__global__ void status_compact_kernel(StatusArgs a);
+__global__ void warm_select_kernel(WarmArgs a);
+__global__ void solve_kernel(SolveArgs a);
+__global__ void pack_kernel(PackArgs a);
+__global__ void restride_kernel(RestrideArgs a);
+
+}  // namespace bmpl

@@ -1,0 +1,160 @@
+// Worst-case analysis (Algorithm 1, step 3): per running signal, pick the atoms
+// outside the active set I with the largest |g_j| that violate |g_j| > lambda
+// (the natural stopping condition, Eq. (9), fails exactly for these), at most k
+// of them, largest first, ties to the lower atom index.
+//
+// One 256-thread workgroup per signal streams its row of correlations once
+// (coalesced).  Each thread keeps a sorted top-KMAX list in registers; each
+// wave then merges its 64 lists with k rounds of a wave-wide argmax on the list
+// heads (cross-lane shuffles, no LDS); the four wave lists are ranked in LDS.
+// On the first pass of the relative lambda rule the row maximum is reduced first
+// and lambda_i = c * ||A^T b_i||_inf is set from it (Section IV-A).
+#include <float.h>
+#include <limits.h>
+
+#include "bmpl_internal.h"
+
+namespace bmpl {
+namespace {
+
+__device__ inline bool better(float v, int i, float w, int j)
+{
+    return v > w || (v == w && i < j);
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
+{
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    const float* g = a.G + (int64_t)row * a.ldg;
+    const uint32_t* ex = a.excl ? a.excl + (int64_t)sig * a.words : nullptr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    __shared__ float s_red[4];
+    __shared__ float s_val[4 * KMAX];
+    __shared__ int s_idx[4 * KMAX];
+    __shared__ double s_lam;
+
+    // Per-signal cap on the number of atoms admitted this pass.
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        int room = a.max_active - a.nI[sig];
+        k = room < k ? (room > 0 ? room : 0) : k;
+    }
+
+    // Pass 1 (relative lambda rule only): lambda_i = c * max_j |g_j|.
+    if (a.lam_rel > 0.0) {
+        float mx = 0.f;
+        for (int j = tid; j < a.m; j += 256) mx = fmaxf(mx, fabsf(g[j]));
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        if (lane == 0) s_red[wave] = mx;
+        __syncthreads();
+        if (tid == 0) {
+            float v = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+            a.lam[sig] = a.lam_rel * (double)v;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) s_lam = a.lam[sig];
+    __syncthreads();
+    const double lam = s_lam;
+
+    float val[KMAX];
+    int idx[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) { val[q] = -1.f; idx[q] = INT_MAX; }
+    float vmx = 0.f;
+    for (int j = tid; j < a.m; j += 256) {
+        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+        float v = fabsf(g[j]);
+        vmx = fmaxf(vmx, v);
+        if (!((double)v > lam) || !(v > val[KMAX - 1])) continue;
+        float cv = v;
+        int ci = j;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {   // stable insertion: equal values keep lower index first
+            bool sw = cv > val[q];
+            float tv = val[q];
+            int ti = idx[q];
+            val[q] = sw ? cv : tv;
+            idx[q] = sw ? ci : ti;
+            cv = sw ? tv : cv;
+            ci = sw ? ti : ci;
+        }
+    }
+    // vmax over the signal (outside I)
+    for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
+    __syncthreads();
+    if (lane == 0) s_red[wave] = vmx;
+
+    // Wave merge: k rounds of argmax over the 64 list heads.
+    for (int r = 0; r < k; ++r) {
+        float bv = val[0];
+        int bi = idx[0];
+        for (int o = 32; o > 0; o >>= 1) {
+            float ov = __shfl_xor(bv, o);
+            int oi = __shfl_xor(bi, o);
+            if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { s_val[wave * KMAX + r] = bv; s_idx[wave * KMAX + r] = bi; }
+        if (bv < 0.f) {
+            for (int rr = r + 1; rr < k && lane == 0; ++rr) { s_val[wave * KMAX + rr] = -1.f; s_idx[wave * KMAX + rr] = INT_MAX; }
+            break;
+        }
+        if (idx[0] == bi) {   // the winning lane pops its head
+#pragma unroll
+            for (int q = 0; q < KMAX - 1; ++q) { val[q] = val[q + 1]; idx[q] = idx[q + 1]; }
+            val[KMAX - 1] = -1.f;
+            idx[KMAX - 1] = INT_MAX;
+        }
+    }
+    __syncthreads();
+    // Rank the 4k wave candidates; candidate c lands at its rank if < k.
+    int cnt = 0;
+    if (tid < 4 * k) {
+        const int w = tid / k, r = tid % k;
+        const float v = s_val[w * KMAX + r];
+        const int i = s_idx[w * KMAX + r];
+        if (v >= 0.f) {
+            int rank = 0;
+            for (int c = 0; c < 4 * k; ++c) {
+                const float ov = s_val[(c / k) * KMAX + c % k];
+                const int oi = s_idx[(c / k) * KMAX + c % k];
+                if (ov >= 0.f && better(ov, oi, v, i)) ++rank;
+            }
+            if (rank < k) a.sel[(int64_t)sig * a.selcap + rank] = i;
+        }
+    }
+    // count = number of valid candidates, capped at k
+    if (tid == 0) {
+        for (int c = 0; c < 4 * k; ++c) cnt += s_val[(c / k) * KMAX + c % k] >= 0.f;
+        cnt = cnt < k ? cnt : k;
+        a.nsel[sig] = cnt;
+        a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+    }
+    __syncthreads();
+    if (tid == 0) { s_red[0] = (float)a.nsel[sig]; }
+    __syncthreads();
+    const int nsel = (int)s_red[0];
+    for (int q = nsel + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
+}
+
+}  // namespace
+
+hipError_t launch_select(const SelectArgs& a, hipStream_t stream)
+{
+    if (a.p_grid <= 0) return hipSuccess;
+    if (a.k <= 0 || a.k > 64 || a.k > a.selcap) return hipErrorInvalidValue;
+    if (a.k <= 16)
+        hipLaunchKernelGGL(select_kernel<16>, dim3(a.p_grid), dim3(256), 0, stream, a);
+    else if (a.k <= 32)
+        hipLaunchKernelGGL(select_kernel<32>, dim3(a.p_grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(select_kernel<64>, dim3(a.p_grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace bmpl

@@ -1,0 +1,74 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/bmpl.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bmpl.h")
+LIB = os.path.join(ROOT, "paper_1302_5010_amd", "libbmpl.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bmpl_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libbmpl.so is not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_options_default", "bmpl_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in bmpl.h but not exported"
+
+
+def test_options_default(lib):
+    from paper_1302_5010_amd._binding import _Options
+    o = _Options()
+    assert lib.bmpl_options_default(ctypes.byref(o)) == 0
+    assert o.rho == 10 and o.max_outer == 0 and o.max_active == 0 and o.kkt_tol == 1e-4 and o.screen == 0
+    assert lib.bmpl_options_default(None) == -1
+
+
+def test_argument_errors_without_gpu(lib):
+    lib.bmpl_last_error.restype = ctypes.c_char_p
+    vp = ctypes.c_void_p
+    lib.bmpl_create.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
+                                vp, vp, ctypes.POINTER(vp)]
+    h = vp()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bmpl_create(None, 4, 4, 4, 0, 0.1, None, None, ctypes.byref(h)) == -1
+    assert b"NULL A" in lib.bmpl_last_error()
+    assert lib.bmpl_create(fake, 2, 4, 4, 0, 0.1, None, None, ctypes.byref(h)) == -1     # lda < n
+    assert lib.bmpl_create(fake, 4, 4, 0, 0, 0.1, None, None, ctypes.byref(h)) == -1     # m = 0
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, -1.0, None, None, ctypes.byref(h)) == -1    # lambda < 0
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, float("nan"), None, None, ctypes.byref(h)) == -1
+    assert lib.bmpl_create(fake, 4, 4, 4, 7, 0.1, None, None, ctypes.byref(h)) == -1     # bad mode
+    from paper_1302_5010_amd._binding import _Options
+    o = _Options()
+    lib.bmpl_options_default(ctypes.byref(o))
+    o.rho = 0
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    o.rho, o.screen = 10, 9
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -4
+    assert h.value is None
+    assert lib.bmpl_solve(None, None, 4, 1, None, None, 0, None, None) == -1
+    assert lib.bmpl_destroy(None) == 0
+    assert lib.bmpl_get_timing(None, None) == -1
+    assert lib.bmpl_correlate(None, None, 4, 1, None, 4, None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_1302_5010_amd._binding as b
+    monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        b._load()

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Kernel-level tests compare the correlation product with a float64 matmul
+within float32's deterministic error bound and the selection with a CPU sort;
+solver-level tests apply the parity rules of tests/parity.py to whole solves
+on seeded workloads, from small ragged shapes up to the 2048 x 16384 x 1024
+compressive-sensing workload in the benchmark's configuration (sampled signals).
+"""
+import numpy as np
+import pytest
+
+import bmpl_inputs as bi
+import oracle
+from tests.parity import check_batch, dense_from_gpu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_5010_amd as pk
+    return pk
+
+
+def lam_rel(At, Bt, c):
+    return c * np.abs(At.astype(np.float64) @ Bt.astype(np.float64).T).max(axis=0)
+
+
+def to_dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+# ---------------------------------------------------------------------------
+# Kernel level
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,p", [(96, 1000, 200), (128, 512, 16), (2048, 16384, 130), (1024, 300, 1)])
+def test_correlate_within_float32_bound(n, m, p):
+    pk = _lib()
+    rng = np.random.default_rng(n + m + p)
+    At = rng.standard_normal((m, n)).astype(np.float32)
+    Rt = rng.standard_normal((p, n)).astype(np.float32)
+    s = pk.Solver(to_dev(At), 0.1)
+    G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
+    A64, R64 = At.astype(np.float64), Rt.astype(np.float64)
+    ref = R64 @ A64.T
+    bound = 2 * n * 2.0 ** -24 * (np.abs(R64) @ np.abs(A64).T) + 1e-30
+    err = np.abs(G - ref)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3f}"
+
+
+@pytest.mark.parametrize("k", [1, 10, 33])
+def test_select_matches_cpu_sort(k):
+    pk = _lib()
+    rng = np.random.default_rng(k)
+    p, m = 37, 5000
+    s = pk.Solver(to_dev(np.eye(m, 64, dtype=np.float32)), 0.1)
+    G = rng.standard_normal((p, m)).astype(np.float32)
+    lam = np.quantile(np.abs(G), rng.uniform(0.9, 0.999, p), axis=1).diagonal().astype(np.float64)
+    lam[3] = 10.0                                   # a row with no violator
+    words = (m + 31) // 32
+    excl_bits = rng.random((p, m)) < 0.3
+    excl = np.zeros((p, words), dtype=np.uint32)
+    for i in range(p):
+        for j in np.nonzero(excl_bits[i])[0]:
+            excl[i, j >> 5] |= np.uint32(1 << (j & 31))
+    sel, nsel, vmax = s.select(to_dev(G), to_dev(lam), k, excl=to_dev(excl.view(np.int32)))
+    sel, nsel, vmax = sel.cpu().numpy(), nsel.cpu().numpy(), vmax.cpu().numpy()
+    for i in range(p):
+        a = np.abs(G[i]).copy()
+        a[excl_bits[i]] = -1
+        cand = np.nonzero(a.astype(np.float64) > lam[i])[0]
+        order = cand[np.lexsort((cand, -a[cand]))][:k]
+        assert nsel[i] == len(order)
+        np.testing.assert_array_equal(sel[i, :len(order)], order)
+        assert np.all(sel[i, len(order):] == -1)
+        assert vmax[i] == np.max(np.where(excl_bits[i], 0, np.abs(G[i])))
+
+
+# ---------------------------------------------------------------------------
+# Whole solves
+# ---------------------------------------------------------------------------
+
+def _solve_and_check(P, rho=None, rows=None, lam=None, **kw):
+    pk = _lib()
+    rho = P.rho if rho is None else rho
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel) if lam is None else lam
+    s = pk.Solver(to_dev(P.At), 0.0, rho=rho, **kw)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    torch.cuda.synchronize()
+    rows = range(P.p) if rows is None else rows
+    ref = oracle.solve(P.At, P.Bt[list(rows)], lam[list(rows)], rho, **{k: v for k, v in kw.items() if k in (
+        "max_outer", "max_active") and v})
+    st = out["status"].cpu().numpy()
+    return s, out, ref, lam, st
+
+
+def test_small_gaussian_full():
+    P = bi.small_gaussian()
+    s, out, ref, lam, st = _solve_and_check(P)
+    pk = _lib()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED)
+    assert np.all(ref["status"] == oracle.ST_CONVERGED)
+    check_batch(P.At, P.Bt, lam, out, ref)
+    kkt = out["kkt"].cpu().numpy()
+    assert np.all(kkt <= 1e-4)
+    # objective and lambda reported by the library
+    np.testing.assert_allclose(out["lambda"].cpu().numpy(), lam, rtol=0, atol=0)
+    np.testing.assert_allclose(out["objective"].cpu().numpy(), ref["objective"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("n,m,p,k,rho", [(96, 700, 150, 8, 3), (64, 4100, 300, 5, 10), (256, 2000, 257, 30, 7)])
+def test_ragged_tiles(n, m, p, k, rho):
+    P = bi.tiny_gaussian(n=n, m=m, p=p, k=k, sigma=0.01, seed=n + m, lambda_rel=0.05, rho=rho)
+    s, out, ref, lam, st = _solve_and_check(P)
+    pk = _lib()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED)
+    check_batch(P.At, P.Bt, lam, out, ref)
+
+
+def test_relative_lambda_rule():
+    pk = _lib()
+    P = bi.small_gaussian()
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho)
+    out = s.solve(to_dev(P.Bt))
+    lam_or = lam_rel(P.At, P.Bt, P.lambda_rel)
+    lam_gpu = out["lambda"].cpu().numpy()
+    np.testing.assert_allclose(lam_gpu, lam_or, rtol=2e-6)
+    ref = oracle.solve(P.At, P.Bt, lam_or, P.rho)
+    check_batch(P.At, P.Bt, lam_or, out, ref)
+
+
+def test_edge_cases():
+    pk = _lib()
+    P = bi.small_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    Bt = P.Bt.copy()
+    Bt[2, 7] = np.nan           # non-finite signal
+    Bt[5] = 0.0                 # zero signal
+    lam2 = lam.copy()
+    lam2[9] = np.abs(P.At.astype(np.float64) @ P.Bt[9].astype(np.float64)).max() * 1.01   # lambda above max
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho)
+    out = s.solve(to_dev(Bt), lam=to_dev(lam2))
+    st = out["status"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    ln = out["supp_len"].cpu().numpy()
+    assert st[2] == pk.BMPL_SIG_NONFINITE and ln[2] == 0
+    assert st[5] == pk.BMPL_SIG_CONVERGED and ln[5] == 0 and it[5] == 0
+    assert st[9] == pk.BMPL_SIG_CONVERGED and ln[9] == 0 and it[9] == 0
+    ok = [i for i in range(P.p) if i not in (2,)]
+    ref = oracle.solve(P.At, Bt[ok], lam2[ok], P.rho)
+    check_batch(P.At, Bt, lam2[ok], out, ref, rows=range(len(ok)), gpu_rows=ok)
+    # a single signal, and an empty batch
+    out1 = s.solve(to_dev(P.Bt[:1]), lam=to_dev(lam[:1]))
+    ref1 = oracle.solve(P.At, P.Bt[:1], lam[:1], P.rho)
+    check_batch(P.At, P.Bt[:1], lam[:1], out1, ref1)
+    out0 = s.solve(to_dev(P.Bt[:0]), lam=to_dev(lam[:0]))
+    assert out0["status"].numel() == 0
+
+
+def test_caps_match_oracle_caps():
+    pk = _lib()
+    P = bi.small_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_outer=2)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    st = out["status"].cpu().numpy()
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho, max_outer=2)
+    assert np.all((st & pk.BMPL_SIG_CAP_ITERS) == (ref["status"] & oracle.ST_CAP_ITERS) * 1)
+    np.testing.assert_array_equal(out["iters"].cpu().numpy(), ref["iters"])
+    # the capped iterate is the exact master solution on the same active sets
+    Xg = dense_from_gpu(out, P.m)
+    np.testing.assert_allclose(Xg, ref["X"], atol=1e-5)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_active=4)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    st = out["status"].cpu().numpy()
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho, max_active=4)
+    assert np.all(((st & pk.BMPL_SIG_CAP_ACTIVE) > 0) == ((ref["status"] & oracle.ST_CAP_ACTIVE) > 0))
+    np.testing.assert_allclose(dense_from_gpu(out, P.m), ref["X"], atol=1e-5)
+
+
+def test_warm_start_proposals_keep_parity():
+    pk = _lib()
+    P = bi.small_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    rng = np.random.default_rng(5)
+    warm = np.full((P.p, 24), -1, dtype=np.int32)
+    for i in range(P.p):
+        if i % 4 == 0:
+            continue                                          # empty proposal
+        prop = list(P.supports[i]) + list(rng.integers(0, P.m, 6))   # truth plus junk
+        if i % 4 == 1:
+            prop = list(rng.integers(0, P.m, 12))                     # all junk
+        prop = prop[:24]
+        warm[i, :len(prop)] = prop
+    warm[3, 0] = P.m + 5                                       # out of range entries are ignored
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam), warm=to_dev(warm))
+    st = out["status"].cpu().numpy()
+    assert np.all(st & pk.BMPL_SIG_CONVERGED)
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+    check_batch(P.At, P.Bt, lam, out, ref)
+    assert np.all(st[1::4] & pk.BMPL_SIG_FALLBACK)              # junk proposals needed the pursuit
+
+
+@pytest.mark.slow
+def test_cs_gaussian_full_size_sampled():
+    """2048 x 16384 dictionary, 1024 signals, rho = 10: the benchmark's workload and launch;
+    every 43rd signal is checked against the oracle."""
+    pk = _lib()
+    P = bi.cs_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho)
+    out = s.solve(to_dev(P.Bt))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED)
+    rows = list(range(0, P.p, 43))
+    np.testing.assert_allclose(out["lambda"].cpu().numpy(), lam, rtol=2e-6)
+    ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
+    errs = check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
+    assert max(e["rel_x"] for e in errs) <= 1e-4
