@@ -96,6 +96,37 @@ def test_duality_gap_of_eq5():
         D = -0.5 * alpha @ alpha + alpha @ b
         assert F - D <= 1e-12 * F
         assert abs(F - r["objective"][i]) <= 1e-12 * F
+        assert abs(r["gap"][i] - (F - D)) <= 1e-12 * F
+
+
+def independent_certificate(At, b, x, lam):
+    A = At.astype(np.float64).T
+    g = A.T @ (b.astype(np.float64) - A @ x)
+    on = x != 0
+    off = np.maximum(np.abs(g[~on]) - lam, 0.0).max(initial=0.0)
+    onv = np.abs(g[on] - lam * np.sign(x[on])).max(initial=0.0)
+    mu = min(np.min(lam - np.abs(g[~on]), initial=np.inf), np.min(np.abs(x[on]), initial=np.inf))
+    return max(off, onv) / lam, mu
+
+
+@pytest.mark.parametrize("max_outer", [1, 2, None])
+def test_reported_certificate_and_margin(max_outer):
+    # kappa and the margin reported by the oracle equal their definitions, also away from the optimum
+    P = bi.small_gaussian(indices=[0, 4, 8])
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    r = oracle.solve(P.At, P.Bt, lam, P.rho, max_outer=max_outer)
+    for i in range(P.p):
+        kap, mu = independent_certificate(P.At, P.Bt[i], r["X"][i], lam[i])
+        assert abs(r["kkt"][i] - kap) <= 1e-9 * max(1.0, kap)
+        A = P.At.astype(np.float64).T
+        b = P.Bt[i].astype(np.float64)
+        res = b - A @ r["X"][i]
+        F = 0.5 * res @ res + lam[i] * np.abs(r["X"][i]).sum()
+        alpha = res * min(1.0, lam[i] / np.abs(A.T @ res).max())
+        assert abs(r["gap"][i] - (F - (-0.5 * alpha @ alpha + alpha @ b))) <= 1e-12 * F
+        assert abs(r["margin"][i] - mu) <= 1e-9 * lam[i]
+        if max_outer == 1:
+            assert kap > 1e-3                        # one iteration is far from optimal here
 
 
 def test_orthonormal_dictionary_closed_form_and_iteration_count():
