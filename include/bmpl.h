@@ -71,7 +71,12 @@ typedef enum {
 #define BMPL_SIG_INEXACT    32   /* a restricted solve hit its step cap */
 
 /* bmpl_options.flags bits. */
-#define BMPL_FLAG_TIMING 1   /* time every kernel launch with HIP events (see bmpl_get_timing) */
+#define BMPL_FLAG_TIMING 1          /* time every kernel launch with HIP events (see bmpl_get_timing) */
+#define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
+
+/* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
+ * precomputed Q of Section III, Eq. (12)) when it is at most this large. */
+#define BMPL_GRAM_TABLE_MAX_BYTES (16.0 * 1024.0 * 1024.0 * 1024.0)
 
 typedef struct {
     int32_t rho;            /* atoms added per outer iteration (Algorithm 1, step 3); default 10 */
@@ -110,7 +115,10 @@ bmpl_status bmpl_options_default(bmpl_options* o);
 /*
  * Create a context for dictionary A (n x m, see conventions) and the lambda rule.
  * The library copies A into its own device memory (float32, rows padded to a
- * multiple of 32 with zeros), so the caller may free A_dev after the call.
+ * multiple of 32 with zeros), so the caller may free A_dev after the call, and
+ * unless BMPL_FLAG_NO_GRAM_TABLE is set (or the table would exceed
+ * BMPL_GRAM_TABLE_MAX_BYTES) computes the float64 Gram table Q = A^T A, from
+ * which the master problem gathers the Gram rows of atoms entering an active set.
  * `o` may be NULL for the defaults.  Work is enqueued on `hip_stream` and the
  * stream is synchronised before returning.  Errors: BMPL_E_INVALID for n <= 0,
  * m <= 0, lda < n, NULL pointers, lambda < 0 or a non-finite lambda, rho <= 0;
@@ -170,6 +178,15 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
 bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
                         const double* lambda_dev, const uint32_t* excl_dev, int32_t k,
                         int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev, void* hip_stream);
+
+/*
+ * Read-only access to the context's float64 Gram table Q = A^T A (the
+ * precomputed Q of Section III, Eq. (12)): *Q_dev receives the device pointer
+ * (owned by the context, valid until bmpl_destroy; NULL when no table was
+ * built) and *ldq its leading dimension (m, or 0).  Q[i*ldq + j] = a_i^T a_j,
+ * accumulated in float64 from the float32 atoms.  Errors: BMPL_E_INVALID for NULL.
+ */
+bmpl_status bmpl_gram_table(const bmpl_ctx* c, const double** Q_dev, int64_t* ldq);
 
 /*
  * Kernel timing accumulated over the solves run since the last reset, recorded

@@ -41,6 +41,7 @@ class Timing(ctypes.Structure):
 
 
 BMPL_FLAG_TIMING = 1
+BMPL_FLAG_NO_GRAM_TABLE = 2
 
 
 class _Result(ctypes.Structure):
@@ -70,9 +71,10 @@ def _load():
     lib.bmpl_correlate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
     lib.bmpl_select.argtypes = [vp, vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.bmpl_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.bmpl_gram_table.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     lib.bmpl_reset_timing.argtypes = [vp]
     for f in ("bmpl_options_default", "bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_correlate",
-              "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing"):
+              "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -84,6 +86,15 @@ def _check(rc: int, what: str):
     if rc != 0:
         msg = _lib.bmpl_last_error().decode(errors="replace")
         raise BmplError(f"{what} failed ({rc}): {msg}")
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    rc = hip.hipMemcpy(dst, src, nbytes, 3)   # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise BmplError(f"hipMemcpy failed ({rc})")
 
 
 def _stream_ptr(stream) -> int:
@@ -111,7 +122,7 @@ class Solver:
 
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
-                 stream=None):
+                 gram_table: bool = True, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
@@ -119,7 +130,7 @@ class Solver:
         _lib.bmpl_options_default(ctypes.byref(o))
         o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
         o.screen = _PREC[screen]
-        o.flags = BMPL_FLAG_TIMING if timing else 0
+        o.flags = (BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
         h = ctypes.c_void_p()
@@ -180,6 +191,19 @@ class Solver:
             _check(_lib.bmpl_solve(self._h, Bt.data_ptr(), n, p, lam_ptr or None, warm_ptr or None, warm_k,
                                    ctypes.byref(r), _stream_ptr(stream)), "bmpl_solve")
         out["_keep"] = (Bt, lam, warm)
+        return out
+
+    def gram_table(self) -> torch.Tensor | None:
+        """A copy of the float64 Gram table Q = A^T A held by the context, or None."""
+        q = ctypes.c_void_p()
+        ld = ctypes.c_int64()
+        _check(_lib.bmpl_gram_table(self._h, ctypes.byref(q), ctypes.byref(ld)), "bmpl_gram_table")
+        if not q.value:
+            return None
+        out = torch.empty((self.m, self.m), dtype=torch.float64, device=self.device)
+        nbytes = self.m * self.m * 8
+        torch.cuda.synchronize(self.device)
+        _memcpy_d2d(out.data_ptr(), q.value, nbytes)
         return out
 
     def timing(self) -> dict:

@@ -70,6 +70,8 @@ struct bmpl_ctx {
     int device = 0;
     int n = 0, m = 0, kpad = 0;
     float* At = nullptr;          // [m][kpad] float32 dictionary, atom-major
+    double* Q = nullptr;          // [m][m] float64 Gram table A^T A, or null
+    size_t lds_dyn_max = 0;       // dynamic LDS a solve workgroup may use (bytes)
     bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
     double lambda = 0.0;
     bmpl_options opt{};
@@ -85,6 +87,10 @@ struct bmpl_ctx {
     int* act[2] = {nullptr, nullptr};
     int* n_act_dev = nullptr;     // [2]
     int* h_count = nullptr;       // pinned host int
+
+    // correlation tile shape per running-signal bucket (>= 512, 64..511, < 64), set by bmpl_autotune
+    int corr_shape[3] = {0, 3, 4};
+    int corr_variant(int n_act) const { return corr_shape[n_act >= 512 ? 0 : (n_act >= 64 ? 1 : 2)]; }
 
     // diagnostic correlate staging
     float* diagR = nullptr;
@@ -164,7 +170,7 @@ void free_slots(Workspace& w)
 
 hipError_t alloc_slots(Workspace& w, int p, int K)
 {
-    const size_t pk = (size_t)p * K, pt = (size_t)p * (size_t)tri(K);
+    const size_t pk = (size_t)p * K, pt = (size_t)p * (size_t)tri(K), pkk = (size_t)p * K * K;
     hipError_t e;
     if ((e = dalloc(&w.slot_atom, pk)) != hipSuccess) return e;
     if ((e = dalloc(&w.x, pk)) != hipSuccess) return e;
@@ -172,9 +178,9 @@ hipError_t alloc_slots(Workspace& w, int p, int K)
     if ((e = dalloc(&w.theta, pk)) != hipSuccess) return e;
     if ((e = dalloc(&w.excl, pk)) != hipSuccess) return e;
     if ((e = dalloc(&w.sord, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.G, pt)) != hipSuccess) return e;
+    if ((e = dalloc(&w.G, pkk)) != hipSuccess) return e;
     if ((e = dalloc(&w.Rinv, pt)) != hipSuccess) return e;
-    if ((e = dalloc(&w.vscratch, pk * 6)) != hipSuccess) return e;
+    if ((e = dalloc(&w.vscratch, pk * 8)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -315,7 +321,31 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
+    // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
+    const double q_bytes = 8.0 * (double)m * (double)m;
+    if (e == hipSuccess && !(opt.flags & BMPL_FLAG_NO_GRAM_TABLE) && q_bytes <= BMPL_GRAM_TABLE_MAX_BYTES) {
+        e = dalloc(&c->Q, (size_t)m * (size_t)m);
+        if (e == hipSuccess) e = launch_gram_table(c->At, c->kpad, m, c->kpad, c->Q, m, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        int per_block = 0, optin = 0;
+        hipFuncAttributes fa{};
+        (void)hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+        if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, c->device) != hipSuccess)
+            optin = 0;
+        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(solve_kernel));
+        if (e == hipSuccess) {
+            size_t total = (size_t)per_block;
+            if (optin > per_block &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    optin - (int)fa.sharedSizeBytes) == hipSuccess)
+                total = (size_t)optin;
+            (void)hipGetLastError();
+            c->lds_dyn_max = total > fa.sharedSizeBytes + 256 ? total - fa.sharedSizeBytes - 256 : 0;
+        }
+    }
     if (e != hipSuccess) {
         bmpl_status st = fail(e == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP, "bmpl_create: %s",
                               hipGetErrorString(e));
@@ -331,6 +361,7 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     if (!c) return BMPL_OK;
     free_signals(c);
     dfree(c->At);
+    dfree(c->Q);
     dfree(c->n_act_dev);
     dfree(c->diagR);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -354,7 +385,7 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
     HIPC(hipMemsetAsync(c->diagR, 0, (size_t)p * c->kpad * sizeof(float), s));
     HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
                           hipMemcpyDeviceToDevice, s));
-    HIPC(launch_corr_gemm_f32(c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, s));
+    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, s));
     return BMPL_OK;
 }
 
@@ -431,7 +462,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const int nxt = 1 - cur;
         c->timing.outer_iters += tm ? 1 : 0;
         size_t e0 = tm ? mark(c, s) : 0;
-        HIPC(launch_corr_gemm_f32(c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur], c->n_act_dev + cur,
+        HIPC(launch_corr_gemm_f32(c->corr_variant(n_act), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur], c->n_act_dev + cur,
                                   n_act, c->Gc, c->ldg, s));
         if (tm) {
             const double mm = c->m, nn = c->n, pp = n_act;
@@ -467,18 +498,24 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const int add = (it == 0 && warm) ? std::max(warm_k, rho) : rho;
         imax = std::min(max_active, imax + add);
         if (imax > c->K_cap) {
-            int K_new = std::min(max_active, std::max(2 * c->K_cap, round_up(imax, 32)));
+            int K_new = std::min(max_active, round_up(std::max(imax + 4 * rho, c->K_cap + c->K_cap / 4), 32));
             st = grow_slots(c, K_new, s);
             if (st != BMPL_OK) return st;
         }
         SolveArgs so{};
         so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
+        so.Q = c->Q; so.ldq = c->m;
         so.act = c->act[nxt]; so.n_act_dev = c->n_act_dev + nxt;
         so.max_steps = 16 * w.K + 256;
-        const size_t lds = (size_t)w.K * (4 * sizeof(double) + sizeof(int));
-        so.use_lds = lds + 20000 <= 65536 ? 1 : 0;
+        // LDS: per-slot vectors first, then the inverse factor sized for this launch's largest |I|.
+        const size_t vec_bytes = (size_t)round_up(w.K * 58, 16);
+        so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
+        so.kl = std::min(imax, w.K);
+        const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
+        so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes <= c->lds_dyn_max) ? 1 : 0;
+        const size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
         e0 = tm ? mark(c, s) : 0;
-        hipLaunchKernelGGL(solve_kernel, dim3(n_act), dim3(256), so.use_lds ? lds : 0, s, so);
+        hipLaunchKernelGGL(solve_kernel, dim3(n_act), dim3(256), lds, s, so);
         HIPC(hipGetLastError());
         if (tm) span(c, e0, mark(c, s), K_SOLVE);
         cur = nxt;
@@ -494,6 +531,14 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         HIPC(hipStreamSynchronize(s));
         fold_timing(c, ev_first, e_last);
     }
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_gram_table(const bmpl_ctx* c, const double** Q_dev, int64_t* ldq)
+{
+    if (!c || !Q_dev || !ldq) return fail(BMPL_E_INVALID, "bmpl_gram_table: NULL argument");
+    *Q_dev = c->Q;
+    *ldq = c->Q ? c->m : 0;
     return BMPL_OK;
 }
 

@@ -49,9 +49,9 @@ struct Workspace {
     signed char* theta; // [p][K] sign per slot (0 = not in S)
     unsigned char* excl;// [p][K] slot excluded from S (linearly dependent)
     int* sord;          // [p][K] slot of each support position
-    double* G;          // [p][tri(K)] Gram of I, packed by slot
+    double* G;          // [p][K*K] Gram of I, row-major by slot
     double* Rinv;       // [p][tri(K)] inverse Cholesky factor of G_SS, packed by position
-    double* vscratch;   // [p][6K] vectors when they do not fit LDS
+    double* vscratch;   // [p][8K] vectors when they do not fit LDS
 };
 
 // Launchers (all asynchronous on `stream`).
@@ -61,10 +61,17 @@ struct Workspace {
 // Rbuf: [*][ldr] float32, ldr % 4 == 0, columns zero-padded to kpad.
 // act == nullptr means the identity map.  If n_act_dev != nullptr the active count is
 // read on the device and `p_grid` only sizes the grid.
-hipError_t launch_corr_gemm_f32(const float* At, int64_t lda, int m, int kpad,
+// `variant` selects the tile shape (0..5, see corr_shape_name).
+constexpr int CORR_VARIANTS = 6;
+const char* corr_shape_name(int variant);
+hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg,
                                 hipStream_t stream);
+
+// Q = A^T A in float64 (m x m, leading dimension ldq), from the padded float32 atoms.
+hipError_t launch_gram_table(const float* At, int64_t lda, int m, int kpad, double* Q, int64_t ldq,
+                             hipStream_t stream);
 
 // Top-k selection per row (worst-case analysis).  See bmpl_select in bmpl.h; here
 // `lam_rel` > 0 computes lambda[sig] = lam_rel * max_j |G| first (first pass).

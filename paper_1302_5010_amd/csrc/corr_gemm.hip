@@ -7,18 +7,22 @@
 // M = running signals, N = atoms, K = n, both operands K-contiguous (the
 // dictionary is stored atom by atom, residuals signal by signal).
 //
-// Tiling (gfx950, wave64): a 256-thread workgroup computes a 128 (signals) x
-// 128 (atoms) tile; each wave a 64 x 64 sub-tile as 2 x 2 v_mfma_f32_32x32x2f32
-// blocks (64 accumulator registers).  K is consumed 32 at a time through LDS;
-// the next K-slice is prefetched into registers while the current one is used.
-// Within each 8-wide k block, lane half h supplies k = 8b + 4h + t at step t, so
-// every LDS fragment read is one 16-byte ds_read per 4 MFMAs (the summation
-// order over k is immaterial to the contraction).
+// Tiling (gfx950, wave64): a workgroup computes a BM (signals) x BN (atoms)
+// tile; each wave a WM x WN sub-tile as (WM/32) x (WN/32) blocks of
+// v_mfma_f32_32x32x2f32.  K is consumed BK = 32 at a time through two LDS
+// buffers (one barrier per stage); the next K-slice is prefetched into
+// registers while the current one feeds the matrix cores.  Within each 8-wide
+// k block, lane half h supplies k = 8b + 4h + t at step t, so every LDS
+// fragment read is one 16-byte ds_read per 4 MFMAs (the summation order over k
+// is immaterial to the contraction).
 //
 // Output: G[a*ldg + j], a = compact index of the running signal, j = atom.  The
-// MFMA's row index carries the signal and its column (lane) index the atom, so
-// each accumulator register stores 32 consecutive atoms of one signal per
+// MFMA's row index carries the signal and its lane index the atom, so each
+// accumulator register stores 32 consecutive atoms of one signal per
 // half-wave (coalesced 128-byte stores).
+//
+// Several tile shapes are instantiated; the host picks one per launch from the
+// number of running signals (autotuned, see bmpl_autotune).
 #include "bmpl_internal.h"
 
 namespace bmpl {
@@ -26,17 +30,27 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128;   // signals per workgroup tile
-constexpr int BN = 128;   // atoms per workgroup tile
-constexpr int BK = 32;    // k per LDS stage
+constexpr int BK = 32;
 constexpr int LDS_STRIDE = BK + 4;   // floats per LDS row (16-byte aligned, staggers banks)
 
-__global__ __launch_bounds__(256) void corr_gemm_f32_kernel(
+template <int BM, int BN, int WM, int WN>
+struct Shape {
+    static constexpr int WAVES = (BM / WM) * (BN / WN);
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int TI = WM / 32;                 // MFMA blocks per wave, signal direction
+    static constexpr int TJ = WN / 32;                 // atom direction
+    static constexpr int LR = BM * (BK / 4) / THREADS; // float4 loads per thread, residual tile
+    static constexpr int LA = BN * (BK / 4) / THREADS; // dictionary tile
+    static_assert(LR * THREADS == BM * (BK / 4) && LA * THREADS == BN * (BK / 4), "tile/thread mismatch");
+};
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f32_kernel(
     const float* __restrict__ At, int64_t lda, int m, int kpad,
     const float* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
-    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg,
-    int tiles_n)
+    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n)
 {
+    using S = Shape<BM, BN, WM, WN>;
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
     // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
     // contiguous run of tiles (atom tiles outer, signal tiles inner) to share A rows in its L2.
@@ -55,96 +69,102 @@ __global__ __launch_bounds__(256) void corr_gemm_f32_kernel(
     const int atom0 = tn * BN;
     if (sig0 >= n_act) return;
 
-    __shared__ float sR[BM * LDS_STRIDE];
-    __shared__ float sA[BN * LDS_STRIDE];
+    __shared__ float sR[2][BM * LDS_STRIDE];
+    __shared__ float sA[2][BN * LDS_STRIDE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
-    // Global -> register staging: 4 float4 per operand per thread.
-    const int c4 = tid & 7;       // which float4 of the 32-wide k slice
-    const int r0 = tid >> 3;      // row 0..31, +32q
-    const float* pR[4];
-    const float* pA[4];
-    bool vR[4], vA[4];
+    // Global -> register staging.
+    const int c4 = tid & 7;                   // which float4 of the 32-wide k slice
+    const int r0 = tid >> 3;                  // first row; rows r0 + (THREADS/8) q
+    constexpr int RSTEP = S::THREADS / 8;
+    const float* pR[S::LR];
+    const float* pA[S::LA];
+    bool vR[S::LR], vA[S::LA];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int a = sig0 + r0 + 32 * q;
+    for (int q = 0; q < S::LR; ++q) {
+        const int a = sig0 + r0 + RSTEP * q;
         vR[q] = a < n_act;
-        int s = vR[q] ? (act ? act[a] : a) : 0;
+        const int s = vR[q] ? (act ? act[a] : a) : 0;
         pR[q] = Rbuf + (int64_t)s * ldr + 4 * c4;
-        int j = atom0 + r0 + 32 * q;
+    }
+#pragma unroll
+    for (int q = 0; q < S::LA; ++q) {
+        const int j = atom0 + r0 + RSTEP * q;
         vA[q] = j < m;
         pA[q] = At + (int64_t)(vA[q] ? j : 0) * lda + 4 * c4;
     }
-    float4 gR[4], gA[4];
+    float4 gR[S::LR], gA[S::LA];
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     auto load_slice = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            gR[q] = vR[q] ? *reinterpret_cast<const float4*>(pR[q] + k0) : zero4;
-            gA[q] = vA[q] ? *reinterpret_cast<const float4*>(pA[q] + k0) : zero4;
-        }
-    };
-    auto store_slice = [&]() {
+        for (int q = 0; q < S::LR; ++q) gR[q] = vR[q] ? *reinterpret_cast<const float4*>(pR[q] + k0) : zero4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            *reinterpret_cast<float4*>(&sR[(r0 + 32 * q) * LDS_STRIDE + 4 * c4]) = gR[q];
-            *reinterpret_cast<float4*>(&sA[(r0 + 32 * q) * LDS_STRIDE + 4 * c4]) = gA[q];
-        }
+        for (int q = 0; q < S::LA; ++q) gA[q] = vA[q] ? *reinterpret_cast<const float4*>(pA[q] + k0) : zero4;
+    };
+    auto store_slice = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < S::LR; ++q)
+            *reinterpret_cast<float4*>(&sR[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gR[q];
+#pragma unroll
+        for (int q = 0; q < S::LA; ++q)
+            *reinterpret_cast<float4*>(&sA[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gA[q];
     };
 
-    floatx16 acc[2][2];
+    floatx16 acc[S::TI][S::TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < S::TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const int ws = (wave & 1) * 64;    // wave's signal offset in the tile
-    const int wa = (wave >> 1) * 64;   // wave's atom offset in the tile
+    constexpr int WAVES_M = BM / WM;
+    const int ws = (wave % WAVES_M) * WM;   // wave's signal offset in the tile
+    const int wa = (wave / WAVES_M) * WN;   // wave's atom offset in the tile
     const int l32 = lane & 31;
     const int h = lane >> 5;
 
     load_slice(0);
-    store_slice();
+    store_slice(0);
     __syncthreads();
+    int cur = 0;
     for (int k0 = 0; k0 < kpad; k0 += BK) {
         const bool more = k0 + BK < kpad;
         if (more) load_slice(k0 + BK);
+        const float* cR = sR[cur];
+        const float* cA = sA[cur];
 #pragma unroll
         for (int kb = 0; kb < BK / 8; ++kb) {
-            float4 fr[2], fa[2];
+            float4 fr[S::TI], fa[S::TJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                fr[i] = *reinterpret_cast<const float4*>(&sR[(ws + 32 * i + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
+            for (int i = 0; i < S::TI; ++i)
+                fr[i] = *reinterpret_cast<const float4*>(&cR[(ws + 32 * i + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                fa[j] = *reinterpret_cast<const float4*>(&sA[(wa + 32 * j + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
+            for (int j = 0; j < S::TJ; ++j)
+                fa[j] = *reinterpret_cast<const float4*>(&cA[(wa + 32 * j + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < S::TJ; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].x, fa[j].x, acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].y, fa[j].y, acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].z, fa[j].z, acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].w, fa[j].w, acc[i][j], 0, 0, 0);
                 }
         }
+        if (more) store_slice(cur ^ 1);
         __syncthreads();
-        if (more) {
-            store_slice();
-            __syncthreads();
-        }
+        cur ^= 1;
     }
 
     // D[row][col] of a 32x32x2 block: lane l, register r -> row 8(r/4) + 4(l/32) + r%4, col l%32.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < S::TJ; ++j) {
             const int atom = atom0 + wa + 32 * j + l32;
             if (atom >= m) continue;
 #pragma unroll
@@ -155,21 +175,51 @@ __global__ __launch_bounds__(256) void corr_gemm_f32_kernel(
         }
 }
 
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const float* Rbuf, int64_t ldr,
+                        const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg,
+                        hipStream_t stream)
+{
+    const int tiles_m = (p_grid + BM - 1) / BM;
+    const int tiles_n = (m + BN - 1) / BN;
+    const int64_t nwg = (int64_t)tiles_m * tiles_n;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((corr_gemm_f32_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg),
+                       dim3(Shape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
+                       n_act_dev, p_grid, G, ldg, tiles_n);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_corr_gemm_f32(const float* At, int64_t lda, int m, int kpad,
+const char* corr_shape_name(int v)
+{
+    switch (v) {
+    case 0: return "128x128 (4 waves of 64x64)";
+    case 1: return "128x256 (8 waves of 64x64)";
+    case 2: return "256x128 (8 waves of 64x64)";
+    case 3: return "64x128 (4 waves of 32x64)";
+    case 4: return "32x64 (2 waves of 32x32)";
+    case 5: return "64x64 (4 waves of 32x32)";
+    default: return "?";
+    }
+}
+
+hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg,
                                 hipStream_t stream)
 {
     if (p_grid <= 0 || m <= 0) return hipSuccess;
-    const int tiles_m = (p_grid + BM - 1) / BM;
-    const int tiles_n = (m + BN - 1) / BN;
-    const int64_t nwg = (int64_t)tiles_m * tiles_n;
-    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(corr_gemm_f32_kernel, dim3((unsigned)nwg), dim3(256), 0, stream,
-                       At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, tiles_n);
-    return hipGetLastError();
+    switch (variant) {
+    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace bmpl

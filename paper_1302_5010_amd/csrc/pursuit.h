@@ -35,9 +35,12 @@ struct SolveArgs {
     Workspace w;
     const float* At; int64_t lda;
     const float* Bw;
+    const double* Q; int64_t ldq;   // Gram table A^T A (float64) or null
     const int* act; const int* n_act_dev;
     int max_steps;
-    int use_lds;
+    int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
+    int kl;
+    int vec_lds;                    // per-slot vectors in LDS
 };
 
 struct PackArgs {

@@ -35,7 +35,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NB = 16;      // new atoms per Gram pass
-constexpr int CH = 128;     // k per Gram staging chunk
+constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
 
 __device__ inline double block_sum(double v, double* red)
 {
@@ -75,73 +75,58 @@ __device__ inline void block_argmin(double& a, int& q, double* red, int* redi)
         if (red[w] < a || (red[w] == a && (unsigned)redi[w] < (unsigned)q)) { a = red[w]; q = redi[w]; }
 }
 
-struct SigView {
+// Per-signal working view inside the solve kernel.  G is global (row-major,
+// stride K); the rest points into LDS or into the global homes.
+struct Sig {
     int K;
-    int* slot_atom;
-    double* x;
-    double* c;
-    signed char* theta;
-    unsigned char* excl;
-    int* sord;
-    double* G;
-    double* Rinv;
+    double* G;            // G_II by slot
+    double* R;            // Rinv, packed lower row-major by support position
+    double* x;            // coefficient by slot
+    double* c;            // a_u^T b by slot
+    signed char* th;      // sign by slot, 0 = not in S
+    unsigned char* ex;    // slot excluded from S
+    int* so;              // slot of each support position
 };
 
-__device__ inline SigView view(const Workspace& w, int sig)
-{
-    SigView v;
-    v.K = w.K;
-    const int64_t K = w.K;
-    v.slot_atom = w.slot_atom + sig * K;
-    v.x = w.x + sig * K;
-    v.c = w.c + sig * K;
-    v.theta = w.theta + sig * K;
-    v.excl = w.excl + sig * K;
-    v.sord = w.sord + sig * K;
-    v.G = w.G + sig * tri(K);
-    v.Rinv = w.Rinv + sig * tri(K);
-    return v;
-}
-
-// Append slot j with sign th at support position s = *nS.  Returns false (and
-// marks j excluded) if its Schur complement pivot vanishes, i.e. a_j is
-// numerically in the span of A_S.
-__device__ bool chol_append(SigView& v, int& nS, int j, signed char th, double* vw, double* vz,
-                            double* red)
+// Append slot j with sign th at support position s = nS (a Cholesky row append
+// held as the inverse factor).  Returns false and excludes j if its Schur
+// complement pivot vanishes, i.e. a_j is numerically in the span of A_S.
+__device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, double* vz, double* red)
 {
     const int s = nS;
     const int tid = threadIdx.x;
-    for (int k = tid; k < s; k += NT) vw[k] = sym_at(v.G, v.sord[k], j);
+    const double* Gj = v.G + (int64_t)j * v.K;
+    for (int k = tid; k < s; k += NT) vw[k] = Gj[v.so[k]];
     __syncthreads();
     double part = 0.0;
-    for (int i = tid; i < s; i += NT) {      // z = Rinv w (row i of the packed factor)
-        const double* Ri = v.Rinv + tri(i);
+    for (int i = tid; i < s; i += NT) {      // z = Rinv w
+        const double* Ri = v.R + tri(i);
         double acc = 0.0;
         for (int k = 0; k <= i; ++k) acc += Ri[k] * vw[k];
         vz[i] = acc;
         part += acc * acc;
     }
     const double zz = block_sum(part, red);
-    const double gjj = v.G[tri(j) + j];
+    const double gjj = Gj[j];
     const double dd = gjj - zz;
     if (!(dd > 1e-11 * gjj)) {
-        if (tid == 0) { v.excl[j] = 1; v.theta[j] = 0; v.x[j] = 0.0; }
+        if (tid == 0) { v.ex[j] = 1; v.th[j] = 0; v.x[j] = 0.0; }
         __syncthreads();
         return false;
     }
     const double d = sqrt(dd);
-    double* Rs = v.Rinv + tri(s);
+    double* Rs = v.R + tri(s);
     for (int k = tid; k < s; k += NT) {      // new row: -(z^T Rinv)_k / d
         const int i0 = k & ~63;
         double acc = 0.0;
         for (int i = i0; i < s; ++i)
-            if (i >= k) acc += vz[i] * v.Rinv[tri(i) + k];
+            if (i >= k) acc += vz[i] * v.R[tri(i) + k];
         Rs[k] = -acc / d;
     }
     if (tid == 0) {
         Rs[s] = 1.0 / d;
-        v.sord[s] = j;
-        v.theta[j] = th;
+        v.so[s] = j;
+        v.th[j] = th;
     }
     nS = s + 1;
     __syncthreads();
@@ -149,16 +134,16 @@ __device__ bool chol_append(SigView& v, int& nS, int j, signed char th, double* 
 }
 
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
-__device__ void sign_fixed_solve(const SigView& v, int nS, double lam, double* vw, double* vz, double* vx)
+__device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, double* vz, double* vx)
 {
     const int tid = threadIdx.x;
     for (int k = tid; k < nS; k += NT) {
-        const int u = v.sord[k];
-        vw[k] = v.c[u] - lam * (double)v.theta[u];
+        const int u = v.so[k];
+        vw[k] = v.c[u] - lam * (double)v.th[u];
     }
     __syncthreads();
     for (int i = tid; i < nS; i += NT) {
-        const double* Ri = v.Rinv + tri(i);
+        const double* Ri = v.R + tri(i);
         double acc = 0.0;
         for (int k = 0; k <= i; ++k) acc += Ri[k] * vw[k];
         vz[i] = acc;
@@ -168,26 +153,106 @@ __device__ void sign_fixed_solve(const SigView& v, int nS, double lam, double* v
         const int i0 = k & ~63;
         double acc = 0.0;
         for (int i = i0; i < nS; ++i)
-            if (i >= k) acc += v.Rinv[tri(i) + k] * vz[i];
+            if (i >= k) acc += v.R[tri(i) + k] * vz[i];
         vx[k] = acc;
     }
     __syncthreads();
 }
 
-// g_u = c_u - sum_{k<nS} G(u, sord[k]) x_{sord[k]} for every slot u < nI (wave per slot).
-__device__ void restricted_gradient(const SigView& v, int nI, int nS, double* vg)
+// g_u = c_u - G_uS x_S for one slot, by one wave (returned in every lane).
+__device__ inline double grad_one(const Sig& v, int u, int nS)
+{
+    const int lane = threadIdx.x & 63;
+    const double* Gu = v.G + (int64_t)u * v.K;
+    double acc = 0.0;
+    for (int k = lane; k < nS; k += 64) {
+        const int sv = v.so[k];
+        acc += Gu[sv] * v.x[sv];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return v.c[u] - acc;
+}
+
+// Gradient of the slots outside S that may still enter it (wave per slot).
+__device__ void grad_outside_support(const Sig& v, int nI, int nS, double* vg)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int u = wave; u < nI; u += NT / 64) {
-        double acc = 0.0;
-        for (int k = lane; k < nS; k += 64) {
-            const int sv = v.sord[k];
-            acc += sym_at(v.G, u, sv) * v.x[sv];
-        }
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) vg[u] = v.c[u] - acc;
+        if (v.th[u] != 0 || v.ex[u]) continue;
+        const double g = grad_one(v, u, nS);
+        if (lane == 0) vg[u] = g;
     }
     __syncthreads();
+}
+
+// Gradient of every slot (wave per slot).
+__device__ void grad_all(const Sig& v, int nI, int nS, double* vg)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int u = wave; u < nI; u += NT / 64) {
+        const double g = grad_one(v, u, nS);
+        if (lane == 0) vg[u] = g;
+    }
+    __syncthreads();
+}
+
+// Gram rows G(q, u) of the new slots q against every slot u, and c_q = a_q^T b,
+// as n-long float64 dot products (used when no Gram table is available).  The
+// new atoms are staged through LDS in chunks; each thread owns one slot u.
+__device__ void gram_rows_direct(const SolveArgs& a, Sig& s, const int* g_atom, const float* bw, int nI0,
+                                 int nnew, int nI)
+{
+    __shared__ double s_new[CH * NB];
+    const int tid = threadIdx.x;
+    const int kpad = a.w.kpad;
+    const int K = s.K;
+    for (int g0 = 0; g0 < nnew; g0 += NB) {
+        const int nb = nnew - g0 < NB ? nnew - g0 : NB;
+        for (int ub = 0; ub <= nI; ub += NT) {
+            const int u = ub + tid;
+            const bool live = u <= nI;
+            const float* col = (u < nI) ? a.At + (int64_t)g_atom[u] * a.lda : bw;
+            double acc[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) acc[t] = 0.0;
+            for (int kc = 0; kc < kpad; kc += CH) {
+                __syncthreads();
+                for (int e = tid; e < nb * CH; e += NT) {
+                    const int t = e / CH, kk = e % CH;
+                    const int atom = g_atom[nI0 + g0 + t];
+                    s_new[kk * NB + t] = (kc + kk < kpad) ? (double)a.At[(int64_t)atom * a.lda + kc + kk] : 0.0;
+                }
+                __syncthreads();
+                if (live) {
+                    const int kend = (kpad - kc) < CH ? (kpad - kc) : CH;
+                    for (int kk = 0; kk < kend; kk += 4) {
+                        const float4 f = *reinterpret_cast<const float4*>(col + kc + kk);
+                        const double fv[4] = {(double)f.x, (double)f.y, (double)f.z, (double)f.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const double* sn = s_new + (kk + e) * NB;
+#pragma unroll
+                            for (int t = 0; t < NB; ++t)
+                                if (t < nb) acc[t] += fv[e] * sn[t];
+                        }
+                    }
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    if (t >= nb) break;
+                    const int q = nI0 + g0 + t;
+                    if (u == nI) {
+                        s.c[q] = acc[t];
+                    } else {
+                        s.G[(int64_t)q * K + u] = acc[t];
+                        s.G[(int64_t)u * K + q] = acc[t];
+                    }
+                }
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -333,13 +398,16 @@ __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
 
 // ---------------------------------------------------------------------------
 // Master problem on I for every running signal, then its residual and objective.
+//
+// Working set: the inverse factor Rinv and the per-slot vectors live in LDS
+// when they fit (copied in at entry, written back at exit), otherwise they are
+// used in place in global memory.  G_II (row-major, stride K) stays global.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
 {
     extern __shared__ double s_dyn[];
     __shared__ double red[4];
     __shared__ int redi[4];
-    __shared__ double s_new[CH * NB];
     __shared__ int s_list[NT];
     __shared__ int s_cnt;
 
@@ -351,76 +419,86 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nnew = w.nsel[sig];
     if (nnew <= 0) return;
-    SigView v = view(w, sig);
     const int K = w.K;
-    double* vb = a.use_lds ? s_dyn : (w.vscratch + (int64_t)sig * 6 * K);
-    double* vw = vb;
-    double* vz = vb + K;
-    double* vx = vb + 2 * K;
-    double* vg = vb + 3 * K;
-    int* vatom = reinterpret_cast<int*>(vb + 4 * K);
-
     const int nI0 = w.nI[sig];
     int nS = w.nS[sig];
     const double lam = w.lam[sig];
     const int nI = nI0 + nnew;
 
-    // 1. New slots.
+    // global homes of this signal's state
+    int* g_atom = w.slot_atom + (int64_t)sig * K;
+    double* g_x = w.x + (int64_t)sig * K;
+    double* g_c = w.c + (int64_t)sig * K;
+    signed char* g_th = w.theta + (int64_t)sig * K;
+    unsigned char* g_ex = w.excl + (int64_t)sig * K;
+    int* g_so = w.sord + (int64_t)sig * K;
+    double* g_R = w.Rinv + (int64_t)sig * tri(K);
+
+    Sig s;
+    s.K = K;
+    s.G = w.G + (int64_t)sig * K * K;
+    char* lp = reinterpret_cast<char*>(s_dyn);
+    if (a.rinv_lds) {
+        s.R = reinterpret_cast<double*>(lp);
+        lp += sizeof(double) * tri(a.kl);
+    } else {
+        s.R = g_R;
+    }
+    double *vw, *vz, *vx, *vg;
+    int* vatom;
+    if (a.vec_lds) {
+        double* d = reinterpret_cast<double*>(lp);
+        s.x = d; s.c = d + K; vw = d + 2 * K; vz = d + 3 * K; vx = d + 4 * K; vg = d + 5 * K;
+        int* ip = reinterpret_cast<int*>(d + 6 * K);
+        s.so = ip; vatom = ip + K;
+        s.th = reinterpret_cast<signed char*>(ip + 2 * K);
+        s.ex = reinterpret_cast<unsigned char*>(s.th + K);
+    } else {
+        double* d = w.vscratch + (int64_t)sig * 8 * K;
+        s.x = g_x; s.c = g_c; s.th = g_th; s.ex = g_ex; s.so = g_so;
+        vw = d; vz = d + K; vx = d + 2 * K; vg = d + 3 * K;
+        vatom = reinterpret_cast<int*>(d + 4 * K);
+    }
+
+    // 1. Load the state, register the new slots.
+    if (a.vec_lds) {
+        for (int u = tid; u < nI0; u += NT) {
+            s.x[u] = g_x[u]; s.c[u] = g_c[u]; s.th[u] = g_th[u]; s.ex[u] = g_ex[u];
+        }
+        for (int k = tid; k < nS; k += NT) s.so[k] = g_so[k];
+    }
+    if (a.rinv_lds)
+        for (int64_t e = tid; e < tri(nS); e += NT) s.R[e] = g_R[e];
     for (int t = tid; t < nnew; t += NT) {
         const int q = nI0 + t;
         const int atom = w.sel[(int64_t)sig * w.selcap + t];
-        v.slot_atom[q] = atom;
-        v.x[q] = 0.0;
-        v.theta[q] = 0;
-        v.excl[q] = 0;
+        g_atom[q] = atom;
+        s.x[q] = 0.0;
+        s.th[q] = 0;
+        s.ex[q] = 0;
         atomicOr(&w.inI[(int64_t)sig * w.words + (atom >> 5)], 1u << (atom & 31));
     }
     __syncthreads();
 
-    // 2. Gram rows of the new slots against every slot, and c = a^T b (slot index nI).
+    // 2. Gram rows of the new slots and c = A_J^T b, in float64.
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
-    for (int g0 = 0; g0 < nnew; g0 += NB) {
-        const int nb = nnew - g0 < NB ? nnew - g0 : NB;
-        for (int ub = 0; ub <= nI; ub += NT) {
-            const int u = ub + tid;
-            const bool live = u <= nI;
-            const float* col = (u < nI) ? a.At + (int64_t)v.slot_atom[u] * a.lda : bw;
-            double acc[NB];
-#pragma unroll
-            for (int t = 0; t < NB; ++t) acc[t] = 0.0;
-            for (int kc = 0; kc < w.kpad; kc += CH) {
-                __syncthreads();
-                for (int e = tid; e < nb * CH; e += NT) {
-                    const int t = e / CH, kk = e % CH;
-                    const int atom = v.slot_atom[nI0 + g0 + t];
-                    s_new[kk * NB + t] = (kc + kk < w.kpad) ? (double)a.At[(int64_t)atom * a.lda + kc + kk] : 0.0;
-                }
-                __syncthreads();
-                if (live) {
-                    const int kend = (w.kpad - kc) < CH ? (w.kpad - kc) : CH;
-                    for (int kk = 0; kk < kend; kk += 4) {
-                        const float4 f = *reinterpret_cast<const float4*>(col + kc + kk);
-                        const double fv[4] = {(double)f.x, (double)f.y, (double)f.z, (double)f.w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const double* sn = s_new + (kk + e) * NB;
-#pragma unroll
-                            for (int t = 0; t < NB; ++t)
-                                if (t < nb) acc[t] += fv[e] * sn[t];
-                        }
-                    }
-                }
-            }
-            if (live) {
-#pragma unroll
-                for (int t = 0; t < NB; ++t) {
-                    if (t >= nb) break;
-                    const int q = nI0 + g0 + t;
-                    if (u == nI) v.c[q] = acc[t];
-                    else if (u <= q) v.G[tri(q) + u] = acc[t];
-                }
-            }
+    if (a.Q) {
+        for (int e = tid; e < nnew * nI; e += NT) {
+            const int t = e / nI, u = e % nI;
+            const int q = nI0 + t;
+            const double val = a.Q[(int64_t)g_atom[q] * a.ldq + g_atom[u]];
+            s.G[(int64_t)q * K + u] = val;
+            s.G[(int64_t)u * K + q] = val;
         }
+        for (int t = wave; t < nnew; t += NT / 64) {
+            const float* aj = a.At + (int64_t)g_atom[nI0 + t] * a.lda;
+            double acc = 0.0;
+            for (int k = lane; k < w.kpad; k += 64) acc += (double)aj[k] * (double)bw[k];
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (lane == 0) s.c[nI0 + t] = acc;
+        }
+    } else {
+        gram_rows_direct(a, s, g_atom, bw, nI0, nnew, nI);
     }
     __syncthreads();
 
@@ -428,14 +506,13 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     int steps = 0;
     bool inexact = false;
     for (;;) {
-        restricted_gradient(v, nI, nS, vg);
-        // violators outside S in slot order (wave 0 ballot scan)
-        if (wave == 0) {
+        grad_outside_support(s, nI, nS, vg);
+        if (wave == 0) {    // violators outside S, in slot order
             int base = 0;
             for (int u0 = 0; u0 < nI && base < NT; u0 += 64) {
                 const int u = u0 + lane;
                 bool viol = false;
-                if (u < nI && v.theta[u] == 0 && !v.excl[u])
+                if (u < nI && s.th[u] == 0 && !s.ex[u])
                     viol = fabs(vg[u]) > lam * (1.0 + 1e-12) && fabs(vg[u]) > 0.0;
                 const unsigned long long bal = __ballot(viol);
                 const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -450,18 +527,22 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         for (int e = 0; e < nv; ++e) {
             const int u = s_list[e];
             const signed char th = vg[u] > 0.0 ? 1 : -1;
-            if (nS >= w.n) { if (tid == 0) v.excl[u] = 1; __syncthreads(); continue; }
-            chol_append(v, nS, u, th, vw, vz, red);
+            if (nS >= w.n) {
+                if (tid == 0) s.ex[u] = 1;
+                __syncthreads();
+                continue;
+            }
+            chol_append(s, nS, u, th, vw, vz, red);
         }
-        // inner loop: move toward the sign-fixed minimiser, dropping at zero crossings
+        // move toward the sign-fixed minimiser, dropping at zero crossings
         for (;;) {
             if (++steps > a.max_steps) { inexact = true; break; }
-            sign_fixed_solve(v, nS, lam, vw, vz, vx);
+            sign_fixed_solve(s, nS, lam, vw, vz, vx);
             double alpha = 1.0;
             int q = -1;
             for (int k = tid; k < nS; k += NT) {
-                const int u = v.sord[k];
-                const double xo = v.x[u], xn = vx[k], th = (double)v.theta[u];
+                const int u = s.so[k];
+                const double xo = s.x[u], xn = vx[k], th = (double)s.th[u];
                 if (xn * th <= 0.0) {
                     const double ak = (xo == 0.0) ? 0.0 : fmax(xo / (xo - xn), 0.0);
                     if (ak < alpha || (ak == alpha && (q < 0 || k < q))) { alpha = ak; q = k; }
@@ -469,27 +550,27 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             }
             block_argmin(alpha, q, red, redi);
             for (int k = tid; k < nS; k += NT) {
-                const int u = v.sord[k];
-                const double xo = v.x[u];
-                v.x[u] = xo + alpha * (vx[k] - xo);
+                const int u = s.so[k];
+                const double xo = s.x[u];
+                s.x[u] = xo + alpha * (vx[k] - xo);
             }
             __syncthreads();
             if (q < 0) break;
-            // drop position q and re-append the later positions in order
+            // drop position q and append the later positions again, in order
             const int ns_old = nS;
-            for (int k = tid; k < ns_old; k += NT) vatom[k] = v.sord[k];
+            for (int k = tid; k < ns_old; k += NT) vatom[k] = s.so[k];
             __syncthreads();
             if (tid == 0) {
                 const int u = vatom[q];
-                v.x[u] = 0.0;
-                v.theta[u] = 0;
+                s.x[u] = 0.0;
+                s.th[u] = 0;
             }
             __syncthreads();
             nS = q;
             for (int k = q + 1; k < ns_old; ++k) {
                 const int u = vatom[k];
-                if (!chol_append(v, nS, u, v.theta[u], vw, vz, red)) {
-                    if (tid == 0) v.x[u] = 0.0;
+                if (!chol_append(s, nS, u, s.th[u], vw, vz, red)) {
+                    if (tid == 0) s.x[u] = 0.0;
                     __syncthreads();
                 }
             }
@@ -498,33 +579,54 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     }
 
     // 4. Certificate on I (float64), residual xi = b - A_S x_S, objective.
-    restricted_gradient(v, nI, nS, vg);
+    grad_all(s, nI, nS, vg);
     double e = 0.0;
     for (int u = tid; u < nI; u += NT) {
         const double gu = vg[u];
-        const int th = v.theta[u];
-        double d = th != 0 ? fabs(gu - lam * th) : fabs(gu) - lam;
+        const int th = s.th[u];
+        const double d = th != 0 ? fabs(gu - lam * th) : fabs(gu) - lam;
         e = fmax(e, d);
     }
     const double kon = block_max(e, red);
     double l1 = 0.0;
     for (int k = tid; k < nS; k += NT) {
-        const int u = v.sord[k];
-        vatom[k] = v.slot_atom[u];
-        vx[k] = v.x[u];
-        l1 += fabs(v.x[u]);
+        const int u = s.so[k];
+        vatom[k] = g_atom[u];
+        vx[k] = s.x[u];
+        l1 += fabs(s.x[u]);
     }
     const double xl1 = block_sum(l1, red);
     double rr = 0.0;
     float* Rres = w.R + (int64_t)sig * w.kpad;
     for (int r = tid; r < w.kpad; r += NT) {
         double acc = (double)bw[r];
-        for (int k = 0; k < nS; ++k) acc -= (double)a.At[(int64_t)vatom[k] * a.lda + r] * vx[k];
+        int k = 0;
+        for (; k + 4 <= nS; k += 4) {
+            const double a0 = a.At[(int64_t)vatom[k] * a.lda + r];
+            const double a1 = a.At[(int64_t)vatom[k + 1] * a.lda + r];
+            const double a2 = a.At[(int64_t)vatom[k + 2] * a.lda + r];
+            const double a3 = a.At[(int64_t)vatom[k + 3] * a.lda + r];
+            acc -= a0 * vx[k];
+            acc -= a1 * vx[k + 1];
+            acc -= a2 * vx[k + 2];
+            acc -= a3 * vx[k + 3];
+        }
+        for (; k < nS; ++k) acc -= (double)a.At[(int64_t)vatom[k] * a.lda + r] * vx[k];
         if (r >= w.n) acc = 0.0;
         Rres[r] = (float)acc;
         rr += acc * acc;
     }
     const double rn = block_sum(rr, red);
+
+    // 5. Write the state back.
+    if (a.vec_lds) {
+        for (int u = tid; u < nI; u += NT) {
+            g_x[u] = s.x[u]; g_c[u] = s.c[u]; g_th[u] = s.th[u]; g_ex[u] = s.ex[u];
+        }
+        for (int k = tid; k < nS; k += NT) g_so[k] = s.so[k];
+    }
+    if (a.rinv_lds)
+        for (int64_t i = tid; i < tri(nS); i += NT) g_R[i] = s.R[i];
     if (tid == 0) {
         w.nI[sig] = nI;
         w.nS[sig] = nS;
@@ -533,7 +635,6 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         w.obj[sig] = 0.5 * rn + lam * xl1;
         if (inexact) w.status[sig] |= BMPL_SIG_INEXACT;
     }
-    (void)lane;
 }
 
 // ---------------------------------------------------------------------------
@@ -543,26 +644,29 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a)
 {
     const int sig = blockIdx.x;
     const Workspace& w = a.w;
-    SigView v = view(w, sig);
+    const int64_t K = w.K;
+    const int* so = w.sord + sig * K;
+    const double* xs = w.x + sig * K;
+    const int* at = w.slot_atom + sig * K;
     const int nS = (w.status[sig] & BMPL_SIG_NONFINITE) ? 0 : w.nS[sig];
     int cnt = 0;
     // rank by atom index among the support positions with a nonzero value
     for (int k = threadIdx.x; k < nS; k += 256) {
-        const int u = v.sord[k];
-        const double xu = v.x[u];
+        const int u = so[k];
+        const double xu = xs[u];
         if (xu == 0.0) continue;
-        const int atom = v.slot_atom[u];
+        const int atom = at[u];
         int rank = 0;
         for (int k2 = 0; k2 < nS; ++k2) {
-            const int u2 = v.sord[k2];
-            if (v.x[u2] != 0.0 && v.slot_atom[u2] < atom) ++rank;
+            const int u2 = so[k2];
+            if (xs[u2] != 0.0 && at[u2] < atom) ++rank;
         }
         if (rank < a.ld_x) {
             a.x_idx[(int64_t)sig * a.ld_x + rank] = atom;
             a.x_val[(int64_t)sig * a.ld_x + rank] = (float)xu;
         }
     }
-    for (int k = threadIdx.x; k < nS; k += 256) cnt += v.x[v.sord[k]] != 0.0;
+    for (int k = threadIdx.x; k < nS; k += 256) cnt += xs[so[k]] != 0.0;
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
     __shared__ int s_c[4];
     if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = cnt;
@@ -596,9 +700,13 @@ __global__ __launch_bounds__(256) void restride_kernel(RestrideArgs a)
         a.dst.excl[n1 + u] = a.src.excl[o1 + u];
     }
     for (int k = threadIdx.x; k < nS; k += 256) a.dst.sord[n1 + k] = a.src.sord[o1 + k];
-    const int64_t go = (int64_t)sig * tri(a.K_old), gn = (int64_t)sig * tri(a.K_new);
-    for (int64_t e = threadIdx.x; e < tri(nI); e += 256) a.dst.G[gn + e] = a.src.G[go + e];
-    for (int64_t e = threadIdx.x; e < tri(nS); e += 256) a.dst.Rinv[gn + e] = a.src.Rinv[go + e];
+    const int64_t go = (int64_t)sig * a.K_old * a.K_old, gn = (int64_t)sig * a.K_new * a.K_new;
+    for (int64_t e = threadIdx.x; e < (int64_t)nI * nI; e += 256) {
+        const int64_t u = e / nI, v = e % nI;
+        a.dst.G[gn + u * a.K_new + v] = a.src.G[go + u * a.K_old + v];
+    }
+    const int64_t ro = (int64_t)sig * tri(a.K_old), rn = (int64_t)sig * tri(a.K_new);
+    for (int64_t e = threadIdx.x; e < tri(nS); e += 256) a.dst.Rinv[rn + e] = a.src.Rinv[ro + e];
 }
 
 }  // namespace bmpl

@@ -120,12 +120,13 @@ def test_small_gaussian_full():
     np.testing.assert_allclose(out["objective"].cpu().numpy(), ref["objective"], rtol=1e-9)
 
 
+@pytest.mark.parametrize("gram_table", [True, False])
 @pytest.mark.parametrize("n,m,p,k,rho,c", [(96, 700, 150, 8, 3, 0.05), (64, 4100, 300, 5, 10, 0.05),
                                            (256, 2000, 257, 30, 7, 0.05),
                                            (320, 3000, 100, 50, 10, 0.03)])   # |I| > 64: capacity growth
-def test_ragged_tiles(n, m, p, k, rho, c):
+def test_ragged_tiles(n, m, p, k, rho, c, gram_table):
     P = bi.tiny_gaussian(n=n, m=m, p=p, k=k, sigma=0.01, seed=n + m, lambda_rel=c, rho=rho)
-    s, out, ref, lam, st = _solve_and_check(P)
+    s, out, ref, lam, st = _solve_and_check(P, gram_table=gram_table)
     pk = _lib()
     assert np.all(st == pk.BMPL_SIG_CONVERGED)
     check_batch(P.At, P.Bt, lam, out, ref)
@@ -233,3 +234,18 @@ def test_cs_gaussian_full_size_sampled():
     ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
     errs = check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
     assert max(e["rel_x"] for e in errs) <= 1e-4
+
+
+@pytest.mark.parametrize("n,m", [(96, 700), (2048, 300), (64, 129)])
+def test_gram_table_matches_float64(n, m):
+    pk = _lib()
+    rng = np.random.default_rng(n * m)
+    At = rng.standard_normal((m, n)).astype(np.float32)
+    s = pk.Solver(to_dev(At), 0.1)
+    Q = s.gram_table().cpu().numpy()
+    A64 = At.astype(np.float64)
+    ref = A64 @ A64.T
+    # float64 accumulation of exact products: within n ulps of the magnitudes
+    bound = n * 2.0 ** -52 * (np.abs(A64) @ np.abs(A64).T) * 2
+    assert np.all(np.abs(Q - ref) <= bound)
+    assert np.array_equal(Q, Q.T)
