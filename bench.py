@@ -71,6 +71,7 @@ def main():
     At = torch.from_numpy(P.At).to(dev)
     Bt = torch.from_numpy(P.Bt).to(dev)
     solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True)
+    tune = solver.autotune(P.p)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -126,9 +127,15 @@ def main():
             "launches": tm["corr_launches"],
             "algorithmic_gflop_per_step": tm["corr_flops"] / args.steps / 1e9,
         },
-        "kernel_ms_per_step": {k: tm[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms", "other_ms",
-                                                                "wall_ms")},
+        "kernel_ms_per_step": {k: tm[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms", "residual_ms",
+                                                                "other_ms", "wall_ms")},
+        "master_problem_counts_per_step": {k: tm[k] / args.steps for k in ("factor_appends", "factor_drops",
+                                                                            "sign_fixed_solves")},
         "outer_iters_per_step": tm["outer_iters"] / args.steps,
+        "solve_phase_us_per_step_summed_over_signals": dict(zip(
+            ("load", "gram", "active_set", "certificate", "unused", "writeback"),
+            [v / args.steps for v in tm["solve_phase_us"]])),
+        "autotune": tune,
         "signals": {"converged_per_step": conv, "kkt_max": float(np.max(kkt)),
                     "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
                     "support_mean": float(np.mean(supp))},

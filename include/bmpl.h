@@ -180,6 +180,26 @@ bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
                         int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev, void* hip_stream);
 
 /*
+ * Autotuner of the correlation product: times every tile shape of the float32
+ * MFMA kernel on this context's dictionary for three running-signal counts
+ * (min(p, 4096), min(p, 128), min(p, 32), representing the buckets >= 512,
+ * 64..511 and < 64 running signals) and keeps the fastest shape per bucket in
+ * the context; later solves use it.  shapes (3 ints) receives the chosen shape
+ * per bucket and ms (3 x 6 doubles, bucket-major) the average milliseconds per
+ * launch of every shape (-1 where not timed or not launchable); both may be
+ * NULL.  Synchronises `hip_stream`.  Errors: BMPL_E_INVALID (NULL context,
+ * p < 1), BMPL_E_NOMEM, BMPL_E_HIP.
+ */
+bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, void* hip_stream);
+
+/*
+ * Set the correlation tile shape per bucket by hand (3 ints in [0, 6), the
+ * same meaning as bmpl_autotune's `shapes`), e.g. from a cached tuning.
+ * Errors: BMPL_E_INVALID for NULL or an out-of-range shape.
+ */
+bmpl_status bmpl_set_tuning(bmpl_ctx* c, const int32_t* shapes);
+
+/*
  * Read-only access to the context's float64 Gram table Q = A^T A (the
  * precomputed Q of Section III, Eq. (12)): *Q_dev receives the device pointer
  * (owned by the context, valid until bmpl_destroy; NULL when no table was
@@ -202,10 +222,18 @@ typedef struct {
     double corr_ms; int64_t corr_launches; double corr_flops; double corr_bytes;
     double select_ms; int64_t select_launches;
     double solve_ms; int64_t solve_launches;
+    double residual_ms;     /* residual xi = b - A_S x_S and objective */
     double other_ms;        /* set-up, compaction, packing */
     double wall_ms;         /* first to last event of each solve, summed */
     int64_t solves;
     int64_t outer_iters;
+    /* master-problem kernel, summed over its workgroups (wall-clock counter, microseconds):
+     * [0] state load, [1] Gram rows, [2] active-set iterations, [3] certificate on I,
+     * [4] (unused), [5] state write-back */
+    double solve_phase_us[6];
+    int64_t factor_appends;     /* Cholesky row appends (including re-appends after drops) */
+    int64_t factor_drops;       /* support positions removed at a zero crossing */
+    int64_t sign_fixed_solves;  /* sign-fixed minimiser evaluations */
 } bmpl_timing;
 
 /* Copy the accumulated timing into *t.  Errors: BMPL_E_INVALID for NULL. */

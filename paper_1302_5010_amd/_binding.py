@@ -33,11 +33,15 @@ class Timing(ctypes.Structure):
     _fields_ = [("corr_ms", ctypes.c_double), ("corr_launches", ctypes.c_int64), ("corr_flops", ctypes.c_double),
                 ("corr_bytes", ctypes.c_double), ("select_ms", ctypes.c_double),
                 ("select_launches", ctypes.c_int64), ("solve_ms", ctypes.c_double),
-                ("solve_launches", ctypes.c_int64), ("other_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-                ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64)]
+                ("solve_launches", ctypes.c_int64), ("residual_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
+                ("wall_ms", ctypes.c_double), ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
+                ("solve_phase_us", ctypes.c_double * 6), ("factor_appends", ctypes.c_int64),
+                ("factor_drops", ctypes.c_int64), ("sign_fixed_solves", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["solve_phase_us"] = list(self.solve_phase_us)
+        return d
 
 
 BMPL_FLAG_TIMING = 1
@@ -72,9 +76,12 @@ def _load():
     lib.bmpl_select.argtypes = [vp, vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.bmpl_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.bmpl_gram_table.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.bmpl_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    lib.bmpl_set_tuning.argtypes = [vp, ctypes.POINTER(i32)]
     lib.bmpl_reset_timing.argtypes = [vp]
     for f in ("bmpl_options_default", "bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_correlate",
-              "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table"):
+              "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table", "bmpl_autotune",
+              "bmpl_set_tuning"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -192,6 +199,19 @@ class Solver:
                                    ctypes.byref(r), _stream_ptr(stream)), "bmpl_solve")
         out["_keep"] = (Bt, lam, warm)
         return out
+
+    def autotune(self, p: int, stream=None) -> dict:
+        """Time every correlation tile shape for this dictionary; the fastest per bucket is kept."""
+        shapes = (ctypes.c_int32 * 3)()
+        ms = (ctypes.c_double * 18)()
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_autotune(self._h, int(p), shapes, ms, _stream_ptr(stream)), "bmpl_autotune")
+        return {"shapes": list(shapes), "ms": [list(ms[b * 6:(b + 1) * 6]) for b in range(3)]}
+
+    def set_tuning(self, shapes):
+        """Correlation tile shape per running-signal bucket (>= 512, 64..511, < 64), each in 0..5."""
+        arr = (ctypes.c_int32 * 3)(*[int(v) for v in shapes])
+        _check(_lib.bmpl_set_tuning(self._h, arr), "bmpl_set_tuning")
 
     def gram_table(self) -> torch.Tensor | None:
         """A copy of the float64 Gram table Q = A^T A held by the context, or None."""

@@ -102,11 +102,13 @@ struct bmpl_ctx {
     size_t ev_used = 0;
     struct Span { size_t a, b; int kind; double flops, bytes; };
     std::vector<Span> spans;
+    uint64_t* phase_dev = nullptr;     // [6] solve-kernel phase ticks
+    int wall_khz = 0;
 };
 
 namespace {
 
-enum { K_CORR = 0, K_SELECT = 1, K_SOLVE = 2, K_OTHER = 3 };
+enum { K_CORR = 0, K_SELECT = 1, K_SOLVE = 2, K_OTHER = 3, K_RESID = 4 };
 
 bool timing_on(const bmpl_ctx* c) { return (c->opt.flags & BMPL_FLAG_TIMING) != 0; }
 
@@ -141,6 +143,7 @@ void fold_timing(bmpl_ctx* c, size_t first, size_t last)
             break;
         case K_SELECT: c->timing.select_ms += ms; c->timing.select_launches++; break;
         case K_SOLVE: c->timing.solve_ms += ms; c->timing.solve_launches++; break;
+        case K_RESID: c->timing.residual_ms += ms; break;
         default: c->timing.other_ms += ms; break;
         }
     }
@@ -203,7 +206,8 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     free_signals(c);
     Workspace& w = c->w;
     const size_t P = p;
-    HIPC(dalloc(&w.R, P * c->kpad));
+    HIPC(dalloc(&w.R, (P + 1) * c->kpad));
+    HIPC(hipMemset(w.R + P * c->kpad, 0, c->kpad * sizeof(float)));   // the correlation's zero row
     HIPC(dalloc(&w.bnorm2, P));
     HIPC(dalloc(&w.lam, P));
     HIPC(dalloc(&w.status, P));
@@ -314,10 +318,10 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     c->w.kpad = c->kpad;
     c->w.m = m;
     c->w.words = (m + 31) / 32;
-    e = dalloc(&c->At, (size_t)m * c->kpad);
+    e = dalloc(&c->At, (size_t)(m + 1) * c->kpad);   // row m stays zero
     if (e == hipSuccess) e = dalloc(&c->n_act_dev, 2);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_count), sizeof(int), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemsetAsync(c->At, 0, (size_t)m * c->kpad * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->At, 0, (size_t)(m + 1) * c->kpad * sizeof(float), s);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
@@ -364,6 +368,7 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     dfree(c->Q);
     dfree(c->n_act_dev);
     dfree(c->diagR);
+    dfree(c->phase_dev);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->h_count) (void)hipHostFree(c->h_count);
     delete c;
@@ -379,13 +384,13 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     if (p > c->diag_cap) {
         dfree(c->diagR);
-        HIPC(dalloc(&c->diagR, (size_t)p * c->kpad));
+        HIPC(dalloc(&c->diagR, (size_t)(p + 1) * c->kpad));
         c->diag_cap = p;
     }
-    HIPC(hipMemsetAsync(c->diagR, 0, (size_t)p * c->kpad * sizeof(float), s));
+    HIPC(hipMemsetAsync(c->diagR, 0, (size_t)(p + 1) * c->kpad * sizeof(float), s));
     HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
                           hipMemcpyDeviceToDevice, s));
-    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, s));
+    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, p, s));
     return BMPL_OK;
 }
 
@@ -440,6 +445,11 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const bool tm = timing_on(c);
     c->spans.clear();
     c->ev_used = 0;
+    if (tm && !c->phase_dev) {
+        HIPC(dalloc(&c->phase_dev, 9));
+        HIPC(hipMemsetAsync(c->phase_dev, 0, 9 * sizeof(uint64_t), s));
+        HIPC(hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, c->device));
+    }
     const size_t ev_first = tm ? mark(c, s) : (size_t)-1;
     PrepArgs pa{w, B_dev, ldb, c->Bw, lambda_dev, c->lambda, rel ? 1 : 0};
     hipLaunchKernelGGL(prep_kernel, dim3(p), dim3(256), 0, s, pa);
@@ -462,8 +472,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const int nxt = 1 - cur;
         c->timing.outer_iters += tm ? 1 : 0;
         size_t e0 = tm ? mark(c, s) : 0;
-        HIPC(launch_corr_gemm_f32(c->corr_variant(n_act), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur], c->n_act_dev + cur,
-                                  n_act, c->Gc, c->ldg, s));
+        HIPC(launch_corr_gemm_f32(c->corr_variant(n_act), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
+                                  c->n_act_dev + cur, n_act, c->Gc, c->ldg, c->p_cap, s));
         if (tm) {
             const double mm = c->m, nn = c->n, pp = n_act;
             span(c, e0, mark(c, s), K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
@@ -507,6 +517,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.Q = c->Q; so.ldq = c->m;
         so.act = c->act[nxt]; so.n_act_dev = c->n_act_dev + nxt;
         so.max_steps = 16 * w.K + 256;
+        so.phase = tm ? c->phase_dev : nullptr;
         // LDS: per-slot vectors first, then the inverse factor sized for this launch's largest |I|.
         const size_t vec_bytes = (size_t)round_up(w.K * 58, 16);
         so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
@@ -517,7 +528,11 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         e0 = tm ? mark(c, s) : 0;
         hipLaunchKernelGGL(solve_kernel, dim3(n_act), dim3(256), lds, s, so);
         HIPC(hipGetLastError());
-        if (tm) span(c, e0, mark(c, s), K_SOLVE);
+        if (tm) { span(c, e0, mark(c, s), K_SOLVE); e0 = mark(c, s); }
+        ResidualArgs ra{w, c->At, c->kpad, c->Bw, c->act[nxt], c->n_act_dev + nxt};
+        hipLaunchKernelGGL(residual_kernel, dim3(n_act), dim3(256), (size_t)w.K * 12, s, ra);
+        HIPC(hipGetLastError());
+        if (tm) span(c, e0, mark(c, s), K_RESID);
         cur = nxt;
     }
     const size_t e_pack = tm ? mark(c, s) : 0;
@@ -534,6 +549,63 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     return BMPL_OK;
 }
 
+bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, void* hip_stream)
+{
+    if (!c) return fail(BMPL_E_INVALID, "bmpl_autotune: NULL context");
+    if (p < 1) return fail(BMPL_E_INVALID, "bmpl_autotune: p must be >= 1");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int rho = c->opt.rho;
+    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), std::max(c->K_cap, 64), std::max(c->selcap, rho));
+    if (st != BMPL_OK) return st;
+    Workspace& w = c->w;
+    HIPC(hipMemsetAsync(w.R, 0, (size_t)p * c->kpad * sizeof(float), s));
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    const int reps[3] = {std::min(p, 4096), std::min(p, 128), std::min(p, 32)};
+    const int lo[3] = {512, 64, 1};
+    for (int b = 0; b < 3; ++b) {
+        const int nb = reps[b];
+        double best = 1e30;
+        for (int v = 0; v < CORR_VARIANTS; ++v) {
+            double t = -1.0;
+            if (nb >= lo[b]) {
+                hipError_t e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr,
+                                                    nb, c->Gc, c->ldg, c->p_cap, s);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                for (int r = 0; r < 3 && e == hipSuccess; ++r)
+                    e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr, nb,
+                                             c->Gc, c->ldg, c->p_cap, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float f = 0.f;
+                if (e == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess) t = f / 3.0;
+                (void)hipGetLastError();
+                if (t > 0.0 && t < best) {
+                    best = t;
+                    c->corr_shape[b] = v;
+                }
+            }
+            if (ms) ms[b * CORR_VARIANTS + v] = t;
+        }
+        if (shapes) shapes[b] = c->corr_shape[b];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(hipStreamSynchronize(s));
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_set_tuning(bmpl_ctx* c, const int32_t* shapes)
+{
+    if (!c || !shapes) return fail(BMPL_E_INVALID, "bmpl_set_tuning: NULL argument");
+    for (int b = 0; b < 3; ++b)
+        if (shapes[b] < 0 || shapes[b] >= CORR_VARIANTS)
+            return fail(BMPL_E_INVALID, "bmpl_set_tuning: shape %d out of range", shapes[b]);
+    for (int b = 0; b < 3; ++b) c->corr_shape[b] = shapes[b];
+    return BMPL_OK;
+}
+
 bmpl_status bmpl_gram_table(const bmpl_ctx* c, const double** Q_dev, int64_t* ldq)
 {
     if (!c || !Q_dev || !ldq) return fail(BMPL_E_INVALID, "bmpl_gram_table: NULL argument");
@@ -546,6 +618,14 @@ bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t)
 {
     if (!c || !t) return fail(BMPL_E_INVALID, "bmpl_get_timing: NULL argument");
     *t = c->timing;
+    if (c->phase_dev && c->wall_khz > 0) {
+        uint64_t ticks[9];
+        HIPC(hipMemcpy(ticks, c->phase_dev, sizeof ticks, hipMemcpyDeviceToHost));
+        for (int i = 0; i < 6; ++i) t->solve_phase_us[i] = (double)ticks[i] * 1e3 / c->wall_khz;
+        t->factor_appends = (int64_t)ticks[6];
+        t->factor_drops = (int64_t)ticks[7];
+        t->sign_fixed_solves = (int64_t)ticks[8];
+    }
     return BMPL_OK;
 }
 
@@ -553,6 +633,7 @@ bmpl_status bmpl_reset_timing(bmpl_ctx* c)
 {
     if (!c) return fail(BMPL_E_INVALID, "bmpl_reset_timing: NULL context");
     c->timing = bmpl_timing{};
+    if (c->phase_dev) HIPC(hipMemset(c->phase_dev, 0, 9 * sizeof(uint64_t)));
     return BMPL_OK;
 }
 

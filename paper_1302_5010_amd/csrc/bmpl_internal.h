@@ -28,7 +28,7 @@ struct Workspace {
     int K;          // slot capacity per signal
     int p;          // signals in the current solve
 
-    float* R;           // [p][kpad] float32 residuals xi_i (zero rows past n)
+    float* R;           // [p_cap + 1][kpad] float32 residuals xi_i (zero rows past n; row p_cap all zero)
     double* bnorm2;     // [p] ||b_i||^2
     double* lam;        // [p] lambda_i
     int* status;        // [p] BMPL_SIG_* bits
@@ -57,8 +57,8 @@ struct Workspace {
 // Launchers (all asynchronous on `stream`).
 
 // G[a*ldg + j] = a_j^T r_{act[a]} for a < n_active, j < m, float32 MFMA.
-// At: atom-major [m][lda] float32 with lda % 4 == 0, zero-padded to kpad.
-// Rbuf: [*][ldr] float32, ldr % 4 == 0, columns zero-padded to kpad.
+// At: atom-major [m + 1][lda] float32 with lda % 4 == 0, zero-padded to kpad, row m all zero.
+// Rbuf: [*][ldr] float32, ldr % 4 == 0, columns zero-padded to kpad; row `zero_row` all zero.
 // act == nullptr means the identity map.  If n_act_dev != nullptr the active count is
 // read on the device and `p_grid` only sizes the grid.
 // `variant` selects the tile shape (0..5, see corr_shape_name).
@@ -66,7 +66,7 @@ constexpr int CORR_VARIANTS = 6;
 const char* corr_shape_name(int variant);
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
-                                const int* n_act_dev, int p_grid, float* G, int64_t ldg,
+                                const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                 hipStream_t stream);
 
 // Q = A^T A in float64 (m x m, leading dimension ldq), from the padded float32 atoms.

@@ -48,7 +48,7 @@ template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f32_kernel(
     const float* __restrict__ At, int64_t lda, int m, int kpad,
     const float* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
-    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n)
+    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row)
 {
     using S = Shape<BM, BN, WM, WN>;
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
@@ -76,42 +76,43 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
-    // Global -> register staging.
+    // Global -> register staging (element offsets from the kernel-argument base pointers, so the
+    // loads stay global and the staging registers are never spilled).  Rows past the end point at
+    // an all-zero row (row `zero_row` of the residuals, row m of the dictionary), so every load is
+    // unconditional and is consumed only by the LDS store at the end of the stage.
     const int c4 = tid & 7;                   // which float4 of the 32-wide k slice
     const int r0 = tid >> 3;                  // first row; rows r0 + (THREADS/8) q
     constexpr int RSTEP = S::THREADS / 8;
-    const float* pR[S::LR];
-    const float* pA[S::LA];
-    bool vR[S::LR], vA[S::LA];
+    int64_t oR[S::LR], oA[S::LA];
+    bool vR[S::LR], vA[S::LA];   // row in range (only used to pick the zero row)
 #pragma unroll
     for (int q = 0; q < S::LR; ++q) {
         const int a = sig0 + r0 + RSTEP * q;
         vR[q] = a < n_act;
-        const int s = vR[q] ? (act ? act[a] : a) : 0;
-        pR[q] = Rbuf + (int64_t)s * ldr + 4 * c4;
+        const int s = vR[q] ? (act ? act[a] : a) : zero_row;
+        oR[q] = (int64_t)s * ldr + 4 * c4;
     }
 #pragma unroll
     for (int q = 0; q < S::LA; ++q) {
         const int j = atom0 + r0 + RSTEP * q;
         vA[q] = j < m;
-        pA[q] = At + (int64_t)(vA[q] ? j : 0) * lda + 4 * c4;
+        oA[q] = (int64_t)(vA[q] ? j : m) * lda + 4 * c4;
     }
     float4 gR[S::LR], gA[S::LA];
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    auto load_slice = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < S::LR; ++q) gR[q] = vR[q] ? *reinterpret_cast<const float4*>(pR[q] + k0) : zero4;
-#pragma unroll
-        for (int q = 0; q < S::LA; ++q) gA[q] = vA[q] ? *reinterpret_cast<const float4*>(pA[q] + k0) : zero4;
-    };
-    auto store_slice = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < S::LR; ++q)
-            *reinterpret_cast<float4*>(&sR[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gR[q];
-#pragma unroll
-        for (int q = 0; q < S::LA; ++q)
-            *reinterpret_cast<float4*>(&sA[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gA[q];
-    };
+#define CORR_LOAD_SLICE(k0)                                                                                 \
+    do {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < S::LR; ++q)                                                  \
+            gR[q] = *reinterpret_cast<const float4*>(Rbuf + oR[q] + (k0));                                  \
+        _Pragma("unroll") for (int q = 0; q < S::LA; ++q)                                                  \
+            gA[q] = *reinterpret_cast<const float4*>(At + oA[q] + (k0));                                    \
+    } while (0)
+#define CORR_STORE_SLICE(buf)                                                                               \
+    do {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < S::LR; ++q)                                                  \
+            *reinterpret_cast<float4*>(&sR[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gR[q];          \
+        _Pragma("unroll") for (int q = 0; q < S::LA; ++q)                                                  \
+            *reinterpret_cast<float4*>(&sA[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gA[q];          \
+    } while (0)
 
     floatx16 acc[S::TI][S::TJ];
 #pragma unroll
@@ -127,13 +128,15 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
     const int l32 = lane & 31;
     const int h = lane >> 5;
 
-    load_slice(0);
-    store_slice(0);
+    CORR_LOAD_SLICE(0);
+    CORR_STORE_SLICE(0);
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < kpad; k0 += BK) {
-        const bool more = k0 + BK < kpad;
-        if (more) load_slice(k0 + BK);
+        // prefetch the next slice (the last iteration re-reads the final slice; its copy is never used)
+        const int kn = k0 + BK < kpad ? k0 + BK : k0;
+        CORR_LOAD_SLICE(kn);
+        asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
         const float* cR = sR[cur];
         const float* cA = sA[cur];
 #pragma unroll
@@ -145,20 +148,36 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
 #pragma unroll
             for (int j = 0; j < S::TJ; ++j)
                 fa[j] = *reinterpret_cast<const float4*>(&cA[(wa + 32 * j + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
+            // k step outermost: consecutive MFMAs write different accumulators
 #pragma unroll
             for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < S::TJ; ++j) {
+                for (int j = 0; j < S::TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].x, fa[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].y, fa[j].y, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].z, fa[j].z, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].w, fa[j].w, acc[i][j], 0, 0, 0);
-                }
         }
-        if (more) store_slice(cur ^ 1);
+        asm volatile("" ::: "memory");       // and consume it only after
+        CORR_STORE_SLICE(cur ^ 1);
         __syncthreads();
         cur ^= 1;
     }
+
+#undef CORR_LOAD_SLICE
+#undef CORR_STORE_SLICE
 
     // D[row][col] of a 32x32x2 block: lane l, register r -> row 8(r/4) + 4(l/32) + r%4, col l%32.
 #pragma unroll
@@ -177,7 +196,7 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
 
 template <int BM, int BN, int WM, int WN>
 hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const float* Rbuf, int64_t ldr,
-                        const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg,
+                        const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                         hipStream_t stream)
 {
     const int tiles_m = (p_grid + BM - 1) / BM;
@@ -186,7 +205,7 @@ hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const flo
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((corr_gemm_f32_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg),
                        dim3(Shape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
-                       n_act_dev, p_grid, G, ldg, tiles_n);
+                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row);
     return hipGetLastError();
 }
 
@@ -207,17 +226,17 @@ const char* corr_shape_name(int v)
 
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
-                                const int* n_act_dev, int p_grid, float* G, int64_t ldg,
+                                const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                 hipStream_t stream)
 {
     if (p_grid <= 0 || m <= 0) return hipSuccess;
     switch (variant) {
-    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
-    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
-    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
-    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
-    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
-    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, stream);
+    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
     default: return hipErrorInvalidValue;
     }
 }

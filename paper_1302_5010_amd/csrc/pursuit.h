@@ -41,6 +41,15 @@ struct SolveArgs {
     int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
+    uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,
+                                    // then counts of factor appends, drops and solves; or null
+};
+
+struct ResidualArgs {
+    Workspace w;
+    const float* At; int64_t lda;
+    const float* Bw;
+    const int* act; const int* n_act_dev;
 };
 
 struct PackArgs {
@@ -65,6 +74,7 @@ __global__ void prep_kernel(PrepArgs a);
 __global__ void status_compact_kernel(StatusArgs a);
 __global__ void warm_select_kernel(WarmArgs a);
 __global__ void solve_kernel(SolveArgs a);
+__global__ void residual_kernel(ResidualArgs a);
 __global__ void pack_kernel(PackArgs a);
 __global__ void restride_kernel(RestrideArgs a);
 

@@ -91,10 +91,12 @@ struct Sig {
 // Append slot j with sign th at support position s = nS (a Cholesky row append
 // held as the inverse factor).  Returns false and excludes j if its Schur
 // complement pivot vanishes, i.e. a_j is numerically in the span of A_S.
-__device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, double* vz, double* red)
+__device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, double* vz, double* red,
+                            uint64_t* cnt)
 {
     const int s = nS;
     const int tid = threadIdx.x;
+    if (cnt && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
     const double* Gj = v.G + (int64_t)j * v.K;
     for (int k = tid; k < s; k += NT) vw[k] = Gj[v.so[k]];
     __syncthreads();
@@ -159,39 +161,29 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
     __syncthreads();
 }
 
-// g_u = c_u - G_uS x_S for one slot, by one wave (returned in every lane).
-__device__ inline double grad_one(const Sig& v, int u, int nS)
+// g_u = c_u - G_uS x_S for the slots u < nI (all of them, or only those outside S
+// that may still enter it), one thread per slot streaming its own row of G.
+__device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outside_only)
 {
-    const int lane = threadIdx.x & 63;
-    const double* Gu = v.G + (int64_t)u * v.K;
-    double acc = 0.0;
-    for (int k = lane; k < nS; k += 64) {
-        const int sv = v.so[k];
-        acc += Gu[sv] * v.x[sv];
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return v.c[u] - acc;
-}
-
-// Gradient of the slots outside S that may still enter it (wave per slot).
-__device__ void grad_outside_support(const Sig& v, int nI, int nS, double* vg)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int u = wave; u < nI; u += NT / 64) {
-        if (v.th[u] != 0 || v.ex[u]) continue;
-        const double g = grad_one(v, u, nS);
-        if (lane == 0) vg[u] = g;
-    }
-    __syncthreads();
-}
-
-// Gradient of every slot (wave per slot).
-__device__ void grad_all(const Sig& v, int nI, int nS, double* vg)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int u = wave; u < nI; u += NT / 64) {
-        const double g = grad_one(v, u, nS);
-        if (lane == 0) vg[u] = g;
+    for (int u = threadIdx.x; u < nI; u += NT) {
+        if (outside_only && (v.th[u] != 0 || v.ex[u])) continue;
+        const double* Gu = v.G + (int64_t)u * v.K;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = 0;
+        for (; k + 8 <= nS; k += 8) {
+            double gv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gv[e] = Gu[v.so[k + e]];
+            a0 += gv[0] * v.x[v.so[k]] + gv[4] * v.x[v.so[k + 4]];
+            a1 += gv[1] * v.x[v.so[k + 1]] + gv[5] * v.x[v.so[k + 5]];
+            a2 += gv[2] * v.x[v.so[k + 2]] + gv[6] * v.x[v.so[k + 6]];
+            a3 += gv[3] * v.x[v.so[k + 3]] + gv[7] * v.x[v.so[k + 7]];
+        }
+        for (; k < nS; ++k) {
+            const int s0 = v.so[k];
+            a0 += Gu[s0] * v.x[s0];
+        }
+        vg[u] = v.c[u] - ((a0 + a1) + (a2 + a3));
     }
     __syncthreads();
 }
@@ -424,6 +416,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     int nS = w.nS[sig];
     const double lam = w.lam[sig];
     const int nI = nI0 + nnew;
+    uint64_t tick = a.phase ? wall_clock64() : 0;
 
     // global homes of this signal's state
     int* g_atom = w.slot_atom + (int64_t)sig * K;
@@ -469,10 +462,12 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     }
     if (a.rinv_lds)
         for (int64_t e = tid; e < tri(nS); e += NT) s.R[e] = g_R[e];
+    for (int u = tid; u < nI0; u += NT) vatom[u] = g_atom[u];
     for (int t = tid; t < nnew; t += NT) {
         const int q = nI0 + t;
         const int atom = w.sel[(int64_t)sig * w.selcap + t];
         g_atom[q] = atom;
+        vatom[q] = atom;
         s.x[q] = 0.0;
         s.th[q] = 0;
         s.ex[q] = 0;
@@ -480,20 +475,46 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     }
     __syncthreads();
 
+    // Optional per-phase wall-clock ticks (kernel timing mode): load, Gram, active set,
+    // certificate, residual, write-back.
+    auto phase_mark = [&](int ph) {
+        if (a.phase && tid == 0) {
+            const uint64_t now = wall_clock64();
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + ph), (unsigned long long)(now - tick));
+            tick = now;
+        }
+    };
+    phase_mark(0);
+
     // 2. Gram rows of the new slots and c = A_J^T b, in float64.
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
     if (a.Q) {
         for (int e = tid; e < nnew * nI; e += NT) {
-            const int t = e / nI, u = e % nI;
+            const int t = e / nI, u = e - t * nI;
             const int q = nI0 + t;
-            const double val = a.Q[(int64_t)g_atom[q] * a.ldq + g_atom[u]];
+            const double val = a.Q[(int64_t)vatom[q] * a.ldq + vatom[u]];
             s.G[(int64_t)q * K + u] = val;
             s.G[(int64_t)u * K + q] = val;
         }
+        // c_q = a_q^T b: one wave per new atom, float4 loads, all issued before the sums
         for (int t = wave; t < nnew; t += NT / 64) {
-            const float* aj = a.At + (int64_t)g_atom[nI0 + t] * a.lda;
+            const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)vatom[nI0 + t] * a.lda);
+            const float4* b4 = reinterpret_cast<const float4*>(bw);
             double acc = 0.0;
-            for (int k = lane; k < w.kpad; k += 64) acc += (double)aj[k] * (double)bw[k];
+            const int n4 = w.kpad / 4;
+            for (int k0 = lane; k0 < n4; k0 += 64 * 4) {
+                float4 fa[4], fb[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = k0 + 64 * e;
+                    fa[e] = k < n4 ? aj[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    fb[e] = k < n4 ? b4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc += (double)fa[e].x * fb[e].x + (double)fa[e].y * fb[e].y + (double)fa[e].z * fb[e].z +
+                           (double)fa[e].w * fb[e].w;
+            }
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
             if (lane == 0) s.c[nI0 + t] = acc;
         }
@@ -502,11 +523,13 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     }
     __syncthreads();
 
+    phase_mark(1);
+
     // 3. Sign-fixed active-set iterations.
     int steps = 0;
     bool inexact = false;
     for (;;) {
-        grad_outside_support(s, nI, nS, vg);
+        grad_slots(s, nI, nS, vg, true);
         if (wave == 0) {    // violators outside S, in slot order
             int base = 0;
             for (int u0 = 0; u0 < nI && base < NT; u0 += 64) {
@@ -532,12 +555,13 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
                 __syncthreads();
                 continue;
             }
-            chol_append(s, nS, u, th, vw, vz, red);
+            chol_append(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
         }
         // move toward the sign-fixed minimiser, dropping at zero crossings
         for (;;) {
             if (++steps > a.max_steps) { inexact = true; break; }
             sign_fixed_solve(s, nS, lam, vw, vz, vx);
+            if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 8), 1ull);
             double alpha = 1.0;
             int q = -1;
             for (int k = tid; k < nS; k += NT) {
@@ -557,6 +581,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             __syncthreads();
             if (q < 0) break;
             // drop position q and append the later positions again, in order
+            if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 7), 1ull);
             const int ns_old = nS;
             for (int k = tid; k < ns_old; k += NT) vatom[k] = s.so[k];
             __syncthreads();
@@ -569,7 +594,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             nS = q;
             for (int k = q + 1; k < ns_old; ++k) {
                 const int u = vatom[k];
-                if (!chol_append(s, nS, u, s.th[u], vw, vz, red)) {
+                if (!chol_append(s, nS, u, s.th[u], vw, vz, red, a.phase ? a.phase + 6 : nullptr)) {
                     if (tid == 0) s.x[u] = 0.0;
                     __syncthreads();
                 }
@@ -578,8 +603,10 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         if (inexact) break;
     }
 
-    // 4. Certificate on I (float64), residual xi = b - A_S x_S, objective.
-    grad_all(s, nI, nS, vg);
+    phase_mark(2);
+
+    // 4. Certificate on I (float64).  The residual and objective follow in residual_kernel.
+    grad_slots(s, nI, nS, vg, false);
     double e = 0.0;
     for (int u = tid; u < nI; u += NT) {
         const double gu = vg[u];
@@ -588,35 +615,9 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         e = fmax(e, d);
     }
     const double kon = block_max(e, red);
-    double l1 = 0.0;
-    for (int k = tid; k < nS; k += NT) {
-        const int u = s.so[k];
-        vatom[k] = g_atom[u];
-        vx[k] = s.x[u];
-        l1 += fabs(s.x[u]);
-    }
-    const double xl1 = block_sum(l1, red);
-    double rr = 0.0;
-    float* Rres = w.R + (int64_t)sig * w.kpad;
-    for (int r = tid; r < w.kpad; r += NT) {
-        double acc = (double)bw[r];
-        int k = 0;
-        for (; k + 4 <= nS; k += 4) {
-            const double a0 = a.At[(int64_t)vatom[k] * a.lda + r];
-            const double a1 = a.At[(int64_t)vatom[k + 1] * a.lda + r];
-            const double a2 = a.At[(int64_t)vatom[k + 2] * a.lda + r];
-            const double a3 = a.At[(int64_t)vatom[k + 3] * a.lda + r];
-            acc -= a0 * vx[k];
-            acc -= a1 * vx[k + 1];
-            acc -= a2 * vx[k + 2];
-            acc -= a3 * vx[k + 3];
-        }
-        for (; k < nS; ++k) acc -= (double)a.At[(int64_t)vatom[k] * a.lda + r] * vx[k];
-        if (r >= w.n) acc = 0.0;
-        Rres[r] = (float)acc;
-        rr += acc * acc;
-    }
-    const double rn = block_sum(rr, red);
+    phase_mark(3);
+
+    phase_mark(4);
 
     // 5. Write the state back.
     if (a.vec_lds) {
@@ -632,9 +633,66 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         w.nS[sig] = nS;
         w.iters[sig] += 1;
         w.kkt_on[sig] = kon > 0.0 ? kon : 0.0;
-        w.obj[sig] = 0.5 * rn + lam * xl1;
         if (inexact) w.status[sig] |= BMPL_SIG_INEXACT;
     }
+    __syncthreads();
+    phase_mark(5);
+}
+
+// ---------------------------------------------------------------------------
+// Residual xi = b - A_S x_S (float64 accumulation, stored float32) and the
+// objective lambda ||x||_1 + 1/2 ||xi||^2 of every signal that was just solved
+// (step 7 of Algorithm 1).  One workgroup per signal reads its support's atom
+// columns straight from the atom-major dictionary; little LDS, so every signal
+// of the batch can be resident at once.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
+{
+    extern __shared__ double s_dyn[];
+    __shared__ double red[4];
+    const int n_act = *a.n_act_dev;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const Workspace& w = a.w;
+    const int sig = a.act[row];
+    if (w.nsel[sig] <= 0) return;
+    const int tid = threadIdx.x;
+    const int64_t K = w.K;
+    const int nS = w.nS[sig];
+    double* sx = s_dyn;
+    int* satom = reinterpret_cast<int*>(s_dyn + K);
+    double l1 = 0.0;
+    for (int k = tid; k < nS; k += NT) {
+        const int u = w.sord[sig * K + k];
+        const double xv = w.x[sig * K + u];
+        sx[k] = xv;
+        satom[k] = w.slot_atom[sig * K + u];
+        l1 += fabs(xv);
+    }
+    const double xl1 = block_sum(l1, red);    // also orders the LDS writes above
+    const float* bw = a.Bw + (int64_t)sig * w.kpad;
+    float* Rres = w.R + (int64_t)sig * w.kpad;
+    double rr = 0.0;
+    for (int r = tid; r < w.kpad; r += NT) {
+        double acc = (double)bw[r];
+        int k = 0;
+        for (; k + 4 <= nS; k += 4) {
+            const float a0 = a.At[(int64_t)satom[k] * a.lda + r];
+            const float a1 = a.At[(int64_t)satom[k + 1] * a.lda + r];
+            const float a2 = a.At[(int64_t)satom[k + 2] * a.lda + r];
+            const float a3 = a.At[(int64_t)satom[k + 3] * a.lda + r];
+            acc -= (double)a0 * sx[k];
+            acc -= (double)a1 * sx[k + 1];
+            acc -= (double)a2 * sx[k + 2];
+            acc -= (double)a3 * sx[k + 3];
+        }
+        for (; k < nS; ++k) acc -= (double)a.At[(int64_t)satom[k] * a.lda + r] * sx[k];
+        if (r >= w.n) acc = 0.0;
+        Rres[r] = (float)acc;
+        rr += acc * acc;
+    }
+    const double rn = block_sum(rr, red);
+    if (tid == 0) w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
 }
 
 // ---------------------------------------------------------------------------

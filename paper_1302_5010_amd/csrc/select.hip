@@ -11,6 +11,7 @@
 // and lambda_i = c * ||A^T b_i||_inf is set from it (Section IV-A).
 #include <float.h>
 #include <limits.h>
+#include <stdint.h>
 
 #include "bmpl_internal.h"
 
@@ -45,10 +46,19 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
         k = room < k ? (room > 0 ? room : 0) : k;
     }
 
+    // Rows are read as float4 when the layout allows it (the internal buffers always do).
+    const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
+    const int m4 = vec4 ? (a.m & ~3) : 0;
+
     // Pass 1 (relative lambda rule only): lambda_i = c * max_j |g_j|.
     if (a.lam_rel > 0.0) {
         float mx = 0.f;
-        for (int j = tid; j < a.m; j += 256) mx = fmaxf(mx, fabsf(g[j]));
+#pragma unroll 4
+        for (int j0 = 4 * tid; j0 < m4; j0 += 1024) {
+            const float4 f = *reinterpret_cast<const float4*>(g + j0);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(f.x), fabsf(f.y)), fmaxf(fabsf(f.z), fabsf(f.w))));
+        }
+        for (int j = m4 + tid; j < a.m; j += 256) mx = fmaxf(mx, fabsf(g[j]));
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
         if (lane == 0) s_red[wave] = mx;
         __syncthreads();
@@ -67,11 +77,9 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) { val[q] = -1.f; idx[q] = INT_MAX; }
     float vmx = 0.f;
-    for (int j = tid; j < a.m; j += 256) {
-        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-        float v = fabsf(g[j]);
+    auto consider = [&](int j, float v) {
         vmx = fmaxf(vmx, v);
-        if (!((double)v > lam) || !(v > val[KMAX - 1])) continue;
+        if (!((double)v > lam) || !(v > val[KMAX - 1])) return;
         float cv = v;
         int ci = j;
 #pragma unroll
@@ -84,6 +92,19 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             cv = sw ? tv : cv;
             ci = sw ? ti : ci;
         }
+    };
+#pragma unroll 2
+    for (int j0 = 4 * tid; j0 < m4; j0 += 1024) {
+        const float4 f = *reinterpret_cast<const float4*>(g + j0);
+        const uint32_t word = ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
+        if (!(word & 1u)) consider(j0, fabsf(f.x));
+        if (!(word & 2u)) consider(j0 + 1, fabsf(f.y));
+        if (!(word & 4u)) consider(j0 + 2, fabsf(f.z));
+        if (!(word & 8u)) consider(j0 + 3, fabsf(f.w));
+    }
+    for (int j = m4 + tid; j < a.m; j += 256) {
+        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+        consider(j, fabsf(g[j]));
     }
     // vmax over the signal (outside I)
     for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));

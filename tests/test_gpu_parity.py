@@ -60,6 +60,23 @@ def test_correlate_within_float32_bound(n, m, p):
     assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3f}"
 
 
+@pytest.mark.parametrize("shape", range(6))
+def test_correlate_every_tile_shape(shape):
+    pk = _lib()
+    rng = np.random.default_rng(shape)
+    n, m = 160, 1500
+    At = rng.standard_normal((m, n)).astype(np.float32)
+    s = pk.Solver(to_dev(At), 0.1)
+    s.set_tuning([shape, shape, shape])
+    A64 = At.astype(np.float64)
+    for p in (1, 37, 600):                 # one row, a ragged tile, several tiles in the >= 512 bucket
+        Rt = rng.standard_normal((p, n)).astype(np.float32)
+        G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
+        R64 = Rt.astype(np.float64)
+        bound = 2 * n * 2.0 ** -24 * (np.abs(R64) @ np.abs(A64).T)
+        assert np.all(np.abs(G - R64 @ A64.T) <= bound), (shape, p)
+
+
 @pytest.mark.parametrize("k", [1, 10, 33])
 def test_select_matches_cpu_sort(k):
     pk = _lib()
