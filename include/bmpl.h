@@ -73,6 +73,8 @@ typedef enum {
 /* bmpl_options.flags bits. */
 #define BMPL_FLAG_TIMING 1          /* time every kernel launch with HIP events (see bmpl_get_timing) */
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
+#define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each,
+                                       one launch and one read-back per segment (ignored with TIMING) */
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
  * precomputed Q of Section III, Eq. (12)) when it is at most this large. */
@@ -229,7 +231,7 @@ typedef struct {
     int64_t outer_iters;
     /* master-problem kernel, summed over its workgroups (wall-clock counter, microseconds):
      * [0] state load, [1] Gram rows, [2] active-set iterations, [3] certificate on I,
-     * [4] (unused), [5] state write-back */
+     * [4] of which inside factor appends, [5] state write-back */
     double solve_phase_us[6];
     int64_t factor_appends;     /* Cholesky row appends (including re-appends after drops) */
     int64_t factor_drops;       /* support positions removed at a zero crossing */

@@ -46,6 +46,7 @@ class Timing(ctypes.Structure):
 
 BMPL_FLAG_TIMING = 1
 BMPL_FLAG_NO_GRAM_TABLE = 2
+BMPL_FLAG_GRAPH = 4
 
 
 class _Result(ctypes.Structure):
@@ -129,7 +130,7 @@ class Solver:
 
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
-                 gram_table: bool = True, stream=None):
+                 gram_table: bool = True, graph: bool = False, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
@@ -137,7 +138,8 @@ class Solver:
         _lib.bmpl_options_default(ctypes.byref(o))
         o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
         o.screen = _PREC[screen]
-        o.flags = (BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
+        o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
+                   | (BMPL_FLAG_GRAPH if graph else 0))
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
         h = ctypes.c_void_p()

@@ -102,8 +102,23 @@ struct bmpl_ctx {
     size_t ev_used = 0;
     struct Span { size_t a, b; int kind; double flops, bytes; };
     std::vector<Span> spans;
-    uint64_t* phase_dev = nullptr;     // [6] solve-kernel phase ticks
+    uint64_t* phase_dev = nullptr;     // [9] solve-kernel phase ticks and counters
     int wall_khz = 0;
+
+    // graph capture of iteration segments (BMPL_FLAG_GRAPH)
+    hipStream_t cap_stream = nullptr;
+    long ws_gen = 0;                   // bumped whenever workspace buffers move
+    struct GraphKey {
+        int p, cur, kl, K, shapes[3];
+        long gen;
+        bool operator==(const GraphKey& o) const
+        {
+            return p == o.p && cur == o.cur && kl == o.kl && K == o.K && gen == o.gen && shapes[0] == o.shapes[0] &&
+                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2];
+        }
+    };
+    struct GraphEntry { GraphKey key; hipGraph_t g; hipGraphExec_t ge; };
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -231,6 +246,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     c->selcap = selcap;
     w.K = K;
     w.selcap = selcap;
+    c->ws_gen++;
     return BMPL_OK;
 }
 
@@ -256,6 +272,51 @@ bmpl_status grow_slots(bmpl_ctx* c, int K_new, hipStream_t s)
     w.sord = nw.sord; w.G = nw.G; w.Rinv = nw.Rinv; w.vscratch = nw.vscratch;
     w.K = K_new;
     c->K_cap = K_new;
+    c->ws_gen++;
+    return BMPL_OK;
+}
+
+constexpr int GRAPH_DEPTH = 4;   // outer iterations per captured segment (even: act buffers return)
+
+void drop_graphs(bmpl_ctx* c)
+{
+    for (auto& e : c->graphs) {
+        (void)hipGraphExecDestroy(e.ge);
+        (void)hipGraphDestroy(e.g);
+    }
+    c->graphs.clear();
+}
+
+// The instantiated graph of one segment for this configuration, captured on first use by
+// `enqueue(stream)` on the context's capture stream.
+template <class F>
+bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, hipGraphExec_t* out, F&& enqueue)
+{
+    bmpl_ctx::GraphKey key{p, cur, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen};
+    for (auto& e : c->graphs)
+        if (e.key == key) {
+            *out = e.ge;
+            return BMPL_OK;
+        }
+    if (c->graphs.size() >= 16) drop_graphs(c);
+    if (!c->cap_stream) HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPC(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    bmpl_status st = enqueue(c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != BMPL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(BMPL_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(BMPL_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    c->graphs.push_back({key, g, ge});
+    *out = ge;
     return BMPL_OK;
 }
 
@@ -369,6 +430,8 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     dfree(c->n_act_dev);
     dfree(c->diagR);
     dfree(c->phase_dev);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->h_count) (void)hipHostFree(c->h_count);
     delete c;
@@ -390,7 +453,7 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
     HIPC(hipMemsetAsync(c->diagR, 0, (size_t)(p + 1) * c->kpad * sizeof(float), s));
     HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
                           hipMemcpyDeviceToDevice, s));
-    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, p, s));
+    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, p, 0, 1 << 30, s));
     return BMPL_OK;
 }
 
@@ -432,9 +495,11 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const int rho = c->opt.rho;
     const int max_outer = c->opt.max_outer > 0 ? c->opt.max_outer : (c->m + rho - 1) / rho;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    // graph capture of whole segments; kernel timing needs per-launch events, so it uses the host loop
+    const bool graph = (c->opt.flags & BMPL_FLAG_GRAPH) != 0 && !timing_on(c);
 
     const int first_add = warm ? std::max(warm_k, rho) : rho;
-    int K0 = std::min(max_active, std::max(64, round_up(2 * first_add, 32)));
+    int K0 = std::min(max_active, std::max(64, round_up(2 * first_add + (graph ? GRAPH_DEPTH * rho : 0), 32)));
     K0 = std::max(K0, std::min(max_active, c->K_cap));
     bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), K0, std::max(rho, warm ? warm_k : 0));
     if (st != BMPL_OK) return st;
@@ -464,76 +529,160 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     int n_act = *c->h_count;
-
-    int cur = 0;
-    int imax = 0;
     if (tm) span(c, ev_first, mark(c, s), K_OTHER);
-    for (int it = 0; n_act > 0; ++it) {
+
+    // One pass of the worst-case analysis on the running list act[cur] (n_grid bounds its
+    // size): correlation, selection, stop test and compaction into act[nxt].  With `gated`
+    // every correlation tile shape is enqueued and each runs only for its own bucket of the
+    // device-side count (graph capture); otherwise the shape of n_grid's bucket is used and,
+    // in timing mode, every kernel is bracketed by events.
+    auto enqueue_select_pass = [&](hipStream_t q, int cur, int n_grid, bool first, bool warm_check,
+                                   bool gated) -> bmpl_status {
         const int nxt = 1 - cur;
-        c->timing.outer_iters += tm ? 1 : 0;
-        size_t e0 = tm ? mark(c, s) : 0;
-        HIPC(launch_corr_gemm_f32(c->corr_variant(n_act), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
-                                  c->n_act_dev + cur, n_act, c->Gc, c->ldg, c->p_cap, s));
-        if (tm) {
-            const double mm = c->m, nn = c->n, pp = n_act;
-            span(c, e0, mark(c, s), K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
-            e0 = mark(c, s);
+        const bool ev = tm && !gated;
+        size_t e0 = ev ? mark(c, q) : 0;
+        if (gated) {
+            const int lo[3] = {512, 64, 1}, hi[3] = {1 << 30, 512, 64};
+            for (int b = 0; b < 3; ++b) {
+                const int grid = std::min(n_grid, hi[b] - 1);
+                if (grid < lo[b]) continue;
+                HIPC(launch_corr_gemm_f32(c->corr_shape[b], c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
+                                          c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo[b], hi[b], q));
+            }
+        } else {
+            HIPC(launch_corr_gemm_f32(c->corr_variant(n_grid), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad,
+                                      c->act[cur], c->n_act_dev + cur, n_grid, c->Gc, c->ldg, c->p_cap, 0, 1 << 30, q));
+        }
+        if (ev) {
+            const double mm = c->m, nn = c->n, pp = n_grid;
+            const size_t e1 = mark(c, q);
+            span(c, e0, e1, K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
+            e0 = e1;
         }
         SelectArgs a{};
         a.G = c->Gc; a.ldg = c->ldg; a.m = c->m;
-        a.act = c->act[cur]; a.n_act_dev = c->n_act_dev + cur; a.p_grid = n_act;
-        a.lam = w.lam; a.lam_rel = (rel && it == 0) ? c->lambda : 0.0;
+        a.act = c->act[cur]; a.n_act_dev = c->n_act_dev + cur; a.p_grid = n_grid;
+        a.lam = w.lam; a.lam_rel = (rel && first) ? c->lambda : 0.0;
         a.excl = w.inI; a.words = w.words;
         a.k = rho; a.sel = w.sel; a.selcap = w.selcap; a.nsel = w.nsel; a.vmax = w.vmax;
         a.nI = w.nI; a.max_active = max_active;
-        HIPC(launch_select(a, s));
-        if (tm) { span(c, e0, mark(c, s), K_SELECT); e0 = mark(c, s); }
-        if (it == 0 && warm) {
+        HIPC(launch_select(a, q));
+        if (ev) {
+            const size_t e1 = mark(c, q);
+            span(c, e0, e1, K_SELECT);
+            e0 = e1;
+        }
+        if (first && warm) {
             WarmArgs wa{w, c->act[cur], c->n_act_dev + cur, warm_idx_dev, warm_k, max_active};
-            hipLaunchKernelGGL(warm_select_kernel, dim3(n_act), dim3(64), 0, s, wa);
+            hipLaunchKernelGGL(warm_select_kernel, dim3(n_grid), dim3(64), 0, q, wa);
             HIPC(hipGetLastError());
         }
-        sa.initial = 0;
-        sa.act_in = c->act[cur]; sa.n_in_dev = c->n_act_dev + cur; sa.n_in = n_act;
-        sa.act_out = c->act[nxt]; sa.n_out_dev = c->n_act_dev + nxt;
-        sa.warm_check = (warm && it == 1) ? 1 : 0;
-        hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
+        StatusArgs sb = sa;
+        sb.w = w;
+        sb.initial = 0;
+        sb.act_in = c->act[cur]; sb.n_in_dev = c->n_act_dev + cur; sb.n_in = n_grid;
+        sb.act_out = c->act[nxt]; sb.n_out_dev = c->n_act_dev + nxt;
+        sb.warm_check = warm_check ? 1 : 0;
+        hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, q, sb);
         HIPC(hipGetLastError());
-        if (tm) span(c, e0, mark(c, s), K_OTHER);
-        HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev + nxt, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPC(hipStreamSynchronize(s));
-        n_act = *c->h_count;
-        if (n_act == 0) break;
+        if (ev) span(c, e0, mark(c, q), K_OTHER);
+        return BMPL_OK;
+    };
 
-        const int add = (it == 0 && warm) ? std::max(warm_k, rho) : rho;
-        imax = std::min(max_active, imax + add);
-        if (imax > c->K_cap) {
-            int K_new = std::min(max_active, round_up(std::max(imax + 4 * rho, c->K_cap + c->K_cap / 4), 32));
-            st = grow_slots(c, K_new, s);
-            if (st != BMPL_OK) return st;
-        }
+    // Master problem and residual for the running list act[idx] (steps 4-8 of Algorithm 1),
+    // with the factor held in LDS for capacity kl when it fits.
+    auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated) -> bmpl_status {
+        const bool ev = tm && !gated;
+        size_t e0 = ev ? mark(c, q) : 0;
         SolveArgs so{};
         so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
         so.Q = c->Q; so.ldq = c->m;
-        so.act = c->act[nxt]; so.n_act_dev = c->n_act_dev + nxt;
         so.max_steps = 16 * w.K + 256;
         so.phase = tm ? c->phase_dev : nullptr;
-        // LDS: per-slot vectors first, then the inverse factor sized for this launch's largest |I|.
         const size_t vec_bytes = (size_t)round_up(w.K * 58, 16);
         so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
-        so.kl = std::min(imax, w.K);
+        so.kl = std::min(kl, w.K);
         const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
         so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes <= c->lds_dyn_max) ? 1 : 0;
         const size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
-        e0 = tm ? mark(c, s) : 0;
-        hipLaunchKernelGGL(solve_kernel, dim3(n_act), dim3(256), lds, s, so);
+        so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
+        hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
         HIPC(hipGetLastError());
-        if (tm) { span(c, e0, mark(c, s), K_SOLVE); e0 = mark(c, s); }
-        ResidualArgs ra{w, c->At, c->kpad, c->Bw, c->act[nxt], c->n_act_dev + nxt};
-        hipLaunchKernelGGL(residual_kernel, dim3(n_act), dim3(256), (size_t)w.K * 12, s, ra);
+        if (ev) {
+            const size_t e1 = mark(c, q);
+            span(c, e0, e1, K_SOLVE);
+            e0 = e1;
+        }
+        ResidualArgs ra{w, c->At, c->kpad, c->Bw, c->act[idx], c->n_act_dev + idx};
+        hipLaunchKernelGGL(residual_kernel, dim3(n_grid), dim3(256), (size_t)w.K * 12, q, ra);
         HIPC(hipGetLastError());
-        if (tm) span(c, e0, mark(c, s), K_RESID);
-        cur = nxt;
+        if (ev) span(c, e0, mark(c, q), K_RESID);
+        return BMPL_OK;
+    };
+    auto grow_to = [&](int need) -> bmpl_status {
+        if (need <= c->K_cap) return BMPL_OK;
+        const int K_new = std::min(max_active, round_up(std::max(need + 4 * rho, c->K_cap + c->K_cap / 4), 32));
+        return grow_slots(c, K_new, s);
+    };
+    auto read_count = [&](int idx) -> bmpl_status {
+        HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev + idx, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        n_act = *c->h_count;
+        return BMPL_OK;
+    };
+
+    // Iteration 0: lambda rule and the first selection (or the warm-start proposal).
+    int cur = 0;
+    if (n_act > 0) {
+        c->timing.outer_iters += tm ? 1 : 0;
+        st = enqueue_select_pass(s, 0, n_act, true, false, false);
+        if (st != BMPL_OK) return st;
+        cur = 1;
+        st = read_count(cur);
+        if (st != BMPL_OK) return st;
+    }
+    // Then per iteration: master problem on I_t, next selection pass.
+    int imax = 0;
+    bool after_warm = warm;
+    while (n_act > 0) {
+        if (graph && !after_warm) {
+            // GRAPH_DEPTH iterations as one captured graph launch.  The kernels read the running
+            // count on the device, so iterations past the last signal's stop are empty launches.
+            const int need = std::min(max_active, imax + GRAPH_DEPTH * rho);
+            st = grow_to(need);
+            if (st != BMPL_OK) return st;
+            hipGraphExec_t ge = nullptr;
+            st = segment_graph(c, p, cur, need, &ge, [&](hipStream_t q) -> bmpl_status {
+                int cc = cur;
+                for (int d = 0; d < GRAPH_DEPTH; ++d) {
+                    bmpl_status r = enqueue_master(q, cc, p, need, true);
+                    if (r != BMPL_OK) return r;
+                    r = enqueue_select_pass(q, cc, p, false, false, true);
+                    if (r != BMPL_OK) return r;
+                    cc = 1 - cc;
+                }
+                return BMPL_OK;
+            });
+            if (st != BMPL_OK) return st;
+            HIPC(hipGraphLaunch(ge, s));
+            imax = need;
+            st = read_count(cur);    // GRAPH_DEPTH is even: the running list is back in act[cur]
+            if (st != BMPL_OK) return st;
+            continue;
+        }
+        const int add = after_warm ? std::max(warm_k, rho) : rho;
+        imax = std::min(max_active, imax + add);
+        st = grow_to(imax);
+        if (st != BMPL_OK) return st;
+        c->timing.outer_iters += tm ? 1 : 0;
+        st = enqueue_master(s, cur, n_act, imax, false);
+        if (st != BMPL_OK) return st;
+        st = enqueue_select_pass(s, cur, n_act, false, after_warm, false);
+        if (st != BMPL_OK) return st;
+        after_warm = false;
+        cur = 1 - cur;
+        st = read_count(cur);
+        if (st != BMPL_OK) return st;
     }
     const size_t e_pack = tm ? mark(c, s) : 0;
     PackArgs pk{w, out->x_val_dev, out->x_idx_dev, out->supp_len_dev, out->iters_dev, out->kkt_dev,
@@ -571,11 +720,11 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
             double t = -1.0;
             if (nb >= lo[b]) {
                 hipError_t e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr,
-                                                    nb, c->Gc, c->ldg, c->p_cap, s);
+                                                    nb, c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
                 if (e == hipSuccess) e = hipEventRecord(e0, s);
                 for (int r = 0; r < 3 && e == hipSuccess; ++r)
                     e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr, nb,
-                                             c->Gc, c->ldg, c->p_cap, s);
+                                             c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
                 if (e == hipSuccess) e = hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float f = 0.f;

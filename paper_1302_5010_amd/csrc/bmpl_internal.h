@@ -67,7 +67,7 @@ const char* corr_shape_name(int variant);
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
-                                hipStream_t stream);
+                                int n_lo, int n_hi, hipStream_t stream);   // runs only if n_lo <= count < n_hi
 
 // Q = A^T A in float64 (m x m, leading dimension ldq), from the padded float32 atoms.
 hipError_t launch_gram_table(const float* At, int64_t lda, int m, int kpad, double* Q, int64_t ldq,

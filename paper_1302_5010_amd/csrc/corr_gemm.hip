@@ -48,10 +48,12 @@ template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f32_kernel(
     const float* __restrict__ At, int64_t lda, int m, int kpad,
     const float* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
-    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row)
+    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row,
+    int n_lo, int n_hi)
 {
     using S = Shape<BM, BN, WM, WN>;
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
+    if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
     // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
     // contiguous run of tiles (atom tiles outer, signal tiles inner) to share A rows in its L2.
     const int nwg = gridDim.x;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
 template <int BM, int BN, int WM, int WN>
 hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const float* Rbuf, int64_t ldr,
                         const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
-                        hipStream_t stream)
+                        int n_lo, int n_hi, hipStream_t stream)
 {
     const int tiles_m = (p_grid + BM - 1) / BM;
     const int tiles_n = (m + BN - 1) / BN;
@@ -205,7 +207,7 @@ hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const flo
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((corr_gemm_f32_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg),
                        dim3(Shape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
-                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row);
+                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi);
     return hipGetLastError();
 }
 
@@ -227,16 +229,16 @@ const char* corr_shape_name(int v)
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
-                                hipStream_t stream)
+                                int n_lo, int n_hi, hipStream_t stream)
 {
     if (p_grid <= 0 || m <= 0) return hipSuccess;
     switch (variant) {
-    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
-    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
-    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
-    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
-    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
-    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, stream);
+    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
     default: return hipErrorInvalidValue;
     }
 }

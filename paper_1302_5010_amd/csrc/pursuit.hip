@@ -79,6 +79,7 @@ __device__ inline void block_argmin(double& a, int& q, double* red, int* redi)
 // stride K); the rest points into LDS or into the global homes.
 struct Sig {
     int K;
+    bool r_lds;           // R lives in LDS (latency-optimised loops) or in global memory (coalesced loops)
     double* G;            // G_II by slot
     double* R;            // Rinv, packed lower row-major by support position
     double* x;            // coefficient by slot
@@ -88,6 +89,48 @@ struct Sig {
     int* so;              // slot of each support position
 };
 
+// sum_{k < len} Ri[k] v[k], four independent accumulators (row i of a packed factor).
+__device__ inline double row_dot(const double* Ri, const double* v, int len)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+        a0 += Ri[k] * v[k];
+        a1 += Ri[k + 1] * v[k + 1];
+        a2 += Ri[k + 2] * v[k + 2];
+        a3 += Ri[k + 3] * v[k + 3];
+    }
+    for (; k < len; ++k) a0 += Ri[k] * v[k];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// sum_{i = k}^{s-1} v[i] R(i, k) over column k of a packed lower factor.
+__device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (f.r_lds) {
+        int i = k;
+        int64_t o = tri(k) + k;              // offset of R(i, k); the next row adds i + 1
+        for (; i + 4 <= s; i += 4) {
+            const int64_t o1 = o + i + 1, o2 = o1 + i + 2, o3 = o2 + i + 3;
+            a0 += v[i] * f.R[o];
+            a1 += v[i + 1] * f.R[o1];
+            a2 += v[i + 2] * f.R[o2];
+            a3 += v[i + 3] * f.R[o3];
+            o = o3 + i + 4;
+        }
+        for (; i < s; ++i) {
+            a0 += v[i] * f.R[o];
+            o += i + 1;
+        }
+    } else {
+        // global factor: rows in lockstep across the wave so loads of one row coalesce
+        for (int i = k & ~63; i < s; ++i)
+            if (i >= k) a0 += v[i] * f.R[tri(i) + k];
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
 // Append slot j with sign th at support position s = nS (a Cholesky row append
 // held as the inverse factor).  Returns false and excludes j if its Schur
 // complement pivot vanishes, i.e. a_j is numerically in the span of A_S.
@@ -96,35 +139,33 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
 {
     const int s = nS;
     const int tid = threadIdx.x;
+    const uint64_t t_in = cnt ? wall_clock64() : 0;
     if (cnt && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
     const double* Gj = v.G + (int64_t)j * v.K;
+    __shared__ double s_gjj;
     for (int k = tid; k < s; k += NT) vw[k] = Gj[v.so[k]];
+    if (tid == 0) s_gjj = Gj[j];
     __syncthreads();
     double part = 0.0;
     for (int i = tid; i < s; i += NT) {      // z = Rinv w
-        const double* Ri = v.R + tri(i);
-        double acc = 0.0;
-        for (int k = 0; k <= i; ++k) acc += Ri[k] * vw[k];
+        const double acc = row_dot(v.R + tri(i), vw, i + 1);
         vz[i] = acc;
         part += acc * acc;
     }
     const double zz = block_sum(part, red);
-    const double gjj = Gj[j];
+    const double gjj = s_gjj;
     const double dd = gjj - zz;
     if (!(dd > 1e-11 * gjj)) {
         if (tid == 0) { v.ex[j] = 1; v.th[j] = 0; v.x[j] = 0.0; }
         __syncthreads();
+        if (cnt && tid == 0)   // cnt[-2]: ticks spent in appends (phase slot 4)
+            atomicAdd(reinterpret_cast<unsigned long long*>(cnt - 2), (unsigned long long)(wall_clock64() - t_in));
         return false;
     }
     const double d = sqrt(dd);
     double* Rs = v.R + tri(s);
-    for (int k = tid; k < s; k += NT) {      // new row: -(z^T Rinv)_k / d
-        const int i0 = k & ~63;
-        double acc = 0.0;
-        for (int i = i0; i < s; ++i)
-            if (i >= k) acc += vz[i] * v.R[tri(i) + k];
-        Rs[k] = -acc / d;
-    }
+    for (int k = tid; k < s; k += NT)        // new row: -(z^T Rinv)_k / d
+        Rs[k] = -col_dot(v, vz, k, s) / d;
     if (tid == 0) {
         Rs[s] = 1.0 / d;
         v.so[s] = j;
@@ -132,6 +173,8 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     }
     nS = s + 1;
     __syncthreads();
+    if (cnt && tid == 0)   // cnt[-2]: ticks spent in appends (phase slot 4)
+        atomicAdd(reinterpret_cast<unsigned long long*>(cnt - 2), (unsigned long long)(wall_clock64() - t_in));
     return true;
 }
 
@@ -144,20 +187,9 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
         vw[k] = v.c[u] - lam * (double)v.th[u];
     }
     __syncthreads();
-    for (int i = tid; i < nS; i += NT) {
-        const double* Ri = v.R + tri(i);
-        double acc = 0.0;
-        for (int k = 0; k <= i; ++k) acc += Ri[k] * vw[k];
-        vz[i] = acc;
-    }
+    for (int i = tid; i < nS; i += NT) vz[i] = row_dot(v.R + tri(i), vw, i + 1);
     __syncthreads();
-    for (int k = tid; k < nS; k += NT) {
-        const int i0 = k & ~63;
-        double acc = 0.0;
-        for (int i = i0; i < nS; ++i)
-            if (i >= k) acc += v.R[tri(i) + k] * vz[i];
-        vx[k] = acc;
-    }
+    for (int k = tid; k < nS; k += NT) vx[k] = col_dot(v, vz, k, nS);
     __syncthreads();
 }
 
@@ -429,6 +461,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
 
     Sig s;
     s.K = K;
+    s.r_lds = a.rinv_lds != 0;
     s.G = w.G + (int64_t)sig * K * K;
     char* lp = reinterpret_cast<char*>(s_dyn);
     if (a.rinv_lds) {
@@ -617,7 +650,6 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     const double kon = block_max(e, red);
     phase_mark(3);
 
-    phase_mark(4);
 
     // 5. Write the state back.
     if (a.vec_lds) {

@@ -266,3 +266,20 @@ def test_gram_table_matches_float64(n, m):
     bound = n * 2.0 ** -52 * (np.abs(A64) @ np.abs(A64).T) * 2
     assert np.all(np.abs(Q - ref) <= bound)
     assert np.array_equal(Q, Q.T)
+
+
+def test_graph_mode_matches_host_loop():
+    """Captured-graph segments (4 iterations per launch, device-side counts) give the same results."""
+    pk = _lib()
+    for P in (bi.small_gaussian(), bi.tiny_gaussian(n=256, m=2000, p=257, k=30, sigma=0.01, seed=77, rho=7)):
+        lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+        host = pk.Solver(to_dev(P.At), 0.0, rho=P.rho).solve(to_dev(P.Bt), lam=to_dev(lam))
+        s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True)
+        for rep in range(3):                       # replays of the cached graphs
+            out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+            torch.cuda.synchronize()
+            for key in ("x_idx", "supp_len", "iters", "status"):
+                assert torch.equal(out[key], host[key]), (rep, key)
+            assert torch.equal(out["x_val"], host["x_val"])
+        ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+        check_batch(P.At, P.Bt, lam, out, ref)
