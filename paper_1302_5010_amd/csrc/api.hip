@@ -64,6 +64,8 @@ void dfree(T*& p)
 
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
+constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
+
 }  // namespace
 
 struct bmpl_ctx {
@@ -71,6 +73,11 @@ struct bmpl_ctx {
     int n = 0, m = 0, kpad = 0;
     float* At = nullptr;          // [m][kpad] float32 dictionary, atom-major
     double* Q = nullptr;          // [m][m] float64 Gram table A^T A, or null
+    uint16_t* A16 = nullptr;      // [m + 1][kpad] bfloat16 dictionary (screening), row m zero
+    double gamma_amax = 0.0;      // bfloat16 band factor: gamma_n * max_j ||a_j||
+    int* cand = nullptr;          // [p_cap][CANDCAP] screening candidates
+    int* ncand = nullptr;         // [p_cap]
+    uint16_t* diag16 = nullptr;   // bfloat16 staging of bmpl_correlate
     size_t lds_dyn_max = 0;       // dynamic LDS a solve workgroup may use (bytes)
     bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
     double lambda = 0.0;
@@ -210,6 +217,7 @@ void free_signals(bmpl_ctx* c)
     dfree(w.kkt); dfree(w.inI);
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
+    dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
     c->p_cap = 0;
     c->K_cap = 0;
 }
@@ -241,6 +249,13 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     HIPC(dalloc(&c->Gc, P * (size_t)c->ldg));
     HIPC(dalloc(&c->act[0], P));
     HIPC(dalloc(&c->act[1], P));
+    if (c->opt.screen != BMPL_PREC_FP32) {
+        HIPC(dalloc(&w.R16, (P + 1) * c->kpad));
+        HIPC(hipMemset(w.R16 + P * c->kpad, 0, c->kpad * sizeof(uint16_t)));
+        HIPC(dalloc(&w.rnorm, P));
+        HIPC(dalloc(&c->cand, P * CANDCAP_DEF));
+        HIPC(dalloc(&c->ncand, P));
+    }
     c->p_cap = p;
     c->K_cap = K;
     c->selcap = selcap;
@@ -360,7 +375,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (o) opt = *o;
     if (opt.rho <= 0 || opt.rho > 64) return fail(BMPL_E_INVALID, "bmpl_create: rho must be in [1, 64]");
     if (!(opt.kkt_tol >= 0.0)) return fail(BMPL_E_INVALID, "bmpl_create: kkt_tol must be >= 0");
-    if (opt.screen != BMPL_PREC_FP32)
+    if (opt.screen != BMPL_PREC_FP32 && opt.screen != BMPL_PREC_BF16)
         return fail(BMPL_E_UNSUPPORTED, "bmpl_create: screening precision %d not available", (int)opt.screen);
     if (opt.max_active > m) opt.max_active = m;
 
@@ -370,7 +385,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e != hipSuccess) { delete c; return fail(BMPL_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)); }
     c->n = n;
     c->m = m;
-    c->kpad = round_up(n, 32);
+    c->kpad = round_up(n, 64);
     c->mode = mode;
     c->lambda = lambda;
     c->opt = opt;
@@ -386,6 +401,25 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
+    // bfloat16 copy of the dictionary and the band factor gamma_n * max_j ||a_j|| for screening.
+    if (e == hipSuccess && opt.screen == BMPL_PREC_BF16) {
+        float* norms = nullptr;
+        e = dalloc(&c->A16, (size_t)(m + 1) * c->kpad);
+        if (e == hipSuccess) e = hipMemsetAsync(c->A16, 0, (size_t)(m + 1) * c->kpad * sizeof(uint16_t), s);
+        if (e == hipSuccess) e = launch_to_bf16(c->At, c->kpad, c->A16, c->kpad, m, c->kpad, s);
+        if (e == hipSuccess) e = dalloc(&norms, (size_t)m);
+        if (e == hipSuccess) e = launch_atom_norms(c->At, c->kpad, c->kpad, norms, m, s);
+        std::vector<float> hn(m);
+        if (e == hipSuccess) e = hipMemcpyAsync(hn.data(), norms, sizeof(float) * m, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (norms) (void)hipFree(norms);
+        if (e == hipSuccess) {
+            double amax = 0.0;
+            for (float v : hn) amax = std::max(amax, (double)v);
+            const double gamma = (std::ldexp(1.0, -7) + std::ldexp(1.0, -16) + n * std::ldexp(1.0, -24)) * 1.01;
+            c->gamma_amax = gamma * amax;
+        }
+    }
     // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
     const double q_bytes = 8.0 * (double)m * (double)m;
     if (e == hipSuccess && !(opt.flags & BMPL_FLAG_NO_GRAM_TABLE) && q_bytes <= BMPL_GRAM_TABLE_MAX_BYTES) {
@@ -427,6 +461,8 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     free_signals(c);
     dfree(c->At);
     dfree(c->Q);
+    dfree(c->A16);
+    dfree(c->diag16);
     dfree(c->n_act_dev);
     dfree(c->diagR);
     dfree(c->phase_dev);
@@ -453,6 +489,15 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
     HIPC(hipMemsetAsync(c->diagR, 0, (size_t)(p + 1) * c->kpad * sizeof(float), s));
     HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
                           hipMemcpyDeviceToDevice, s));
+    if (c->A16) {
+        dfree(c->diag16);
+        HIPC(dalloc(&c->diag16, (size_t)(p + 1) * c->kpad));
+        HIPC(launch_to_bf16(c->diagR, c->kpad, c->diag16, c->kpad, p + 1, c->kpad, s));
+        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->kpad, c->m, c->kpad, c->diag16, c->kpad, nullptr,
+                                   nullptr, p, G_dev, ldg, p, 0, 1 << 30, s));
+        HIPC(hipStreamSynchronize(s));
+        return BMPL_OK;
+    }
     HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, p, 0, 1 << 30, s));
     return BMPL_OK;
 }
@@ -541,17 +586,22 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const int nxt = 1 - cur;
         const bool ev = tm && !gated;
         size_t e0 = ev ? mark(c, q) : 0;
+        auto gemm = [&](int shape, int grid, int lo, int hi) -> hipError_t {
+            if (c->A16)
+                return launch_corr_gemm_bf16(shape, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, c->act[cur],
+                                             c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
+            return launch_corr_gemm_f32(shape, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
+                                        c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
+        };
         if (gated) {
             const int lo[3] = {512, 64, 1}, hi[3] = {1 << 30, 512, 64};
             for (int b = 0; b < 3; ++b) {
                 const int grid = std::min(n_grid, hi[b] - 1);
                 if (grid < lo[b]) continue;
-                HIPC(launch_corr_gemm_f32(c->corr_shape[b], c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
-                                          c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo[b], hi[b], q));
+                HIPC(gemm(c->corr_shape[b], grid, lo[b], hi[b]));
             }
         } else {
-            HIPC(launch_corr_gemm_f32(c->corr_variant(n_grid), c->At, c->kpad, c->m, c->kpad, w.R, c->kpad,
-                                      c->act[cur], c->n_act_dev + cur, n_grid, c->Gc, c->ldg, c->p_cap, 0, 1 << 30, q));
+            HIPC(gemm(c->corr_variant(n_grid), n_grid, 0, 1 << 30));
         }
         if (ev) {
             const double mm = c->m, nn = c->n, pp = n_grid;
@@ -566,7 +616,30 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         a.excl = w.inI; a.words = w.words;
         a.k = rho; a.sel = w.sel; a.selcap = w.selcap; a.nsel = w.nsel; a.vmax = w.vmax;
         a.nI = w.nI; a.max_active = max_active;
-        HIPC(launch_select(a, q));
+        if (c->A16) {
+            ScreenArgs sc{};
+            sc.G = c->Gc; sc.ldg = c->ldg; sc.m = c->m;
+            sc.act = c->act[cur]; sc.n_act_dev = c->n_act_dev + cur; sc.p_grid = n_grid;
+            sc.lam = w.lam; sc.lam_rel = a.lam_rel;
+            sc.rnorm = w.rnorm; sc.gamma_amax = c->gamma_amax;
+            sc.excl = w.inI; sc.words = w.words;
+            sc.k = rho; sc.nI = w.nI; sc.max_active = max_active;
+            sc.cand = c->cand; sc.candcap = CANDCAP_DEF; sc.ncand = c->ncand;
+            HIPC(launch_screen(sc, q));
+            RescoreArgs rs{};
+            rs.At = c->At; rs.lda = c->kpad; rs.kpad = c->kpad;
+            rs.R = w.R; rs.ldr = c->kpad;
+            rs.act = c->act[cur]; rs.n_act_dev = c->n_act_dev + cur; rs.p_grid = n_grid;
+            rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
+            rs.candcap_lds = (int)std::min<size_t>(CANDCAP_DEF, c->lds_dyn_max / sizeof(double));
+            rs.ncand = c->ncand;
+            rs.lam = w.lam; rs.lam_rel = a.lam_rel;
+            rs.k = rho; rs.nI = w.nI; rs.max_active = max_active;
+            rs.sel = w.sel; rs.selcap = w.selcap; rs.nsel = w.nsel; rs.vmax = w.vmax; rs.status = w.status;
+            HIPC(launch_rescore(rs, q));
+        } else {
+            HIPC(launch_select(a, q));
+        }
         if (ev) {
             const size_t e1 = mark(c, q);
             span(c, e0, e1, K_SELECT);
@@ -708,6 +781,14 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
     if (st != BMPL_OK) return st;
     Workspace& w = c->w;
     HIPC(hipMemsetAsync(w.R, 0, (size_t)p * c->kpad * sizeof(float), s));
+    if (w.R16) HIPC(hipMemsetAsync(w.R16, 0, (size_t)p * c->kpad * sizeof(uint16_t), s));
+    auto gemm = [&](int v, int nb) -> hipError_t {
+        if (c->A16)
+            return launch_corr_gemm_bf16(v, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, nullptr, nullptr, nb,
+                                         c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
+        return launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr, nb, c->Gc,
+                                    c->ldg, c->p_cap, 0, 1 << 30, s);
+    };
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));
@@ -719,12 +800,10 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
         for (int v = 0; v < CORR_VARIANTS; ++v) {
             double t = -1.0;
             if (nb >= lo[b]) {
-                hipError_t e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr,
-                                                    nb, c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
+                hipError_t e = gemm(v, nb);
                 if (e == hipSuccess) e = hipEventRecord(e0, s);
                 for (int r = 0; r < 3 && e == hipSuccess; ++r)
-                    e = launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr, nb,
-                                             c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
+                    e = gemm(v, nb);
                 if (e == hipSuccess) e = hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float f = 0.f;

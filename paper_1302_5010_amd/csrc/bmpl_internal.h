@@ -52,6 +52,9 @@ struct Workspace {
     double* G;          // [p][K*K] Gram of I, row-major by slot
     double* Rinv;       // [p][tri(K)] inverse Cholesky factor of G_SS, packed by position
     double* vscratch;   // [p][8K] vectors when they do not fit LDS
+    // reduced-precision screening (null in float32 mode)
+    uint16_t* R16;      // [p_cap + 1][kpad] bfloat16 copy of R (row p_cap all zero)
+    double* rnorm;      // [p] ||xi_i||_2
 };
 
 // Launchers (all asynchronous on `stream`).
@@ -73,6 +76,12 @@ hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m
 hipError_t launch_gram_table(const float* At, int64_t lda, int m, int kpad, double* Q, int64_t ldq,
                              hipStream_t stream);
 
+// The same product with bfloat16 operands (raw 16-bit storage), float32 accumulation.
+hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, int m, int kpad,
+                                 const uint16_t* Rbuf, int64_t ldr, const int* act,
+                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
+                                 int n_lo, int n_hi, hipStream_t stream);
+
 // Top-k selection per row (worst-case analysis).  See bmpl_select in bmpl.h; here
 // `lam_rel` > 0 computes lambda[sig] = lam_rel * max_j |G| first (first pass).
 struct SelectArgs {
@@ -86,5 +95,39 @@ struct SelectArgs {
     const int* nI; int max_active;
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
+
+// Reduced-precision screening (screen.hip).
+struct ScreenArgs {
+    const float* G; int64_t ldg; int m;
+    const int* act; const int* n_act_dev; int p_grid;
+    const double* lam; double lam_rel;       // lam_rel > 0: first pass of the relative rule
+    const double* rnorm; double gamma_amax;  // band eps_i = gamma_amax * rnorm[sig]
+    const uint32_t* excl; int words;
+    int k; const int* nI; int max_active;
+    int* cand; int candcap; int* ncand;
+};
+struct RescoreArgs {
+    const float* At; int64_t lda; int kpad;  // float32 atoms
+    const float* R; int64_t ldr;             // float32 residuals
+    const int* act; const int* n_act_dev; int p_grid;
+    const int* cand; int candcap; int candcap_lds; const int* ncand;
+    double* lam; double lam_rel;
+    int k; const int* nI; int max_active;
+    int* sel; int selcap; int* nsel; float* vmax; int* status;
+};
+hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd, int rows, int cols,
+                          hipStream_t stream);
+hipError_t launch_atom_norms(const float* At, int64_t lda, int n, float* norms, int m, hipStream_t stream);
+hipError_t launch_screen(const ScreenArgs& a, hipStream_t stream);
+hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream);
+
+// Round-to-nearest-even float32 -> bfloat16 (raw bits).
+__device__ inline uint16_t bf16_round(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x0040u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 }  // namespace bmpl

@@ -29,9 +29,12 @@ namespace bmpl {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BK = 32;
-constexpr int LDS_STRIDE = BK + 4;   // floats per LDS row (16-byte aligned, staggers banks)
+// Each LDS stage holds 128 bytes of k per row: 32 float32 or 64 bfloat16 values, read back as
+// one 16-byte fragment per lane per 8 (float32) or 16 (bfloat16) k values.
+constexpr int ROW_BYTES = 128;
+constexpr int LDS_ROW = ROW_BYTES + 16;   // bytes per LDS row (16-byte aligned, staggers banks)
 
 template <int BM, int BN, int WM, int WN>
 struct Shape {
@@ -39,19 +42,21 @@ struct Shape {
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int TI = WM / 32;                 // MFMA blocks per wave, signal direction
     static constexpr int TJ = WN / 32;                 // atom direction
-    static constexpr int LR = BM * (BK / 4) / THREADS; // float4 loads per thread, residual tile
-    static constexpr int LA = BN * (BK / 4) / THREADS; // dictionary tile
-    static_assert(LR * THREADS == BM * (BK / 4) && LA * THREADS == BN * (BK / 4), "tile/thread mismatch");
+    static constexpr int LR = BM * 8 / THREADS;        // 16-byte loads per thread, residual tile
+    static constexpr int LA = BN * 8 / THREADS;        // dictionary tile
+    static_assert(LR * THREADS == BM * 8 && LA * THREADS == BN * 8, "tile/thread mismatch");
 };
 
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f32_kernel(
-    const float* __restrict__ At, int64_t lda, int m, int kpad,
-    const float* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
+template <class E, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_kernel(
+    const E* __restrict__ At, int64_t lda, int m, int kpad,
+    const E* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
     const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row,
     int n_lo, int n_hi)
 {
     using S = Shape<BM, BN, WM, WN>;
+    constexpr int BK = ROW_BYTES / (int)sizeof(E);   // k per stage
+    constexpr int VE = 16 / (int)sizeof(E);          // k per 16-byte chunk
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
     if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
     // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
@@ -71,8 +76,8 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
     const int atom0 = tn * BN;
     if (sig0 >= n_act) return;
 
-    __shared__ float sR[2][BM * LDS_STRIDE];
-    __shared__ float sA[2][BN * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) char sR[2][BM * LDS_ROW];
+    __shared__ __attribute__((aligned(16))) char sA[2][BN * LDS_ROW];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -92,13 +97,13 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
         const int a = sig0 + r0 + RSTEP * q;
         vR[q] = a < n_act;
         const int s = vR[q] ? (act ? act[a] : a) : zero_row;
-        oR[q] = (int64_t)s * ldr + 4 * c4;
+        oR[q] = (int64_t)s * ldr + VE * c4;
     }
 #pragma unroll
     for (int q = 0; q < S::LA; ++q) {
         const int j = atom0 + r0 + RSTEP * q;
         vA[q] = j < m;
-        oA[q] = (int64_t)(vA[q] ? j : m) * lda + 4 * c4;
+        oA[q] = (int64_t)(vA[q] ? j : m) * lda + VE * c4;
     }
     float4 gR[S::LR], gA[S::LA];
 #define CORR_LOAD_SLICE(k0)                                                                                 \
@@ -111,9 +116,9 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
 #define CORR_STORE_SLICE(buf)                                                                               \
     do {                                                                                                    \
         _Pragma("unroll") for (int q = 0; q < S::LR; ++q)                                                  \
-            *reinterpret_cast<float4*>(&sR[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gR[q];          \
+            *reinterpret_cast<float4*>(&sR[buf][(r0 + RSTEP * q) * LDS_ROW + 16 * c4]) = gR[q];            \
         _Pragma("unroll") for (int q = 0; q < S::LA; ++q)                                                  \
-            *reinterpret_cast<float4*>(&sA[buf][(r0 + RSTEP * q) * LDS_STRIDE + 4 * c4]) = gA[q];          \
+            *reinterpret_cast<float4*>(&sA[buf][(r0 + RSTEP * q) * LDS_ROW + 16 * c4]) = gA[q];            \
     } while (0)
 
     floatx16 acc[S::TI][S::TJ];
@@ -139,38 +144,49 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
         const int kn = k0 + BK < kpad ? k0 + BK : k0;
         CORR_LOAD_SLICE(kn);
         asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
-        const float* cR = sR[cur];
-        const float* cA = sA[cur];
+        const char* cR = sR[cur];
+        const char* cA = sA[cur];
 #pragma unroll
-        for (int kb = 0; kb < BK / 8; ++kb) {
+        for (int kb = 0; kb < 4; ++kb) {       // 4 x 16-byte chunks per lane half per stage
             float4 fr[S::TI], fa[S::TJ];
 #pragma unroll
             for (int i = 0; i < S::TI; ++i)
-                fr[i] = *reinterpret_cast<const float4*>(&cR[(ws + 32 * i + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
+                fr[i] = *reinterpret_cast<const float4*>(&cR[(ws + 32 * i + l32) * LDS_ROW + kb * 32 + 16 * h]);
 #pragma unroll
             for (int j = 0; j < S::TJ; ++j)
-                fa[j] = *reinterpret_cast<const float4*>(&cA[(wa + 32 * j + l32) * LDS_STRIDE + kb * 8 + 4 * h]);
-            // k step outermost: consecutive MFMAs write different accumulators
+                fa[j] = *reinterpret_cast<const float4*>(&cA[(wa + 32 * j + l32) * LDS_ROW + kb * 32 + 16 * h]);
+            if constexpr (sizeof(E) == 2) {
+                // bfloat16: one v_mfma_f32_32x32x16_bf16 per block; lane half h supplies 8 consecutive k
 #pragma unroll
-            for (int i = 0; i < S::TI; ++i)
+                for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < S::TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].x, fa[j].x, acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fr[i]), __builtin_bit_cast(bf16x8, fa[j]), acc[i][j], 0, 0, 0);
+            } else {
+                // float32: four v_mfma_f32_32x32x2f32 per block, k step outermost so consecutive MFMAs
+                // write different accumulators
 #pragma unroll
-            for (int i = 0; i < S::TI; ++i)
+                for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < S::TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].y, fa[j].y, acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].x, fa[j].x, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < S::TI; ++i)
+                for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < S::TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].z, fa[j].z, acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].y, fa[j].y, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < S::TI; ++i)
+                for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-                for (int j = 0; j < S::TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].w, fa[j].w, acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].z, fa[j].z, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[i].w, fa[j].w, acc[i][j], 0, 0, 0);
+            }
         }
         asm volatile("" ::: "memory");       // and consume it only after
         CORR_STORE_SLICE(cur ^ 1);
@@ -181,7 +197,8 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
 #undef CORR_LOAD_SLICE
 #undef CORR_STORE_SLICE
 
-    // D[row][col] of a 32x32x2 block: lane l, register r -> row 8(r/4) + 4(l/32) + r%4, col l%32.
+    // D[row][col] of a 32x32 block (both instructions): lane l, register r -> row 8(r/4) + 4(l/32) + r%4,
+    // col l%32.
 #pragma unroll
     for (int i = 0; i < S::TI; ++i)
 #pragma unroll
@@ -196,8 +213,8 @@ __global__ __launch_bounds__((Shape<BM, BN, WM, WN>::THREADS)) void corr_gemm_f3
         }
 }
 
-template <int BM, int BN, int WM, int WN>
-hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const float* Rbuf, int64_t ldr,
+template <class E, int BM, int BN, int WM, int WN>
+hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                         const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                         int n_lo, int n_hi, hipStream_t stream)
 {
@@ -205,10 +222,28 @@ hipError_t launch_shape(const float* At, int64_t lda, int m, int kpad, const flo
     const int tiles_n = (m + BN - 1) / BN;
     const int64_t nwg = (int64_t)tiles_m * tiles_n;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((corr_gemm_f32_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg),
+    hipLaunchKernelGGL((corr_gemm_kernel<E, BM, BN, WM, WN>), dim3((unsigned)nwg),
                        dim3(Shape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
                        n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi);
     return hipGetLastError();
+}
+
+template <class E>
+hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
+                          const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
+                          int n_lo, int n_hi, hipStream_t stream)
+{
+    if (p_grid <= 0 || m <= 0) return hipSuccess;
+    if (kpad % (ROW_BYTES / (int)sizeof(E))) return hipErrorInvalidValue;
+    switch (variant) {
+    case 0: return launch_shape<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 1: return launch_shape<E, 128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 2: return launch_shape<E, 256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -231,16 +266,18 @@ hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m
                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                 int n_lo, int n_hi, hipStream_t stream)
 {
-    if (p_grid <= 0 || m <= 0) return hipSuccess;
-    switch (variant) {
-    case 0: return launch_shape<128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 1: return launch_shape<128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 2: return launch_shape<256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 3: return launch_shape<64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 4: return launch_shape<32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 5: return launch_shape<64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    default: return hipErrorInvalidValue;
-    }
+    return launch_variant<float>(variant, At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row,
+                                 n_lo, n_hi, stream);
+}
+
+hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, int m, int kpad,
+                                 const uint16_t* Rbuf, int64_t ldr, const int* act,
+                                 const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
+                                 int n_lo, int n_hi, hipStream_t stream)
+{
+    return launch_variant<__bf16>(variant, reinterpret_cast<const __bf16*>(At), lda, m, kpad,
+                                  reinterpret_cast<const __bf16*>(Rbuf), ldr, act, n_act_dev, p_grid, G, ldg,
+                                  zero_row, n_lo, n_hi, stream);
 }
 
 }  // namespace bmpl

@@ -303,6 +303,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         if (!isfinite(v)) bad = 1;
         Bw[r] = v;
         R[r] = v;
+        if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round(v);
         part += (double)v * (double)v;
     }
     if (bad) atomicOr(&s_bad, 1);
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.kkt_on[sig] = 0.0;
         w.kkt[sig] = 0.0;
         w.obj[sig] = 0.5 * bb;
+        if (w.rnorm) w.rnorm[sig] = sqrt(bb);
     }
 }
 
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                     if (ns == 0 && vm <= lam) {
                         if (kk <= a.kkt_tol) st |= BMPL_SIG_CONVERGED;
                     } else if (ns == 0) {
-                        st |= BMPL_SIG_CAP_ACTIVE;
+                        if (!(st & BMPL_SIG_INEXACT)) st |= BMPL_SIG_CAP_ACTIVE;
                     } else {
                         st |= BMPL_SIG_CAP_ITERS;
                     }
@@ -721,10 +723,14 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
         for (; k < nS; ++k) acc -= (double)a.At[(int64_t)satom[k] * a.lda + r] * sx[k];
         if (r >= w.n) acc = 0.0;
         Rres[r] = (float)acc;
+        if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round((float)acc);
         rr += acc * acc;
     }
     const double rn = block_sum(rr, red);
-    if (tid == 0) w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
+    if (tid == 0) {
+        w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
+        if (w.rnorm) w.rnorm[sig] = sqrt(rn);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,263 @@
+// Reduced-precision screening of the worst-case analysis (Algorithm 1, step 3).
+//
+// With a bfloat16 correlation product g~ = bf16(A)^T bf16(xi) (float32
+// accumulation) every entry is within a certified band of the float32 value:
+//     |g~_j - g_j| <= eps_i = gamma_n * max_j ||a_j|| * ||xi_i||,
+//     gamma_n = (2^-7 + 2^-16 + n 2^-24) * 1.01,
+// (each operand rounds with relative error 2^-8, the products are exact, the
+// float32 accumulation adds n 2^-24 of sum |a_j||xi|, and sum |a_j||xi| <=
+// ||a_j|| ||xi|| by Cauchy-Schwarz).  The screen keeps every atom whose band
+// could reach the selection threshold, the candidates are re-scored exactly
+// (float32 data, float64 accumulation), and only re-scored values decide which
+// atoms enter I and whether the natural stopping condition Eq. (9) holds.  So
+// the selected atoms are exactly the float32 top-rho violators and the stop is
+// certified, as with the float32 product.
+//
+// Candidate rule for signal i (atoms outside I, L_j = |g~_j| - eps, U_j = |g~_j| + eps):
+//   tau = rho-th largest L_j (or -inf), thr = max(lambda, tau);  C = { j : U_j > thr }.
+// Every true top-rho violator lies in C (its |g_j| is at least tau and above lambda), and
+// when tau <= lambda every possible violator does.  For the relative lambda rule on the
+// first pass, lambda is replaced by the lower bound c (max|g~| - eps) and C also holds every
+// atom that may attain max_j |g_j| (U_j >= max|g~| - eps), so the exact maximum sets lambda.
+#include <float.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "../../include/bmpl.h"
+#include "bmpl_internal.h"
+
+namespace bmpl {
+namespace {
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ src, int64_t lds,
+                                                      uint16_t* __restrict__ dst, int64_t ldd, int rows, int cols)
+{
+    const int r = blockIdx.x;
+    if (r >= rows) return;
+    for (int c = threadIdx.x; c < cols; c += 256) dst[(int64_t)r * ldd + c] = bf16_round(src[(int64_t)r * lds + c]);
+}
+
+__global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict__ At, int64_t lda, int n,
+                                                        float* __restrict__ norms, int m)
+{
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const double v = At[(int64_t)j * lda + k];
+        s += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) norms[j] = (float)sqrt(red[0] + red[1] + red[2] + red[3]) * (1.0f + 1e-6f);
+}
+
+constexpr int KMAX = 64;
+
+__global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
+{
+    __shared__ float s_top[4][KMAX];
+    __shared__ float s_red[8];
+    __shared__ int s_cnt;
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    const float* g = a.G + (int64_t)row * a.ldg;
+    const uint32_t* ex = a.excl ? a.excl + (int64_t)sig * a.words : nullptr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float eps = (float)(a.gamma_amax * a.rnorm[sig]);
+
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        const int room = a.max_active - a.nI[sig];
+        k = room < k ? (room > 0 ? room : 0) : k;
+    }
+    // Pass 1: the k largest |g~| outside I (values only) and the largest |g~| overall.
+    float top[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) top[q] = -1.f;
+    float gall = 0.f;
+    for (int j = tid; j < a.m; j += 256) {
+        const float v = fabsf(g[j]);
+        gall = fmaxf(gall, v);
+        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+        if (!(v > top[KMAX - 1])) continue;
+        float cv = v;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            const bool sw = cv > top[q];
+            const float t = top[q];
+            top[q] = sw ? cv : t;
+            cv = sw ? t : cv;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
+    // wave merge of the per-thread lists: k rounds of a wave max on the heads
+    for (int r = 0; r < k; ++r) {
+        float b = top[0];
+        for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+        if (lane == 0) s_top[wave][r] = b;
+        // the first lane holding the head value pops it
+        const unsigned long long owners = __ballot(top[0] == b);
+        if (owners && lane == __ffsll((long long)owners) - 1) {
+#pragma unroll
+            for (int q = 0; q < KMAX - 1; ++q) top[q] = top[q + 1];
+            top[KMAX - 1] = -1.f;
+        }
+    }
+    if (lane == 0) s_red[wave] = gall;
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    // k-th largest over the four wave lists
+    float kth = -1.f;
+    if (k > 0) {
+        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        for (int r = 0; r < k; ++r) {
+            const float v0 = p0 < k ? s_top[0][p0] : -1.f, v1 = p1 < k ? s_top[1][p1] : -1.f;
+            const float v2 = p2 < k ? s_top[2][p2] : -1.f, v3 = p3 < k ? s_top[3][p3] : -1.f;
+            const float b = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+            kth = b;
+            if (b == v0) ++p0; else if (b == v1) ++p1; else if (b == v2) ++p2; else ++p3;
+        }
+    }
+    const float gmax = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+    const double lam_lo = a.lam_rel > 0.0 ? a.lam_rel * ((double)gmax - eps) : a.lam[sig];
+    const double tau = kth >= 0.f ? (double)kth - eps : -1.0;
+    const double thr = lam_lo > tau ? lam_lo : tau;
+    const double thr_max = a.lam_rel > 0.0 ? (double)gmax - eps : DBL_MAX;   // U_j >= this: may attain the max
+
+    // Pass 2: collect the candidates.
+    int* cand = a.cand + (int64_t)sig * a.candcap;
+    for (int j0 = 0; j0 < a.m; j0 += 256) {
+        const int j = j0 + tid;
+        bool take = false;
+        if (j < a.m && !(ex && ((ex[j >> 5] >> (j & 31)) & 1u))) {
+            const double u = (double)fabsf(g[j]) + eps;
+            take = (u > thr) || (u >= thr_max);
+        }
+        const unsigned long long bal = __ballot(take);
+        int base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&s_cnt, __popcll(bal));
+        base = __shfl(base, 0);
+        if (take) {
+            const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+            if (pos < a.candcap) cand[pos] = j;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) a.ncand[sig] = s_cnt;
+}
+
+// Exact re-score of the candidates, then the selection itself.
+__global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
+{
+    extern __shared__ double s_val[];           // [candcap_lds] |g_j| of the candidates
+    __shared__ double red[4];
+    __shared__ int s_lim;
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nc_all = a.ncand[sig];
+    const bool overflow = nc_all > a.candcap || nc_all > a.candcap_lds;
+    const int nc = overflow ? 0 : nc_all;
+    const int* cand = a.cand + (int64_t)sig * a.candcap;
+    const float* r = a.R + (int64_t)sig * a.ldr;
+
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        const int room = a.max_active - a.nI[sig];
+        k = room < k ? (room > 0 ? room : 0) : k;
+    }
+    // exact a_j^T xi (float32 data, float64 accumulation), one wave per candidate
+    for (int c = wave; c < nc; c += 4) {
+        const float* aj = a.At + (int64_t)cand[c] * a.lda;
+        double acc = 0.0;
+        for (int q = lane; q < a.kpad; q += 64) acc += (double)aj[q] * (double)r[q];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) s_val[c] = fabs(acc);
+    }
+    __syncthreads();
+    double mx = 0.0;
+    for (int c = tid; c < nc; c += 256) mx = fmax(mx, s_val[c]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double lam = a.lam[sig];
+    if (a.lam_rel > 0.0) {
+        lam = a.lam_rel * mx;
+        if (tid == 0) a.lam[sig] = lam;
+    }
+    // rank the violators: larger |g| first, ties to the lower atom index
+    int cnt = 0;
+    for (int c = tid; c < nc; c += 256) {
+        const double v = s_val[c];
+        if (!(v > lam)) continue;
+        const int j = cand[c];
+        int rank = 0;
+        for (int d = 0; d < nc; ++d) {
+            const double w = s_val[d];
+            if (w > lam && (w > v || (w == v && cand[d] < j))) ++rank;
+        }
+        if (rank < k) a.sel[(int64_t)sig * a.selcap + rank] = j;
+        ++cnt;
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) red[wave] = (double)cnt;
+    __syncthreads();
+    if (tid == 0) {
+        int nv = (int)(red[0] + red[1] + red[2] + red[3]);
+        nv = nv < k ? nv : k;
+        a.nsel[sig] = nv;
+        float vm = (float)mx;
+        if (nv == 0 && (double)vm > lam) vm = nextafterf(vm, 0.f);   // keep the float copy <= lambda
+        a.vmax[sig] = vm;
+        if (overflow) {
+            a.nsel[sig] = 0;
+            a.vmax[sig] = FLT_MAX;
+            a.status[sig] |= BMPL_SIG_INEXACT;
+        }
+        s_lim = a.nsel[sig];
+    }
+    __syncthreads();
+    for (int q = s_lim + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
+}
+
+}  // namespace
+
+hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd, int rows, int cols,
+                          hipStream_t stream)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(rows), dim3(256), 0, stream, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_atom_norms(const float* At, int64_t lda, int n, float* norms, int m, hipStream_t stream)
+{
+    hipLaunchKernelGGL(atom_norm_kernel, dim3(m), dim3(256), 0, stream, At, lda, n, norms, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(const ScreenArgs& a, hipStream_t stream)
+{
+    if (a.p_grid <= 0) return hipSuccess;
+    if (a.k < 0 || a.k > KMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(screen_select_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream)
+{
+    if (a.p_grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rescore_kernel, dim3(a.p_grid), dim3(256), (size_t)a.candcap_lds * sizeof(double), stream,
+                       a);
+    return hipGetLastError();
+}
+
+}  // namespace bmpl

@@ -283,3 +283,76 @@ def test_graph_mode_matches_host_loop():
             assert torch.equal(out["x_val"], host["x_val"])
         ref = oracle.solve(P.At, P.Bt, lam, P.rho)
         check_batch(P.At, P.Bt, lam, out, ref)
+
+
+# ---------------------------------------------------------------------------
+# Reduced-precision screening (bfloat16 product, exact re-score)
+# ---------------------------------------------------------------------------
+
+def bf16_band(At, Rt):
+    """Per-entry certified band gamma_n ||a_j|| ||r_i|| of the bfloat16 product."""
+    n = At.shape[1]
+    gamma = (2.0 ** -7 + 2.0 ** -16 + n * 2.0 ** -24) * 1.01
+    an = np.linalg.norm(At.astype(np.float64), axis=1)
+    rn = np.linalg.norm(Rt.astype(np.float64), axis=1)
+    return gamma * np.outer(rn, an)
+
+
+@pytest.mark.parametrize("n,m,p", [(128, 700, 33), (2048, 4100, 130)])
+def test_bf16_correlate_within_band(n, m, p):
+    pk = _lib()
+    rng = np.random.default_rng(n + p)
+    At = rng.standard_normal((m, n)).astype(np.float32)
+    At /= np.linalg.norm(At, axis=1, keepdims=True)
+    Rt = rng.standard_normal((p, n)).astype(np.float32)
+    s = pk.Solver(to_dev(At), 0.1, screen="bf16")
+    G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
+    ref = Rt.astype(np.float64) @ At.astype(np.float64).T
+    band = bf16_band(At, Rt)
+    assert np.all(np.abs(G - ref) <= band)
+    # and it is a bfloat16 product, not a float32 one: errors well above float32's
+    assert np.max(np.abs(G - ref)) > 1e-4 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_bf16_screening_parity(graph):
+    pk = _lib()
+    for P in (bi.small_gaussian(), bi.tiny_gaussian(n=256, m=2000, p=257, k=30, sigma=0.01, seed=91, rho=7)):
+        lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+        s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, screen="bf16", graph=graph)
+        out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+        st = out["status"].cpu().numpy()
+        assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st)
+        ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+        check_batch(P.At, P.Bt, lam, out, ref)
+        # same selections as the float32 path up to near-ties: identical supports here
+        f32 = pk.Solver(to_dev(P.At), 0.0, rho=P.rho).solve(to_dev(P.Bt), lam=to_dev(lam))
+        assert torch.equal(out["supp_len"], f32["supp_len"]) and torch.equal(out["x_idx"], f32["x_idx"])
+
+
+def test_bf16_relative_lambda_is_exact_maximum():
+    pk = _lib()
+    P = bi.small_gaussian()
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho, screen="bf16")
+    out = s.solve(to_dev(P.Bt))
+    lam_or = lam_rel(P.At, P.Bt, P.lambda_rel)
+    # re-scored in float64 from float32 data: far tighter than the bfloat16 band
+    np.testing.assert_allclose(out["lambda"].cpu().numpy(), lam_or, rtol=1e-12)
+    ref = oracle.solve(P.At, P.Bt, lam_or, P.rho)
+    check_batch(P.At, P.Bt, lam_or, out, ref)
+
+
+@pytest.mark.slow
+def test_cs_gaussian_bf16_full_size_sampled():
+    pk = _lib()
+    P = bi.cs_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho, screen="bf16", graph=True)
+    out = s.solve(to_dev(P.Bt))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED)
+    np.testing.assert_allclose(out["lambda"].cpu().numpy(), lam, rtol=1e-12)
+    rows = list(range(7, P.p, 61))
+    ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
+    check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
