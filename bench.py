@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
 PEAK_HBM_GBS = 8000.0
 
 
@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--workload", default="cs2048x16384")
     ap.add_argument("--cpu-sample", type=int, default=32, help="signals the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16"),
+                    help="precision of the correlation product (bf16: certified screening + float32 re-score)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary bf16-screened measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (signals shard with no "
@@ -71,7 +74,7 @@ def main():
     At = torch.from_numpy(P.At).to(dev)
     Bt = torch.from_numpy(P.Bt).to(dev)
     # Throughput: graph-captured segments, no instrumentation.
-    solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True)
+    solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=args.screen)
     tune = solver.autotune(P.p)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -92,7 +95,7 @@ def main():
 
     # Kernel breakdown and the correlation kernel's roofline: the same steps again with every
     # launch bracketed by HIP events on the solve stream (host-driven loop, same tile shapes).
-    timed = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True)
+    timed = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen=args.screen)
     timed.set_tuning(tune["shapes"])
     for _ in range(args.warmup):
         timed.solve(Bt)
@@ -107,13 +110,14 @@ def main():
     corr_avg_s = tm["corr_ms"] / max(1, tm["corr_launches"]) * 1e-3
     achieved = tm["corr_flops"] / (tm["corr_ms"] * 1e-3) / 1e12 if tm["corr_ms"] > 0 else 0.0
     traffic = None
-    rec = load_traffic(os.path.join(ROOT, "profiles", f"corr_gemm_f32_{args.workload}_pmc.json"),
+    rec = load_traffic(os.path.join(ROOT, "profiles", f"corr_gemm_{args.screen}_{args.workload}_pmc.json"),
                        os.path.join(ROOT, "paper_1302_5010_amd", "csrc", "corr_gemm.hip"))
     if rec is not None:
         traffic = rec.get("hbm_bytes_per_launch")
 
     result = {
-        "metric": "signals solved/sec at KKT tol 1e-4 (plain FP32 BMPL)",
+        "metric": "signals solved/sec at KKT tol 1e-4 (" + ("plain FP32" if args.screen == "fp32"
+                                                          else "BF16-screened") + " BMPL)",
         "value": sum(conv) / elapsed,
         "unit": "signals/s",
         "n_gpus": 1,
@@ -123,17 +127,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.screen == "fp32" else "bf16",
         "data": "synthetic (seeded)",
         "config": {"workload": P.name, "n": P.n, "m": P.m, "p": P.p, "rho": P.rho,
-                   "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": "fp32"},
+                   "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": args.screen, "graph": True},
         "roofline": {
             "bound": "mfma",
-            "kernel": "corr_gemm_f32",
+            "kernel": "corr_gemm_" + args.screen,
             "achieved": achieved,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": PEAK_TFLOPS[args.screen],
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "frac": achieved / PEAK_TFLOPS[args.screen],
             "traffic": traffic,
             "avg_launch_ms": corr_avg_s * 1e3,
             "launches": tm["corr_launches"],
@@ -153,6 +157,41 @@ def main():
                     "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
                     "support_mean": float(np.mean(supp))},
     }
+
+    if args.screen == "fp32" and not args.no_extra:
+        # The same workload with the bfloat16 screening product (certified band + exact re-score).
+        bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
+        bf.autotune(P.p)
+        for _ in range(args.warmup):
+            bf.solve(Bt)
+        torch.cuda.synchronize()
+        solved_bf = []
+        t4 = time.perf_counter()
+        for _ in range(args.steps):
+            solved_bf.append(bf.solve(Bt)["status"])
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        conv_bf = [int(((s & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for s in solved_bf]
+        bft = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen="bf16")
+        bft.set_tuning(bf.autotune(P.p)["shapes"])
+        bft.solve(Bt)
+        torch.cuda.synchronize()
+        bft.reset_timing()
+        for _ in range(args.steps):
+            bft.solve(Bt)
+        torch.cuda.synchronize()
+        tb = bft.timing()
+        ach_bf = tb["corr_flops"] / (tb["corr_ms"] * 1e-3) / 1e12 if tb["corr_ms"] > 0 else 0.0
+        result["bf16_screened"] = {
+            "value": sum(conv_bf) / (t5 - t4), "unit": "signals/s", "ms_per_step": (t5 - t4) / args.steps * 1e3,
+            "converged_per_step": conv_bf,
+            "corr_gemm_bf16": {"achieved_tflops": ach_bf, "peak_tflops": PEAK_TFLOPS["bf16"],
+                               "frac": ach_bf / PEAK_TFLOPS["bf16"],
+                               "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"])},
+            "kernel_ms_per_step": {k: tb[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms",
+                                                                    "residual_ms", "other_ms", "wall_ms")},
+        }
+        del bf, bft
 
     if not args.no_cpu and args.cpu_sample > 0:
         import oracle

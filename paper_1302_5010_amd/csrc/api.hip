@@ -629,9 +629,11 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             RescoreArgs rs{};
             rs.At = c->At; rs.lda = c->kpad; rs.kpad = c->kpad;
             rs.R = w.R; rs.ldr = c->kpad;
+            rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.gamma_amax = c->gamma_amax;
             rs.act = c->act[cur]; rs.n_act_dev = c->n_act_dev + cur; rs.p_grid = n_grid;
             rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
-            rs.candcap_lds = (int)std::min<size_t>(CANDCAP_DEF, c->lds_dyn_max / sizeof(double));
+            // candidate values (12 bytes each) and the staged residual within 60 KB of LDS
+            rs.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));
             rs.ncand = c->ncand;
             rs.lam = w.lam; rs.lam_rel = a.lam_rel;
             rs.k = rho; rs.nI = w.nI; rs.max_active = max_active;

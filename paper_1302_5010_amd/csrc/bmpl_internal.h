@@ -109,6 +109,8 @@ struct ScreenArgs {
 struct RescoreArgs {
     const float* At; int64_t lda; int kpad;  // float32 atoms
     const float* R; int64_t ldr;             // float32 residuals
+    const float* G; int64_t ldg;             // screening product (row per running signal)
+    const double* rnorm; double gamma_amax;  // the band
     const int* act; const int* n_act_dev; int p_grid;
     const int* cand; int candcap; int candcap_lds; const int* ncand;
     double* lam; double lam_rel;

@@ -54,8 +54,7 @@ __global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict_
     if (threadIdx.x == 0) norms[j] = (float)sqrt(red[0] + red[1] + red[2] + red[3]) * (1.0f + 1e-6f);
 }
 
-constexpr int KMAX = 64;
-
+template <int KMAX>
 __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
 {
     __shared__ float s_top[4][KMAX];
@@ -80,11 +79,8 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) top[q] = -1.f;
     float gall = 0.f;
-    for (int j = tid; j < a.m; j += 256) {
-        const float v = fabsf(g[j]);
-        gall = fmaxf(gall, v);
-        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-        if (!(v > top[KMAX - 1])) continue;
+    auto consider = [&](float v) {
+        if (!(v > top[KMAX - 1])) return;
         float cv = v;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) {
@@ -93,6 +89,24 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
             top[q] = sw ? cv : t;
             cv = sw ? t : cv;
         }
+    };
+    const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
+    const int m4 = vec4 ? (a.m & ~3) : 0;
+    for (int j0 = 4 * tid; j0 < m4; j0 += 1024) {
+        const float4 f = *reinterpret_cast<const float4*>(g + j0);
+        const float v0 = fabsf(f.x), v1 = fabsf(f.y), v2 = fabsf(f.z), v3 = fabsf(f.w);
+        gall = fmaxf(gall, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
+        const uint32_t word = ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
+        if (!(word & 1u)) consider(v0);
+        if (!(word & 2u)) consider(v1);
+        if (!(word & 4u)) consider(v2);
+        if (!(word & 8u)) consider(v3);
+    }
+    for (int j = m4 + tid; j < a.m; j += 256) {
+        const float v = fabsf(g[j]);
+        gall = fmaxf(gall, v);
+        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+        consider(v);
     }
     for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
     // wave merge of the per-thread lists: k rounds of a wave max on the heads
@@ -151,11 +165,15 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
     if (tid == 0) a.ncand[sig] = s_cnt;
 }
 
-// Exact re-score of the candidates, then the selection itself.
+// Exact re-score of the candidates (float32 data, float64 accumulation), then the
+// selection itself.  Scored in two stages: first the k candidates with the largest
+// |g~| (their k-th exact value v_k bounds the true k-th largest from below), then only
+// the candidates whose band still reaches max(lambda, v_k); the rest cannot enter the
+// top k nor violate.  The residual is staged in LDS once per signal.
 __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
 {
-    extern __shared__ double s_val[];           // [candcap_lds] |g_j| of the candidates
-    __shared__ double red[4];
+    extern __shared__ double s_dyn[];
+    __shared__ double red[8];
     __shared__ int s_lim;
     const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
     const int row = blockIdx.x;
@@ -167,19 +185,83 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     const int nc = overflow ? 0 : nc_all;
     const int* cand = a.cand + (int64_t)sig * a.candcap;
     const float* r = a.R + (int64_t)sig * a.ldr;
+    const float* gt = a.G + (int64_t)row * a.ldg;
+    double* s_val = s_dyn;                                       // [candcap_lds] exact |g|, -1 = unscored
+    float* s_gt = reinterpret_cast<float*>(s_dyn + a.candcap_lds);   // [candcap_lds] |g~|
+    float* s_r = s_gt + a.candcap_lds;                           // [kpad] residual
+    const double eps = a.gamma_amax * a.rnorm[sig];
 
     int k = a.k;
     if (a.nI && a.max_active > 0) {
         const int room = a.max_active - a.nI[sig];
         k = room < k ? (room > 0 ? room : 0) : k;
     }
-    // exact a_j^T xi (float32 data, float64 accumulation), one wave per candidate
-    for (int c = wave; c < nc; c += 4) {
-        const float* aj = a.At + (int64_t)cand[c] * a.lda;
+    for (int q = tid; q < a.kpad; q += 256) s_r[q] = r[q];
+    for (int c = tid; c < nc; c += 256) {
+        s_val[c] = -1.0;
+        s_gt[c] = fabsf(gt[cand[c]]);
+    }
+    __syncthreads();
+    auto score = [&](int c) {     // by one wave; returns in every lane
+        const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)cand[c] * a.lda);
+        const float4* r4 = reinterpret_cast<const float4*>(s_r);
         double acc = 0.0;
-        for (int q = lane; q < a.kpad; q += 64) acc += (double)aj[q] * (double)r[q];
+        for (int q = lane; q < a.kpad / 4; q += 64) {
+            const float4 x = aj[q], y = r4[q];
+            acc += (double)x.x * y.x + (double)x.y * y.y + (double)x.z * y.z + (double)x.w * y.w;
+        }
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) s_val[c] = fabs(acc);
+        return fabs(acc);
+    };
+    // Stage 1: the candidates ranked among the first k by |g~| (ties to the lower atom).
+    for (int c = wave; c < nc; c += 4) {
+        const float v = s_gt[c];
+        const int j = cand[c];
+        int rank = 0;
+        for (int d = lane; d < nc; d += 64) {
+            const float w = s_gt[d];
+            rank += (w > v || (w == v && cand[d] < j)) ? 1 : 0;
+        }
+        for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o);
+        if (rank < (k > 0 ? k : 1)) {
+            const double e = score(c);
+            if (lane == 0) s_val[c] = e;
+        }
+    }
+    __syncthreads();
+    // v_k (k-th largest exact value so far) and the largest exact value so far.
+    if (tid == 0) { red[0] = -1.0; red[1] = 0.0; }
+    __syncthreads();
+    double e1 = 0.0;
+    for (int c = tid; c < nc; c += 256) {
+        const double v = s_val[c];
+        if (v < 0.0) continue;
+        e1 = fmax(e1, v);
+        int gt = 0, ge = 0;
+        for (int d = 0; d < nc; ++d) {
+            const double w = s_val[d];
+            gt += w > v;
+            ge += w >= v;
+        }
+        if (k > 0 && gt < k && ge >= k) red[0] = v;   // every writer stores the same value
+    }
+    for (int o = 32; o > 0; o >>= 1) e1 = fmax(e1, __shfl_xor(e1, o));
+    __syncthreads();
+    if (lane == 0) red[2 + wave] = e1;   // red[0] = v_k, red[2..5] = per-wave maxima
+    __syncthreads();
+    const double vk = red[0];
+    e1 = fmax(fmax(red[2], red[3]), fmax(red[4], red[5]));
+    __syncthreads();
+    const bool rel = a.lam_rel > 0.0;
+    const double lam_lo = rel ? a.lam_rel * e1 : a.lam[sig];    // lambda >= this (the max is >= e1)
+    const double thr = lam_lo > vk ? lam_lo : vk;
+    // Stage 2: every remaining candidate whose band reaches thr (or, for the relative rule, the max).
+    for (int c = wave; c < nc; c += 4) {
+        if (s_val[c] >= 0.0) continue;
+        const double u = (double)s_gt[c] + eps;
+        if (!(u > thr) && !(rel && u >= e1)) continue;
+        const double e = score(c);
+        if (lane == 0) s_val[c] = e;
     }
     __syncthreads();
     double mx = 0.0;
@@ -189,10 +271,11 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     __syncthreads();
     mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     double lam = a.lam[sig];
-    if (a.lam_rel > 0.0) {
+    if (rel) {
         lam = a.lam_rel * mx;
         if (tid == 0) a.lam[sig] = lam;
     }
+    __syncthreads();
     // rank the violators: larger |g| first, ties to the lower atom index
     int cnt = 0;
     for (int c = tid; c < nc; c += 256) {
@@ -247,16 +330,21 @@ hipError_t launch_atom_norms(const float* At, int64_t lda, int n, float* norms, 
 hipError_t launch_screen(const ScreenArgs& a, hipStream_t stream)
 {
     if (a.p_grid <= 0) return hipSuccess;
-    if (a.k < 0 || a.k > KMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(screen_select_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
+    if (a.k < 0 || a.k > 64) return hipErrorInvalidValue;
+    if (a.k <= 16)
+        hipLaunchKernelGGL(screen_select_kernel<16>, dim3(a.p_grid), dim3(256), 0, stream, a);
+    else if (a.k <= 32)
+        hipLaunchKernelGGL(screen_select_kernel<32>, dim3(a.p_grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(screen_select_kernel<64>, dim3(a.p_grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream)
 {
     if (a.p_grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rescore_kernel, dim3(a.p_grid), dim3(256), (size_t)a.candcap_lds * sizeof(double), stream,
-                       a);
+    const size_t lds = (size_t)a.candcap_lds * (sizeof(double) + sizeof(float)) + (size_t)a.kpad * sizeof(float);
+    hipLaunchKernelGGL(rescore_kernel, dim3(a.p_grid), dim3(256), lds, stream, a);
     return hipGetLastError();
 }
 

@@ -356,3 +356,76 @@ def test_cs_gaussian_bf16_full_size_sampled():
     rows = list(range(7, P.p, 61))
     ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
     check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
+
+
+# ---------------------------------------------------------------------------
+# Ragged supports (1024 x 32768, k ~ U{10..400}) and the face-like dictionary
+# ---------------------------------------------------------------------------
+
+def _golden_ragged():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ragged1024x32768_oracle.npz")
+    g = np.load(path)
+    X = np.zeros((len(g["rows"]), 32768))
+    off = 0
+    for q, ln in enumerate(g["supp_len"]):
+        X[q, g["idx"][off:off + ln]] = g["val"][off:off + ln]
+        off += ln
+    return g, X
+
+
+def test_ragged_supports_against_stored_oracle():
+    """Six signals of the ragged workload (supports 10 to 955 atoms, 1 to 152 iterations), solved as
+    one batch, against oracle results stored by tests/golden/make_golden.py."""
+    pk = _lib()
+    g, X = _golden_ragged()
+    rows = [int(r) for r in g["rows"]]
+    P = bi.ragged_gaussian(indices=rows)
+    lam = g["lam"]
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    torch.cuda.synchronize()
+    assert np.all(out["status"].cpu().numpy() == pk.BMPL_SIG_CONVERGED)
+    ref = {"X": X}
+    check_batch(P.At, P.Bt, lam, out, ref)
+    np.testing.assert_array_equal(out["iters"].cpu().numpy(), g["iters"])
+
+
+@pytest.mark.slow
+def test_ragged_full_batch():
+    """All 4096 ragged signals in one solve (graph segments, capacity growth to ~1000 slots);
+    the stored rows must match, every signal must converge."""
+    pk = _lib()
+    g, X = _golden_ragged()
+    rows = [int(r) for r in g["rows"]]
+    P = bi.ragged_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    np.testing.assert_allclose(lam[rows], g["lam"], rtol=1e-15)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    check_batch(P.At, P.Bt, lam[rows], out, {"X": X}, rows=range(len(rows)), gpu_rows=rows)
+
+
+@pytest.mark.parametrize("screen", ["fp32", "bf16"])
+def test_face_like_sampled(screen):
+    """Correlated class-structured dictionary (200 classes x 100 atoms, rank-8 class subspaces):
+    all 8192 signals solved, 64 sampled signals against the oracle; supports stay in-class."""
+    pk = _lib()
+    P = bi.face_like()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho, screen=screen, graph=True)
+    out = s.solve(to_dev(P.Bt))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    rows = list(range(3, P.p, 128))
+    ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
+    check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
+    cls = P.meta["class_of_atom"]
+    Xg = dense_from_gpu(out, P.m)
+    for i in rows:
+        S = np.nonzero(Xg[i])[0]
+        assert len(np.unique(cls[S])) == 1 and cls[S[0]] == P.supports[i][0] // 100
