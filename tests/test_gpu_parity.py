@@ -363,13 +363,18 @@ def test_cs_gaussian_bf16_full_size_sampled():
 # ---------------------------------------------------------------------------
 
 def _golden_ragged():
+    import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "ragged1024x32768_oracle.npz")
-    g = np.load(path)
+    path = os.path.join(os.path.dirname(__file__), "golden", "ragged1024x32768_oracle.json")
+    with open(path) as f:
+        raw = json.load(f)
+    g = {"rows": np.array(raw["rows"]), "iters": np.array(raw["iters"]),
+         "lam": np.array([float.fromhex(v) for v in raw["lam"]])}
+    val = [float.fromhex(v) for v in raw["val"]]
     X = np.zeros((len(g["rows"]), 32768))
     off = 0
-    for q, ln in enumerate(g["supp_len"]):
-        X[q, g["idx"][off:off + ln]] = g["val"][off:off + ln]
+    for q, ln in enumerate(raw["supp_len"]):
+        X[q, raw["idx"][off:off + ln]] = val[off:off + ln]
         off += ln
     return g, X
 
