@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16"),
                     help="precision of the correlation product (bf16: certified screening + float32 re-score)")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary bf16-screened measurement")
+    ap.add_argument("--host-loop", action="store_true",
+                    help="drive the outer iterations from the host instead of replaying captured graph segments")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (signals shard with no "
@@ -74,7 +76,8 @@ def main():
     At = torch.from_numpy(P.At).to(dev)
     Bt = torch.from_numpy(P.Bt).to(dev)
     # Throughput: graph-captured segments, no instrumentation.
-    solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=args.screen)
+    solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=not args.host_loop,
+                       screen=args.screen)
     tune = solver.autotune(P.p)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -130,7 +133,8 @@ def main():
         "dtype": "f32" if args.screen == "fp32" else "bf16",
         "data": "synthetic (seeded)",
         "config": {"workload": P.name, "n": P.n, "m": P.m, "p": P.p, "rho": P.rho,
-                   "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": args.screen, "graph": True},
+                   "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": args.screen,
+                   "graph": not args.host_loop},
         "roofline": {
             "bound": "mfma",
             "kernel": "corr_gemm_" + args.screen,

@@ -417,7 +417,8 @@ def test_ragged_full_batch():
 @pytest.mark.parametrize("screen", ["fp32", "bf16"])
 def test_face_like_sampled(screen):
     """Correlated class-structured dictionary (200 classes x 100 atoms, rank-8 class subspaces):
-    all 8192 signals solved, 64 sampled signals against the oracle; supports stay in-class."""
+    all 8192 signals solved, 64 sampled signals against the oracle; the l1 mass sits in the true class
+    (a few LASSO solutions carry tiny out-of-class coefficients, which the oracle shares)."""
     pk = _lib()
     P = bi.face_like()
     lam = lam_rel(P.At, P.Bt, P.lambda_rel)
@@ -433,4 +434,6 @@ def test_face_like_sampled(screen):
     Xg = dense_from_gpu(out, P.m)
     for i in rows:
         S = np.nonzero(Xg[i])[0]
-        assert len(np.unique(cls[S])) == 1 and cls[S[0]] == P.supports[i][0] // 100
+        mass = np.bincount(cls[S], weights=np.abs(Xg[i][S]), minlength=int(cls.max()) + 1)
+        true_cls = P.supports[i][0] // 100
+        assert np.argmax(mass) == true_cls and mass[true_cls] >= 0.99 * mass.sum()
