@@ -190,6 +190,27 @@ def tiny_gaussian(n: int, m: int, p: int, k: int, sigma: float, seed: int,
     return Problem(f"tiny{n}x{m}", At, Bt, lambda_rel, rho, S, a, {"k": k, "sigma": sigma})
 
 
+def projection(m: int, d: int, seed: int = 0) -> np.ndarray:
+    """Fixed random projection of the proposal network's input: m x d, i.i.d. N(0, 1/d), float32."""
+    rng = _rng(200, seed, 0)
+    return (rng.standard_normal((m, d)) / np.sqrt(d)).astype(np.float32)
+
+
+def mlp_init(d: int, h: int, m: int, seed: int = 0, prior: float | None = None) -> np.ndarray:
+    """Initial flat parameters of the proposal network (layout W1, b1, W2, b2, W3, b3).
+
+    Weights i.i.d. N(0, 1/fan_in); hidden biases zero; output biases at the
+    log-odds of `prior` (the expected fraction of atoms in a support), so the
+    first scores already sit near the base rate.  float32.
+    """
+    rng = _rng(201, seed, 0)
+    w1 = rng.standard_normal((h, d)) / np.sqrt(d)
+    w2 = rng.standard_normal((h, h)) / np.sqrt(h)
+    w3 = rng.standard_normal((m, h)) / np.sqrt(h)
+    b3 = np.full(m, 0.0 if prior is None else np.log(prior / (1.0 - prior)))
+    return np.concatenate([w1.ravel(), np.zeros(h), w2.ravel(), np.zeros(h), w3.ravel(), b3]).astype(np.float32)
+
+
 WORKLOADS = {
     "gauss128x512": small_gaussian,
     "cs2048x16384": cs_gaussian,
