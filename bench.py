@@ -46,6 +46,87 @@ def load_traffic(path: str, kernel_src: str):
         return None
 
 
+def learned_comparison(args, pk, torch) -> dict:
+    """Plain FP32, plain BF16-screened and BF16-screened + learned warm start on the face-like
+    dictionary (1024 x 20000, 200 classes of rank-8 subspaces), lambda_i = 0.01 ||A^T b_i||_inf,
+    rho = 10.  The proposal network (2048 -> 2048 -> 2048 -> 20000) is trained on supports that
+    BMPL returned for signals of a distinct seed stream (not timed); the timed learned step is
+    proposal (embedding, network, top-256) + warm-started solve."""
+    import bmpl_inputs as bi
+    from paper_1302_5010_amd import learned as ln
+    dev = torch.device("cuda:0")
+    P = bi.face_like(p=args.learned_signals)
+    At = torch.from_numpy(P.At).to(dev)
+    Bt = torch.from_numpy(P.Bt).to(dev)
+    rec = {"workload": f"face20000 (p = {P.p})", "train_signals": args.train_signals, "epochs": args.epochs}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        outs = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs.append(fn())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        conv = int(ln.converged(outs[-1]).sum().item())
+        return outs[-1], {"value": conv / dt, "unit": "signals/s", "ms_per_step": dt * 1e3, "converged": conv,
+                          "iters_mean": float(outs[-1]["iters"].float().mean().item())}
+
+    plain32 = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="fp32")
+    plain32.autotune(P.p)
+    out32, rec["plain_fp32"] = timed(lambda: plain32.solve(Bt))
+    del plain32
+    bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
+    bf.autotune(P.p)
+    outbf, rec["plain_bf16"] = timed(lambda: bf.solve(Bt))
+
+    # training data: BMPL supports of signals from a distinct seed stream
+    t0 = time.perf_counter()
+    T = bi.face_like(p=args.train_signals, stream=2)
+    Bt_tr = torch.from_numpy(T.Bt).to(dev)
+    del T
+    t1 = time.perf_counter()
+    lab = ln.label_supports(bf, Bt_tr)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    d = h = 2048
+    net = pk.ProposalNet(At, torch.from_numpy(bi.projection(P.m, d, seed=0)).to(dev), h, max_batch=4096)
+    net.set_params(torch.from_numpy(bi.mlp_init(d, h, P.m, seed=0, prior=10.0 / P.m)).to(dev))
+    losses = ln.train_proposal(net, Bt_tr, lab["x_idx"], lab["supp_len"], epochs=args.epochs, batch=1024,
+                               lr=1e-3, pos_weight=20.0, record_every=50)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rec["training"] = {"generate_s": t1 - t0, "label_s": t2 - t1, "train_s": t3 - t2,
+                       "labelled_converged": int(ln.converged(lab).sum().item()),
+                       "loss_every_50_steps": [float(v.item()) for v in losses]}
+    del Bt_tr, lab
+    outl, rec["bf16_learned"] = timed(lambda: ln.solve_with_proposal(bf, net, Bt, 256))
+    xi, sl, pr = outbf["x_idx"].cpu().numpy(), outbf["supp_len"].cpu().numpy(), outl["proposal"].cpu().numpy()
+    rec["bf16_learned"]["recall_at_256"] = float(np.mean([np.isin(xi[i, :sl[i]], pr[i]).mean()
+                                                          for i in range(P.p) if sl[i] > 0]))
+    rec["bf16_learned"]["fallback_fraction"] = float(((outl["status"] & pk.BMPL_SIG_FALLBACK) > 0).float().mean())
+    rec["speedup_learned_vs_plain_fp32"] = rec["bf16_learned"]["value"] / rec["plain_fp32"]["value"]
+    rec["speedup_learned_vs_plain_bf16"] = rec["bf16_learned"]["value"] / rec["plain_bf16"]["value"]
+    # the learned run against the plain FP32 run on a sample of signals
+    rows = list(range(0, P.p, max(1, P.p // 32)))
+    X32, Xl = sparse_rows(out32, rows, P.m), sparse_rows(outl, rows, P.m)
+    rec["max_rel_x_learned_vs_fp32_sample"] = float(max(
+        np.linalg.norm(Xl[q] - X32[q]) / max(np.linalg.norm(X32[q]), 1e-300) for q in range(len(rows))))
+    del bf, net
+    return rec
+
+
+def sparse_rows(out: dict, rows, m: int) -> np.ndarray:
+    """Dense float64 copies of the solutions of the given signals."""
+    idx, val, ln = out["x_idx"][rows].cpu().numpy(), out["x_val"][rows].cpu().numpy(), out["supp_len"][rows].cpu().numpy()
+    X = np.zeros((len(rows), m))
+    for q in range(len(rows)):
+        X[q, idx[q, :ln[q]]] = val[q, :ln[q]]
+    return X
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +138,11 @@ def main():
     ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16"),
                     help="precision of the correlation product (bf16: certified screening + float32 re-score)")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary bf16-screened measurement")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal comparison on the face-like dictionary")
+    ap.add_argument("--learned-signals", type=int, default=16384, help="inference signals of the learned comparison")
+    ap.add_argument("--train-signals", type=int, default=200000, help="BMPL-labelled training signals")
+    ap.add_argument("--epochs", type=int, default=2)
     ap.add_argument("--host-loop", action="store_true",
                     help="drive the outer iterations from the host instead of replaying captured graph segments")
     args = ap.parse_args()
@@ -196,6 +282,9 @@ def main():
                                                                     "residual_ms", "other_ms", "wall_ms")},
         }
         del bf, bft
+
+    if not args.no_learned:
+        result["learned"] = learned_comparison(args, pk, torch)
 
     if not args.no_cpu and args.cpu_sample > 0:
         import oracle

@@ -75,6 +75,9 @@ typedef enum {
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
 #define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each,
                                        one launch and one read-back per segment (ignored with TIMING) */
+#define BMPL_FLAG_SINGLE_APPEND 8   /* grow the master problem's inverse Cholesky factor one atom at a
+                                       time instead of in blocks of up to 8 (same factor in exact
+                                       arithmetic; a diagnostic and comparison switch) */
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
  * precomputed Q of Section III, Eq. (12)) when it is at most this large. */
@@ -243,6 +246,128 @@ bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t);
 
 /* Zero the accumulated timing.  Errors: BMPL_E_INVALID for NULL. */
 bmpl_status bmpl_reset_timing(bmpl_ctx* c);
+
+/* ------------------------------------------------------------------------
+ * Learned support proposal.
+ *
+ * Not part of the paper.  Algorithm 1 keeps the previous iterate as the warm
+ * start of every master problem (step 5), and its natural stopping condition
+ * (Eq. (9)) certifies the final answer whatever the starting active set was;
+ * this network only proposes that starting set (bmpl_solve's warm_idx_dev).
+ * A wrong proposal costs iterations, never correctness: atoms proposed in
+ * error end with a zero coefficient, atoms it misses are added by the
+ * ordinary worst-case analysis, and the signal's status carries
+ * BMPL_SIG_FALLBACK when the first check after the proposal found violators.
+ *
+ * Model, for a signal b (column of B):
+ *   z  = (A P)^T b scaled to unit root-mean-square (P: a fixed m x d_in
+ *        matrix supplied by the caller, e.g. i.i.d. N(0, 1/d_in); the LASSO
+ *        support under the relative lambda rule does not depend on the scale
+ *        of b, so neither does the proposal)
+ *   h1 = gelu(W1 z + b1), h2 = gelu(W2 h1 + b2), s = W3 h2 + b3   (s: m scores)
+ *   gelu(u) = u * Phi(u), Phi the standard normal CDF (exact erf form).
+ * Training loss: binary cross-entropy with logits and positive-class weight
+ * w, summed over the m atoms and averaged over the batch:
+ *   l(s, y) = w y log(1 + e^-s) + (1 - y) log(1 + e^s),
+ * targets y_j = 1 for the atoms of a given support (e.g. the supports a
+ * bmpl_solve returned).  Optimiser: Adam with bias correction.
+ * Arithmetic: bfloat16 weights and activations in the matrix products
+ * (MFMA, float32 accumulation); float32 master weights, pre-activations,
+ * scores, gradients and Adam moments.
+ *
+ * Flat parameter vector (float32, row-major blocks in this order):
+ *   W1 [d_hidden][d_in], b1 [d_hidden], W2 [d_hidden][d_hidden], b2 [d_hidden],
+ *   W3 [m][d_hidden], b3 [m];  length bmpl_mlp_param_count(d_in, d_hidden, m).
+ * ---------------------------------------------------------------------- */
+typedef struct bmpl_mlp bmpl_mlp;
+
+typedef struct {
+    double lr;      /* step size */
+    double beta1;   /* first-moment decay (0.9 is usual) */
+    double beta2;   /* second-moment decay (0.999) */
+    double eps;     /* denominator guard (1e-8) */
+} bmpl_adam;
+
+/* Number of floats in the flat parameter vector. */
+int64_t bmpl_mlp_param_count(int32_t d_in, int32_t d_hidden, int32_t m);
+
+/*
+ * Create a proposal network for the dictionary A (column-major n x m,
+ * leading dimension lda >= n, the layout of bmpl_create) and the projection
+ * P_dev (row-major m x d_in float32: P[j*d_in + c]).  Computes (A P)^T once
+ * (float32 accumulation, stored as bfloat16); A and P may be freed after the
+ * call returns.  Parameters start at zero: set them with bmpl_mlp_set_params.
+ * max_batch bounds the rows of one bmpl_mlp_loss_grad call and the chunk of
+ * signals that bmpl_mlp_forward / bmpl_mlp_propose process at once (they
+ * accept any p).  Requires d_in and d_hidden to be positive multiples of 64,
+ * m <= 38912 (one row of scores fits the selection kernel's LDS), n, m,
+ * max_batch >= 1.  Errors: BMPL_E_INVALID, BMPL_E_NOMEM, BMPL_E_HIP.
+ */
+bmpl_status bmpl_mlp_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, const float* P_dev,
+                            int32_t d_in, int32_t d_hidden, int32_t max_batch, void* hip_stream,
+                            bmpl_mlp** out);
+
+/* Release everything the network owns.  NULL is accepted. */
+bmpl_status bmpl_mlp_destroy(bmpl_mlp* net);
+
+/*
+ * Copy a flat parameter vector (device, float32) into the network's float32
+ * master weights, refresh their bfloat16 copies and reset the Adam moments
+ * and step count.  bmpl_mlp_get_params copies the master weights out.
+ */
+bmpl_status bmpl_mlp_set_params(bmpl_mlp* net, const float* params_dev, void* hip_stream);
+bmpl_status bmpl_mlp_get_params(const bmpl_mlp* net, float* params_dev, void* hip_stream);
+
+/*
+ * The unit-RMS embeddings z of p signals (B column-major n x p, ldb >= n),
+ * rounded to bfloat16 as the network consumes them and returned widened to
+ * float32: Z_dev[i*ldz + c], ldz >= d_in.
+ */
+bmpl_status bmpl_mlp_embed(bmpl_mlp* net, const float* B_dev, int64_t ldb, int32_t p, float* Z_dev,
+                           int64_t ldz, void* hip_stream);
+
+/* Scores s of p signals: S_dev[i*lds + j], j < m, lds >= m (float32). */
+bmpl_status bmpl_mlp_forward(bmpl_mlp* net, const float* B_dev, int64_t ldb, int32_t p, float* S_dev,
+                             int64_t lds, void* hip_stream);
+
+/*
+ * Loss and gradient on one batch of p <= max_batch signals with target
+ * supports supp_dev[i*ld_supp + t], t < supp_len_dev[i] (atom indices;
+ * entries outside [0, m) are ignored, so bmpl_solve's x_idx / supp_len can
+ * be passed as they are).  *loss_dev (device double) receives the mean loss;
+ * grad_dev (device float32, bmpl_mlp_param_count floats, flat layout)
+ * receives the gradient, or NULL to keep it inside the network for
+ * bmpl_mlp_adam_step.  pos_weight > 0.
+ */
+bmpl_status bmpl_mlp_loss_grad(bmpl_mlp* net, const float* B_dev, int64_t ldb, int32_t p,
+                               const int32_t* supp_dev, int32_t ld_supp, const int32_t* supp_len_dev,
+                               double pos_weight, float* grad_dev, double* loss_dev, void* hip_stream);
+
+/*
+ * One Adam step on the master weights with the gradient grad_dev (flat
+ * layout), or with the gradient of the last bmpl_mlp_loss_grad when NULL;
+ * refreshes the bfloat16 copies.  The step count t starts at 1 after
+ * bmpl_mlp_set_params.
+ */
+bmpl_status bmpl_mlp_adam_step(bmpl_mlp* net, const float* grad_dev, const bmpl_adam* hp, void* hip_stream);
+
+/*
+ * Proposal: for each of p signals the k (1..256) atoms with the largest
+ * scores, ties to the lower index, listed in ascending atom order:
+ * idx_dev[i*ld_idx + q], q < k (ld_idx >= k).  This is the warm_idx_dev /
+ * warm_k input of bmpl_solve.
+ */
+bmpl_status bmpl_mlp_propose(bmpl_mlp* net, const float* B_dev, int64_t ldb, int32_t p, int32_t k,
+                             int32_t* idx_dev, int32_t ld_idx, void* hip_stream);
+
+/*
+ * The selection step of bmpl_mlp_propose on its own, for any score matrix:
+ * per row of S_dev[r*lds + j], j < L, the k (1..256) largest entries' column
+ * indices in ascending order, ties to the lower index, NaN ranked lowest,
+ * -1 padding when L < k.  L <= 38912.
+ */
+bmpl_status bmpl_topk(const float* S_dev, int64_t lds, int32_t rows, int32_t L, int32_t k, int32_t* idx_dev,
+                      int32_t ld_idx, void* hip_stream);
 
 #ifdef __cplusplus
 }

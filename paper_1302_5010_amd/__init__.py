@@ -18,6 +18,9 @@ from ._binding import (  # noqa: F401
     BMPL_SIG_INEXACT,
     BMPL_SIG_NONFINITE,
     BmplError,
+    ProposalNet,
     Solver,
     library_path,
+    mlp_param_count,
+    topk,
 )

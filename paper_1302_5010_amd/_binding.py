@@ -47,6 +47,7 @@ class Timing(ctypes.Structure):
 BMPL_FLAG_TIMING = 1
 BMPL_FLAG_NO_GRAM_TABLE = 2
 BMPL_FLAG_GRAPH = 4
+BMPL_FLAG_SINGLE_APPEND = 8
 
 
 class _Result(ctypes.Structure):
@@ -55,6 +56,11 @@ class _Result(ctypes.Structure):
                 ("kkt_dev", ctypes.c_void_p), ("lambda_dev", ctypes.c_void_p),
                 ("objective_dev", ctypes.c_void_p), ("sig_status_dev", ctypes.c_void_p),
                 ("ld_x", ctypes.c_int32)]
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -80,9 +86,23 @@ def _load():
     lib.bmpl_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
     lib.bmpl_set_tuning.argtypes = [vp, ctypes.POINTER(i32)]
     lib.bmpl_reset_timing.argtypes = [vp]
+    lib.bmpl_mlp_param_count.argtypes = [i32, i32, i32]
+    lib.bmpl_mlp_param_count.restype = i64
+    lib.bmpl_mlp_create.argtypes = [vp, i64, i32, i32, vp, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    lib.bmpl_mlp_destroy.argtypes = [vp]
+    lib.bmpl_mlp_set_params.argtypes = [vp, vp, vp]
+    lib.bmpl_mlp_get_params.argtypes = [vp, vp, vp]
+    lib.bmpl_mlp_embed.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    lib.bmpl_mlp_forward.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    lib.bmpl_mlp_loss_grad.argtypes = [vp, vp, i64, i32, vp, i32, vp, dbl, vp, vp, vp]
+    lib.bmpl_mlp_adam_step.argtypes = [vp, vp, ctypes.POINTER(AdamParams), vp]
+    lib.bmpl_mlp_propose.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp]
+    lib.bmpl_topk.argtypes = [vp, i64, i32, i32, i32, vp, i32, vp]
     for f in ("bmpl_options_default", "bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_correlate",
               "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table", "bmpl_autotune",
-              "bmpl_set_tuning"):
+              "bmpl_set_tuning", "bmpl_mlp_create", "bmpl_mlp_destroy", "bmpl_mlp_set_params",
+              "bmpl_mlp_get_params", "bmpl_mlp_embed", "bmpl_mlp_forward", "bmpl_mlp_loss_grad",
+              "bmpl_mlp_adam_step", "bmpl_mlp_propose", "bmpl_topk"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -130,7 +150,7 @@ class Solver:
 
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
-                 gram_table: bool = True, graph: bool = False, stream=None):
+                 gram_table: bool = True, graph: bool = False, block_append: bool = True, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
@@ -139,7 +159,7 @@ class Solver:
         o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
-                   | (BMPL_FLAG_GRAPH if graph else 0))
+                   | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND))
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
         h = ctypes.c_void_p()
@@ -263,3 +283,111 @@ class Solver:
                                     sel.data_ptr(), nsel.data_ptr(), vmax.data_ptr(), _stream_ptr(stream)),
                    "bmpl_select")
         return sel, nsel, vmax
+
+
+def topk(S: torch.Tensor, k: int, L: int | None = None, stream=None) -> torch.Tensor:
+    """Per row of ``S`` ((rows, lds) float32), the k largest of the first L columns' indices,
+    ascending, ties to the lower index (bmpl_topk)."""
+    S = _dev(S, torch.float32, "S")
+    rows, lds = S.shape
+    L = lds if L is None else L
+    out = torch.empty((rows, k), dtype=torch.int32, device=S.device)
+    with torch.cuda.device(S.device):
+        _check(_lib.bmpl_topk(S.data_ptr(), lds, rows, L, k, out.data_ptr(), k, _stream_ptr(stream)), "bmpl_topk")
+    return out
+
+
+def mlp_param_count(d_in: int, d_hidden: int, m: int) -> int:
+    return int(_lib.bmpl_mlp_param_count(d_in, d_hidden, m))
+
+
+class ProposalNet:
+    """The learned support proposal (bmpl_mlp_*): z = unit-RMS (A P)^T b, two GELU layers of
+    width ``d_hidden``, m atom scores.  ``At``: (m, n) float32 dictionary, ``P``: (m, d_in)
+    float32 projection, both CUDA tensors."""
+
+    def __init__(self, At: torch.Tensor, P: torch.Tensor, d_hidden: int, max_batch: int, stream=None):
+        At = _dev(At, torch.float32, "At")
+        P = _dev(P, torch.float32, "P")
+        self.m, self.n = At.shape
+        if P.shape[0] != self.m:
+            raise BmplError("P must have one row per atom")
+        self.d_in, self.d_hidden, self.max_batch = P.shape[1], d_hidden, max_batch
+        self.device = At.device
+        self.count = mlp_param_count(self.d_in, d_hidden, self.m)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_create(At.data_ptr(), self.n, self.n, self.m, P.data_ptr(), self.d_in, d_hidden,
+                                        max_batch, _stream_ptr(stream), ctypes.byref(h)), "bmpl_mlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.bmpl_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: torch.Tensor, stream=None):
+        params = _dev(params, torch.float32, "params")
+        if params.numel() != self.count:
+            raise BmplError(f"params must hold {self.count} floats")
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_set_params(self._h, params.data_ptr(), _stream_ptr(stream)), "bmpl_mlp_set_params")
+
+    def get_params(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_get_params(self._h, out.data_ptr(), _stream_ptr(stream)), "bmpl_mlp_get_params")
+        return out
+
+    def embed(self, Bt: torch.Tensor, stream=None) -> torch.Tensor:
+        Bt = _dev(Bt, torch.float32, "Bt")
+        Z = torch.empty((Bt.shape[0], self.d_in), dtype=torch.float32, device=Bt.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_embed(self._h, Bt.data_ptr(), Bt.shape[1], Bt.shape[0], Z.data_ptr(), self.d_in,
+                                       _stream_ptr(stream)), "bmpl_mlp_embed")
+        return Z
+
+    def forward(self, Bt: torch.Tensor, stream=None) -> torch.Tensor:
+        Bt = _dev(Bt, torch.float32, "Bt")
+        S = torch.empty((Bt.shape[0], self.m), dtype=torch.float32, device=Bt.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_forward(self._h, Bt.data_ptr(), Bt.shape[1], Bt.shape[0], S.data_ptr(), self.m,
+                                         _stream_ptr(stream)), "bmpl_mlp_forward")
+        return S
+
+    def loss_grad(self, Bt: torch.Tensor, supp: torch.Tensor, supp_len: torch.Tensor, pos_weight: float,
+                  want_grad: bool = True, stream=None):
+        """Mean loss (device float64 scalar) and, if ``want_grad``, the flat gradient."""
+        Bt = _dev(Bt, torch.float32, "Bt")
+        supp = _dev(supp, torch.int32, "supp")
+        supp_len = _dev(supp_len, torch.int32, "supp_len")
+        loss = torch.zeros(1, dtype=torch.float64, device=Bt.device)
+        g = torch.empty(self.count, dtype=torch.float32, device=Bt.device) if want_grad else None
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_loss_grad(self._h, Bt.data_ptr(), Bt.shape[1], Bt.shape[0], supp.data_ptr(),
+                                           supp.shape[1], supp_len.data_ptr(), float(pos_weight),
+                                           g.data_ptr() if g is not None else None, loss.data_ptr(),
+                                           _stream_ptr(stream)), "bmpl_mlp_loss_grad")
+        return loss, g
+
+    def adam_step(self, lr: float, grad: torch.Tensor | None = None, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None):
+        hp = AdamParams(lr, beta1, beta2, eps)
+        gp = _dev(grad, torch.float32, "grad").data_ptr() if grad is not None else None
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_adam_step(self._h, gp, ctypes.byref(hp), _stream_ptr(stream)), "bmpl_mlp_adam_step")
+
+    def propose(self, Bt: torch.Tensor, k: int, stream=None) -> torch.Tensor:
+        """(p, k) int32: the k highest-scoring atoms per signal, ascending (bmpl_solve's warm start)."""
+        Bt = _dev(Bt, torch.float32, "Bt")
+        out = torch.empty((Bt.shape[0], k), dtype=torch.int32, device=Bt.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.bmpl_mlp_propose(self._h, Bt.data_ptr(), Bt.shape[1], Bt.shape[0], k, out.data_ptr(), k,
+                                         _stream_ptr(stream)), "bmpl_mlp_propose")
+        return out

@@ -19,50 +19,12 @@
 
 #include "../../include/bmpl.h"
 #include "bmpl_internal.h"
+#include "host_util.h"
 #include "pursuit.h"
 
 using namespace bmpl;
 
 namespace {
-
-thread_local std::string g_err;
-
-bmpl_status fail(bmpl_status st, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return st;
-}
-
-#define HIPC(call)                                                                      \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(e_ == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP,          \
-                        "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
-                        __LINE__);                                                      \
-    } while (0)
-
-template <class T>
-hipError_t dalloc(T** p, size_t count)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-}
-
-template <class T>
-void dfree(T*& p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
 
@@ -79,6 +41,7 @@ struct bmpl_ctx {
     int* ncand = nullptr;         // [p_cap]
     uint16_t* diag16 = nullptr;   // bfloat16 staging of bmpl_correlate
     size_t lds_dyn_max = 0;       // dynamic LDS a solve workgroup may use (bytes)
+    bool block_append = true;     // inverse-factor appends in blocks (BMPL_FLAG_SINGLE_APPEND clears it)
     bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
     double lambda = 0.0;
     bmpl_options opt{};
@@ -420,6 +383,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
             c->gamma_amax = gamma * amax;
         }
     }
+    c->block_append = !(opt.flags & BMPL_FLAG_SINGLE_APPEND);
     // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
     const double q_bytes = 8.0 * (double)m * (double)m;
     if (e == hipSuccess && !(opt.flags & BMPL_FLAG_NO_GRAM_TABLE) && q_bytes <= BMPL_GRAM_TABLE_MAX_BYTES) {
@@ -544,7 +508,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const bool graph = (c->opt.flags & BMPL_FLAG_GRAPH) != 0 && !timing_on(c);
 
     const int first_add = warm ? std::max(warm_k, rho) : rho;
-    int K0 = std::min(max_active, std::max(64, round_up(2 * first_add + (graph ? GRAPH_DEPTH * rho : 0), 32)));
+    // slot capacity for the first iterations: a proposal's atoms plus a few iterations of growth
+    const int grow0 = (graph ? GRAPH_DEPTH * rho : 0) + (warm ? 2 * rho : first_add);
+    int K0 = std::min(max_active, std::max(64, round_up(first_add + grow0, 32)));
     K0 = std::max(K0, std::min(max_active, c->K_cap));
     bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), K0, std::max(rho, warm ? warm_k : 0));
     if (st != BMPL_OK) return st;
@@ -649,7 +615,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         }
         if (first && warm) {
             WarmArgs wa{w, c->act[cur], c->n_act_dev + cur, warm_idx_dev, warm_k, max_active};
-            hipLaunchKernelGGL(warm_select_kernel, dim3(n_grid), dim3(64), 0, q, wa);
+            hipLaunchKernelGGL(warm_select_kernel, dim3(n_grid), dim3(256), 0, q, wa);
             HIPC(hipGetLastError());
         }
         StatusArgs sb = sa;
@@ -674,12 +640,14 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.Q = c->Q; so.ldq = c->m;
         so.max_steps = 16 * w.K + 256;
         so.phase = tm ? c->phase_dev : nullptr;
-        const size_t vec_bytes = (size_t)round_up(w.K * 58, 16);
+        const size_t vec_bytes = vec_area_bytes(w.K);
         so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
         so.kl = std::min(kl, w.K);
         const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
         so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes <= c->lds_dyn_max) ? 1 : 0;
-        const size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
+        size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
+        so.zs_lds = (c->block_append && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;
+        if (so.zs_lds) lds += block_scratch_bytes(w.K);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
         hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
         HIPC(hipGetLastError());

@@ -1,0 +1,165 @@
+// Shared MFMA main loop for the contractions C[r][c] = sum_k X[r][k] W[c][k]
+// with both operands K-contiguous (rows of X and of W are k-vectors).
+//
+// Tiling (gfx950, wave64): a workgroup computes a BM x BN tile of C; each wave
+// a WM x WN sub-tile as (WM/32) x (WN/32) blocks of 32x32 MFMA accumulators.
+// K is consumed 128 bytes at a time (32 float32 or 64 bfloat16 values) through
+// two LDS buffers, one barrier per stage; the next K-slice is prefetched into
+// registers while the current one feeds the matrix cores.  Within each 16-byte
+// chunk of k, lane half h supplies the chunk's half h (float32: k = 8b + 4h + t
+// at step t of four v_mfma_f32_32x32x2f32; bfloat16: 8 consecutive k of one
+// v_mfma_f32_32x32x16_bf16), so every LDS fragment read is one 16-byte ds_read
+// (the summation order over k is immaterial to the contraction).
+//
+// The caller owns the row mapping: it passes, per staging load, the element
+// offset of the row start (plus this thread's 16-byte column) in X and in W.
+// Every load is unconditional, so rows past the end must point at readable
+// memory (a zero row or a clamped row whose results are discarded).
+//
+// Accumulator layout of a 32x32 block (both instructions): lane l, register r
+// holds row 8(r/4) + 4(l/32) + r%4 and column l%32 of the block, the row
+// coming from X and the column from W.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmpl {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TILE_ROW_BYTES = 128;                 // k bytes per LDS stage and row
+constexpr int TILE_LDS_ROW = TILE_ROW_BYTES + 16;   // 16-byte aligned, staggers banks
+
+template <int BM, int BN, int WM, int WN>
+struct TileShape {
+    static constexpr int WAVES = (BM / WM) * (BN / WN);
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int TI = WM / 32;                 // MFMA blocks per wave along X rows
+    static constexpr int TJ = WN / 32;                 // along W rows
+    static constexpr int LX = BM * 8 / THREADS;        // 16-byte loads per thread, X tile
+    static constexpr int LW = BN * 8 / THREADS;        // W tile
+    static constexpr int RSTEP = THREADS / 8;          // row step between a thread's loads
+    static constexpr int WAVES_M = BM / WM;
+    static_assert(LX * THREADS == BM * 8 && LW * THREADS == BN * 8, "tile/thread mismatch");
+};
+
+template <int BM, int BN>
+struct TileLds {
+    char x[2][BM * TILE_LDS_ROW];
+    char w[2][BN * TILE_LDS_ROW];
+};
+
+// Thread-to-load mapping: 16-byte column c4 = tid % 8 of the k slice, rows r0 + RSTEP q.
+__device__ __forceinline__ int tile_c4(int tid) { return tid & 7; }
+__device__ __forceinline__ int tile_r0(int tid) { return tid >> 3; }
+
+// Run the K loop of one tile.  ws / wa: the wave's row offsets within the tile (X / W rows).
+template <class E, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const int64_t (&oX)[TileShape<BM, BN, WM, WN>::LX],
+                                               const E* __restrict__ W, const int64_t (&oW)[TileShape<BM, BN, WM, WN>::LW],
+                                               int kpad, TileLds<BM, BN>& lds, int ws, int wa,
+                                               floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    constexpr int BK = TILE_ROW_BYTES / (int)sizeof(E);   // k per stage
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int c4 = tile_c4(tid);
+    const int r0 = tile_r0(tid);
+    const int l32 = lane & 31;
+    const int h = lane >> 5;
+
+#pragma unroll
+    for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < S::TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    float4 gX[S::LX], gW[S::LW];
+#define TILE_LOAD_SLICE(k0)                                                                                 \
+    do {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < S::LX; ++q)                                                  \
+            gX[q] = *reinterpret_cast<const float4*>(X + oX[q] + (k0));                                     \
+        _Pragma("unroll") for (int q = 0; q < S::LW; ++q)                                                  \
+            gW[q] = *reinterpret_cast<const float4*>(W + oW[q] + (k0));                                     \
+    } while (0)
+#define TILE_STORE_SLICE(buf)                                                                               \
+    do {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < S::LX; ++q)                                                  \
+            *reinterpret_cast<float4*>(&lds.x[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gX[q];  \
+        _Pragma("unroll") for (int q = 0; q < S::LW; ++q)                                                  \
+            *reinterpret_cast<float4*>(&lds.w[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gW[q];  \
+    } while (0)
+
+    TILE_LOAD_SLICE(0);
+    TILE_STORE_SLICE(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kpad; k0 += BK) {
+        // prefetch the next slice (the last iteration re-reads the final slice; its copy is never used)
+        const int kn = k0 + BK < kpad ? k0 + BK : k0;
+        TILE_LOAD_SLICE(kn);
+        asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
+        const char* cX = lds.x[cur];
+        const char* cW = lds.w[cur];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {       // 4 x 16-byte chunks per lane half per stage
+            float4 fx[S::TI], fw[S::TJ];
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+                fx[i] = *reinterpret_cast<const float4*>(&cX[(ws + 32 * i + l32) * TILE_LDS_ROW + kb * 32 + 16 * h]);
+#pragma unroll
+            for (int j = 0; j < S::TJ; ++j)
+                fw[j] = *reinterpret_cast<const float4*>(&cW[(wa + 32 * j + l32) * TILE_LDS_ROW + kb * 32 + 16 * h]);
+            if constexpr (sizeof(E) == 2) {
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fx[i]), __builtin_bit_cast(bf16x8, fw[j]), acc[i][j], 0, 0, 0);
+            } else {
+                // k step outermost so consecutive MFMAs write different accumulators
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].x, fw[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].y, fw[j].y, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].z, fw[j].z, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].w, fw[j].w, acc[i][j], 0, 0, 0);
+            }
+        }
+        asm volatile("" ::: "memory");       // and consume it only after
+        TILE_STORE_SLICE(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+#undef TILE_LOAD_SLICE
+#undef TILE_STORE_SLICE
+}
+
+// XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
+// contiguous run of tile indices (neighbouring tiles share operand rows in that XCD's L2).
+__device__ __forceinline__ int xcd_tile_index(int wid, int nwg)
+{
+    const int per = nwg / 8, rem = nwg % 8, xcd = wid % 8, loc = wid / 8;
+    return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+}
+
+}  // namespace bmpl

@@ -31,6 +31,12 @@ struct WarmArgs {
     int max_active;
 };
 
+// Atoms per block append of the inverse factor, and the LDS layout of the solve kernel's per-slot
+// vectors (x, c, w, z, x_new, g as float64; support order and atoms as int; theta and exclusion bytes).
+constexpr int SOLVE_JB = 8;
+__host__ __device__ inline size_t vec_area_bytes(int K) { return ((size_t)K * 58 + 15) / 16 * 16; }
+__host__ __device__ inline size_t block_scratch_bytes(int K) { return (size_t)K * SOLVE_JB * 8; }
+
 struct SolveArgs {
     Workspace w;
     const float* At; int64_t lda;
@@ -41,6 +47,7 @@ struct SolveArgs {
     int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
+    int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
     uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,
                                     // then counts of factor appends, drops and solves; or null
 };

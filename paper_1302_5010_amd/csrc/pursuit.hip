@@ -36,6 +36,8 @@ namespace {
 constexpr int NT = 256;
 constexpr int NB = 16;      // new atoms per Gram pass
 constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
+constexpr int JADD = 16;    // violators added to S per active-set step (the largest ones)
+constexpr int JB = SOLVE_JB;   // atoms per block factor append
 
 __device__ inline double block_sum(double v, double* red)
 {
@@ -176,6 +178,169 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     if (cnt && tid == 0)   // cnt[-2]: ticks spent in appends (phase slot 4)
         atomicAdd(reinterpret_cast<unsigned long long*>(cnt - 2), (unsigned long long)(wall_clock64() - t_in));
     return true;
+}
+
+// Append the slots list[0..J) (J <= JB), in list order, at support positions nS, nS + 1, ...
+// as one block.  With s0 = nS, W = G(S, list) and Z = Rinv W (s0 x J), the Schur complement
+// C = G(list, list) - Z^T Z is factored in list order with the single-append pivot rule (an atom
+// whose pivot C_ee - |l_e|^2 falls to 1e-11 g_ee or below is excluded, as chol_append would), and
+// the accepted atoms A get the inverse-factor rows [-L22^{-1} Z_A^T Rinv, L22^{-1}].  The same
+// factor as J single appends in exact arithmetic, for two passes over Rinv instead of 2J.
+// Signs come from vg (sign of the gradient) or, with vg == nullptr, from the slots' current theta.
+// zs: LDS scratch of (s0 + 1) * JB doubles.
+__device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const double* vg, double* zs,
+                                  uint64_t* cnt)
+{
+    __shared__ double s_C[JB * JB];     // Schur complement (lower), then L22^{-1}
+    __shared__ double s_L[JB * JB];     // L22, rows in accepted order
+    __shared__ int s_acc[JB];
+    __shared__ int s_na;
+    const int s0 = nS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t t_in = cnt ? wall_clock64() : 0;
+    if (cnt && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), (unsigned long long)J);
+
+    // 1. W = G(S, list): row k = support position, JB columns, zero past J
+    for (int t = tid; t < s0 * JB; t += NT) {
+        const int k = t / JB, e = t - k * JB;
+        zs[t] = e < J ? v.G[(int64_t)list[e] * v.K + v.so[k]] : 0.0;
+    }
+    __syncthreads();
+    // 2. Z = Rinv W in place.  Rows from the bottom, one per wave per round; row i needs the W rows
+    //    at or below it, so a round's rows are written only after every wave has read them.
+    for (int top = s0 - 1; top >= 0; top -= NT / 64) {
+        const int i = top - wave;
+        double acc[JB];
+#pragma unroll
+        for (int e = 0; e < JB; ++e) acc[e] = 0.0;
+        if (i >= 0) {
+            const double* Ri = v.R + tri(i);
+            for (int k = lane; k <= i; k += 64) {
+                const double r = Ri[k];
+                const double* wk = zs + k * JB;
+#pragma unroll
+                for (int e = 0; e < JB; ++e) acc[e] += r * wk[e];
+            }
+#pragma unroll
+            for (int e = 0; e < JB; ++e)
+                for (int o = 32; o > 0; o >>= 1) acc[e] += __shfl_xor(acc[e], o);
+        }
+        __syncthreads();
+        if (i >= 0 && lane < JB) {
+            double val = 0.0;
+#pragma unroll
+            for (int e = 0; e < JB; ++e) val = lane == e ? acc[e] : val;
+            zs[i * JB + lane] = val;
+        }
+    }
+    __syncthreads();
+    // 3. C = G(list, list) - Z^T Z, lower triangle
+    for (int t = tid; t < J * J; t += NT) {
+        const int e = t / J, f = t - e * J;
+        if (f > e) continue;
+        double sum = 0.0;
+        for (int i = 0; i < s0; ++i) sum += zs[i * JB + e] * zs[i * JB + f];
+        s_C[e * JB + f] = v.G[(int64_t)list[e] * v.K + list[f]] - sum;
+    }
+    __syncthreads();
+    // 4. Cholesky of C in list order with exclusion, then L22^{-1} into s_C (one thread, J <= JB)
+    if (tid == 0) {
+        int na = 0;
+        for (int e = 0; e < J; ++e) {
+            double dd = s_C[e * JB + e];
+            for (int b = 0; b < na; ++b) {
+                double x = s_C[e * JB + s_acc[b]];          // C(e, A_b), A_b < e
+                for (int c = 0; c < b; ++c) x -= s_L[na * JB + c] * s_L[b * JB + c];
+                x /= s_L[b * JB + b];
+                s_L[na * JB + b] = x;
+                dd -= x * x;
+            }
+            const int u = list[e];
+            const double gjj = v.G[(int64_t)u * v.K + u];
+            if (dd > 1e-11 * gjj) {
+                s_L[na * JB + na] = sqrt(dd);
+                s_acc[na++] = e;
+            } else {
+                v.ex[u] = 1; v.th[u] = 0; v.x[u] = 0.0;
+            }
+        }
+        for (int a2 = 0; a2 < na; ++a2) {
+            const double dinv = 1.0 / s_L[a2 * JB + a2];
+            for (int b = 0; b < a2; ++b) {
+                double x = 0.0;
+                for (int c = b; c < a2; ++c) x += s_L[a2 * JB + c] * s_C[c * JB + b];
+                s_C[a2 * JB + b] = -x * dinv;
+            }
+            s_C[a2 * JB + a2] = dinv;
+        }
+        s_na = na;
+    }
+    __syncthreads();
+    const int na = s_na;
+    if (na < J) {   // keep only the accepted columns of Z, in accepted order
+        for (int i = tid; i < s0; i += NT) {
+            double* zi = zs + i * JB;
+            for (int b = 0; b < na; ++b) zi[b] = zi[s_acc[b]];
+        }
+        __syncthreads();
+    }
+    // 5. New rows: R(s0 + a, k) = -sum_{b <= a} L22^{-1}(a, b) M(b, k), M(b, k) = sum_{i >= k} Z(i, b) R(i, k).
+    //    Threads own columns k; a wave's lanes walk the rows in lockstep so reads of one row coalesce.
+    for (int kb = 0; kb < s0; kb += NT) {
+        const int k = kb + tid;
+        double acc[JB];
+#pragma unroll
+        for (int b = 0; b < JB; ++b) acc[b] = 0.0;
+        for (int i = kb + wave * 64; i < s0; ++i) {
+            if (i >= k) {
+                const double r = v.R[tri(i) + k];
+                const double* zi = zs + i * JB;
+#pragma unroll
+                for (int b = 0; b < JB; ++b) acc[b] += r * zi[b];
+            }
+        }
+        if (k < s0) {
+#pragma unroll
+            for (int a2 = 0; a2 < JB; ++a2) {
+                if (a2 >= na) break;
+                double val = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a2; ++b) val += s_C[a2 * JB + b] * acc[b];
+                v.R[tri(s0 + a2) + k] = -val;
+            }
+        }
+    }
+    for (int t = tid; t < na * JB; t += NT) {
+        const int a2 = t / JB, b = t - a2 * JB;
+        if (b <= a2) v.R[tri(s0 + a2) + s0 + b] = s_C[a2 * JB + b];
+    }
+    if (tid < na) {
+        const int u = list[s_acc[tid]];
+        v.so[s0 + tid] = u;
+        v.th[u] = vg ? (vg[u] > 0.0 ? 1 : -1) : v.th[u];
+    }
+    nS = s0 + na;
+    __syncthreads();
+    if (cnt && tid == 0)   // cnt[-2]: ticks spent in appends (phase slot 4)
+        atomicAdd(reinterpret_cast<unsigned long long*>(cnt - 2), (unsigned long long)(wall_clock64() - t_in));
+}
+
+// Append the slots list[0..nv) in order, in blocks of JB, stopping at nmax support positions
+// (the remaining slots are excluded).
+__device__ void append_list(Sig& v, int& nS, const int* list, int nv, const double* vg, int nmax, double* zs,
+                            uint64_t* cnt)
+{
+    for (int e = 0; e < nv;) {
+        if (nS >= nmax) {
+            for (int t = threadIdx.x; t < nv - e; t += NT) v.ex[list[e + t]] = 1;
+            __syncthreads();
+            return;
+        }
+        int J = nv - e < JB ? nv - e : JB;
+        J = J < nmax - nS ? J : nmax - nS;
+        chol_append_block(v, nS, list + e, J, vg, zs, cnt);
+        e += J;
+    }
 }
 
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
@@ -397,28 +562,33 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
 {
-    __shared__ int s_sel[256];
+    __shared__ int s_w[256];
+    __shared__ int s_cnt[4];
     const int n_act = *a.n_act_dev;
     const int row = blockIdx.x;
     if (row >= n_act) return;
     const int sig = a.act[row];
     const Workspace& w = a.w;
-    if (threadIdx.x == 0) {
-        int cnt = 0;
-        int cap = a.max_active < w.selcap ? a.max_active : w.selcap;
-        cap = cap < 256 ? cap : 256;
-        for (int q = 0; q < a.warm_k && cnt < cap; ++q) {
-            const int j = a.warm[(int64_t)sig * a.warm_k + q];
-            if (j < 0 || j >= w.m) continue;
-            bool dup = false;
-            for (int t = 0; t < cnt; ++t) dup |= s_sel[t] == j;
-            if (!dup) s_sel[cnt++] = j;
-        }
-        // an empty proposal keeps this pass's own selection
-        if (cnt > 0) {
-            for (int t = 0; t < cnt; ++t) w.sel[(int64_t)sig * w.selcap + t] = s_sel[t];
-            w.nsel[sig] = cnt;
-        }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int cap = a.max_active < w.selcap ? a.max_active : w.selcap;
+    cap = cap < 256 ? cap : 256;
+    // proposal entry tid: valid atom, first occurrence in the list
+    const int j = tid < a.warm_k ? a.warm[(int64_t)sig * a.warm_k + tid] : -1;
+    s_w[tid] = j;
+    __syncthreads();
+    bool keep = j >= 0 && j < w.m;
+    for (int t = 0; t < tid && keep; ++t) keep = s_w[t] != j;
+    const unsigned long long bal = __ballot(keep);
+    if (lane == 0) s_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0;
+    for (int w2 = 0; w2 < wave; ++w2) before += s_cnt[w2];
+    const int total = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    const int pos = before + __popcll(bal & ((1ull << lane) - 1ull));
+    // an empty proposal keeps this pass's own selection
+    if (total > 0) {
+        if (keep && pos < cap) w.sel[(int64_t)sig * w.selcap + pos] = j;
+        if (tid == 0) w.nsel[sig] = total < cap ? total : cap;
     }
 }
 
@@ -487,6 +657,8 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         vw = d; vz = d + K; vx = d + 2 * K; vg = d + 3 * K;
         vatom = reinterpret_cast<int*>(d + 4 * K);
     }
+    // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
+    double* zs = a.zs_lds ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0)) : nullptr;
 
     // 1. Load the state, register the new slots.
     if (a.vec_lds) {
@@ -580,17 +752,47 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             if (lane == 0) s_cnt = base < NT ? base : NT;
         }
         __syncthreads();
-        const int nv = s_cnt;
+        int nv = s_cnt;
         if (nv == 0) break;
-        for (int e = 0; e < nv; ++e) {
-            const int u = s_list[e];
-            const signed char th = vg[u] > 0.0 ? 1 : -1;
-            if (nS >= w.n) {
-                if (tid == 0) s.ex[u] = 1;
-                __syncthreads();
-                continue;
+        if (nv > JADD) {
+            // keep the JADD largest violations (ties to the lower slot), in slot order: adding a few at a
+            // time keeps sign changes, and with them drops, rare when many atoms of I violate at once
+            int u = -1, rank = 0;
+            double gu = 0.0;
+            if (tid < nv) {
+                u = s_list[tid];
+                gu = fabs(vg[u]);
+                for (int e = 0; e < nv; ++e) {
+                    const int o = s_list[e];
+                    const double go = fabs(vg[o]);
+                    rank += (go > gu) || (go == gu && o < u);
+                }
             }
-            chol_append(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
+            __syncthreads();
+            const bool keep = tid < nv && rank < JADD;
+            // compact the kept slots in slot order (s_list is in slot order)
+            const unsigned long long bal = __ballot(keep);
+            if (lane == 0) redi[wave] = __popcll(bal);
+            __syncthreads();
+            int before = 0;
+            for (int w2 = 0; w2 < wave; ++w2) before += redi[w2];
+            if (keep) s_list[before + __popcll(bal & ((1ull << lane) - 1ull))] = u;
+            __syncthreads();
+            nv = JADD;
+        }
+        if (zs) {
+            append_list(s, nS, s_list, nv, vg, w.n, zs, a.phase ? a.phase + 6 : nullptr);
+        } else {
+            for (int e = 0; e < nv; ++e) {
+                const int u = s_list[e];
+                const signed char th = vg[u] > 0.0 ? 1 : -1;
+                if (nS >= w.n) {
+                    if (tid == 0) s.ex[u] = 1;
+                    __syncthreads();
+                    continue;
+                }
+                chol_append(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
+            }
         }
         // move toward the sign-fixed minimiser, dropping at zero crossings
         for (;;) {
@@ -627,11 +829,15 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             }
             __syncthreads();
             nS = q;
-            for (int k = q + 1; k < ns_old; ++k) {
-                const int u = vatom[k];
-                if (!chol_append(s, nS, u, s.th[u], vw, vz, red, a.phase ? a.phase + 6 : nullptr)) {
-                    if (tid == 0) s.x[u] = 0.0;
-                    __syncthreads();
+            if (zs) {
+                append_list(s, nS, vatom + q + 1, ns_old - q - 1, nullptr, w.n, zs, a.phase ? a.phase + 6 : nullptr);
+            } else {
+                for (int k = q + 1; k < ns_old; ++k) {
+                    const int u = vatom[k];
+                    if (!chol_append(s, nS, u, s.th[u], vw, vz, red, a.phase ? a.phase + 6 : nullptr)) {
+                        if (tid == 0) s.x[u] = 0.0;
+                        __syncthreads();
+                    }
                 }
             }
         }

@@ -72,3 +72,33 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         b._load()
+
+
+def test_proposal_argument_errors_without_gpu(lib):
+    lib.bmpl_last_error.restype = ctypes.c_char_p
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.bmpl_mlp_param_count.restype = i64
+    lib.bmpl_mlp_param_count.argtypes = [i32, i32, i32]
+    assert lib.bmpl_mlp_param_count(2048, 2048, 20000) == 2048 * 2048 * 2 + 2048 * 2 + 20000 * 2048 + 20000
+    assert lib.bmpl_mlp_param_count(0, 64, 10) == 0
+    lib.bmpl_mlp_create.argtypes = [vp, i64, i32, i32, vp, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    h = vp()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bmpl_mlp_create(None, 4, 4, 4, fake, 64, 64, 8, None, ctypes.byref(h)) == -1
+    assert b"NULL A or P" in lib.bmpl_last_error()
+    assert lib.bmpl_mlp_create(fake, 4, 4, 4, fake, 100, 64, 8, None, ctypes.byref(h)) == -1   # d_in % 64
+    assert lib.bmpl_mlp_create(fake, 4, 4, 4, fake, 64, 0, 8, None, ctypes.byref(h)) == -1    # d_hidden
+    assert lib.bmpl_mlp_create(fake, 4, 4, 40000, fake, 64, 64, 8, None, ctypes.byref(h)) == -1   # m too wide
+    assert b"exceeds" in lib.bmpl_last_error()
+    assert lib.bmpl_mlp_create(fake, 2, 4, 4, fake, 64, 64, 8, None, ctypes.byref(h)) == -1   # lda < n
+    assert h.value is None
+    assert lib.bmpl_mlp_destroy(None) == 0
+    lib.bmpl_mlp_forward.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    assert lib.bmpl_mlp_forward(None, fake, 4, 1, fake, 4, None) == -1
+    lib.bmpl_topk.argtypes = [vp, i64, i32, i32, i32, vp, i32, vp]
+    assert lib.bmpl_topk(fake, 10, 1, 10, 0, fake, 4, None) == -1       # k = 0
+    assert lib.bmpl_topk(fake, 10, 1, 10, 257, fake, 300, None) == -1   # k > 256
+    assert lib.bmpl_topk(fake, 10, 1, 10, 8, fake, 4, None) == -1       # ld_idx < k
+    assert lib.bmpl_topk(fake, 50000, 1, 50000, 8, fake, 8, None) == -1  # row too long
+    lib.bmpl_mlp_adam_step.argtypes = [vp, vp, vp, vp]
+    assert lib.bmpl_mlp_adam_step(None, None, None, None) == -1

@@ -149,6 +149,18 @@ def test_ragged_tiles(n, m, p, k, rho, c, gram_table):
     check_batch(P.At, P.Bt, lam, out, ref)
 
 
+@pytest.mark.parametrize("block_append", [True, False])
+@pytest.mark.parametrize("n,m,p,k,rho,c", [(320, 3000, 100, 50, 10, 0.03), (256, 1500, 64, 60, 25, 0.02)])
+def test_block_and_single_appends(n, m, p, k, rho, c, block_append):
+    """The inverse factor grown in blocks (default) and one atom at a time: both meet the parity
+    rules, including rho above the block width and supports of a few hundred atoms with drops."""
+    P = bi.tiny_gaussian(n=n, m=m, p=p, k=k, sigma=0.01, seed=n + k, lambda_rel=c, rho=rho)
+    s, out, ref, lam, st = _solve_and_check(P, block_append=block_append)
+    pk = _lib()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    check_batch(P.At, P.Bt, lam, out, ref)
+
+
 def test_relative_lambda_rule():
     pk = _lib()
     P = bi.small_gaussian()
