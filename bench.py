@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
 PEAK_HBM_GBS = 8000.0
 
 
@@ -44,6 +44,43 @@ def load_traffic(path: str, kernel_src: str):
         return rec
     except (OSError, ValueError):
         return None
+
+
+def screened_measurement(args, pk, torch, At, Bt, P, screen: str) -> dict:
+    """Throughput in graph mode and the instrumented kernel breakdown of one screening precision."""
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=screen)
+    shapes = s.autotune(P.p)["shapes"]
+    for _ in range(args.warmup):
+        s.solve(Bt)
+    torch.cuda.synchronize()
+    solved = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solved.append(s.solve(Bt)["status"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    conv = [int(((st & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for st in solved]
+    del s
+    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen=screen)
+    st.set_tuning(shapes)
+    st.solve(Bt)
+    torch.cuda.synchronize()
+    st.reset_timing()
+    for _ in range(args.steps):
+        st.solve(Bt)
+    torch.cuda.synchronize()
+    tb = st.timing()
+    ach = tb["corr_flops"] / (tb["corr_ms"] * 1e-3) / 1e12 if tb["corr_ms"] > 0 else 0.0
+    peak = PEAK_TFLOPS[screen]
+    return {
+        "value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
+        "converged_per_step": conv,
+        "main_product": {"dtype": screen, "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
+                         "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"]),
+                         "note": "first pass (lambda rule) in bfloat16 for fp8" if screen == "fp8" else ""},
+        "kernel_ms_per_step": {k: tb[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms", "residual_ms",
+                                                                "other_ms", "wall_ms")},
+    }
 
 
 def learned_comparison(args, pk, torch) -> dict:
@@ -78,6 +115,10 @@ def learned_comparison(args, pk, torch) -> dict:
     plain32.autotune(P.p)
     out32, rec["plain_fp32"] = timed(lambda: plain32.solve(Bt))
     del plain32
+    f8 = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="fp8")
+    f8.autotune(P.p)
+    _, rec["plain_fp8"] = timed(lambda: f8.solve(Bt))
+    del f8
     bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
     bf.autotune(P.p)
     outbf, rec["plain_bf16"] = timed(lambda: bf.solve(Bt))
@@ -135,9 +176,9 @@ def main():
     ap.add_argument("--workload", default="cs2048x16384")
     ap.add_argument("--cpu-sample", type=int, default=32, help="signals the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16"),
+    ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16", "fp8"),
                     help="precision of the correlation product (bf16: certified screening + float32 re-score)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the secondary bf16-screened measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the bf16-screened and fp8-ranked measurements")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal comparison on the face-like dictionary")
     ap.add_argument("--learned-signals", type=int, default=16384, help="inference signals of the learned comparison")
@@ -205,8 +246,8 @@ def main():
         traffic = rec.get("hbm_bytes_per_launch")
 
     result = {
-        "metric": "signals solved/sec at KKT tol 1e-4 (" + ("plain FP32" if args.screen == "fp32"
-                                                          else "BF16-screened") + " BMPL)",
+        "metric": "signals solved/sec at KKT tol 1e-4 (" + {"fp32": "plain FP32", "bf16": "BF16-screened",
+                                                             "fp8": "FP8-ranked"}[args.screen] + " BMPL)",
         "value": sum(conv) / elapsed,
         "unit": "signals/s",
         "n_gpus": 1,
@@ -216,7 +257,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.screen == "fp32" else "bf16",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.screen],
         "data": "synthetic (seeded)",
         "config": {"workload": P.name, "n": P.n, "m": P.m, "p": P.p, "rho": P.rho,
                    "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": args.screen,
@@ -249,39 +290,10 @@ def main():
     }
 
     if args.screen == "fp32" and not args.no_extra:
-        # The same workload with the bfloat16 screening product (certified band + exact re-score).
-        bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
-        bf.autotune(P.p)
-        for _ in range(args.warmup):
-            bf.solve(Bt)
-        torch.cuda.synchronize()
-        solved_bf = []
-        t4 = time.perf_counter()
-        for _ in range(args.steps):
-            solved_bf.append(bf.solve(Bt)["status"])
-        torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        conv_bf = [int(((s & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for s in solved_bf]
-        bft = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen="bf16")
-        bft.set_tuning(bf.autotune(P.p)["shapes"])
-        bft.solve(Bt)
-        torch.cuda.synchronize()
-        bft.reset_timing()
-        for _ in range(args.steps):
-            bft.solve(Bt)
-        torch.cuda.synchronize()
-        tb = bft.timing()
-        ach_bf = tb["corr_flops"] / (tb["corr_ms"] * 1e-3) / 1e12 if tb["corr_ms"] > 0 else 0.0
-        result["bf16_screened"] = {
-            "value": sum(conv_bf) / (t5 - t4), "unit": "signals/s", "ms_per_step": (t5 - t4) / args.steps * 1e3,
-            "converged_per_step": conv_bf,
-            "corr_gemm_bf16": {"achieved_tflops": ach_bf, "peak_tflops": PEAK_TFLOPS["bf16"],
-                               "frac": ach_bf / PEAK_TFLOPS["bf16"],
-                               "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"])},
-            "kernel_ms_per_step": {k: tb[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms",
-                                                                    "residual_ms", "other_ms", "wall_ms")},
-        }
-        del bf, bft
+        # The same workload with the reduced-precision products: bfloat16 screening (certified band +
+        # exact re-score) and e4m3 ranking (exact re-score of the top candidates, bfloat16 certification).
+        result["bf16_screened"] = screened_measurement(args, pk, torch, At, Bt, P, "bf16")
+        result["fp8_ranked"] = screened_measurement(args, pk, torch, At, Bt, P, "fp8")
 
     if not args.no_learned:
         result["learned"] = learned_comparison(args, pk, torch)

@@ -59,7 +59,10 @@ typedef enum {
 typedef enum {
     BMPL_PREC_FP32 = 0,   /* correlation product in float32 (MFMA, float32 accumulation) */
     BMPL_PREC_BF16 = 1,   /* bfloat16 screening product, float32 re-score before admission */
-    BMPL_PREC_FP8 = 2     /* fp8 e4m3 screening product, float32 re-score before admission */
+    BMPL_PREC_FP8 = 2     /* e4m3 ranking product (power-of-two scales per atom and per signal) after
+                             the first pass: its highest-ranked atoms are re-scored in float32 and the
+                             exact violators among them admitted; a signal with none is decided by the
+                             certified bfloat16 pass, which also runs the first pass (lambda rule) */
 } bmpl_precision;
 
 /* Per-signal status bits (bmpl_result.sig_status). */
@@ -164,7 +167,8 @@ const char* bmpl_last_error(void);
 /*
  * The batched correlation step: G[i*ldg + j] = a_j^T r_i for j < m, i < p,
  * where r_i = R_dev + i*ldr (n float32 values, ldr >= n), in the context's
- * screening precision with float32 accumulation.  This is the full
+ * screening precision with float32 accumulation (FP8 contexts: e4m3 operands
+ * with power-of-two scales per atom and per residual, the ranking product).  This is the full
  * matrix-vector product g = A^T xi of Algorithm 1, step 3, for p residuals at
  * once.  ldg >= m.  Errors: BMPL_E_INVALID.
  */

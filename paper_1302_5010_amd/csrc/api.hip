@@ -27,6 +27,7 @@ using namespace bmpl;
 namespace {
 
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
+constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 4 rho by default)
 
 }  // namespace
 
@@ -36,6 +37,15 @@ struct bmpl_ctx {
     float* At = nullptr;          // [m][kpad] float32 dictionary, atom-major
     double* Q = nullptr;          // [m][m] float64 Gram table A^T A, or null
     uint16_t* A16 = nullptr;      // [m + 1][kpad] bfloat16 dictionary (screening), row m zero
+    uint8_t* A8 = nullptr;        // [m + 1][kpad] e4m3 dictionary (FP8 ranking), row m zero
+    float* ascale8 = nullptr;     // [m + 1] power-of-two scale per e4m3 atom
+    int* cand8 = nullptr;         // [p_cap][CAND8] e4m3-ranked candidates
+    int* ncand8 = nullptr;        // [p_cap]
+    float* vmax8 = nullptr;       // [p_cap] scratch of the ranking pass
+    double* zeros = nullptr;      // [p_cap] zero thresholds for the ranking pass
+    int* cert = nullptr;          // [p_cap] left for the certified pass
+    int* cert_act = nullptr;      // [p_cap] compacted list of those signals
+    int* n_cert_dev = nullptr;    // its length
     double gamma_amax = 0.0;      // bfloat16 band factor: gamma_n * max_j ||a_j||
     int* cand = nullptr;          // [p_cap][CANDCAP] screening candidates
     int* ncand = nullptr;         // [p_cap]
@@ -181,6 +191,8 @@ void free_signals(bmpl_ctx* c)
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
+    dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
+    dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
     c->p_cap = 0;
     c->K_cap = 0;
 }
@@ -218,6 +230,21 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
         HIPC(dalloc(&w.rnorm, P));
         HIPC(dalloc(&c->cand, P * CANDCAP_DEF));
         HIPC(dalloc(&c->ncand, P));
+    }
+    if (c->opt.screen == BMPL_PREC_FP8) {
+        HIPC(dalloc(&w.R8, (P + 1) * c->kpad));
+        HIPC(hipMemset(w.R8 + P * c->kpad, 0, c->kpad));
+        HIPC(dalloc(&w.rscale8, P + 1));
+        const float one = 1.0f;
+        HIPC(hipMemcpy(w.rscale8 + P, &one, sizeof(float), hipMemcpyHostToDevice));
+        HIPC(dalloc(&c->cand8, P * CAND8));
+        HIPC(dalloc(&c->ncand8, P));
+        HIPC(dalloc(&c->vmax8, P));
+        HIPC(dalloc(&c->zeros, P));
+        HIPC(hipMemset(c->zeros, 0, P * sizeof(double)));
+        HIPC(dalloc(&c->cert, P));
+        HIPC(dalloc(&c->cert_act, P));
+        HIPC(dalloc(&c->n_cert_dev, 1));
     }
     c->p_cap = p;
     c->K_cap = K;
@@ -338,7 +365,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (o) opt = *o;
     if (opt.rho <= 0 || opt.rho > 64) return fail(BMPL_E_INVALID, "bmpl_create: rho must be in [1, 64]");
     if (!(opt.kkt_tol >= 0.0)) return fail(BMPL_E_INVALID, "bmpl_create: kkt_tol must be >= 0");
-    if (opt.screen != BMPL_PREC_FP32 && opt.screen != BMPL_PREC_BF16)
+    if (opt.screen != BMPL_PREC_FP32 && opt.screen != BMPL_PREC_BF16 && opt.screen != BMPL_PREC_FP8)
         return fail(BMPL_E_UNSUPPORTED, "bmpl_create: screening precision %d not available", (int)opt.screen);
     if (opt.max_active > m) opt.max_active = m;
 
@@ -348,7 +375,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e != hipSuccess) { delete c; return fail(BMPL_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)); }
     c->n = n;
     c->m = m;
-    c->kpad = round_up(n, 64);
+    c->kpad = round_up(n, opt.screen == BMPL_PREC_FP8 ? 128 : 64);   // whole k stages of every product
     c->mode = mode;
     c->lambda = lambda;
     c->opt = opt;
@@ -365,7 +392,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
     // bfloat16 copy of the dictionary and the band factor gamma_n * max_j ||a_j|| for screening.
-    if (e == hipSuccess && opt.screen == BMPL_PREC_BF16) {
+    if (e == hipSuccess && opt.screen != BMPL_PREC_FP32) {
         float* norms = nullptr;
         e = dalloc(&c->A16, (size_t)(m + 1) * c->kpad);
         if (e == hipSuccess) e = hipMemsetAsync(c->A16, 0, (size_t)(m + 1) * c->kpad * sizeof(uint16_t), s);
@@ -382,6 +409,16 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
             const double gamma = (std::ldexp(1.0, -7) + std::ldexp(1.0, -16) + n * std::ldexp(1.0, -24)) * 1.01;
             c->gamma_amax = gamma * amax;
         }
+    }
+    // e4m3 copy with per-atom power-of-two scales for the FP8 ranking product (row m zero, scale 1)
+    if (e == hipSuccess && opt.screen == BMPL_PREC_FP8) {
+        e = dalloc(&c->A8, (size_t)(m + 1) * c->kpad);
+        if (e == hipSuccess) e = hipMemsetAsync(c->A8, 0, (size_t)(m + 1) * c->kpad, s);
+        if (e == hipSuccess) e = dalloc(&c->ascale8, (size_t)m + 1);
+        if (e == hipSuccess) e = launch_atoms_fp8(c->At, c->kpad, c->kpad, c->A8, c->ascale8, m, s);
+        const float one = 1.0f;
+        if (e == hipSuccess) e = hipMemcpyAsync(c->ascale8 + m, &one, sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     c->block_append = !(opt.flags & BMPL_FLAG_SINGLE_APPEND);
     // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
@@ -426,6 +463,8 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     dfree(c->At);
     dfree(c->Q);
     dfree(c->A16);
+    dfree(c->A8);
+    dfree(c->ascale8);
     dfree(c->diag16);
     dfree(c->n_act_dev);
     dfree(c->diagR);
@@ -453,6 +492,21 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
     HIPC(hipMemsetAsync(c->diagR, 0, (size_t)(p + 1) * c->kpad * sizeof(float), s));
     HIPC(hipMemcpy2DAsync(c->diagR, c->kpad * sizeof(float), R_dev, ldr * sizeof(float), c->n * sizeof(float), p,
                           hipMemcpyDeviceToDevice, s));
+    if (c->A8) {
+        uint8_t* d8 = nullptr;
+        float* sc8 = nullptr;
+        hipError_t e = dalloc(&d8, (size_t)(p + 1) * c->kpad);
+        if (e == hipSuccess) e = dalloc(&sc8, (size_t)p + 1);
+        if (e == hipSuccess) e = launch_atoms_fp8(c->diagR, c->kpad, c->kpad, d8, sc8, p + 1, s);
+        if (e == hipSuccess)
+            e = launch_corr_gemm_fp8(c->corr_variant(p), c->A8, c->kpad, c->m, c->kpad, d8, c->kpad, nullptr,
+                                     nullptr, p, G_dev, ldg, p, 0, 1 << 30, c->ascale8, sc8, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dfree(d8);
+        dfree(sc8);
+        HIPC(e);
+        return BMPL_OK;
+    }
     if (c->A16) {
         dfree(c->diag16);
         HIPC(dalloc(&c->diag16, (size_t)(p + 1) * c->kpad));
@@ -551,30 +605,67 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
                                    bool gated) -> bmpl_status {
         const int nxt = 1 - cur;
         const bool ev = tm && !gated;
+        // e4m3 ranking for every pass after the first; the first (the lambda rule) is certified in bfloat16
+        const bool fp8 = c->A8 && !first;
         size_t e0 = ev ? mark(c, q) : 0;
-        auto gemm = [&](int shape, int grid, int lo, int hi) -> hipError_t {
-            if (c->A16)
-                return launch_corr_gemm_bf16(shape, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, c->act[cur],
-                                             c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
-            return launch_corr_gemm_f32(shape, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, c->act[cur],
-                                        c->n_act_dev + cur, grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
-        };
-        if (gated) {
-            const int lo[3] = {512, 64, 1}, hi[3] = {1 << 30, 512, 64};
-            for (int b = 0; b < 3; ++b) {
-                const int grid = std::min(n_grid, hi[b] - 1);
-                if (grid < lo[b]) continue;
-                HIPC(gemm(c->corr_shape[b], grid, lo[b], hi[b]));
+        // One correlation product over a running list (prec 0 float32, 1 bfloat16, 2 e4m3).  Gated:
+        // every tile shape is enqueued and runs only for its own bucket of the device-side count.
+        auto product = [&](int prec, const int* lst, const int* cnt, bool gate) -> hipError_t {
+            auto gemm = [&](int shape, int grid, int lo, int hi) -> hipError_t {
+                if (prec == 2)
+                    return launch_corr_gemm_fp8(shape, c->A8, c->kpad, c->m, c->kpad, w.R8, c->kpad, lst, cnt, grid,
+                                                c->Gc, c->ldg, c->p_cap, lo, hi, c->ascale8, w.rscale8, q);
+                if (prec == 1)
+                    return launch_corr_gemm_bf16(shape, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, lst, cnt,
+                                                 grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
+                return launch_corr_gemm_f32(shape, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, lst, cnt, grid,
+                                            c->Gc, c->ldg, c->p_cap, lo, hi, q);
+            };
+            if (gate) {
+                const int lo[3] = {512, 64, 1}, hi[3] = {1 << 30, 512, 64};
+                for (int b = 0; b < 3; ++b) {
+                    const int grid = std::min(n_grid, hi[b] - 1);
+                    if (grid < lo[b]) continue;
+                    const hipError_t e = gemm(c->corr_shape[b], grid, lo[b], hi[b]);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
             }
-        } else {
-            HIPC(gemm(c->corr_variant(n_grid), n_grid, 0, 1 << 30));
-        }
+            return gemm(c->corr_variant(n_grid), n_grid, 0, 1 << 30);
+        };
+        HIPC(product(fp8 ? 2 : (c->A16 ? 1 : 0), c->act[cur], c->n_act_dev + cur, gated));
         if (ev) {
             const double mm = c->m, nn = c->n, pp = n_grid;
             const size_t e1 = mark(c, q);
             span(c, e0, e1, K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
             e0 = e1;
         }
+        // certified bfloat16 screening of a list: band test, candidates, exact re-score and selection
+        auto screen_pass = [&](const int* lst, const int* cnt) -> hipError_t {
+            ScreenArgs sc{};
+            sc.G = c->Gc; sc.ldg = c->ldg; sc.m = c->m;
+            sc.act = lst; sc.n_act_dev = cnt; sc.p_grid = n_grid;
+            sc.lam = w.lam; sc.lam_rel = (rel && first) ? c->lambda : 0.0;
+            sc.rnorm = w.rnorm; sc.gamma_amax = c->gamma_amax;
+            sc.excl = w.inI; sc.words = w.words;
+            sc.k = rho; sc.nI = w.nI; sc.max_active = max_active;
+            sc.cand = c->cand; sc.candcap = CANDCAP_DEF; sc.ncand = c->ncand;
+            hipError_t e = launch_screen(sc, q);
+            if (e != hipSuccess) return e;
+            RescoreArgs rs{};
+            rs.At = c->At; rs.lda = c->kpad; rs.kpad = c->kpad;
+            rs.R = w.R; rs.ldr = c->kpad;
+            rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.gamma_amax = c->gamma_amax;
+            rs.act = lst; rs.n_act_dev = cnt; rs.p_grid = n_grid;
+            rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
+            // candidate values (12 bytes each) and the staged residual within 60 KB of LDS
+            rs.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));
+            rs.ncand = c->ncand;
+            rs.lam = w.lam; rs.lam_rel = sc.lam_rel;
+            rs.k = rho; rs.nI = w.nI; rs.max_active = max_active;
+            rs.sel = w.sel; rs.selcap = w.selcap; rs.nsel = w.nsel; rs.vmax = w.vmax; rs.status = w.status;
+            return launch_rescore(rs, q);
+        };
         SelectArgs a{};
         a.G = c->Gc; a.ldg = c->ldg; a.m = c->m;
         a.act = c->act[cur]; a.n_act_dev = c->n_act_dev + cur; a.p_grid = n_grid;
@@ -582,29 +673,28 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         a.excl = w.inI; a.words = w.words;
         a.k = rho; a.sel = w.sel; a.selcap = w.selcap; a.nsel = w.nsel; a.vmax = w.vmax;
         a.nI = w.nI; a.max_active = max_active;
-        if (c->A16) {
-            ScreenArgs sc{};
-            sc.G = c->Gc; sc.ldg = c->ldg; sc.m = c->m;
-            sc.act = c->act[cur]; sc.n_act_dev = c->n_act_dev + cur; sc.p_grid = n_grid;
-            sc.lam = w.lam; sc.lam_rel = a.lam_rel;
-            sc.rnorm = w.rnorm; sc.gamma_amax = c->gamma_amax;
-            sc.excl = w.inI; sc.words = w.words;
-            sc.k = rho; sc.nI = w.nI; sc.max_active = max_active;
-            sc.cand = c->cand; sc.candcap = CANDCAP_DEF; sc.ncand = c->ncand;
-            HIPC(launch_screen(sc, q));
-            RescoreArgs rs{};
-            rs.At = c->At; rs.lda = c->kpad; rs.kpad = c->kpad;
-            rs.R = w.R; rs.ldr = c->kpad;
-            rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.gamma_amax = c->gamma_amax;
-            rs.act = c->act[cur]; rs.n_act_dev = c->n_act_dev + cur; rs.p_grid = n_grid;
-            rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
-            // candidate values (12 bytes each) and the staged residual within 60 KB of LDS
-            rs.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));
-            rs.ncand = c->ncand;
-            rs.lam = w.lam; rs.lam_rel = a.lam_rel;
-            rs.k = rho; rs.nI = w.nI; rs.max_active = max_active;
-            rs.sel = w.sel; rs.selcap = w.selcap; rs.nsel = w.nsel; rs.vmax = w.vmax; rs.status = w.status;
-            HIPC(launch_rescore(rs, q));
+        if (fp8) {
+            // ranking: the 4 rho largest |g~| outside I (zero threshold) ...
+            SelectArgs r8 = a;
+            r8.lam = c->zeros; r8.lam_rel = 0.0;
+            r8.k = std::min(CAND8, 4 * rho); r8.sel = c->cand8; r8.selcap = CAND8; r8.nsel = c->ncand8;
+            r8.vmax = c->vmax8;
+            HIPC(launch_select(r8, q));
+            // ... re-scored exactly; the exact violators among them are admitted
+            Rank8Args rk{};
+            rk.At = c->At; rk.lda = c->kpad; rk.kpad = c->kpad; rk.R = w.R; rk.ldr = c->kpad;
+            rk.act = c->act[cur]; rk.n_act_dev = c->n_act_dev + cur; rk.p_grid = n_grid;
+            rk.cand = c->cand8; rk.candcap = CAND8; rk.ncand = c->ncand8;
+            rk.lam = w.lam; rk.k = rho; rk.nI = w.nI; rk.max_active = max_active;
+            rk.sel = w.sel; rk.selcap = w.selcap; rk.nsel = w.nsel; rk.vmax = w.vmax; rk.cert = c->cert;
+            HIPC(launch_rank8(rk, q));
+            // signals with no exact violator among their candidates: the certified bfloat16 pass decides
+            HIPC(launch_flag_compact(c->act[cur], c->n_act_dev + cur, n_grid, c->cert, c->cert_act, c->n_cert_dev,
+                                     q));
+            HIPC(product(1, c->cert_act, c->n_cert_dev, true));
+            HIPC(screen_pass(c->cert_act, c->n_cert_dev));
+        } else if (c->A16) {
+            HIPC(screen_pass(c->act[cur], c->n_act_dev + cur));
         } else {
             HIPC(launch_select(a, q));
         }
@@ -646,7 +736,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
         so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes <= c->lds_dyn_max) ? 1 : 0;
         size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
-        so.zs_lds = (c->block_append && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;
+        // block appends pay off when the factor streams from global memory; with an LDS-resident
+        // factor single appends are cheaper and keep the workgroup's LDS (and occupancy) smaller
+        so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;
         if (so.zs_lds) lds += block_scratch_bytes(w.K);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
         hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
@@ -752,7 +844,16 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
     Workspace& w = c->w;
     HIPC(hipMemsetAsync(w.R, 0, (size_t)p * c->kpad * sizeof(float), s));
     if (w.R16) HIPC(hipMemsetAsync(w.R16, 0, (size_t)p * c->kpad * sizeof(uint16_t), s));
+    if (w.R8) HIPC(hipMemsetAsync(w.R8, 0, (size_t)p * c->kpad, s));
+    if (w.rscale8) {
+        std::vector<float> ones(p, 1.0f);
+        HIPC(hipMemcpyAsync(w.rscale8, ones.data(), sizeof(float) * p, hipMemcpyHostToDevice, s));
+        HIPC(hipStreamSynchronize(s));
+    }
     auto gemm = [&](int v, int nb) -> hipError_t {
+        if (c->A8)   // the product of every outer iteration after the first
+            return launch_corr_gemm_fp8(v, c->A8, c->kpad, c->m, c->kpad, w.R8, c->kpad, nullptr, nullptr, nb,
+                                        c->Gc, c->ldg, c->p_cap, 0, 1 << 30, c->ascale8, w.rscale8, s);
         if (c->A16)
             return launch_corr_gemm_bf16(v, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, nullptr, nullptr, nb,
                                          c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);

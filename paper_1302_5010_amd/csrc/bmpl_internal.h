@@ -55,6 +55,8 @@ struct Workspace {
     // reduced-precision screening (null in float32 mode)
     uint16_t* R16;      // [p_cap + 1][kpad] bfloat16 copy of R (row p_cap all zero)
     double* rnorm;      // [p] ||xi_i||_2
+    uint8_t* R8;        // [p_cap + 1][kpad] e4m3 copy of R / rscale8 (FP8 ranking only; row p_cap zero)
+    float* rscale8;     // [p_cap + 1] power-of-two scale of each R8 row
 };
 
 // Launchers (all asynchronous on `stream`).
@@ -81,6 +83,13 @@ hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, i
                                  const uint16_t* Rbuf, int64_t ldr, const int* act,
                                  const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                  int n_lo, int n_hi, hipStream_t stream);
+
+// The same product with e4m3 operands (raw bytes), per-atom and per-signal power-of-two scales
+// applied in the epilogue: G = (A8 R8^T) * ascale[j] * rscale[signal].  kpad % 128 == 0.
+hipError_t launch_corr_gemm_fp8(int variant, const uint8_t* A8, int64_t lda, int m, int kpad,
+                                const uint8_t* R8, int64_t ldr, const int* act,
+                                const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
+                                int n_lo, int n_hi, const float* ascale, const float* rscale, hipStream_t stream);
 
 // Top-k selection per row (worst-case analysis).  See bmpl_select in bmpl.h; here
 // `lam_rel` > 0 computes lambda[sig] = lam_rel * max_j |G| first (first pass).
@@ -117,11 +126,59 @@ struct RescoreArgs {
     int k; const int* nI; int max_active;
     int* sel; int selcap; int* nsel; float* vmax; int* status;
 };
+// e4m3 ranking (screen.hip): exact re-score of the candidates that the e4m3 product ranked highest,
+// admission of the exact violators among them, and the list of signals left for a certified pass.
+struct Rank8Args {
+    const float* At; int64_t lda; int kpad;  // float32 atoms
+    const float* R; int64_t ldr;             // float32 residuals
+    const int* act; const int* n_act_dev; int p_grid;
+    const int* cand; int candcap; const int* ncand;   // top |g~| outside I per signal
+    const double* lam;
+    int k; const int* nI; int max_active;
+    int* sel; int selcap; int* nsel; float* vmax;
+    int* cert;                               // [p] 1: no exact violator among the candidates
+};
+hipError_t launch_rank8(const Rank8Args& a, hipStream_t stream);
+// act_out = the signals of act_in (device count n_in_dev) with flag[sig] != 0, in order; count to n_out_dev.
+hipError_t launch_flag_compact(const int* act_in, const int* n_in_dev, int n_in, const int* flag, int* act_out,
+                               int* n_out_dev, hipStream_t stream);
+// A8[j] = e4m3(a_j / ascale[j]), ascale[j] the power of two that brings max |a_j| to at most 448.
+hipError_t launch_atoms_fp8(const float* At, int64_t lda, int kpad, uint8_t* A8, float* ascale, int m,
+                            hipStream_t stream);
 hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd, int rows, int cols,
                           hipStream_t stream);
 hipError_t launch_atom_norms(const float* At, int64_t lda, int n, float* norms, int m, hipStream_t stream);
 hipError_t launch_screen(const ScreenArgs& a, hipStream_t stream);
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream);
+
+// float32 -> OCP e4m3 (bias 7, largest finite 448, no infinities), round to nearest, ties to even,
+// saturating at +-448; NaN -> 0x7F.  Normal codes (|x| >= 2^-6) keep 3 mantissa bits, subnormal
+// codes are multiples of 2^-9 (code 8 = 2^-6, the smallest normal, so the two ranges meet).
+__host__ __device__ inline uint8_t fp8_e4m3(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    const uint8_t sgn = (uint8_t)((u >> 24) & 0x80u);
+    const uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return 0x7F;
+    if (a >= 0x3c800000u) {                          // |x| >= 2^-6
+        const uint32_t b = a + 0x7ffffu + ((a >> 20) & 1u);
+        const int e = (int)(b >> 23) - 127;
+        const uint32_t q = (b >> 20) & 7u;
+        if (e > 8 || (e == 8 && q > 6)) return sgn | 0x7E;
+        return sgn | (uint8_t)(((e + 7) << 3) | (int)q);
+    }
+    const float q = __builtin_rintf(__builtin_bit_cast(float, a) * 512.0f);   // exact scaling by 2^9
+    return sgn | (uint8_t)q;
+}
+
+// Smallest power of two s with maxabs / s <= 448 (1 for maxabs == 0): x / s is exact and fits e4m3.
+__host__ __device__ inline float fp8_pow2_scale(float maxabs)
+{
+    if (!(maxabs > 0.f) || !(maxabs < 3.0e38f)) return 1.f;
+    int e;
+    const float f = __builtin_frexpf(maxabs / 448.0f, &e);   // maxabs / 448 = f 2^e, f in [0.5, 1)
+    return __builtin_ldexpf(1.0f, f == 0.5f ? e - 1 : e);
+}
 
 // Round-to-nearest-even float32 -> bfloat16 (raw bits).
 __device__ inline uint16_t bf16_round(float f)

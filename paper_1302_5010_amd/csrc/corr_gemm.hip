@@ -27,7 +27,7 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     const E* __restrict__ At, int64_t lda, int m, int kpad,
     const E* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
     const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row,
-    int n_lo, int n_hi)
+    int n_lo, int n_hi, const float* __restrict__ ascale, const float* __restrict__ rscale)
 {
     using S = TileShape<BM, BN, WM, WN>;
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
@@ -73,24 +73,41 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
 
     // D[row][col] of a 32x32 block (both instructions): lane l, register r -> row 8(r/4) + 4(l/32) + r%4,
     // col l%32.
+    if constexpr (sizeof(E) == 1) {
+        // e4m3 operands carry power-of-two scales: one per atom, one per signal
 #pragma unroll
-    for (int i = 0; i < S::TI; ++i)
+        for (int i = 0; i < S::TI; ++i)
 #pragma unroll
-        for (int j = 0; j < S::TJ; ++j) {
-            const int atom = atom0 + wa + 32 * j + l32;
-            if (atom >= m) continue;
+            for (int j = 0; j < S::TJ; ++j) {
+                const int atom = atom0 + wa + 32 * j + l32;
+                if (atom >= m) continue;
+                const float sa = ascale[atom];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r];
+                for (int r = 0; r < 16; ++r) {
+                    const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r] * sa * rscale[act ? act[a] : a];
+                }
             }
-        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+            for (int j = 0; j < S::TJ; ++j) {
+                const int atom = atom0 + wa + 32 * j + l32;
+                if (atom >= m) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r];
+                }
+            }
+    }
 }
 
 template <class E, int BM, int BN, int WM, int WN>
 hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                         const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
-                        int n_lo, int n_hi, hipStream_t stream)
+                        int n_lo, int n_hi, const float* ascale, const float* rscale, hipStream_t stream)
 {
     const int tiles_m = (p_grid + BM - 1) / BM;
     const int tiles_n = (m + BN - 1) / BN;
@@ -98,24 +115,25 @@ hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((corr_gemm_kernel<E, BM, BN, WM, WN>), dim3((unsigned)nwg),
                        dim3(TileShape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
-                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi);
+                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi, ascale, rscale);
     return hipGetLastError();
 }
 
 template <class E>
 hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                           const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
-                          int n_lo, int n_hi, hipStream_t stream)
+                          int n_lo, int n_hi, hipStream_t stream, const float* ascale = nullptr,
+                          const float* rscale = nullptr)
 {
     if (p_grid <= 0 || m <= 0) return hipSuccess;
     if (kpad % (TILE_ROW_BYTES / (int)sizeof(E))) return hipErrorInvalidValue;
     switch (variant) {
-    case 0: return launch_shape<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 1: return launch_shape<E, 128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 2: return launch_shape<E, 256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
-    case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+    case 0: return launch_shape<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 1: return launch_shape<E, 128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 2: return launch_shape<E, 256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -142,6 +160,16 @@ hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m
 {
     return launch_variant<float>(variant, At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row,
                                  n_lo, n_hi, stream);
+}
+
+hipError_t launch_corr_gemm_fp8(int variant, const uint8_t* A8, int64_t lda, int m, int kpad,
+                                const uint8_t* R8, int64_t ldr, const int* act,
+                                const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
+                                int n_lo, int n_hi, const float* ascale, const float* rscale, hipStream_t stream)
+{
+    if (!ascale || !rscale) return hipErrorInvalidValue;
+    return launch_variant<uint8_t>(variant, A8, lda, m, kpad, R8, ldr, act, n_act_dev, p_grid, G, ldg, zero_row,
+                                   n_lo, n_hi, stream, ascale, rscale);
 }
 
 hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, int m, int kpad,

@@ -3,13 +3,15 @@
 //
 // Tiling (gfx950, wave64): a workgroup computes a BM x BN tile of C; each wave
 // a WM x WN sub-tile as (WM/32) x (WN/32) blocks of 32x32 MFMA accumulators.
-// K is consumed 128 bytes at a time (32 float32 or 64 bfloat16 values) through
+// K is consumed 128 bytes at a time (32 float32, 64 bfloat16 or 128 e4m3 values) through
 // two LDS buffers, one barrier per stage; the next K-slice is prefetched into
 // registers while the current one feeds the matrix cores.  Within each 16-byte
 // chunk of k, lane half h supplies the chunk's half h (float32: k = 8b + 4h + t
 // at step t of four v_mfma_f32_32x32x2f32; bfloat16: 8 consecutive k of one
-// v_mfma_f32_32x32x16_bf16), so every LDS fragment read is one 16-byte ds_read
-// (the summation order over k is immaterial to the contraction).
+// v_mfma_f32_32x32x16_bf16; e4m3: 32 consecutive bytes of k for one
+// v_mfma_scale_f32_32x32x64_f8f6f4), so every LDS fragment read is one or two 16-byte ds_reads; both
+// operands use the same lane-to-k assignment, so the summation order over k is immaterial to the
+// contraction.
 //
 // The caller owns the row mapping: it passes, per staging load, the element
 // offset of the row start (plus this thread's 16-byte column) in X and in W.
@@ -28,6 +30,7 @@ namespace bmpl {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
 constexpr int TILE_ROW_BYTES = 128;                 // k bytes per LDS stage and row
 constexpr int TILE_LDS_ROW = TILE_ROW_BYTES + 16;   // 16-byte aligned, staggers banks
@@ -105,6 +108,36 @@ __device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const in
         asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
         const char* cX = lds.x[cur];
         const char* cW = lds.w[cur];
+        if constexpr (sizeof(E) == 1) {
+            // e4m3: two v_mfma_scale_f32_32x32x64_f8f6f4 per stage (unit scales); lane half h supplies
+            // the 32 bytes [64 t + 32 h, +32) of k to both operands
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                intx8 fx[S::TI], fw[S::TJ];
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i) {
+                    const char* pp = &cX[(ws + 32 * i + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
+                    const float4 lo = *reinterpret_cast<const float4*>(pp);
+                    const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
+                    fx[i] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                                  __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
+                }
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j) {
+                    const char* pp = &cW[(wa + 32 * j + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
+                    const float4 lo = *reinterpret_cast<const float4*>(pp);
+                    const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
+                    fw[j] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                                  __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
+                }
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fx[i], fw[j], acc[i][j], 0, 0, 0, 127,
+                                                                                   0, 127);
+            }
+        } else {
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {       // 4 x 16-byte chunks per lane half per stage
             float4 fx[S::TI], fw[S::TJ];
@@ -144,6 +177,7 @@ __device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const in
                     for (int j = 0; j < S::TJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].w, fw[j].w, acc[i][j], 0, 0, 0);
             }
+        }
         }
         asm volatile("" ::: "memory");       // and consume it only after
         TILE_STORE_SLICE(cur ^ 1);

@@ -59,6 +59,20 @@ __device__ inline double block_max(double v, double* red)
     return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+// e4m3 copy of residual row `sig` (already written to R by this workgroup) with its power-of-two
+// scale, for the e4m3 ranking product.
+__device__ inline void write_residual_fp8(const Workspace& w, int sig, double* red)
+{
+    const float* R = w.R + (int64_t)sig * w.kpad;
+    double mx = 0.0;
+    for (int r = threadIdx.x; r < w.kpad; r += NT) mx = fmax(mx, (double)fabsf(R[r]));
+    const float s = fp8_pow2_scale((float)block_max(mx, red));   // the barriers also publish R
+    const float inv = 1.0f / s;
+    uint8_t* R8 = w.R8 + (int64_t)sig * w.kpad;
+    for (int r = threadIdx.x; r < w.kpad; r += NT) R8[r] = fp8_e4m3(R[r] * inv);
+    if (threadIdx.x == 0) w.rscale8[sig] = s;
+}
+
 // (alpha, position) minimum, ties to the smaller position.
 __device__ inline void block_argmin(double& a, int& q, double* red, int* redi)
 {
@@ -106,6 +120,27 @@ __device__ inline double row_dot(const double* Ri, const double* v, int len)
     return (a0 + a1) + (a2 + a3);
 }
 
+// z[i] = sum_{k <= i} R(i, k) w[k] for i < s with the factor in global memory: one row per wave at a
+// time, lanes across the row (coalesced, four loads in flight), a wave reduction per row.
+__device__ inline void rows_matvec_global(const double* R, const double* w, double* z, int s)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < s; i += NT / 64) {
+        const double* Ri = R + tri(i);
+        double a0 = 0.0, a1 = 0.0;
+        int k = lane;
+        for (; k + 192 <= i; k += 256) {
+            const double r0 = Ri[k], r1 = Ri[k + 64], r2 = Ri[k + 128], r3 = Ri[k + 192];
+            a0 += r0 * w[k] + r2 * w[k + 128];
+            a1 += r1 * w[k + 64] + r3 * w[k + 192];
+        }
+        for (; k <= i; k += 64) a0 += Ri[k] * w[k];
+        double acc = a0 + a1;
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) z[i] = acc;
+    }
+}
+
 // sum_{i = k}^{s-1} v[i] R(i, k) over column k of a packed lower factor.
 __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
 {
@@ -126,8 +161,20 @@ __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
             o += i + 1;
         }
     } else {
-        // global factor: rows in lockstep across the wave so loads of one row coalesce
-        for (int i = k & ~63; i < s; ++i)
+        // global factor: rows in lockstep across the wave so loads of one row coalesce; four rows'
+        // loads in flight
+        int i = k & ~63;
+        for (; i + 4 <= s; i += 4) {
+            const double r0 = i >= k ? f.R[tri(i) + k] : 0.0;
+            const double r1 = i + 1 >= k ? f.R[tri(i + 1) + k] : 0.0;
+            const double r2 = i + 2 >= k ? f.R[tri(i + 2) + k] : 0.0;
+            const double r3 = i + 3 >= k ? f.R[tri(i + 3) + k] : 0.0;
+            a0 += v[i] * r0;
+            a1 += v[i + 1] * r1;
+            a2 += v[i + 2] * r2;
+            a3 += v[i + 3] * r3;
+        }
+        for (; i < s; ++i)
             if (i >= k) a0 += v[i] * f.R[tri(i) + k];
     }
     return (a0 + a1) + (a2 + a3);
@@ -149,10 +196,16 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     if (tid == 0) s_gjj = Gj[j];
     __syncthreads();
     double part = 0.0;
-    for (int i = tid; i < s; i += NT) {      // z = Rinv w
-        const double acc = row_dot(v.R + tri(i), vw, i + 1);
-        vz[i] = acc;
-        part += acc * acc;
+    if (v.r_lds) {
+        for (int i = tid; i < s; i += NT) {      // z = Rinv w
+            const double acc = row_dot(v.R + tri(i), vw, i + 1);
+            vz[i] = acc;
+            part += acc * acc;
+        }
+    } else {
+        rows_matvec_global(v.R, vw, vz, s);
+        __syncthreads();
+        for (int i = tid; i < s; i += NT) part += vz[i] * vz[i];
     }
     const double zz = block_sum(part, red);
     const double gjj = s_gjj;
@@ -215,7 +268,19 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
         for (int e = 0; e < JB; ++e) acc[e] = 0.0;
         if (i >= 0) {
             const double* Ri = v.R + tri(i);
-            for (int k = lane; k <= i; k += 64) {
+            int k = lane;
+            for (; k + 192 <= i; k += 256) {      // four loads in flight per lane
+                double r[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = Ri[k + 64 * q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double* wk = zs + (k + 64 * q) * JB;
+#pragma unroll
+                    for (int e = 0; e < JB; ++e) acc[e] += r[q] * wk[e];
+                }
+            }
+            for (; k <= i; k += 64) {
                 const double r = Ri[k];
                 const double* wk = zs + k * JB;
 #pragma unroll
@@ -291,7 +356,19 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
         double acc[JB];
 #pragma unroll
         for (int b = 0; b < JB; ++b) acc[b] = 0.0;
-        for (int i = kb + wave * 64; i < s0; ++i) {
+        int i = kb + wave * 64;
+        for (; i + 4 <= s0; i += 4) {              // four rows' loads in flight
+            double r[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = (i + q >= k) ? v.R[tri(i + q) + k] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double* zi = zs + (i + q) * JB;
+#pragma unroll
+                for (int b = 0; b < JB; ++b) acc[b] += r[q] * zi[b];
+            }
+        }
+        for (; i < s0; ++i) {
             if (i >= k) {
                 const double r = v.R[tri(i) + k];
                 const double* zi = zs + i * JB;
@@ -343,6 +420,53 @@ __device__ void append_list(Sig& v, int& nS, const int* list, int nv, const doub
     }
 }
 
+// Remove support position q from the inverse factor in O(|S|^2).  Moving column q of Rinv to the end
+// only relabels G's order; Givens rotations of consecutive rows j, j + 1 (j = q .. s-2), each chosen to
+// clear row j's entry in the moved column, then restore triangularity.  Rotations act on the left of
+// Rinv, so Rinv^T Rinv = G^{-1} is unchanged for the remaining positions, and the leading
+// (s-1) x (s-1) block is the new inverse factor (rows may change sign, which no product of the solver
+// sees).  One barrier per row: row j's new values land where no later step reads, and the next step's
+// writes (row j + 1) wait until every thread has read the old row j + 1.  The caller shifts the support
+// order.  Returns false (and changes nothing) when a row is longer than the per-thread register budget.
+constexpr int DROP_CT = 16;   // columns per thread: supports up to 16 * NT positions
+__device__ bool chol_drop(Sig& v, int s, int q)
+{
+    const int tid = threadIdx.x;
+    if (s > DROP_CT * NT) return false;
+    double carry[DROP_CT];
+#pragma unroll
+    for (int t = 0; t < DROP_CT; ++t) {
+        const int c = tid + NT * t;
+        carry[t] = c < q ? v.R[tri(q) + c] : 0.0;
+    }
+    double last = v.R[tri(q) + q];
+    __syncthreads();
+    for (int j = q; j < s - 1; ++j) {
+        const double* nx = v.R + tri(j + 1);
+        const double b = nx[q];
+        double nxt[DROP_CT];
+#pragma unroll
+        for (int t = 0; t < DROP_CT; ++t) {
+            const int c = tid + NT * t;
+            nxt[t] = c <= j ? nx[c < q ? c : c + 1] : 0.0;
+        }
+        const double r = hypot(last, b);
+        const double cs = r > 0.0 ? b / r : 1.0;
+        const double sn = r > 0.0 ? -last / r : 0.0;
+        double* out = v.R + tri(j);
+#pragma unroll
+        for (int t = 0; t < DROP_CT; ++t) {
+            const int c = tid + NT * t;
+            const double nw = cs * carry[t] + sn * nxt[t];
+            carry[t] = -sn * carry[t] + cs * nxt[t];
+            if (c <= j) out[c] = nw;
+        }
+        last = r;
+        __syncthreads();
+    }
+    return true;
+}
+
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
 __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, double* vz, double* vx)
 {
@@ -352,7 +476,11 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
         vw[k] = v.c[u] - lam * (double)v.th[u];
     }
     __syncthreads();
-    for (int i = tid; i < nS; i += NT) vz[i] = row_dot(v.R + tri(i), vw, i + 1);
+    if (v.r_lds) {
+        for (int i = tid; i < nS; i += NT) vz[i] = row_dot(v.R + tri(i), vw, i + 1);
+    } else {
+        rows_matvec_global(v.R, vw, vz, nS);
+    }
     __syncthreads();
     for (int k = tid; k < nS; k += NT) vx[k] = col_dot(v, vz, k, nS);
     __syncthreads();
@@ -491,6 +619,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.obj[sig] = 0.5 * bb;
         if (w.rnorm) w.rnorm[sig] = sqrt(bb);
     }
+    if (w.R8) write_residual_fp8(w, sig, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -817,7 +946,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             }
             __syncthreads();
             if (q < 0) break;
-            // drop position q and append the later positions again, in order
+            // drop position q: downdate the factor (or truncate it and append the later positions again)
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 7), 1ull);
             const int ns_old = nS;
             for (int k = tid; k < ns_old; k += NT) vatom[k] = s.so[k];
@@ -828,10 +957,16 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
                 s.th[u] = 0;
             }
             __syncthreads();
-            nS = q;
-            if (zs) {
+            if (chol_drop(s, ns_old, q)) {
+                // factor downdated in place; support positions past q move down by one
+                for (int k = q + 1 + tid; k < ns_old; k += NT) s.so[k - 1] = vatom[k];
+                nS = ns_old - 1;
+                __syncthreads();
+            } else if (zs) {
+                nS = q;
                 append_list(s, nS, vatom + q + 1, ns_old - q - 1, nullptr, w.n, zs, a.phase ? a.phase + 6 : nullptr);
             } else {
+                nS = q;
                 for (int k = q + 1; k < ns_old; ++k) {
                     const int u = vatom[k];
                     if (!chol_append(s, nS, u, s.th[u], vw, vz, red, a.phase ? a.phase + 6 : nullptr)) {
@@ -937,6 +1072,7 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
         w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
         if (w.rnorm) w.rnorm[sig] = sqrt(rn);
     }
+    if (w.R8) write_residual_fp8(w, sig, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -311,6 +311,116 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     for (int q = s_lim + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
 }
 
+// ---------------------------------------------------------------------------
+// e4m3 ranking.  The e4m3 product only orders the atoms: its error (about 2^-3 of
+// ||a|| ||xi||, far wider than bfloat16's) is too large to certify anything.  The
+// highest-ranked candidates are re-scored exactly (float32 data, float64 sums); the
+// exact violators among them, largest first (ties to the lower index), are admitted,
+// at most k.  A signal with no exact violator among its candidates may have converged
+// or may hide violators the ranking missed: it is flagged for the certified pass.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void rank8_kernel(Rank8Args a)
+{
+    constexpr int CMAX = 64;
+    __shared__ double s_val[CMAX];
+    __shared__ int s_idx[CMAX];
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nc = min(a.ncand[sig], min(a.candcap, CMAX));
+    const float* r = a.R + (int64_t)sig * a.ldr;
+    for (int c = wave; c < nc; c += 4) {
+        const int j = a.cand[(int64_t)sig * a.candcap + c];
+        const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)j * a.lda);
+        const float4* r4 = reinterpret_cast<const float4*>(r);
+        double acc = 0.0;
+        for (int q = lane; q < a.kpad / 4; q += 64) {
+            const float4 x = aj[q], y = r4[q];
+            acc += (double)x.x * y.x + (double)x.y * y.y + (double)x.z * y.z + (double)x.w * y.w;
+        }
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) { s_val[c] = fabs(acc); s_idx[c] = j; }
+    }
+    __syncthreads();
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        const int room = a.max_active - a.nI[sig];
+        k = room < k ? (room > 0 ? room : 0) : k;
+    }
+    const double lam = a.lam[sig];
+    int nsel = 0;
+    double vmx = 0.0;
+    for (int c = 0; c < nc; ++c) {             // every thread, small loops: counts and the maximum
+        vmx = fmax(vmx, s_val[c]);
+        nsel += s_val[c] > lam;
+    }
+    nsel = nsel < k ? nsel : k;
+    if (tid < nc && s_val[tid] > lam) {
+        const double v = s_val[tid];
+        const int j = s_idx[tid];
+        int rank = 0;
+        for (int c = 0; c < nc; ++c)
+            rank += s_val[c] > lam && (s_val[c] > v || (s_val[c] == v && s_idx[c] < j));
+        if (rank < k) a.sel[(int64_t)sig * a.selcap + rank] = j;
+    }
+    if (tid == 0) {
+        a.nsel[sig] = nsel;
+        a.vmax[sig] = (float)vmx;
+        a.cert[sig] = nsel == 0 ? 1 : 0;
+    }
+}
+
+// One workgroup: stable compaction of the flagged signals of a running list.
+__global__ __launch_bounds__(1024) void flag_compact_kernel(const int* act_in, const int* n_in_dev, int n_in,
+                                                            const int* flag, int* act_out, int* n_out_dev)
+{
+    __shared__ int s_wave[16];
+    __shared__ int s_base;
+    const int n = n_in_dev ? *n_in_dev : n_in;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_base = 0;
+    __syncthreads();
+    for (int r0 = 0; r0 < n; r0 += 1024) {
+        const int r = r0 + tid;
+        const int sig = r < n ? (act_in ? act_in[r] : r) : -1;
+        const bool keep = sig >= 0 && flag[sig] != 0;
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) s_wave[wave] = __popcll(bal);
+        __syncthreads();
+        int before = s_base;
+        for (int w2 = 0; w2 < wave; ++w2) before += s_wave[w2];
+        if (keep) act_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = sig;
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int w2 = 0; w2 < 16; ++w2) t += s_wave[w2];
+            s_base += t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *n_out_dev = s_base;
+}
+
+__global__ __launch_bounds__(256) void atoms_fp8_kernel(const float* __restrict__ At, int64_t lda, int kpad,
+                                                        uint8_t* __restrict__ A8, float* __restrict__ ascale, int m)
+{
+    __shared__ float red[4];
+    const int j = blockIdx.x;
+    if (j >= m) return;
+    const float* a = At + (int64_t)j * lda;
+    float mx = 0.f;
+    for (int k = threadIdx.x; k < kpad; k += 256) mx = fmaxf(mx, fabsf(a[k]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    const float s = fp8_pow2_scale(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+    const float inv = 1.0f / s;        // exact: s is a power of two
+    for (int k = threadIdx.x; k < kpad; k += 256) A8[(int64_t)j * kpad + k] = fp8_e4m3(a[k] * inv);
+    if (threadIdx.x == 0) ascale[j] = s;
+}
+
 }  // namespace
 
 hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd, int rows, int cols,
@@ -345,6 +455,30 @@ hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream)
     if (a.p_grid <= 0) return hipSuccess;
     const size_t lds = (size_t)a.candcap_lds * (sizeof(double) + sizeof(float)) + (size_t)a.kpad * sizeof(float);
     hipLaunchKernelGGL(rescore_kernel, dim3(a.p_grid), dim3(256), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank8(const Rank8Args& a, hipStream_t stream)
+{
+    if (a.p_grid <= 0) return hipSuccess;
+    if (a.kpad % 4 || a.lda % 4 || a.ldr % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rank8_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_compact(const int* act_in, const int* n_in_dev, int n_in, const int* flag, int* act_out,
+                               int* n_out_dev, hipStream_t stream)
+{
+    hipLaunchKernelGGL(flag_compact_kernel, dim3(1), dim3(1024), 0, stream, act_in, n_in_dev, n_in, flag, act_out,
+                       n_out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_atoms_fp8(const float* At, int64_t lda, int kpad, uint8_t* A8, float* ascale, int m,
+                            hipStream_t stream)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(atoms_fp8_kernel, dim3(m), dim3(256), 0, stream, At, lda, kpad, A8, ascale, m);
     return hipGetLastError();
 }
 
