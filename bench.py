@@ -31,15 +31,25 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense ma
 PEAK_HBM_GBS = 8000.0
 
 
-def load_traffic(path: str, kernel_src: str):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
+KERNEL_SOURCES = ("paper_1302_5010_amd/csrc/corr_gemm.hip", "paper_1302_5010_amd/csrc/gemm_tile.h")
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the sha256 of the correlation kernel's sources, concatenated."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was taken on these kernel sources."""
     try:
-        import hashlib
         with open(path) as f:
             rec = json.load(f)
-        with open(kernel_src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
-        if rec.get("kernel_sha256_16") != h:
+        if rec.get("kernel_sha256_16") != kernel_source_hash():
             return None
         return rec
     except (OSError, ValueError):
@@ -240,8 +250,7 @@ def main():
     corr_avg_s = tm["corr_ms"] / max(1, tm["corr_launches"]) * 1e-3
     achieved = tm["corr_flops"] / (tm["corr_ms"] * 1e-3) / 1e12 if tm["corr_ms"] > 0 else 0.0
     traffic = None
-    rec = load_traffic(os.path.join(ROOT, "profiles", f"corr_gemm_{args.screen}_{args.workload}_pmc.json"),
-                       os.path.join(ROOT, "paper_1302_5010_amd", "csrc", "corr_gemm.hip"))
+    rec = load_traffic(os.path.join(ROOT, "profiles", f"corr_gemm_{args.screen}_{args.workload}_pmc.json"))
     if rec is not None:
         traffic = rec.get("hbm_bytes_per_launch")
 

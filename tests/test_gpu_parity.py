@@ -173,7 +173,8 @@ def test_relative_lambda_rule():
     check_batch(P.At, P.Bt, lam_or, out, ref)
 
 
-def test_edge_cases():
+@pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
+def test_edge_cases(screen):
     pk = _lib()
     P = bi.small_gaussian()
     lam = lam_rel(P.At, P.Bt, P.lambda_rel)
@@ -182,7 +183,7 @@ def test_edge_cases():
     Bt[5] = 0.0                 # zero signal
     lam2 = lam.copy()
     lam2[9] = np.abs(P.At.astype(np.float64) @ P.Bt[9].astype(np.float64)).max() * 1.01   # lambda above max
-    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, screen=screen)
     out = s.solve(to_dev(Bt), lam=to_dev(lam2))
     st = out["status"].cpu().numpy()
     it = out["iters"].cpu().numpy()
