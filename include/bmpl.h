@@ -78,9 +78,17 @@ typedef enum {
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
 #define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each,
                                        one launch and one read-back per segment (ignored with TIMING) */
+#define BMPL_FLAG_PHASES 16         /* with TIMING: also count the master-problem kernel's phases, factor
+                                       appends, drops and solves (device atomics and clock reads inside the
+                                       kernel, which slow it; the per-kernel times of TIMING alone do not) */
 #define BMPL_FLAG_SINGLE_APPEND 8   /* grow the master problem's inverse Cholesky factor one atom at a
                                        time instead of in blocks of up to 8 (same factor in exact
                                        arithmetic; a diagnostic and comparison switch) */
+
+/* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning): 128x128, 128x256, 256x128,
+ * 64x128, 32x64, 64x64 signals x atoms with 64x64 or 32x32 waves, then 256x256 and 128x256 with
+ * 128x128 and 64x128 waves. */
+#define BMPL_CORR_SHAPES 8
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
  * precomputed Q of Section III, Eq. (12)) when it is at most this large. */
@@ -189,12 +197,14 @@ bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
                         int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev, void* hip_stream);
 
 /*
- * Autotuner of the correlation product: times every tile shape of the float32
- * MFMA kernel on this context's dictionary for three running-signal counts
- * (min(p, 4096), min(p, 128), min(p, 32), representing the buckets >= 512,
- * 64..511 and < 64 running signals) and keeps the fastest shape per bucket in
- * the context; later solves use it.  shapes (3 ints) receives the chosen shape
- * per bucket and ms (3 x 6 doubles, bucket-major) the average milliseconds per
+ * Autotuner of the correlation product: times every tile shape of the MFMA
+ * kernel that runs the outer iterations (float32, bfloat16 or e4m3 by the
+ * context's screening precision) on this context's dictionary for three
+ * running-signal counts (min(p, 4096), min(p, 128), min(p, 32), representing the
+ * buckets >= 512, 64..511 and < 64 running signals) and keeps the fastest shape
+ * per bucket in the context; later solves use it.  shapes (3 ints) receives the
+ * chosen shape per bucket and ms (3 x BMPL_CORR_SHAPES doubles, bucket-major) the
+ * average milliseconds per
  * launch of every shape (-1 where not timed or not launchable); both may be
  * NULL.  Synchronises `hip_stream`.  Errors: BMPL_E_INVALID (NULL context,
  * p < 1), BMPL_E_NOMEM, BMPL_E_HIP.
@@ -202,7 +212,7 @@ bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
 bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, void* hip_stream);
 
 /*
- * Set the correlation tile shape per bucket by hand (3 ints in [0, 6), the
+ * Set the correlation tile shape per bucket by hand (3 ints in [0, BMPL_CORR_SHAPES), the
  * same meaning as bmpl_autotune's `shapes`), e.g. from a cached tuning.
  * Errors: BMPL_E_INVALID for NULL or an out-of-range shape.
  */
@@ -236,7 +246,8 @@ typedef struct {
     double wall_ms;         /* first to last event of each solve, summed */
     int64_t solves;
     int64_t outer_iters;
-    /* master-problem kernel, summed over its workgroups (wall-clock counter, microseconds):
+    /* master-problem kernel, summed over its workgroups (wall-clock counter, microseconds; these and
+     * the three counts below need BMPL_FLAG_PHASES):
      * [0] state load, [1] Gram rows, [2] active-set iterations, [3] certificate on I,
      * [4] of which inside factor appends, [5] state write-back */
     double solve_phase_us[6];

@@ -48,6 +48,8 @@ BMPL_FLAG_TIMING = 1
 BMPL_FLAG_NO_GRAM_TABLE = 2
 BMPL_FLAG_GRAPH = 4
 BMPL_FLAG_SINGLE_APPEND = 8
+BMPL_FLAG_PHASES = 16
+CORR_SHAPES = 8        # BMPL_CORR_SHAPES
 
 
 class _Result(ctypes.Structure):
@@ -150,7 +152,8 @@ class Solver:
 
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
-                 gram_table: bool = True, graph: bool = False, block_append: bool = True, stream=None):
+                 gram_table: bool = True, graph: bool = False, block_append: bool = True, phases: bool = False,
+                 stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
@@ -159,7 +162,8 @@ class Solver:
         o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
-                   | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND))
+                   | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND)
+                   | (BMPL_FLAG_PHASES if phases else 0))
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
         h = ctypes.c_void_p()
@@ -225,13 +229,13 @@ class Solver:
     def autotune(self, p: int, stream=None) -> dict:
         """Time every correlation tile shape for this dictionary; the fastest per bucket is kept."""
         shapes = (ctypes.c_int32 * 3)()
-        ms = (ctypes.c_double * 18)()
+        ms = (ctypes.c_double * (3 * CORR_SHAPES))()
         with torch.cuda.device(self.device):
             _check(_lib.bmpl_autotune(self._h, int(p), shapes, ms, _stream_ptr(stream)), "bmpl_autotune")
-        return {"shapes": list(shapes), "ms": [list(ms[b * 6:(b + 1) * 6]) for b in range(3)]}
+        return {"shapes": list(shapes), "ms": [list(ms[b * CORR_SHAPES:(b + 1) * CORR_SHAPES]) for b in range(3)]}
 
     def set_tuning(self, shapes):
-        """Correlation tile shape per running-signal bucket (>= 512, 64..511, < 64), each in 0..5."""
+        """Correlation tile shape per running-signal bucket (>= 512, 64..511, < 64), each in 0..7."""
         arr = (ctypes.c_int32 * 3)(*[int(v) for v in shapes])
         _check(_lib.bmpl_set_tuning(self._h, arr), "bmpl_set_tuning")
 

@@ -27,7 +27,7 @@ using namespace bmpl;
 namespace {
 
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
-constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 4 rho by default)
+constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 2 rho are used)
 
 }  // namespace
 
@@ -575,7 +575,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const bool tm = timing_on(c);
     c->spans.clear();
     c->ev_used = 0;
-    if (tm && !c->phase_dev) {
+    const bool phases = tm && (c->opt.flags & BMPL_FLAG_PHASES);
+    if (phases && !c->phase_dev) {
         HIPC(dalloc(&c->phase_dev, 9));
         HIPC(hipMemsetAsync(c->phase_dev, 0, 9 * sizeof(uint64_t), s));
         HIPC(hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, c->device));
@@ -674,10 +675,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         a.k = rho; a.sel = w.sel; a.selcap = w.selcap; a.nsel = w.nsel; a.vmax = w.vmax;
         a.nI = w.nI; a.max_active = max_active;
         if (fp8) {
-            // ranking: the 4 rho largest |g~| outside I (zero threshold) ...
+            // ranking: the 2 rho largest |g~| outside I (zero threshold) ...
             SelectArgs r8 = a;
             r8.lam = c->zeros; r8.lam_rel = 0.0;
-            r8.k = std::min(CAND8, 4 * rho); r8.sel = c->cand8; r8.selcap = CAND8; r8.nsel = c->ncand8;
+            r8.k = std::min(CAND8, 2 * rho); r8.sel = c->cand8; r8.selcap = CAND8; r8.nsel = c->ncand8;
             r8.vmax = c->vmax8;
             HIPC(launch_select(r8, q));
             // ... re-scored exactly; the exact violators among them are admitted
@@ -729,7 +730,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
         so.Q = c->Q; so.ldq = c->m;
         so.max_steps = 16 * w.K + 256;
-        so.phase = tm ? c->phase_dev : nullptr;
+        so.phase = phases ? c->phase_dev : nullptr;
         const size_t vec_bytes = vec_area_bytes(w.K);
         so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
         so.kl = std::min(kl, w.K);

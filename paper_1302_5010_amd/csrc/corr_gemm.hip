@@ -15,7 +15,9 @@
 // half-wave (coalesced 128-byte stores).
 //
 // Several tile shapes are instantiated; the host picks one per launch from the
-// number of running signals (autotuned, see bmpl_autotune).
+// number of running signals (autotuned, see bmpl_autotune).  The large-wave shapes
+// (128 x 128 and 64 x 128 per wave) issue more matrix instructions per LDS fragment
+// read, which the short bfloat16 and e4m3 instructions need.
 #include "bmpl_internal.h"
 #include "gemm_tile.h"
 
@@ -134,6 +136,8 @@ hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad
     case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 6: return launch_shape<E, 256, 256, 128, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 7: return launch_shape<E, 128, 256, 64, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -149,6 +153,8 @@ const char* corr_shape_name(int v)
     case 3: return "64x128 (4 waves of 32x64)";
     case 4: return "32x64 (2 waves of 32x32)";
     case 5: return "64x64 (4 waves of 32x32)";
+    case 6: return "256x256 (4 waves of 128x128)";
+    case 7: return "128x256 (4 waves of 64x128)";
     default: return "?";
     }
 }

@@ -60,20 +60,24 @@ def test_correlate_within_float32_bound(n, m, p):
     assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3f}"
 
 
-@pytest.mark.parametrize("shape", range(6))
-def test_correlate_every_tile_shape(shape):
+@pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", range(8))
+def test_correlate_every_tile_shape(shape, screen):
     pk = _lib()
     rng = np.random.default_rng(shape)
     n, m = 160, 1500
     At = rng.standard_normal((m, n)).astype(np.float32)
-    s = pk.Solver(to_dev(At), 0.1)
+    s = pk.Solver(to_dev(At), 0.1, screen=screen)
     s.set_tuning([shape, shape, shape])
     A64 = At.astype(np.float64)
     for p in (1, 37, 600):                 # one row, a ragged tile, several tiles in the >= 512 bucket
         Rt = rng.standard_normal((p, n)).astype(np.float32)
         G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
         R64 = Rt.astype(np.float64)
-        bound = 2 * n * 2.0 ** -24 * (np.abs(R64) @ np.abs(A64).T)
+        if screen == "fp32":
+            bound = 2 * n * 2.0 ** -24 * (np.abs(R64) @ np.abs(A64).T)
+        else:
+            bound = (bf16_band if screen == "bf16" else fp8_band)(At, Rt)
         assert np.all(np.abs(G - R64 @ A64.T) <= bound), (shape, p)
 
 
@@ -159,6 +163,24 @@ def test_block_and_single_appends(n, m, p, k, rho, c, block_append):
     pk = _lib()
     assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
     check_batch(P.At, P.Bt, lam, out, ref)
+
+
+def test_timing_counters():
+    """Kernel timing and master-problem counters are reported and do not change the results."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=256, m=2000, p=64, k=30, sigma=0.01, seed=5, rho=7)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    plain = pk.Solver(to_dev(P.At), 0.0, rho=P.rho).solve(to_dev(P.Bt), lam=to_dev(lam))
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, timing=True, phases=True)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    t = s.timing()
+    assert torch.equal(out["x_idx"], plain["x_idx"]) and torch.equal(out["x_val"], plain["x_val"])
+    assert t["solves"] == 1 and t["corr_launches"] >= int(out["iters"].max()) and t["corr_ms"] > 0
+    assert t["wall_ms"] >= t["corr_ms"] + t["solve_ms"]
+    assert t["corr_flops"] >= 2.0 * P.m * P.n * P.p          # the first pass covers every signal
+    assert t["factor_appends"] >= int(out["supp_len"].sum()) and t["sign_fixed_solves"] > 0
+    s.reset_timing()
+    assert s.timing()["corr_launches"] == 0 and s.timing()["factor_appends"] == 0
 
 
 def test_relative_lambda_rule():
