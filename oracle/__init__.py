@@ -38,11 +38,11 @@ def _load():
     lib.mpl_oracle_solve.restype = ctypes.c_int
     lib.mpl_oracle_solve.argtypes = [_fp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _fp, ctypes.c_int64,
                                      ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                     _dp, ctypes.c_int64, _ip, _dp, _dp, _dp, _dp, _ip, _ip]
+                                     ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp, _dp, _dp, _ip, _ip]
     lib.mpl_oracle_trace.restype = ctypes.c_int
     lib.mpl_oracle_trace.argtypes = [_fp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _fp, ctypes.c_double,
-                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _ip, _dp, _dp, _dp, _dp,
-                                     _ip, _ip, _dp, _ip, _dp, _ip]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _ip, _dp, _dp,
+                                     _dp, _dp, _ip, _ip, _dp, _ip, _dp, _ip]
     lib.mpl_oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -57,8 +57,9 @@ def max_threads() -> int:
 
 
 def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None = None,
-          max_active: int | None = None, nthreads: int = 0) -> dict:
-    """Solve every row of Bt; returns dense X (p, m) float64 and per-signal arrays."""
+          max_active: int | None = None, nthreads: int = 0, omega: int = 1) -> dict:
+    """Solve every row of Bt; returns dense X (p, m) float64 and per-signal arrays.
+    omega > 1 runs subspace exploratory matching (Algorithm 2, SMPL) with omega * rho candidates."""
     lib = _load()
     At = np.ascontiguousarray(At, dtype=np.float32)
     Bt = np.ascontiguousarray(np.atleast_2d(Bt), dtype=np.float32)
@@ -74,8 +75,8 @@ def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None =
     kkt, obj, mar, gap = (np.zeros(p) for _ in range(4))
     st = np.zeros(p, np.int32)
     sl = np.zeros(p, np.int32)
-    rc = lib.mpl_oracle_solve(_ptr(At, _fp), n, n, m, _ptr(Bt, _fp), n, p, _ptr(lam, _dp), rho, max_outer,
-                              max_active, nthreads, _ptr(X, _dp), m, _ptr(it, _ip), _ptr(kkt, _dp),
+    rc = lib.mpl_oracle_solve(_ptr(At, _fp), n, n, m, _ptr(Bt, _fp), n, p, _ptr(lam, _dp), rho, omega,
+                              max_outer, max_active, nthreads, _ptr(X, _dp), m, _ptr(it, _ip), _ptr(kkt, _dp),
                               _ptr(obj, _dp), _ptr(mar, _dp), _ptr(gap, _dp), _ptr(st, _ip), _ptr(sl, _ip))
     if rc != 0:
         raise ValueError("mpl_oracle_solve rejected its arguments")
@@ -84,7 +85,7 @@ def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None =
 
 
 def trace(At: np.ndarray, b: np.ndarray, lam: float, rho: int, max_outer: int | None = None,
-          max_active: int | None = None) -> dict:
+          max_active: int | None = None, omega: int = 1) -> dict:
     """One signal, with the objective after every outer iteration and the atoms added."""
     lib = _load()
     At = np.ascontiguousarray(At, dtype=np.float32)
@@ -103,7 +104,7 @@ def trace(At: np.ndarray, b: np.ndarray, lam: float, rho: int, max_outer: int | 
     added = np.full(max(1, max_outer * rho), -1, np.int32)
     gsel = np.zeros(max(1, max_outer * rho))
     nadd = np.zeros(max(1, max_outer), np.int32)
-    rc = lib.mpl_oracle_trace(_ptr(At, _fp), n, n, m, _ptr(b, _fp), float(lam), rho, max_outer, max_active,
+    rc = lib.mpl_oracle_trace(_ptr(At, _fp), n, n, m, _ptr(b, _fp), float(lam), rho, omega, max_outer, max_active,
                               _ptr(x, _dp), _ptr(it, _ip), _ptr(kkt, _dp), _ptr(obj, _dp), _ptr(mar, _dp),
                               _ptr(gap, _dp), _ptr(st, _ip), _ptr(sl, _ip), _ptr(ot, _dp), _ptr(added, _ip),
                               _ptr(gsel, _dp), _ptr(nadd, _ip))

@@ -21,6 +21,11 @@
  *      the "Stopping Conditions" subsection (checked here outside I to a
  *      relative 1e-12, since atoms inside I satisfy it through step 3).
  * Without early stopping the result is the LASSO solution (same subsection).
+ * With omega > 1, step 2 becomes subspace exploratory matching (Algorithm 2,
+ * SMPL): the omega*rho largest violators J_omega enter, the master problem is
+ * solved on I u J_omega, the rho atoms of J_omega with the largest |u_j| (ties
+ * to the lower index) form J_t and the others leave I; step 3 then solves on
+ * I_t warm-started from u restricted to I_t.
  *
  * The paper solves the master problem with proximal gradient (lambda > 0) or
  * conjugate gradient (lambda = 0) to a small tolerance.  This oracle solves it
@@ -369,8 +374,39 @@ static double objective(const sig_state* st)
 }
 
 /* Solve one signal; results go to the output slots of signal `col`. */
+/* Subspace exploratory matching (Algorithm 2): of the atoms J_omega appended since slot `first`
+ * (after the master problem on I u J_omega was solved), keep the `keep` with the largest |u_j|, ties to
+ * the lower atom index, in their selection order; the others leave I.  The kept atoms are appended
+ * again (fresh Gram rows and c) with their u values, the old slots keep theirs. */
+static void smpl_prune(sig_state* st, int first, int keep)
+{
+    int nj = st->nI - first;
+    if (nj <= keep) return;
+    int* atoms = (int*)malloc(sizeof(int) * nj);
+    double* u = (double*)malloc(sizeof(double) * nj);
+    unsigned char* kept = (unsigned char*)calloc(nj, 1);
+    for (int q = 0; q < nj; ++q) { atoms[q] = st->I[first + q]; u[q] = st->x[first + q]; }
+    for (int r = 0; r < keep; ++r) {          /* r-th largest |u|, ties to the lower atom index */
+        int best = -1;
+        for (int q = 0; q < nj; ++q) {
+            if (kept[q]) continue;
+            if (best < 0 || fabs(u[q]) > fabs(u[best]) || (fabs(u[q]) == fabs(u[best]) && atoms[q] < atoms[best]))
+                best = q;
+        }
+        kept[best] = 1;
+    }
+    for (int q = 0; q < nj; ++q) st->inI[atoms[q]] = 0;
+    st->nI = first;
+    for (int q = 0; q < nj; ++q) {
+        if (!kept[q]) continue;
+        append_atom(st, atoms[q]);
+        st->x[st->nI - 1] = u[q];
+    }
+    free(atoms); free(u); free(kept);
+}
+
 static void solve_one(const float* A, int64_t lda, int n, int m, const float* b, double lam,
-                      int rho, int max_outer, int max_active,
+                      int rho, int omega, int max_outer, int max_active,
                       double* xdense, int* iters, double* kkt, double* obj, double* margin,
                       double* gap, int* status, int* supp_len, trace_t* tr)
 {
@@ -403,10 +439,12 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
         if (st.nI >= max_active) { stat |= ST_CAP_ACTIVE; break; }
         int want = rho;
         if (st.nI + want > max_active) want = max_active - st.nI;
-        if (grow(&st, st.nI + want) != 0) { stat |= ST_INEXACT; break; }
-        /* J_t: the largest |g_j| outside I that exceed lambda, ties to the lower index. */
+        const int explore = omega > 1 ? omega * want : want;   /* SMPL: omega rho candidates (Algorithm 2) */
+        if (grow(&st, st.nI + explore) != 0) { stat |= ST_INEXACT; break; }
+        const int first = st.nI;
+        /* J_t (or J_omega): the largest |g_j| outside I that exceed lambda, ties to the lower index. */
         int nsel = 0;
-        for (int q = 0; q < want; ++q) {
+        for (int q = 0; q < explore; ++q) {
             int best = -1;
             double bv = lam;
             for (int j = 0; j < m; ++j) {
@@ -415,14 +453,22 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
                 if (v > bv) { bv = v; best = j; }
             }
             if (best < 0) break;
-            if (tr) {
-                tr->added[t * rho + nsel] = best;
-                tr->gsel[t * rho + nsel] = st.g[best];
-            }
             append_atom(&st, best);
             ++nsel;
         }
-        if (tr) tr->nadd[t] = nsel;
+        if (omega > 1 && nsel > want) {
+            /* exploratory master problem on I u J_omega, then keep the `want` atoms with the largest |u| */
+            stat |= master_solve(&st);
+            smpl_prune(&st, first, want);
+            nsel = st.nI - first;
+        }
+        if (tr) {
+            for (int q = 0; q < nsel; ++q) {
+                tr->added[t * rho + q] = st.I[first + q];
+                tr->gsel[t * rho + q] = st.g[st.I[first + q]];
+            }
+            tr->nadd[t] = nsel;
+        }
         stat |= master_solve(&st);
         residual(&st);
         ++t;
@@ -465,7 +511,7 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
     free_state(&st);
 }
 
-int mpl_oracle_abi_version(void) { return 1; }
+int mpl_oracle_abi_version(void) { return 2; }
 
 /*
  * Batch solve: p independent signals (Eq. (3)), one per OpenMP thread.
@@ -474,19 +520,19 @@ int mpl_oracle_abi_version(void) { return 1; }
  * Per-signal outputs are arrays of length p.  Returns 0, or -1 on bad arguments.
  */
 int mpl_oracle_solve(const float* At, int64_t lda, int n, int m, const float* Bt, int64_t ldb,
-                     int p, const double* lam, int rho, int max_outer, int max_active, int nthreads,
+                     int p, const double* lam, int rho, int omega, int max_outer, int max_active, int nthreads,
                      double* X, int64_t ldx, int* iters, double* kkt, double* obj, double* margin,
                      double* gap, int* status, int* supp_len)
 {
     if (!At || !Bt || !lam || !X || n <= 0 || m <= 0 || p < 0 || lda < n || ldb < n || ldx < m
-        || rho <= 0 || max_outer < 0 || max_active <= 0)
+        || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0)
         return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int i = 0; i < p; ++i)
-        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, max_outer, max_active,
+        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, omega, max_outer, max_active,
                   X + (size_t)i * ldx, iters + i, kkt + i, obj + i, margin + i, gap + i,
                   status + i, supp_len + i, NULL);
     return 0;
@@ -508,14 +554,14 @@ int mpl_oracle_max_threads(void)
  * max_outer + 1 (obj), max_outer * rho (added, gsel) and max_outer (nadd).
  */
 int mpl_oracle_trace(const float* At, int64_t lda, int n, int m, const float* b, double lam,
-                     int rho, int max_outer, int max_active, double* x, int* iters, double* kkt,
+                     int rho, int omega, int max_outer, int max_active, double* x, int* iters, double* kkt,
                      double* objv, double* margin, double* gap, int* status, int* supp_len,
                      double* obj_trace, int* added, double* gsel, int* nadd)
 {
-    if (!At || !b || !x || n <= 0 || m <= 0 || lda < n || rho <= 0 || max_outer < 0 || max_active <= 0)
+    if (!At || !b || !x || n <= 0 || m <= 0 || lda < n || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0)
         return -1;
     trace_t tr = { obj_trace, added, gsel, nadd, max_outer };
-    solve_one(At, lda, n, m, b, lam, rho, max_outer, max_active, x, iters, kkt, objv, margin, gap,
+    solve_one(At, lda, n, m, b, lam, rho, omega, max_outer, max_active, x, iters, kkt, objv, margin, gap,
               status, supp_len, &tr);
     return 0;
 }

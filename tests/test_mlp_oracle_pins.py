@@ -146,3 +146,34 @@ def test_loss_decreases_under_plain_gradient_descent():
         assert l1 < loss0
         # first-order prediction
         assert (loss0 - l1) == pytest.approx(lr * g @ g, rel=0.05)
+
+
+def test_src_classification_reference():
+    """Class-residual rule: exact single-class reconstructions, the empty support, ties, relabelling."""
+    from oracle import src_oracle as so
+    rng = np.random.default_rng(2)
+    n, per, classes = 30, 4, 5
+    A = rng.standard_normal((classes * per, n))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    A[9] = 0.0
+    A[9, 0] = 1.0                           # two exactly representable atoms for an exact tie
+    A[17] = 0.0
+    A[17, 1] = 1.0
+    cls = np.repeat(np.arange(classes), per)
+    X = np.zeros((4, classes * per))
+    X[0, 4:6] = [1.0, -2.0]                 # class 1 only: b reconstructed exactly
+    X[1, [1, 13]] = [3.0, 0.1]              # mostly class 0, a little class 3
+    X[2, 9] = 1.0                           # two classes explain b equally well (see below)
+    X[2, 17] = 1.0
+    B = X @ A
+    B[1] += 0.01 * rng.standard_normal(n)
+    B[2] = A[9] + A[17]                     # b = a_9 + a_17: both single-class residuals have norm 1
+    lab, res = so.classify(A, B, X, cls)
+    assert lab[0] == 1 and res[0] < 1e-12
+    assert lab[1] == 0
+    assert lab[2] == 2 and abs(res[2] - 1.0) < 1e-12      # tie between classes 2 and 4 -> the lower
+    assert lab[3] == -1 and np.isnan(res[3])               # empty support
+    # relabelling classes permutes the labels the same way
+    perm = np.array([3, 0, 4, 1, 2])
+    lab2, _ = so.classify(A, B, X, perm[cls])
+    assert lab2[0] == perm[1] and lab2[1] == perm[0] and lab2[3] == -1

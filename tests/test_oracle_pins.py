@@ -313,3 +313,57 @@ def test_caps_and_nonfinite():
     Bt[1, 5] = np.nan
     r = oracle.solve(P.At, Bt, lam, P.rho)
     assert r["status"][1] == oracle.ST_NONFINITE and r["status"][0] == oracle.ST_CONVERGED
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_smpl_reaches_the_lasso_solution(seed):
+    """Subspace exploratory matching (Algorithm 2) changes the path, not the answer: the unique LASSO
+    solution, certified by its optimality conditions, and the MPL result to solver precision."""
+    P = bi.tiny_gaussian(n=48, m=300, p=6, k=8, sigma=0.01, seed=seed, lambda_rel=0.05, rho=3)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    mpl = oracle.solve(P.At, P.Bt, lam, P.rho)
+    smpl = oracle.solve(P.At, P.Bt, lam, P.rho, omega=3)
+    assert np.all(smpl["status"] == oracle.ST_CONVERGED)
+    for i in range(P.p):
+        off, on = kkt_residuals(P.At, P.Bt[i], smpl["X"][i], lam[i])
+        assert off <= 1e-9 * lam[i] and on <= 1e-9 * lam[i]
+        np.testing.assert_allclose(smpl["X"][i], mpl["X"][i], rtol=0, atol=1e-9 * np.abs(mpl["X"][i]).max())
+
+
+def test_smpl_brute_force_and_monotone_objective():
+    """On m = 10 the SMPL result is the brute-force LASSO minimiser; per outer iteration the objective
+    never increases (atoms are never removed from I_t once kept), at most rho atoms are kept."""
+    for seed in range(4):
+        P = bi.tiny_gaussian(n=6, m=10, p=1, k=3, sigma=0.05, seed=200 + seed, lambda_rel=0.1, rho=2)
+        lam = lam_rel(P.At, P.Bt, P.lambda_rel)[0]
+        sols = brute_force_lasso(P.At, P.Bt[0], lam)
+        assert len(sols) == 1
+        tr = oracle.trace(P.At, P.Bt[0], lam, 2, omega=3)
+        np.testing.assert_allclose(tr["x"], sols[0], atol=1e-10)
+        ob = tr["obj_trace"]
+        assert np.all(np.diff(ob) <= 1e-12 * ob[0])
+        assert all(len(a) <= 2 for a, _ in tr["steps"])
+
+
+def test_smpl_keeps_the_atom_with_the_largest_restricted_coefficient():
+    """First SMPL iteration with rho = 1, omega = 3, checked by brute force: J_omega = the three largest
+    |a_j^T b| (all violating), u = the LASSO minimiser restricted to J_omega (enumeration), and the atom
+    kept must be the one with the largest |u_j|."""
+    checked = 0
+    for seed in range(12):
+        P = bi.tiny_gaussian(n=8, m=40, p=1, k=3, sigma=0.05, seed=300 + seed, lambda_rel=0.2, rho=1)
+        b = P.Bt[0]
+        g = P.At.astype(np.float64) @ b.astype(np.float64)
+        lam = 0.2 * np.abs(g).max()
+        order = np.lexsort((np.arange(P.m), -np.abs(g)))
+        J = order[:3]
+        if np.abs(g[J]).min() <= lam:
+            continue                      # fewer than three violators: not this case
+        u = brute_force_lasso(P.At[J], b, lam)
+        assert len(u) == 1
+        u = u[0]
+        kept = J[np.lexsort((J, -np.abs(u)))[0]]
+        tr = oracle.trace(P.At, b, lam, 1, omega=3)
+        assert list(tr["steps"][0][0]) == [kept]
+        checked += 1
+    assert checked >= 4
