@@ -93,6 +93,39 @@ def screened_measurement(args, pk, torch, At, Bt, P, screen: str) -> dict:
     }
 
 
+def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma) -> dict:
+    """Section III's correlation (g = beta - Q_{:,S} x_S, float64, HBM-bound on Q's rows) in place of the
+    MFMA product, same workload: throughput and the correlation time per step against the MFMA's."""
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, q_route=True)
+    for _ in range(args.warmup):
+        s.solve(Bt)
+    torch.cuda.synchronize()
+    solved = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solved.append(s.solve(Bt)["status"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    conv = [int(((st & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for st in solved]
+    del s
+    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, q_route=True)
+    st.solve(Bt)
+    torch.cuda.synchronize()
+    st.reset_timing()
+    for _ in range(args.steps):
+        st.solve(Bt)
+    torch.cuda.synchronize()
+    tq = st.timing()
+    return {"value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
+            "converged_per_step": conv,
+            "correlation_ms_per_step": tq["corr_ms"] / args.steps,
+            "mfma_correlation_ms_per_step": tm_mfma["corr_ms"] / args.steps,
+            "note": "the first pass (lambda rule) stays the MFMA product in both; the Q-route adds the float64 "
+                    "beta = A^T b at set-up (in other_ms)",
+            "kernel_ms_per_step": {k: tq[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms", "residual_ms",
+                                                                    "other_ms", "wall_ms")}}
+
+
 def learned_comparison(args, pk, torch) -> dict:
     """Plain FP32, plain BF16-screened and BF16-screened + learned warm start on the face-like
     dictionary (1024 x 20000, 200 classes of rank-8 subspaces), lambda_i = 0.01 ||A^T b_i||_inf,
@@ -132,6 +165,16 @@ def learned_comparison(args, pk, torch) -> dict:
     bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
     bf.autotune(P.p)
     outbf, rec["plain_bf16"] = timed(lambda: bf.solve(Bt))
+    # the face application: class-residual classification of the codes (synthetic classes)
+    cls = torch.from_numpy(P.meta["class_of_atom"].astype(np.int32)).to(dev)
+    labels, _ = bf.classify(Bt, outbf, cls)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    labels, _ = bf.classify(Bt, outbf, cls)
+    torch.cuda.synchronize()
+    truth = np.array([s[0] // P.meta["per_class"] for s in P.supports])
+    rec["src_classification"] = {"recognition_rate": float(np.mean(labels.cpu().numpy() == truth)),
+                                 "ms": (time.perf_counter() - t0) * 1e3, "classes": P.meta["classes"]}
 
     # training data: BMPL supports of signals from a distinct seed stream
     t0 = time.perf_counter()
@@ -311,6 +354,7 @@ def main():
         # exact re-score) and e4m3 ranking (exact re-score of the top candidates, bfloat16 certification).
         result["bf16_screened"] = screened_measurement(args, pk, torch, At, Bt, P, "bf16")
         result["fp8_ranked"] = screened_measurement(args, pk, torch, At, Bt, P, "fp8")
+        result["q_route"] = q_route_measurement(args, pk, torch, At, Bt, P, tm)
 
     if not args.no_learned:
         result["learned"] = learned_comparison(args, pk, torch)

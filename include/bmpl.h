@@ -78,6 +78,10 @@ typedef enum {
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
 #define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each,
                                        one launch and one read-back per segment (ignored with TIMING) */
+#define BMPL_FLAG_Q_ROUTE 32        /* Section III's batch correlation, Eq. (12): after the first pass,
+                                       g = beta - Q_{:,S} x_S with beta = A^T b (float64, computed once
+                                       per solve) and the float64 Gram table, instead of the MFMA product
+                                       A^T xi; needs the Gram table and the float32 screen */
 #define BMPL_FLAG_PHASES 16         /* with TIMING: also count the master-problem kernel's phases, factor
                                        appends, drops and solves (device atomics and clock reads inside the
                                        kernel, which slow it; the per-kernel times of TIMING alone do not) */
@@ -195,6 +199,23 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
 bmpl_status bmpl_select(bmpl_ctx* c, const float* G_dev, int64_t ldg, int32_t p,
                         const double* lambda_dev, const uint32_t* excl_dev, int32_t k,
                         int32_t* sel_dev, int32_t* nsel_dev, float* vmax_dev, void* hip_stream);
+
+/*
+ * Sparse-representation classification, the face-recognition use of the solver
+ * (Section V follows the class-residual rule of sparse-representation-based
+ * classification): for signal i (B column-major, ldb >= n) with the code of
+ * `sol` (x_idx / x_val / supp_len / ld_x as filled by bmpl_solve), every class c
+ * with an atom in the support is scored by ||b_i - A delta_c(x_i)||_2, where
+ * delta_c keeps the coefficients of the atoms j with class_of_atom_dev[j] == c
+ * (device int32 array of m class indices >= 0).  labels_dev[i] receives the
+ * class with the smallest residual (ties to the lower class index; -1 for an
+ * empty support) and resid_dev[i] (optional, float64) that residual.  Float64
+ * sums from the float32 data; asynchronous on hip_stream.
+ * Errors: BMPL_E_INVALID.
+ */
+bmpl_status bmpl_classify(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, const bmpl_result* sol,
+                          const int32_t* class_of_atom_dev, int32_t* labels_dev, double* resid_dev,
+                          void* hip_stream);
 
 /*
  * Autotuner of the correlation product: times every tile shape of the MFMA

@@ -49,6 +49,7 @@ BMPL_FLAG_NO_GRAM_TABLE = 2
 BMPL_FLAG_GRAPH = 4
 BMPL_FLAG_SINGLE_APPEND = 8
 BMPL_FLAG_PHASES = 16
+BMPL_FLAG_Q_ROUTE = 32
 CORR_SHAPES = 8        # BMPL_CORR_SHAPES
 
 
@@ -88,6 +89,7 @@ def _load():
     lib.bmpl_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
     lib.bmpl_set_tuning.argtypes = [vp, ctypes.POINTER(i32)]
     lib.bmpl_reset_timing.argtypes = [vp]
+    lib.bmpl_classify.argtypes = [vp, vp, i64, i32, ctypes.POINTER(_Result), vp, vp, vp, vp]
     lib.bmpl_mlp_param_count.argtypes = [i32, i32, i32]
     lib.bmpl_mlp_param_count.restype = i64
     lib.bmpl_mlp_create.argtypes = [vp, i64, i32, i32, vp, i32, i32, i32, vp, ctypes.POINTER(vp)]
@@ -104,7 +106,7 @@ def _load():
               "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table", "bmpl_autotune",
               "bmpl_set_tuning", "bmpl_mlp_create", "bmpl_mlp_destroy", "bmpl_mlp_set_params",
               "bmpl_mlp_get_params", "bmpl_mlp_embed", "bmpl_mlp_forward", "bmpl_mlp_loss_grad",
-              "bmpl_mlp_adam_step", "bmpl_mlp_propose", "bmpl_topk"):
+              "bmpl_mlp_adam_step", "bmpl_mlp_propose", "bmpl_topk", "bmpl_classify"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -153,7 +155,7 @@ class Solver:
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
                  gram_table: bool = True, graph: bool = False, block_append: bool = True, phases: bool = False,
-                 stream=None):
+                 q_route: bool = False, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
@@ -163,7 +165,7 @@ class Solver:
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
                    | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND)
-                   | (BMPL_FLAG_PHASES if phases else 0))
+                   | (BMPL_FLAG_PHASES if phases else 0) | (BMPL_FLAG_Q_ROUTE if q_route else 0))
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)
         h = ctypes.c_void_p()
@@ -225,6 +227,23 @@ class Solver:
                                    ctypes.byref(r), _stream_ptr(stream)), "bmpl_solve")
         out["_keep"] = (Bt, lam, warm)
         return out
+
+    def classify(self, Bt: torch.Tensor, out: dict, class_of_atom: torch.Tensor, stream=None):
+        """Class-residual labels (p,) int32 and winning residual norms (p,) float64 for the codes in
+        ``out`` (a result of :meth:`solve` on the same ``Bt``); ``class_of_atom`` (m,) int32."""
+        Bt = _dev(Bt, torch.float32, "Bt")
+        cls = _dev(class_of_atom, torch.int32, "class_of_atom")
+        if cls.numel() != self.m:
+            raise BmplError("class_of_atom must hold one class per atom")
+        p = Bt.shape[0]
+        labels = torch.empty(p, dtype=torch.int32, device=Bt.device)
+        resid = torch.empty(p, dtype=torch.float64, device=Bt.device)
+        r = _Result(out["x_val"].data_ptr(), out["x_idx"].data_ptr(), out["supp_len"].data_ptr(), None, None, None,
+                    None, None, out["x_idx"].shape[1])
+        with torch.cuda.device(Bt.device):
+            _check(_lib.bmpl_classify(self._h, Bt.data_ptr(), Bt.shape[1], p, ctypes.byref(r), cls.data_ptr(),
+                                      labels.data_ptr(), resid.data_ptr(), _stream_ptr(stream)), "bmpl_classify")
+        return labels, resid
 
     def autotune(self, p: int, stream=None) -> dict:
         """Time every correlation tile shape for this dictionary; the fastest per bucket is kept."""

@@ -19,8 +19,10 @@
 
 #include "../../include/bmpl.h"
 #include "bmpl_internal.h"
+#include "classify.h"
 #include "host_util.h"
 #include "pursuit.h"
+#include "qroute.h"
 
 using namespace bmpl;
 
@@ -52,6 +54,8 @@ struct bmpl_ctx {
     uint16_t* diag16 = nullptr;   // bfloat16 staging of bmpl_correlate
     size_t lds_dyn_max = 0;       // dynamic LDS a solve workgroup may use (bytes)
     bool block_append = true;     // inverse-factor appends in blocks (BMPL_FLAG_SINGLE_APPEND clears it)
+    bool qroute = false;          // correlation as beta - Q_{:,S} x_S after the first pass (BMPL_FLAG_Q_ROUTE)
+    double* beta = nullptr;       // [p_cap][ldg] beta = A^T b in float64 (Q-route)
     bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
     double lambda = 0.0;
     bmpl_options opt{};
@@ -193,6 +197,7 @@ void free_signals(bmpl_ctx* c)
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
     dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
     dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
+    dfree(c->beta);
     c->p_cap = 0;
     c->K_cap = 0;
 }
@@ -231,6 +236,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
         HIPC(dalloc(&c->cand, P * CANDCAP_DEF));
         HIPC(dalloc(&c->ncand, P));
     }
+    if (c->qroute) HIPC(dalloc(&c->beta, P * (size_t)c->ldg));
     if (c->opt.screen == BMPL_PREC_FP8) {
         HIPC(dalloc(&w.R8, (P + 1) * c->kpad));
         HIPC(hipMemset(w.R8 + P * c->kpad, 0, c->kpad));
@@ -421,6 +427,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     c->block_append = !(opt.flags & BMPL_FLAG_SINGLE_APPEND);
+    c->qroute = (opt.flags & BMPL_FLAG_Q_ROUTE) != 0;
     // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
     const double q_bytes = 8.0 * (double)m * (double)m;
     if (e == hipSuccess && !(opt.flags & BMPL_FLAG_NO_GRAM_TABLE) && q_bytes <= BMPL_GRAM_TABLE_MAX_BYTES) {
@@ -428,6 +435,11 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         if (e == hipSuccess) e = launch_gram_table(c->At, c->kpad, m, c->kpad, c->Q, m, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && c->qroute && (!c->Q || opt.screen != BMPL_PREC_FP32)) {
+        bmpl_destroy(c);
+        return fail(BMPL_E_UNSUPPORTED, "bmpl_create: the Q-route needs the Gram table (at most %.0f bytes, not "
+                                        "disabled) and the float32 screen", (double)BMPL_GRAM_TABLE_MAX_BYTES);
+    }
     if (e == hipSuccess) {
         int per_block = 0, optin = 0;
         hipFuncAttributes fa{};
@@ -585,6 +597,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     PrepArgs pa{w, B_dev, ldb, c->Bw, lambda_dev, c->lambda, rel ? 1 : 0};
     hipLaunchKernelGGL(prep_kernel, dim3(p), dim3(256), 0, s, pa);
     HIPC(hipGetLastError());
+    if (c->qroute) HIPC(launch_atb_f64(c->At, c->kpad, c->m, c->Bw, c->kpad, p, c->n, c->beta, c->ldg, s));
 
     StatusArgs sa{};
     sa.w = w; sa.act_in = nullptr; sa.n_in_dev = nullptr; sa.n_in = p;
@@ -634,11 +647,18 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             }
             return gemm(c->corr_variant(n_grid), n_grid, 0, 1 << 30);
         };
-        HIPC(product(fp8 ? 2 : (c->A16 ? 1 : 0), c->act[cur], c->n_act_dev + cur, gated));
+        const bool qr = c->qroute && !first;
+        if (qr) {
+            QCorrArgs qa{w, c->Q, c->m, c->beta, c->ldg, c->act[cur], c->n_act_dev + cur, n_grid, c->Gc, c->ldg};
+            HIPC(launch_q_corr(qa, q));
+        } else {
+            HIPC(product(fp8 ? 2 : (c->A16 ? 1 : 0), c->act[cur], c->n_act_dev + cur, gated));
+        }
         if (ev) {
             const double mm = c->m, nn = c->n, pp = n_grid;
             const size_t e1 = mark(c, q);
-            span(c, e0, e1, K_CORR, 2.0 * mm * nn * pp, 4.0 * (mm * nn + nn * pp + mm * pp));
+            // the Q-route's work depends on the supports: its time is kept, its flops are not counted
+            span(c, e0, e1, K_CORR, qr ? 0.0 : 2.0 * mm * nn * pp, qr ? 0.0 : 4.0 * (mm * nn + nn * pp + mm * pp));
             e0 = e1;
         }
         // certified bfloat16 screening of a list: band test, candidates, exact re-score and selection
@@ -831,6 +851,25 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         HIPC(hipStreamSynchronize(s));
         fold_timing(c, ev_first, e_last);
     }
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_classify(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, const bmpl_result* sol,
+                          const int32_t* class_of_atom_dev, int32_t* labels_dev, double* resid_dev, void* hip_stream)
+{
+    if (!c || !sol) return fail(BMPL_E_INVALID, "bmpl_classify: NULL context or solution");
+    if (p < 0 || ldb < c->n) return fail(BMPL_E_INVALID, "bmpl_classify: bad p=%d or ldb=%lld", p, (long long)ldb);
+    if (p == 0) return BMPL_OK;
+    if (!B_dev || !class_of_atom_dev || !labels_dev || !sol->x_idx_dev || !sol->x_val_dev || !sol->supp_len_dev ||
+        sol->ld_x < 1)
+        return fail(BMPL_E_INVALID, "bmpl_classify: signals, classes, labels and the solution's x_idx, x_val, "
+                                    "supp_len (ld_x >= 1) are required");
+    ClassifyArgs a{};
+    a.At = c->At; a.lda = c->kpad; a.n = c->n; a.m = c->m;
+    a.B = B_dev; a.ldb = ldb; a.p = p;
+    a.x_idx = sol->x_idx_dev; a.x_val = sol->x_val_dev; a.supp_len = sol->supp_len_dev; a.ld_x = sol->ld_x;
+    a.class_of_atom = class_of_atom_dev; a.labels = labels_dev; a.resid = resid_dev;
+    HIPC(launch_classify(a, reinterpret_cast<hipStream_t>(hip_stream)));
     return BMPL_OK;
 }
 

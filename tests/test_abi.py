@@ -102,3 +102,9 @@ def test_proposal_argument_errors_without_gpu(lib):
     assert lib.bmpl_topk(fake, 50000, 1, 50000, 8, fake, 8, None) == -1  # row too long
     lib.bmpl_mlp_adam_step.argtypes = [vp, vp, vp, vp]
     assert lib.bmpl_mlp_adam_step(None, None, None, None) == -1
+
+
+def test_classify_argument_errors_without_gpu(lib):
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.bmpl_classify.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp]
+    assert lib.bmpl_classify(None, None, 4, 1, None, None, None, None, None) == -1

@@ -605,3 +605,66 @@ def test_face_like_sampled(screen):
         mass = np.bincount(cls[S], weights=np.abs(Xg[i][S]), minlength=int(cls.max()) + 1)
         true_cls = P.supports[i][0] // 100
         assert np.argmax(mass) == true_cls and mass[true_cls] >= 0.99 * mass.sum()
+
+
+def test_src_classification_face_like():
+    """Class-residual classification of the face-like signals from the GPU codes: labels and residuals
+    against the float64 reference on the same codes (sampled), and the recognition rate."""
+    pk = _lib()
+    from oracle import src_oracle
+    P = bi.face_like(indices=range(2048))
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho, screen="bf16", graph=True)
+    Bt = to_dev(P.Bt)
+    out = s.solve(Bt)
+    cls = P.meta["class_of_atom"].astype(np.int32)
+    labels, resid = s.classify(Bt, out, to_dev(cls))
+    labels = labels.cpu().numpy()
+    resid = resid.cpu().numpy()
+    rows = list(range(0, P.p, 16))
+    X = dense_from_gpu({k: out[k][rows] for k in ("x_idx", "x_val", "supp_len")}, P.m)
+    lab_ref, res_ref = src_oracle.classify(P.At, P.Bt[rows], X, cls)
+    np.testing.assert_array_equal(labels[rows], lab_ref)
+    np.testing.assert_allclose(resid[rows], res_ref, rtol=1e-9)
+    truth = np.array([P.supports[i][0] // 100 for i in range(P.p)])
+    acc = float(np.mean(labels == truth))
+    print(f"recognition rate {acc:.4f}")
+    assert acc >= 0.99
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_q_route_parity(graph):
+    """Section III's correlation g = beta - Q_{:,S} x_S (float64) in place of the MFMA product."""
+    pk = _lib()
+    for P in (bi.small_gaussian(), bi.tiny_gaussian(n=256, m=2000, p=257, k=30, sigma=0.01, seed=91, rho=7),
+              bi.tiny_gaussian(n=320, m=3000, p=100, k=50, sigma=0.01, seed=650, lambda_rel=0.03, rho=10)):
+        lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+        s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, q_route=True, graph=graph)
+        out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+        st = out["status"].cpu().numpy()
+        assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+        ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+        check_batch(P.At, P.Bt, lam, out, ref)
+
+
+def test_q_route_needs_the_gram_table():
+    pk = _lib()
+    P = bi.small_gaussian()
+    with pytest.raises(pk.BmplError):
+        pk.Solver(to_dev(P.At), 0.1, q_route=True, gram_table=False)
+    with pytest.raises(pk.BmplError):
+        pk.Solver(to_dev(P.At), 0.1, q_route=True, screen="bf16")
+
+
+@pytest.mark.slow
+def test_cs_gaussian_q_route_full_size_sampled():
+    pk = _lib()
+    P = bi.cs_gaussian()
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), P.lambda_rel, mode="rel", rho=P.rho, q_route=True, graph=True)
+    out = s.solve(to_dev(P.Bt))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED)
+    rows = list(range(3, P.p, 61))
+    ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
+    check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
