@@ -126,6 +126,27 @@ def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma) -> dict:
                                                                     "other_ms", "wall_ms")}}
 
 
+def smpl_measurement(args, pk, torch, At, Bt, P, out_mpl) -> dict:
+    """Subspace exploratory matching (Algorithm 2, omega = 3) on the same workload: throughput and
+    outer iterations against plain MPL's."""
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, omega=3)
+    s.autotune(P.p)
+    for _ in range(args.warmup):
+        s.solve(Bt)
+    torch.cuda.synchronize()
+    solved = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solved.append(s.solve(Bt))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    conv = [int(((o["status"] & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for o in solved]
+    return {"omega": 3, "value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
+            "converged_per_step": conv,
+            "iters_mean": float(solved[-1]["iters"].float().mean().item()),
+            "mpl_iters_mean": float(out_mpl["iters"].float().mean().item())}
+
+
 def learned_comparison(args, pk, torch) -> dict:
     """Plain FP32, plain BF16-screened and BF16-screened + learned warm start on the face-like
     dictionary (1024 x 20000, 200 classes of rank-8 subspaces), lambda_i = 0.01 ||A^T b_i||_inf,
@@ -355,6 +376,7 @@ def main():
         result["bf16_screened"] = screened_measurement(args, pk, torch, At, Bt, P, "bf16")
         result["fp8_ranked"] = screened_measurement(args, pk, torch, At, Bt, P, "fp8")
         result["q_route"] = q_route_measurement(args, pk, torch, At, Bt, P, tm)
+        result["smpl"] = smpl_measurement(args, pk, torch, At, Bt, P, out)
 
     if not args.no_learned:
         result["learned"] = learned_comparison(args, pk, torch)

@@ -105,6 +105,11 @@ typedef struct {
     double kkt_tol;         /* certificate tolerance relative to lambda_i; default 1e-4 */
     bmpl_precision screen;  /* precision of the correlation product; default FP32 */
     int32_t flags;          /* BMPL_FLAG_* bits; default 0 */
+    int32_t omega;          /* subspace exploratory matching (Algorithm 2, SMPL) when > 1: omega * rho
+                               candidates enter, the master problem is solved on I u J_omega, the rho
+                               with the largest |u_j| stay (ties to the lower index) and the master
+                               problem is solved again on I_t; needs the Gram table and
+                               omega * rho <= 64; default 1 (MPL) */
 } bmpl_options;
 
 /*

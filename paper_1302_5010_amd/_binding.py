@@ -26,7 +26,8 @@ class BmplError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("kkt_tol", ctypes.c_double), ("screen", ctypes.c_int), ("flags", ctypes.c_int32)]
+                ("kkt_tol", ctypes.c_double), ("screen", ctypes.c_int), ("flags", ctypes.c_int32),
+                ("omega", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -155,13 +156,13 @@ class Solver:
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
                  gram_table: bool = True, graph: bool = False, block_append: bool = True, phases: bool = False,
-                 q_route: bool = False, stream=None):
+                 q_route: bool = False, omega: int = 1, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
         o = _Options()
         _lib.bmpl_options_default(ctypes.byref(o))
-        o.rho, o.max_outer, o.max_active, o.kkt_tol = rho, max_outer, max_active, kkt_tol
+        o.rho, o.max_outer, o.max_active, o.kkt_tol, o.omega = rho, max_outer, max_active, kkt_tol, omega
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
                    | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND)

@@ -349,6 +349,7 @@ bmpl_status bmpl_options_default(bmpl_options* o)
     o->kkt_tol = 1e-4;
     o->screen = BMPL_PREC_FP32;
     o->flags = 0;
+    o->omega = 1;
     return BMPL_OK;
 }
 
@@ -370,6 +371,8 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     bmpl_options_default(&opt);
     if (o) opt = *o;
     if (opt.rho <= 0 || opt.rho > 64) return fail(BMPL_E_INVALID, "bmpl_create: rho must be in [1, 64]");
+    if (opt.omega < 1 || opt.omega * opt.rho > 64)
+        return fail(BMPL_E_INVALID, "bmpl_create: omega must be >= 1 with omega * rho <= 64");
     if (!(opt.kkt_tol >= 0.0)) return fail(BMPL_E_INVALID, "bmpl_create: kkt_tol must be >= 0");
     if (opt.screen != BMPL_PREC_FP32 && opt.screen != BMPL_PREC_BF16 && opt.screen != BMPL_PREC_FP8)
         return fail(BMPL_E_UNSUPPORTED, "bmpl_create: screening precision %d not available", (int)opt.screen);
@@ -435,6 +438,11 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         if (e == hipSuccess) e = launch_gram_table(c->At, c->kpad, m, c->kpad, c->Q, m, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && opt.omega > 1 && !c->Q) {
+        bmpl_destroy(c);
+        return fail(BMPL_E_UNSUPPORTED, "bmpl_create: subspace exploratory matching (omega > 1) needs the Gram "
+                                        "table");
+    }
     if (e == hipSuccess && c->qroute && (!c->Q || opt.screen != BMPL_PREC_FP32)) {
         bmpl_destroy(c);
         return fail(BMPL_E_UNSUPPORTED, "bmpl_create: the Q-route needs the Gram table (at most %.0f bytes, not "
@@ -567,8 +575,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     if (warm_k < 0 || warm_k > 256 || (warm_k > 0 && !warm_idx_dev))
         return fail(BMPL_E_INVALID, "bmpl_solve: warm_k must be in [0, 256] with a proposal array");
     const bool warm = warm_idx_dev && warm_k > 0;
-    const int rho = c->opt.rho;
-    const int max_outer = c->opt.max_outer > 0 ? c->opt.max_outer : (c->m + rho - 1) / rho;
+    const int max_outer = c->opt.max_outer > 0 ? c->opt.max_outer : (c->m + c->opt.rho - 1) / c->opt.rho;
+    // atoms selected per pass: rho, or omega rho candidates of which rho stay (subspace exploratory matching)
+    const int rho = c->opt.rho * c->opt.omega;
+    const int smpl_keep = c->opt.omega > 1 ? c->opt.rho : 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     // graph capture of whole segments; kernel timing needs per-launch events, so it uses the host loop
     const bool graph = (c->opt.flags & BMPL_FLAG_GRAPH) != 0 && !timing_on(c);
@@ -743,13 +753,15 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
 
     // Master problem and residual for the running list act[idx] (steps 4-8 of Algorithm 1),
     // with the factor held in LDS for capacity kl when it fits.
-    auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated) -> bmpl_status {
+    // `explore`: the pass before selected omega rho candidates (not a warm-start proposal)
+    auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated, bool explore) -> bmpl_status {
         const bool ev = tm && !gated;
         size_t e0 = ev ? mark(c, q) : 0;
         SolveArgs so{};
         so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
         so.Q = c->Q; so.ldq = c->m;
         so.max_steps = 16 * w.K + 256;
+        so.smpl_keep = explore ? smpl_keep : 0;
         so.phase = phases ? c->phase_dev : nullptr;
         const size_t vec_bytes = vec_area_bytes(w.K);
         so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
@@ -811,7 +823,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             st = segment_graph(c, p, cur, need, &ge, [&](hipStream_t q) -> bmpl_status {
                 int cc = cur;
                 for (int d = 0; d < GRAPH_DEPTH; ++d) {
-                    bmpl_status r = enqueue_master(q, cc, p, need, true);
+                    bmpl_status r = enqueue_master(q, cc, p, need, true, true);
                     if (r != BMPL_OK) return r;
                     r = enqueue_select_pass(q, cc, p, false, false, true);
                     if (r != BMPL_OK) return r;
@@ -831,7 +843,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         st = grow_to(imax);
         if (st != BMPL_OK) return st;
         c->timing.outer_iters += tm ? 1 : 0;
-        st = enqueue_master(s, cur, n_act, imax, false);
+        st = enqueue_master(s, cur, n_act, imax, false, !after_warm);
         if (st != BMPL_OK) return st;
         st = enqueue_select_pass(s, cur, n_act, false, after_warm, false);
         if (st != BMPL_OK) return st;

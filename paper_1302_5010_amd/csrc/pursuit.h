@@ -48,6 +48,7 @@ struct SolveArgs {
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
     int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
+    int smpl_keep;                  // > 0: subspace exploratory matching keeps this many of the new atoms
     uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,
                                     // then counts of factor appends, drops and solves; or null
 };

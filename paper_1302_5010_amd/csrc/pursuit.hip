@@ -748,7 +748,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     const int nI0 = w.nI[sig];
     int nS = w.nS[sig];
     const double lam = w.lam[sig];
-    const int nI = nI0 + nnew;
+    int nI = nI0 + nnew;
     uint64_t tick = a.phase ? wall_clock64() : 0;
 
     // global homes of this signal's state
@@ -861,9 +861,12 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
 
     phase_mark(1);
 
-    // 3. Sign-fixed active-set iterations.
+    // 3. Sign-fixed active-set iterations (twice with subspace exploratory matching: on I u J_omega,
+    //    then, after the pruning below, on I_t).
     int steps = 0;
     bool inexact = false;
+    bool explored = false;
+active_set:
     for (;;) {
         grad_slots(s, nI, nS, vg, true);
         if (wave == 0) {    // violators outside S, in slot order
@@ -977,6 +980,78 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             }
         }
         if (inexact) break;
+    }
+    if (a.smpl_keep > 0 && !explored && !inexact && nnew > a.smpl_keep && nnew <= NT && a.Q) {
+        // Subspace exploratory matching (Algorithm 2): keep the smpl_keep new atoms with the largest |u_j|
+        // (ties to the lower atom index); the others leave S (downdates) and I, the kept slots move down
+        // to nI0.., and the master problem continues on I_t from u restricted to it.
+        explored = true;
+        __shared__ int s_keep[NT];
+        __shared__ int s_newpos[NT];
+        if (tid < nnew) {
+            const int u = nI0 + tid;
+            const double xu = fabs(s.x[u]);
+            const int au = g_atom[u];
+            int rank = 0;
+            for (int e = 0; e < nnew; ++e) {
+                const double xe = fabs(s.x[nI0 + e]);
+                const int ae = g_atom[nI0 + e];
+                rank += (xe > xu) || (xe == xu && ae < au);
+            }
+            s_keep[tid] = rank < a.smpl_keep ? 1 : 0;
+        }
+        __syncthreads();
+        if (tid == 0) {                         // new positions of the kept slots, in slot order
+            int pos = nI0;
+            for (int e = 0; e < nnew; ++e) s_newpos[e] = s_keep[e] ? pos++ : -1;
+        }
+        __syncthreads();
+        // discarded atoms in S leave it, from the last support position down
+        for (int k = nS - 1; k >= 0; --k) {
+            const int u = s.so[k];
+            if (u < nI0 || s_keep[u - nI0]) continue;
+            for (int q = tid; q < nS; q += NT) vatom[q] = s.so[q];   // vatom is scratch after the Gram phase
+            __syncthreads();
+            if (!chol_drop(s, nS, k)) { inexact = true; break; }
+            for (int q = k + 1 + tid; q < nS; q += NT) s.so[q - 1] = vatom[q];
+            --nS;
+            __syncthreads();
+        }
+        if (!inexact) {
+            // move the kept slots' state down; a slot only moves to a lower position, in increasing
+            // order, so every destination has been read already
+            for (int e = 0; e < nnew; ++e) {
+                const int np = s_newpos[e], u = nI0 + e;
+                if (tid == 0) {
+                    if (np < 0) {
+                        const int atom = g_atom[u];
+                        atomicAnd(&w.inI[(int64_t)sig * w.words + (atom >> 5)], ~(1u << (atom & 31)));
+                    } else if (np != u) {
+                        s.x[np] = s.x[u]; s.c[np] = s.c[u]; s.th[np] = s.th[u]; s.ex[np] = s.ex[u];
+                        g_atom[np] = g_atom[u];
+                    }
+                }
+                __syncthreads();
+            }
+            for (int k = tid; k < nS; k += NT) {
+                const int u = s.so[k];
+                if (u >= nI0) s.so[k] = s_newpos[u - nI0];
+            }
+            int kept = 0;
+            for (int e = 0; e < nnew; ++e) kept += s_keep[e];
+            nI = nI0 + kept;
+            __syncthreads();
+            // Gram rows of the moved slots again, from the table
+            for (int e = tid; e < kept * nI; e += NT) {
+                const int t = e / nI, u = e - t * nI;
+                const int q = nI0 + t;
+                const double val = a.Q[(int64_t)g_atom[q] * a.ldq + g_atom[u]];
+                s.G[(int64_t)q * K + u] = val;
+                s.G[(int64_t)u * K + q] = val;
+            }
+            __syncthreads();
+            goto active_set;
+        }
     }
 
     phase_mark(2);

@@ -36,6 +36,7 @@ def test_options_default(lib):
     o = _Options()
     assert lib.bmpl_options_default(ctypes.byref(o)) == 0
     assert o.rho == 10 and o.max_outer == 0 and o.max_active == 0 and o.kkt_tol == 1e-4 and o.screen == 0
+    assert o.omega == 1 and o.flags == 0
     assert lib.bmpl_options_default(None) == -1
 
 
@@ -58,7 +59,11 @@ def test_argument_errors_without_gpu(lib):
     lib.bmpl_options_default(ctypes.byref(o))
     o.rho = 0
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
-    o.rho, o.screen = 10, 9
+    o.rho, o.omega = 10, 0
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    o.omega = 7                                  # omega * rho > 64
+    assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    o.omega, o.screen = 1, 9
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -4
     assert h.value is None
     assert lib.bmpl_solve(None, None, 4, 1, None, None, 0, None, None) == -1

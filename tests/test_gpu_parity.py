@@ -668,3 +668,30 @@ def test_cs_gaussian_q_route_full_size_sampled():
     rows = list(range(3, P.p, 61))
     ref = oracle.solve(P.At, P.Bt[rows], lam[rows], P.rho)
     check_batch(P.At, P.Bt, lam[rows], out, ref, rows=range(len(rows)), gpu_rows=rows)
+
+
+@pytest.mark.parametrize("graph,screen", [(False, "fp32"), (True, "fp32"), (True, "bf16")])
+def test_smpl_parity(graph, screen):
+    """Subspace exploratory matching (Algorithm 2, omega = 3): the LASSO solution at the parity rules,
+    and iteration counts close to the SMPL oracle's (the path is the same up to near-ties in |u|)."""
+    pk = _lib()
+    for P in (bi.small_gaussian(), bi.tiny_gaussian(n=256, m=2000, p=257, k=30, sigma=0.01, seed=91, rho=7),
+              bi.tiny_gaussian(n=320, m=3000, p=100, k=50, sigma=0.01, seed=650, lambda_rel=0.03, rho=10)):
+        lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+        s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, omega=3, graph=graph, screen=screen)
+        out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+        st = out["status"].cpu().numpy()
+        assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+        ref = oracle.solve(P.At, P.Bt, lam, P.rho, omega=3)
+        check_batch(P.At, P.Bt, lam, out, ref)
+        it = out["iters"].cpu().numpy()
+        assert np.mean(np.abs(it - ref["iters"])) <= 1.0, (it[:10], ref["iters"][:10])
+
+
+def test_smpl_needs_the_gram_table_and_a_width_limit():
+    pk = _lib()
+    P = bi.small_gaussian()
+    with pytest.raises(pk.BmplError):
+        pk.Solver(to_dev(P.At), 0.1, omega=3, gram_table=False)
+    with pytest.raises(pk.BmplError):
+        pk.Solver(to_dev(P.At), 0.1, rho=30, omega=3)
