@@ -26,6 +26,9 @@
  * solved on I u J_omega, the rho atoms of J_omega with the largest |u_j| (ties
  * to the lower index) form J_t and the others leave I; step 3 then solves on
  * I_t warm-started from u restricted to I_t.
+ * With eps_early > 0 the solver also stops early (status 64) by the rule of
+ * Eq. (13): once an outer iteration lowered the objective by at most
+ * eps_early * rho * ||b||^2 (checked after the natural stop).
  *
  * The paper solves the master problem with proximal gradient (lambda > 0) or
  * conjugate gradient (lambda = 0) to a small tolerance.  This oracle solves it
@@ -57,6 +60,7 @@
 #define ST_CAP_ACTIVE  4
 #define ST_NONFINITE   8
 #define ST_INEXACT     32   /* restricted solve could not be verified exact */
+#define ST_EARLY       64   /* stopped by the objective-decrease rule, Eq. (13) */
 
 #define STOP_REL   1e-12    /* natural stop test outside I, relative to lambda */
 #define VERIFY_REL 1e-10    /* restricted optimality accepted to this, relative to lambda */
@@ -406,7 +410,7 @@ static void smpl_prune(sig_state* st, int first, int keep)
 }
 
 static void solve_one(const float* A, int64_t lda, int n, int m, const float* b, double lam,
-                      int rho, int omega, int max_outer, int max_active,
+                      int rho, int omega, double eps_early, int max_outer, int max_active,
                       double* xdense, int* iters, double* kkt, double* obj, double* margin,
                       double* gap, int* status, int* supp_len, trace_t* tr)
 {
@@ -429,12 +433,18 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
     }
     residual(&st);
     if (tr) tr->obj[0] = objective(&st);
+    double bb = 0.0;
+    for (int k = 0; k < n; ++k) bb += (double)b[k] * (double)b[k];
+    double f_prev = objective(&st), f_cur = f_prev;
     for (;;) {
         full_correlation(&st);
         double vmax = 0.0;
         for (int j = 0; j < m; ++j)
             if (!st.inI[j] && fabs(st.g[j]) > vmax) vmax = fabs(st.g[j]);
         if (vmax <= lam * (1.0 + STOP_REL)) { stat |= ST_CONVERGED; break; }
+        /* early stop, Eq. (13): the last outer iteration lowered the objective by at most
+         * eps * rho * ||b||^2 (off unless eps_early > 0) */
+        if (eps_early > 0.0 && t >= 1 && fabs(f_prev - f_cur) <= eps_early * rho * bb) { stat |= ST_EARLY; break; }
         if (t >= max_outer) { stat |= ST_CAP_ITERS; break; }
         if (st.nI >= max_active) { stat |= ST_CAP_ACTIVE; break; }
         int want = rho;
@@ -472,7 +482,9 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
         stat |= master_solve(&st);
         residual(&st);
         ++t;
-        if (tr) tr->obj[t] = objective(&st);
+        f_prev = f_cur;
+        f_cur = objective(&st);
+        if (tr) tr->obj[t] = f_cur;
     }
     /* Outputs: x, the certificate kappa, the objective, the margin and the duality gap of Eq. (5). */
     double F = objective(&st);
@@ -511,7 +523,7 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
     free_state(&st);
 }
 
-int mpl_oracle_abi_version(void) { return 2; }
+int mpl_oracle_abi_version(void) { return 3; }
 
 /*
  * Batch solve: p independent signals (Eq. (3)), one per OpenMP thread.
@@ -520,7 +532,8 @@ int mpl_oracle_abi_version(void) { return 2; }
  * Per-signal outputs are arrays of length p.  Returns 0, or -1 on bad arguments.
  */
 int mpl_oracle_solve(const float* At, int64_t lda, int n, int m, const float* Bt, int64_t ldb,
-                     int p, const double* lam, int rho, int omega, int max_outer, int max_active, int nthreads,
+                     int p, const double* lam, int rho, int omega, double eps_early, int max_outer, int max_active,
+                     int nthreads,
                      double* X, int64_t ldx, int* iters, double* kkt, double* obj, double* margin,
                      double* gap, int* status, int* supp_len)
 {
@@ -532,7 +545,7 @@ int mpl_oracle_solve(const float* At, int64_t lda, int n, int m, const float* Bt
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int i = 0; i < p; ++i)
-        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, omega, max_outer, max_active,
+        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, omega, eps_early, max_outer, max_active,
                   X + (size_t)i * ldx, iters + i, kkt + i, obj + i, margin + i, gap + i,
                   status + i, supp_len + i, NULL);
     return 0;
@@ -554,14 +567,15 @@ int mpl_oracle_max_threads(void)
  * max_outer + 1 (obj), max_outer * rho (added, gsel) and max_outer (nadd).
  */
 int mpl_oracle_trace(const float* At, int64_t lda, int n, int m, const float* b, double lam,
-                     int rho, int omega, int max_outer, int max_active, double* x, int* iters, double* kkt,
+                     int rho, int omega, double eps_early, int max_outer, int max_active, double* x, int* iters,
+                     double* kkt,
                      double* objv, double* margin, double* gap, int* status, int* supp_len,
                      double* obj_trace, int* added, double* gsel, int* nadd)
 {
     if (!At || !b || !x || n <= 0 || m <= 0 || lda < n || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0)
         return -1;
     trace_t tr = { obj_trace, added, gsel, nadd, max_outer };
-    solve_one(At, lda, n, m, b, lam, rho, omega, max_outer, max_active, x, iters, kkt, objv, margin, gap,
+    solve_one(At, lda, n, m, b, lam, rho, omega, eps_early, max_outer, max_active, x, iters, kkt, objv, margin, gap,
               status, supp_len, &tr);
     return 0;
 }

@@ -367,3 +367,27 @@ def test_smpl_keeps_the_atom_with_the_largest_restricted_coefficient():
         assert list(tr["steps"][0][0]) == [kept]
         checked += 1
     assert checked >= 4
+
+
+def test_early_stop_rule_eq13():
+    """The objective-decrease stop of Eq. (13): the solver stops at the first outer iteration whose
+    decrease is at most eps * rho * ||b||^2, not before; with eps = 0 it runs to the natural stop."""
+    P = bi.tiny_gaussian(n=64, m=400, p=4, k=20, sigma=0.02, seed=21, lambda_rel=0.002, rho=2)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    for i in range(P.p):
+        b = P.Bt[i]
+        bb = float(b.astype(np.float64) @ b.astype(np.float64))
+        full = oracle.trace(P.At, b, lam[i], P.rho)
+        eps = 1e-4
+        tr = oracle.trace(P.At, b, lam[i], P.rho, eps_early=eps)
+        ob = tr["obj_trace"]
+        T = tr["iters"]
+        dec = np.abs(np.diff(ob))
+        if tr["status"] & oracle.ST_EARLY:
+            assert dec[T - 1] <= eps * P.rho * bb
+            assert np.all(dec[:T - 1] > eps * P.rho * bb)
+            assert T < full["iters"]
+            np.testing.assert_allclose(ob, full["obj_trace"][:T + 1], rtol=1e-12)   # the same path so far
+        else:
+            assert tr["status"] & oracle.ST_CONVERGED and np.all(dec > eps * P.rho * bb)
+        assert full["status"] & oracle.ST_CONVERGED
