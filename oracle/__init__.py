@@ -7,7 +7,7 @@ float64, OpenMP over signals); this file marshals numpy arrays through ctypes.
 
 Status bits returned per signal: 1 converged (natural stop, Eq. (9)),
 2 iteration cap, 4 active-set cap, 8 non-finite input, 32 a restricted solve
-could not be verified exact.
+could not be verified exact, 64 an early stop (Eq. (10) or Eq. (13)).
 """
 from __future__ import annotations
 
@@ -37,13 +37,13 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.mpl_oracle_solve.restype = ctypes.c_int
     lib.mpl_oracle_solve.argtypes = [_fp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _fp, ctypes.c_int64,
-                                     ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp, _dp, _dp, _ip,
+                                     ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp, _dp, _dp, _ip,
                                      _ip]
     lib.mpl_oracle_trace.restype = ctypes.c_int
     lib.mpl_oracle_trace.argtypes = [_fp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _fp, ctypes.c_double,
-                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp,
-                                     _ip, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _ip, _dp, _ip]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, _dp, _ip, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _ip, _dp, _ip]
     lib.mpl_oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -58,10 +58,12 @@ def max_threads() -> int:
 
 
 def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None = None,
-          max_active: int | None = None, nthreads: int = 0, omega: int = 1, eps_early: float = 0.0) -> dict:
+          max_active: int | None = None, nthreads: int = 0, omega: int = 1, eps_early: float = 0.0,
+          r_inf_rel: float = 0.0, r2_rel: float = 0.0) -> dict:
     """Solve every row of Bt; returns dense X (p, m) float64 and per-signal arrays.
     omega > 1 runs subspace exploratory matching (Algorithm 2, SMPL) with omega * rho candidates;
-    eps_early > 0 adds the objective-decrease stop of Eq. (13)."""
+    eps_early > 0 adds the objective-decrease stop of Eq. (13); r_inf_rel / r2_rel > 0 add the stops of
+    Eq. (10) with r_inf = r_inf_rel ||A^T b||_inf and r_2 = r2_rel ||b||."""
     lib = _load()
     At = np.ascontiguousarray(At, dtype=np.float32)
     Bt = np.ascontiguousarray(np.atleast_2d(Bt), dtype=np.float32)
@@ -78,7 +80,7 @@ def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None =
     st = np.zeros(p, np.int32)
     sl = np.zeros(p, np.int32)
     rc = lib.mpl_oracle_solve(_ptr(At, _fp), n, n, m, _ptr(Bt, _fp), n, p, _ptr(lam, _dp), rho, omega,
-                              float(eps_early), max_outer, max_active, nthreads, _ptr(X, _dp), m, _ptr(it, _ip), _ptr(kkt, _dp),
+                              float(eps_early), float(r_inf_rel), float(r2_rel), max_outer, max_active, nthreads, _ptr(X, _dp), m, _ptr(it, _ip), _ptr(kkt, _dp),
                               _ptr(obj, _dp), _ptr(mar, _dp), _ptr(gap, _dp), _ptr(st, _ip), _ptr(sl, _ip))
     if rc != 0:
         raise ValueError("mpl_oracle_solve rejected its arguments")
@@ -87,7 +89,8 @@ def solve(At: np.ndarray, Bt: np.ndarray, lam, rho: int, max_outer: int | None =
 
 
 def trace(At: np.ndarray, b: np.ndarray, lam: float, rho: int, max_outer: int | None = None,
-          max_active: int | None = None, omega: int = 1, eps_early: float = 0.0) -> dict:
+          max_active: int | None = None, omega: int = 1, eps_early: float = 0.0, r_inf_rel: float = 0.0,
+          r2_rel: float = 0.0) -> dict:
     """One signal, with the objective after every outer iteration and the atoms added."""
     lib = _load()
     At = np.ascontiguousarray(At, dtype=np.float32)
@@ -107,7 +110,7 @@ def trace(At: np.ndarray, b: np.ndarray, lam: float, rho: int, max_outer: int | 
     gsel = np.zeros(max(1, max_outer * rho))
     nadd = np.zeros(max(1, max_outer), np.int32)
     rc = lib.mpl_oracle_trace(_ptr(At, _fp), n, n, m, _ptr(b, _fp), float(lam), rho, omega, float(eps_early),
-                              max_outer, max_active,
+                              float(r_inf_rel), float(r2_rel), max_outer, max_active,
                               _ptr(x, _dp), _ptr(it, _ip), _ptr(kkt, _dp), _ptr(obj, _dp), _ptr(mar, _dp),
                               _ptr(gap, _dp), _ptr(st, _ip), _ptr(sl, _ip), _ptr(ot, _dp), _ptr(added, _ip),
                               _ptr(gsel, _dp), _ptr(nadd, _ip))

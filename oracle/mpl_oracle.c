@@ -26,9 +26,18 @@
  * solved on I u J_omega, the rho atoms of J_omega with the largest |u_j| (ties
  * to the lower index) form J_t and the others leave I; step 3 then solves on
  * I_t warm-started from u restricted to I_t.
- * With eps_early > 0 the solver also stops early (status 64) by the rule of
- * Eq. (13): once an outer iteration lowered the objective by at most
- * eps_early * rho * ||b||^2 (checked after the natural stop).
+ * Early stops (status 64), each off at 0 and checked after the natural stop,
+ * in this order:
+ *   - Eq. (10): ||A^T xi||_inf <= r_inf or ||xi|| <= r_2, with the two radii
+ *     given relative to the signal, r_inf = r_inf_rel ||A^T b||_inf and
+ *     r_2 = r2_rel ||b|| (the paper leaves their values open).  Atoms in I
+ *     satisfy |a_j^T xi| <= lambda after step 3, so the maximum is taken
+ *     outside I: when r_inf < lambda the natural stop comes first anyway.
+ *   - Eq. (13): the last outer iteration lowered the objective by at most
+ *     eps_early * rho * ||b||^2.  Eq. (11) with tolerance eps is the same
+ *     rule with eps_early = eps / 2, since f(x^0) = ||b||^2 / 2.
+ * For lambda = 0 and rho = 1 this is OMP (end of the "Stopping Conditions"
+ * subsection), and the r_2 rule is OMP's usual residual-norm stop.
  *
  * The paper solves the master problem with proximal gradient (lambda > 0) or
  * conjugate gradient (lambda = 0) to a small tolerance.  This oracle solves it
@@ -410,8 +419,8 @@ static void smpl_prune(sig_state* st, int first, int keep)
 }
 
 static void solve_one(const float* A, int64_t lda, int n, int m, const float* b, double lam,
-                      int rho, int omega, double eps_early, int max_outer, int max_active,
-                      double* xdense, int* iters, double* kkt, double* obj, double* margin,
+                      int rho, int omega, double eps_early, double r_inf_rel, double r2_rel,
+                      int max_outer, int max_active, double* xdense, int* iters, double* kkt, double* obj, double* margin,
                       double* gap, int* status, int* supp_len, trace_t* tr)
 {
     sig_state st;
@@ -436,12 +445,22 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
     double bb = 0.0;
     for (int k = 0; k < n; ++k) bb += (double)b[k] * (double)b[k];
     double f_prev = objective(&st), f_cur = f_prev;
+    double r_inf = 0.0;                       /* r_inf_rel ||A^T b||_inf, set at t = 0 */
+    const double r_2 = r2_rel * sqrt(bb);
     for (;;) {
         full_correlation(&st);
         double vmax = 0.0;
         for (int j = 0; j < m; ++j)
             if (!st.inI[j] && fabs(st.g[j]) > vmax) vmax = fabs(st.g[j]);
+        if (t == 0) r_inf = r_inf_rel * vmax;
         if (vmax <= lam * (1.0 + STOP_REL)) { stat |= ST_CONVERGED; break; }
+        /* early stop, Eq. (10): small correlations or a small residual (off unless the radii are > 0) */
+        if (r_inf_rel > 0.0 && vmax <= r_inf) { stat |= ST_EARLY; break; }
+        if (r2_rel > 0.0) {
+            double rr = 0.0;
+            for (int k = 0; k < n; ++k) rr += st.r[k] * st.r[k];
+            if (sqrt(rr) <= r_2) { stat |= ST_EARLY; break; }
+        }
         /* early stop, Eq. (13): the last outer iteration lowered the objective by at most
          * eps * rho * ||b||^2 (off unless eps_early > 0) */
         if (eps_early > 0.0 && t >= 1 && fabs(f_prev - f_cur) <= eps_early * rho * bb) { stat |= ST_EARLY; break; }
@@ -523,7 +542,7 @@ static void solve_one(const float* A, int64_t lda, int n, int m, const float* b,
     free_state(&st);
 }
 
-int mpl_oracle_abi_version(void) { return 3; }
+int mpl_oracle_abi_version(void) { return 4; }
 
 /*
  * Batch solve: p independent signals (Eq. (3)), one per OpenMP thread.
@@ -532,20 +551,23 @@ int mpl_oracle_abi_version(void) { return 3; }
  * Per-signal outputs are arrays of length p.  Returns 0, or -1 on bad arguments.
  */
 int mpl_oracle_solve(const float* At, int64_t lda, int n, int m, const float* Bt, int64_t ldb,
-                     int p, const double* lam, int rho, int omega, double eps_early, int max_outer, int max_active,
+                     int p, const double* lam, int rho, int omega, double eps_early, double r_inf_rel,
+                     double r2_rel, int max_outer, int max_active,
                      int nthreads,
                      double* X, int64_t ldx, int* iters, double* kkt, double* obj, double* margin,
                      double* gap, int* status, int* supp_len)
 {
     if (!At || !Bt || !lam || !X || n <= 0 || m <= 0 || p < 0 || lda < n || ldb < n || ldx < m
-        || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0)
+        || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0
+        || !(eps_early >= 0.0) || !(r_inf_rel >= 0.0) || !(r2_rel >= 0.0))
         return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int i = 0; i < p; ++i)
-        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, omega, eps_early, max_outer, max_active,
+        solve_one(At, lda, n, m, Bt + (size_t)i * ldb, lam[i], rho, omega, eps_early, r_inf_rel, r2_rel,
+                  max_outer, max_active,
                   X + (size_t)i * ldx, iters + i, kkt + i, obj + i, margin + i, gap + i,
                   status + i, supp_len + i, NULL);
     return 0;
@@ -567,15 +589,18 @@ int mpl_oracle_max_threads(void)
  * max_outer + 1 (obj), max_outer * rho (added, gsel) and max_outer (nadd).
  */
 int mpl_oracle_trace(const float* At, int64_t lda, int n, int m, const float* b, double lam,
-                     int rho, int omega, double eps_early, int max_outer, int max_active, double* x, int* iters,
+                     int rho, int omega, double eps_early, double r_inf_rel, double r2_rel,
+                     int max_outer, int max_active, double* x, int* iters,
                      double* kkt,
                      double* objv, double* margin, double* gap, int* status, int* supp_len,
                      double* obj_trace, int* added, double* gsel, int* nadd)
 {
-    if (!At || !b || !x || n <= 0 || m <= 0 || lda < n || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0)
+    if (!At || !b || !x || n <= 0 || m <= 0 || lda < n || rho <= 0 || omega < 1 || max_outer < 0 || max_active <= 0
+        || !(eps_early >= 0.0) || !(r_inf_rel >= 0.0) || !(r2_rel >= 0.0))
         return -1;
     trace_t tr = { obj_trace, added, gsel, nadd, max_outer };
-    solve_one(At, lda, n, m, b, lam, rho, omega, eps_early, max_outer, max_active, x, iters, kkt, objv, margin, gap,
+    solve_one(At, lda, n, m, b, lam, rho, omega, eps_early, r_inf_rel, r2_rel, max_outer, max_active, x, iters, kkt,
+              objv, margin, gap,
               status, supp_len, &tr);
     return 0;
 }

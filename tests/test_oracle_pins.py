@@ -391,3 +391,81 @@ def test_early_stop_rule_eq13():
         else:
             assert tr["status"] & oracle.ST_CONVERGED and np.all(dec > eps * P.rho * bb)
         assert full["status"] & oracle.ST_CONVERGED
+
+
+def omp_residual_stop(A, b, eps_r, eps_g, max_steps):
+    """Textbook OMP that stops once ||r|| <= eps_r or max_{j not in I} |a_j^T r| <= eps_g
+    (the classical residual-norm and correlation stops)."""
+    r = b.copy()
+    I = []
+    xs = np.zeros(0)
+    for _ in range(max_steps):
+        c = np.abs(A.T @ r)
+        c[I] = -1
+        if c.max() <= eps_g or np.linalg.norm(r) <= eps_r:
+            break
+        I.append(int(np.argmax(c)))
+        xs, *_ = np.linalg.lstsq(A[:, I], b, rcond=None)
+        r = b - A[:, I] @ xs
+    x = np.zeros(A.shape[1])
+    x[I] = xs
+    return I, x
+
+
+@pytest.mark.parametrize("seed,r2_rel,rinf_rel", [(0, 0.05, 0.0), (1, 0.2, 0.0), (2, 0.0, 0.1), (3, 0.0, 0.3)])
+def test_early_stop_eq10_is_omp_with_its_stop(seed, r2_rel, rinf_rel):
+    """Eq. (10) at lambda = 0, rho = 1: OMP with the residual-norm stop ||xi|| <= r_2, or the
+    correlation stop ||A^T xi||_inf <= r_inf (radii relative to ||b|| and ||A^T b||_inf)."""
+    P = bi.tiny_gaussian(n=64, m=200, p=1, k=12, sigma=0.02, seed=40 + seed)
+    A = P.At.astype(np.float64).T
+    b = P.Bt[0].astype(np.float64)
+    eps_r = r2_rel * np.linalg.norm(b) if r2_rel > 0 else -1.0
+    eps_g = rinf_rel * np.abs(A.T @ b).max() if rinf_rel > 0 else -1.0
+    I_omp, x_omp = omp_residual_stop(A, b, eps_r, eps_g, 40)
+    t = oracle.trace(P.At, P.Bt[0], 0.0, 1, max_outer=40, r2_rel=r2_rel, r_inf_rel=rinf_rel)
+    assert t["status"] & oracle.ST_EARLY
+    assert 0 < len(I_omp) < 40
+    assert [int(a[0]) for a, _ in t["steps"]] == I_omp
+    np.testing.assert_allclose(t["x"], x_omp, atol=1e-9)
+
+
+def test_early_stop_eq10_lasso_rule_along_the_path():
+    """Eq. (10) with lambda > 0: the solver stops at the first outer iteration at which the largest
+    correlation outside I is at most r_inf (or the residual norm at most r_2), not before, on the same
+    path as the full solve."""
+    P = bi.tiny_gaussian(n=64, m=400, p=4, k=20, sigma=0.02, seed=22, lambda_rel=0.002, rho=2)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    A = P.At.astype(np.float64).T
+    for i in range(P.p):
+        b = P.Bt[i]
+        b64 = b.astype(np.float64)
+        full = oracle.trace(P.At, b, lam[i], P.rho)
+        for rinf_rel, r2_rel in ((0.05, 0.0), (0.0, 0.1)):
+            tr = oracle.trace(P.At, b, lam[i], P.rho, r_inf_rel=rinf_rel, r2_rel=r2_rel)
+            T = tr["iters"]
+            assert tr["status"] & oracle.ST_EARLY and 0 < T < full["iters"]
+            np.testing.assert_allclose(tr["obj_trace"], full["obj_trace"][:T + 1], rtol=1e-12)
+            r_inf = rinf_rel * np.abs(A.T @ b64).max()
+            r_2 = r2_rel * np.linalg.norm(b64)
+            inI = np.zeros(A.shape[1], bool)
+            for t, (added, gsel) in enumerate(tr["steps"]):
+                # before step t: neither the correlation rule (largest |g| outside I is the first pick)
+                # nor the residual rule held
+                x_t = full_x_after(P.At, b, lam[i], P.rho, t)
+                if rinf_rel > 0:
+                    assert abs(gsel[0]) > r_inf
+                if r2_rel > 0:
+                    assert np.linalg.norm(b64 - A @ x_t) > r_2
+                inI[added] = True
+            rT = b64 - A @ tr["x"]
+            if rinf_rel > 0:
+                assert np.abs(A.T @ rT)[~inI].max() <= r_inf * (1 + 1e-12)
+            if r2_rel > 0:
+                assert np.linalg.norm(rT) <= r_2 * (1 + 1e-12)
+
+
+def full_x_after(At, b, lam, rho, t):
+    """x after t outer iterations (the iteration cap of the oracle stops it there)."""
+    if t == 0:
+        return np.zeros(At.shape[0])
+    return oracle.trace(At, b, lam, rho, max_outer=t)["x"]
