@@ -72,6 +72,8 @@ typedef enum {
 #define BMPL_SIG_NONFINITE   8   /* b_i or lambda_i not finite: x_i = 0 */
 #define BMPL_SIG_FALLBACK   16   /* a warm-start proposal failed the certificate */
 #define BMPL_SIG_INEXACT    32   /* a restricted solve hit its step cap */
+#define BMPL_SIG_EARLY      64   /* stopped early by Eq. (10) or Eq. (13) (bmpl_options.eps_early,
+                                    r_inf_rel, r2_rel); kkt reports how far from the natural stop */
 
 /* bmpl_options.flags bits. */
 #define BMPL_FLAG_TIMING 1          /* time every kernel launch with HIP events (see bmpl_get_timing) */
@@ -110,6 +112,19 @@ typedef struct {
                                with the largest |u_j| stay (ties to the lower index) and the master
                                problem is solved again on I_t; needs the Gram table and
                                omega * rho <= 64; default 1 (MPL) */
+    /* Early stops of the "Stopping Conditions" subsection and of the experimental settings, each off at
+     * 0 (the default) and tested, per signal, after the natural stop at the start of an outer iteration,
+     * in this order (status BMPL_SIG_EARLY, the current x is returned):
+     *   Eq. (10): max_{j not in I} |a_j^T xi| <= r_inf_rel * ||A^T b_i||_inf (atoms in I meet
+     *             |a_j^T xi| <= lambda_i, so this is ||A^T xi||_inf <= r_inf once r_inf >= lambda_i), or
+     *             ||xi|| <= r2_rel * ||b_i||; ||A^T b_i||_inf comes from the first correlation pass;
+     *   Eq. (13): the last outer iteration lowered the objective by at most eps_early * rho * ||b_i||^2
+     *             (rho = the rho above).  Eq. (11) with tolerance eps is eps_early = eps / 2, since
+     *             f(x^0) = ||b_i||^2 / 2.
+     * With lambda = 0 and rho = 1 the solve is OMP and r2_rel its residual-norm stop. */
+    double eps_early;
+    double r_inf_rel;
+    double r2_rel;
 } bmpl_options;
 
 /*

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     BMPL_SIG_CAP_ACTIVE,
     BMPL_SIG_CAP_ITERS,
     BMPL_SIG_CONVERGED,
+    BMPL_SIG_EARLY,
     BMPL_SIG_FALLBACK,
     BMPL_SIG_INEXACT,
     BMPL_SIG_NONFINITE,

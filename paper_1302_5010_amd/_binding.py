@@ -15,6 +15,7 @@ BMPL_SIG_CAP_ACTIVE = 4
 BMPL_SIG_NONFINITE = 8
 BMPL_SIG_FALLBACK = 16
 BMPL_SIG_INEXACT = 32
+BMPL_SIG_EARLY = 64
 
 _PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
 _MODE = {"abs": 0, "rel": 1}
@@ -27,7 +28,8 @@ class BmplError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("max_active", ctypes.c_int32),
                 ("kkt_tol", ctypes.c_double), ("screen", ctypes.c_int), ("flags", ctypes.c_int32),
-                ("omega", ctypes.c_int32)]
+                ("omega", ctypes.c_int32), ("eps_early", ctypes.c_double), ("r_inf_rel", ctypes.c_double),
+                ("r2_rel", ctypes.c_double)]
 
 
 class Timing(ctypes.Structure):
@@ -156,13 +158,15 @@ class Solver:
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
                  gram_table: bool = True, graph: bool = False, block_append: bool = True, phases: bool = False,
-                 q_route: bool = False, omega: int = 1, stream=None):
+                 q_route: bool = False, omega: int = 1, eps_early: float = 0.0, r_inf_rel: float = 0.0,
+                 r2_rel: float = 0.0, stream=None):
         At = _dev(At, torch.float32, "At")
         self.m, self.n = At.shape
         self.device = At.device
         o = _Options()
         _lib.bmpl_options_default(ctypes.byref(o))
         o.rho, o.max_outer, o.max_active, o.kkt_tol, o.omega = rho, max_outer, max_active, kkt_tol, omega
+        o.eps_early, o.r_inf_rel, o.r2_rel = eps_early, r_inf_rel, r2_rel
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
                    | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND)

@@ -191,7 +191,7 @@ void free_signals(bmpl_ctx* c)
     Workspace& w = c->w;
     dfree(w.R); dfree(w.bnorm2); dfree(w.lam); dfree(w.status); dfree(w.iters); dfree(w.nI);
     dfree(w.nS); dfree(w.nsel); dfree(w.sel); dfree(w.vmax); dfree(w.kkt_on); dfree(w.obj);
-    dfree(w.kkt); dfree(w.inI);
+    dfree(w.kkt); dfree(w.inI); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
@@ -222,6 +222,9 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     HIPC(dalloc(&w.vmax, P));
     HIPC(dalloc(&w.kkt_on, P));
     HIPC(dalloc(&w.obj, P));
+    HIPC(dalloc(&w.obj_prev, P));
+    HIPC(dalloc(&w.rr2, P));
+    HIPC(dalloc(&w.g0max, P));
     HIPC(dalloc(&w.kkt, P));
     HIPC(dalloc(&w.inI, P * w.words));
     HIPC(alloc_slots(w, p, K));
@@ -350,6 +353,9 @@ bmpl_status bmpl_options_default(bmpl_options* o)
     o->screen = BMPL_PREC_FP32;
     o->flags = 0;
     o->omega = 1;
+    o->eps_early = 0.0;
+    o->r_inf_rel = 0.0;
+    o->r2_rel = 0.0;
     return BMPL_OK;
 }
 
@@ -374,6 +380,9 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (opt.omega < 1 || opt.omega * opt.rho > 64)
         return fail(BMPL_E_INVALID, "bmpl_create: omega must be >= 1 with omega * rho <= 64");
     if (!(opt.kkt_tol >= 0.0)) return fail(BMPL_E_INVALID, "bmpl_create: kkt_tol must be >= 0");
+    if (!(opt.eps_early >= 0.0) || !(opt.r_inf_rel >= 0.0) || !(opt.r2_rel >= 0.0) || !std::isfinite(opt.eps_early)
+        || !std::isfinite(opt.r_inf_rel) || !std::isfinite(opt.r2_rel))
+        return fail(BMPL_E_INVALID, "bmpl_create: eps_early, r_inf_rel and r2_rel must be finite and >= 0");
     if (opt.screen != BMPL_PREC_FP32 && opt.screen != BMPL_PREC_BF16 && opt.screen != BMPL_PREC_FP8)
         return fail(BMPL_E_UNSUPPORTED, "bmpl_create: screening precision %d not available", (int)opt.screen);
     if (opt.max_active > m) opt.max_active = m;
@@ -613,6 +622,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     sa.w = w; sa.act_in = nullptr; sa.n_in_dev = nullptr; sa.n_in = p;
     sa.act_out = c->act[0]; sa.n_out_dev = c->n_act_dev; sa.initial = 1;
     sa.max_outer = max_outer; sa.kkt_tol = c->opt.kkt_tol; sa.warm_check = 0;
+    sa.eps_early = c->opt.eps_early; sa.r_inf_rel = c->opt.r_inf_rel; sa.r2_rel = c->opt.r2_rel;
+    sa.rho = c->opt.rho;
     hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev, sizeof(int), hipMemcpyDeviceToHost, s));

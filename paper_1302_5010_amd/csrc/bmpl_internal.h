@@ -41,6 +41,9 @@ struct Workspace {
     float* vmax;        // [p] max |g_j| outside I in the last correlation pass
     double* kkt_on;     // [p] restricted optimality residual on I (absolute)
     double* obj;        // [p] objective after the last master solve
+    double* obj_prev;   // [p] objective after the master solve before it (Eq. (13))
+    double* rr2;        // [p] ||xi_i||^2 after the last master solve, float64 (Eq. (10))
+    float* g0max;       // [p] ||A^T b_i||_inf from the first correlation pass (Eq. (10))
     double* kkt;        // [p] final certificate (relative to lambda_i)
     uint32_t* inI;      // [p][words] membership bitmap of I
     int* slot_atom;     // [p][K]

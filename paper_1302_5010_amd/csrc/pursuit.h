@@ -22,6 +22,10 @@ struct StatusArgs {
     int max_outer;
     double kkt_tol;
     int warm_check;     // pass right after a warm-started master solve
+    double eps_early;   // Eq. (13) tolerance, 0 = off
+    double r_inf_rel;   // Eq. (10) correlation radius relative to ||A^T b_i||_inf, 0 = off
+    double r2_rel;      // Eq. (10) residual radius relative to ||b_i||, 0 = off
+    int rho;            // atoms per outer iteration in the Eq. (13) normalisation
 };
 
 struct WarmArgs {

@@ -617,6 +617,9 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.kkt_on[sig] = 0.0;
         w.kkt[sig] = 0.0;
         w.obj[sig] = 0.5 * bb;
+        w.obj_prev[sig] = 0.5 * bb;
+        w.rr2[sig] = bb;
+        w.g0max[sig] = 0.f;
         if (w.rnorm) w.rnorm[sig] = sqrt(bb);
     }
     if (w.R8) write_residual_fp8(w, sig, red);
@@ -624,8 +627,9 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
 
 // ---------------------------------------------------------------------------
 // Stop test and compaction.  For each running signal after a selection pass:
-// no admitted atom -> stop (natural stop if no violator remains, else the
-// active-set cap was hit); iteration cap -> stop; otherwise keep it running.
+// no violator left -> natural stop; an early-stop rule (Eq. (10), Eq. (13))
+// holds -> early stop; no admitted atom -> the active-set cap was hit;
+// iteration cap -> stop; otherwise keep it running.
 // One workgroup; the running list stays in signal order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
@@ -648,15 +652,31 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                 const double lam = w.lam[sig];
                 const int ns = w.nsel[sig];
                 const double vm = (double)w.vmax[sig];
-                if (ns == 0 || w.iters[sig] >= a.max_outer) {
+                const int it = w.iters[sig];
+                if (it == 0) w.g0max[sig] = w.vmax[sig];   // first pass: I is empty, so this is ||A^T b||_inf
+                const bool natural = ns == 0 && vm <= lam;
+                bool early = false;
+                if (!natural) {
+                    const double bb = w.bnorm2[sig];
+                    if (a.r_inf_rel > 0.0 && vm <= a.r_inf_rel * (double)w.g0max[sig])
+                        early = true;                                             // Eq. (10), correlations
+                    else if (a.r2_rel > 0.0 && sqrt(w.rr2[sig]) <= a.r2_rel * sqrt(bb))
+                        early = true;                                             // Eq. (10), residual norm
+                    else if (a.eps_early > 0.0 && it >= 1 &&
+                             fabs(w.obj_prev[sig] - w.obj[sig]) <= a.eps_early * a.rho * bb)
+                        early = true;                                             // Eq. (13)
+                }
+                if (ns == 0 || it >= a.max_outer || early) {
                     double off = vm - lam;
                     off = off > 0.0 ? off : 0.0;
                     double kk = fmax(off, w.kkt_on[sig]);
                     kk = lam > 0.0 ? kk / lam : kk;
                     w.kkt[sig] = kk;
                     if (a.warm_check && ns != 0) st |= BMPL_SIG_FALLBACK;
-                    if (ns == 0 && vm <= lam) {
+                    if (natural) {
                         if (kk <= a.kkt_tol) st |= BMPL_SIG_CONVERGED;
+                    } else if (early) {
+                        st |= BMPL_SIG_EARLY;
                     } else if (ns == 0) {
                         if (!(st & BMPL_SIG_INEXACT)) st |= BMPL_SIG_CAP_ACTIVE;
                     } else {
@@ -866,6 +886,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     int steps = 0;
     bool inexact = false;
     bool explored = false;
+    bool resolve = false;   // after the pruning: solve on I_t even if no slot outside S violates
 active_set:
     for (;;) {
         grad_slots(s, nI, nS, vg, true);
@@ -885,7 +906,8 @@ active_set:
         }
         __syncthreads();
         int nv = s_cnt;
-        if (nv == 0) break;
+        if (nv == 0 && !resolve) break;
+        resolve = false;
         if (nv > JADD) {
             // keep the JADD largest violations (ties to the lower slot), in slot order: adding a few at a
             // time keeps sign changes, and with them drops, rare when many atoms of I violate at once
@@ -912,7 +934,9 @@ active_set:
             __syncthreads();
             nv = JADD;
         }
-        if (zs) {
+        if (nv == 0) {
+            // nothing to append: the pruned problem on I_t is solved from u restricted to it
+        } else if (zs) {
             append_list(s, nS, s_list, nv, vg, w.n, zs, a.phase ? a.phase + 6 : nullptr);
         } else {
             for (int e = 0; e < nv; ++e) {
@@ -1050,6 +1074,7 @@ active_set:
                 s.G[(int64_t)u * K + q] = val;
             }
             __syncthreads();
+            resolve = true;
             goto active_set;
         }
     }
@@ -1144,7 +1169,9 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     }
     const double rn = block_sum(rr, red);
     if (tid == 0) {
+        w.obj_prev[sig] = w.obj[sig];
         w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
+        w.rr2[sig] = rn;
         if (w.rnorm) w.rnorm[sig] = sqrt(rn);
     }
     if (w.R8) write_residual_fp8(w, sig, red);

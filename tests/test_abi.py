@@ -37,6 +37,7 @@ def test_options_default(lib):
     assert lib.bmpl_options_default(ctypes.byref(o)) == 0
     assert o.rho == 10 and o.max_outer == 0 and o.max_active == 0 and o.kkt_tol == 1e-4 and o.screen == 0
     assert o.omega == 1 and o.flags == 0
+    assert o.eps_early == 0.0 and o.r_inf_rel == 0.0 and o.r2_rel == 0.0
     assert lib.bmpl_options_default(None) == -1
 
 
@@ -63,7 +64,14 @@ def test_argument_errors_without_gpu(lib):
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
     o.omega = 7                                  # omega * rho > 64
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
-    o.omega, o.screen = 1, 9
+    o.omega = 1
+    for field in ("eps_early", "r_inf_rel", "r2_rel"):   # early-stop tolerances: finite, >= 0
+        for bad in (-1e-3, float("nan"), float("inf")):
+            setattr(o, field, bad)
+            assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
+            assert b"eps_early" in lib.bmpl_last_error()
+        setattr(o, field, 0.0)
+    o.screen = 9
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -4
     assert h.value is None
     assert lib.bmpl_solve(None, None, 4, 1, None, None, 0, None, None) == -1
