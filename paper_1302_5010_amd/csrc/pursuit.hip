@@ -1118,8 +1118,9 @@ active_set:
 // Residual xi = b - A_S x_S (float64 accumulation, stored float32) and the
 // objective lambda ||x||_1 + 1/2 ||xi||^2 of every signal that was just solved
 // (step 7 of Algorithm 1).  One workgroup per signal reads its support's atom
-// columns straight from the atom-major dictionary; little LDS, so every signal
-// of the batch can be resident at once.
+// columns straight from the atom-major dictionary, four rows per thread and eight
+// atoms' loads in flight; little LDS, so every signal of the batch can be
+// resident at once.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
 {
@@ -1148,24 +1149,47 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
     float* Rres = w.R + (int64_t)sig * w.kpad;
     double rr = 0.0;
-    for (int r = tid; r < w.kpad; r += NT) {
-        double acc = (double)bw[r];
+    // rows 4 q .. 4 q + 3 per step (kpad and lda are multiples of 4)
+    const int n4 = w.kpad / 4;
+    const int64_t lda4 = a.lda / 4;
+    const float4* At4 = reinterpret_cast<const float4*>(a.At);
+    constexpr int CH = 8;
+    for (int q = tid; q < n4; q += NT) {
+        const float4 bv = reinterpret_cast<const float4*>(bw)[q];
+        double acc[4] = {(double)bv.x, (double)bv.y, (double)bv.z, (double)bv.w};
         int k = 0;
-        for (; k + 4 <= nS; k += 4) {
-            const float a0 = a.At[(int64_t)satom[k] * a.lda + r];
-            const float a1 = a.At[(int64_t)satom[k + 1] * a.lda + r];
-            const float a2 = a.At[(int64_t)satom[k + 2] * a.lda + r];
-            const float a3 = a.At[(int64_t)satom[k + 3] * a.lda + r];
-            acc -= (double)a0 * sx[k];
-            acc -= (double)a1 * sx[k + 1];
-            acc -= (double)a2 * sx[k + 2];
-            acc -= (double)a3 * sx[k + 3];
+        for (; k + CH <= nS; k += CH) {
+            float4 f[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) f[e] = At4[(int64_t)satom[k + e] * lda4 + q];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const double xv = sx[k + e];
+                acc[0] -= (double)f[e].x * xv;
+                acc[1] -= (double)f[e].y * xv;
+                acc[2] -= (double)f[e].z * xv;
+                acc[3] -= (double)f[e].w * xv;
+            }
         }
-        for (; k < nS; ++k) acc -= (double)a.At[(int64_t)satom[k] * a.lda + r] * sx[k];
-        if (r >= w.n) acc = 0.0;
-        Rres[r] = (float)acc;
-        if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round((float)acc);
-        rr += acc * acc;
+        for (; k < nS; ++k) {
+            const float4 f = At4[(int64_t)satom[k] * lda4 + q];
+            const double xv = sx[k];
+            acc[0] -= (double)f.x * xv;
+            acc[1] -= (double)f.y * xv;
+            acc[2] -= (double)f.z * xv;
+            acc[3] -= (double)f.w * xv;
+        }
+        float4 out;
+        float* o = reinterpret_cast<float*>(&out);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 4 * q + e;
+            if (r >= w.n) acc[e] = 0.0;
+            o[e] = (float)acc[e];
+            if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round(o[e]);
+            rr += acc[e] * acc[e];
+        }
+        reinterpret_cast<float4*>(Rres)[q] = out;
     }
     const double rn = block_sum(rr, red);
     if (tid == 0) {

@@ -54,6 +54,29 @@ __global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict_
     if (threadIdx.x == 0) norms[j] = (float)sqrt(red[0] + red[1] + red[2] + red[3]) * (1.0f + 1e-6f);
 }
 
+// x . y over n4 float4 (float32 data, float64 accumulation) by one wave; every lane gets the sum.
+// Eight 16-byte loads of each operand per lane are in flight before the first is used.
+__device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4* __restrict__ y, int n4, int lane)
+{
+    constexpr int CH = 8;
+    double acc = 0.0;
+    for (int q0 = lane; q0 < n4; q0 += 64 * CH) {
+        float4 fx[CH], fy[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = q0 + 64 * e;
+            fx[e] = q < n4 ? x[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            fy[e] = q < n4 ? y[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int e = 0; e < CH; ++e)
+            acc += (double)fx[e].x * fy[e].x + (double)fx[e].y * fy[e].y + (double)fx[e].z * fy[e].z +
+                   (double)fx[e].w * fy[e].w;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return acc;
+}
+
 template <int KMAX>
 __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
 {
@@ -74,13 +97,72 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
         const int room = a.max_active - a.nI[sig];
         k = room < k ? (room > 0 ? room : 0) : k;
     }
-    // Pass 1: the k largest |g~| outside I (values only) and the largest |g~| overall.
+    // Pass 1: the k largest |g~| outside I (values only) and the largest |g~| overall, in two sweeps:
+    // each thread's maximum first (the k-th largest of the 256 thread maxima bounds the k-th largest
+    // entry from below), then per-thread sorted lists of only the entries at or above that bound.
+    const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
+    const int m4 = vec4 ? (a.m & ~3) : 0;
+    // visit(|g~_j|, outside I) for every atom, in increasing j per thread
+    auto scan = [&](auto&& visit) {
+        constexpr int CH = 8;   // loads per thread issued before the first is used
+        for (int base = 4 * tid; base < m4; base += 1024 * CH) {
+            float4 f[CH];
+            uint32_t word[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int j0 = base + 1024 * q;
+                const bool in = j0 < m4;
+                f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                if (base + 1024 * q >= m4) break;
+                visit(fabsf(f[q].x), !(word[q] & 1u));
+                visit(fabsf(f[q].y), !(word[q] & 2u));
+                visit(fabsf(f[q].z), !(word[q] & 4u));
+                visit(fabsf(f[q].w), !(word[q] & 8u));
+            }
+        }
+        for (int j = m4 + tid; j < a.m; j += 256)
+            visit(fabsf(g[j]), !(ex && ((ex[j >> 5] >> (j & 31)) & 1u)));
+    };
+    float gall = 0.f, tmax = -1.f;
+    scan([&](float v, bool out) {
+        gall = fmaxf(gall, v);
+        if (out) tmax = fmaxf(tmax, v);
+    });
+    {
+        float cur = tmax;
+        for (int r = 0; r < k; ++r) {
+            float b = cur;
+            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            if (lane == 0) s_top[wave][r] = b;
+            const unsigned long long owners = __ballot(cur == b);
+            if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float T = INFINITY;
+        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        for (int r = 0; r < k; ++r) {
+            const float v0 = p0 < k ? s_top[0][p0] : -3.f, v1 = p1 < k ? s_top[1][p1] : -3.f;
+            const float v2 = p2 < k ? s_top[2][p2] : -3.f, v3 = p3 < k ? s_top[3][p3] : -3.f;
+            const float b = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+            T = b;
+            if (b == v0) ++p0; else if (b == v1) ++p1; else if (b == v2) ++p2; else ++p3;
+        }
+        s_red[4] = T;
+    }
+    __syncthreads();
+    const float T = s_red[4];
+    __syncthreads();
     float top[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) top[q] = -1.f;
-    float gall = 0.f;
-    auto consider = [&](float v) {
-        if (!(v > top[KMAX - 1])) return;
+    auto consider = [&](float v, bool out) {
+        if (!out || !(v >= T) || !(v > top[KMAX - 1])) return;
         float cv = v;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) {
@@ -90,24 +172,7 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
             cv = sw ? t : cv;
         }
     };
-    const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
-    const int m4 = vec4 ? (a.m & ~3) : 0;
-    for (int j0 = 4 * tid; j0 < m4; j0 += 1024) {
-        const float4 f = *reinterpret_cast<const float4*>(g + j0);
-        const float v0 = fabsf(f.x), v1 = fabsf(f.y), v2 = fabsf(f.z), v3 = fabsf(f.w);
-        gall = fmaxf(gall, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
-        const uint32_t word = ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
-        if (!(word & 1u)) consider(v0);
-        if (!(word & 2u)) consider(v1);
-        if (!(word & 4u)) consider(v2);
-        if (!(word & 8u)) consider(v3);
-    }
-    for (int j = m4 + tid; j < a.m; j += 256) {
-        const float v = fabsf(g[j]);
-        gall = fmaxf(gall, v);
-        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-        consider(v);
-    }
+    if (T <= FLT_MAX) scan(consider);
     for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
     // wave merge of the per-thread lists: k rounds of a wave max on the heads
     for (int r = 0; r < k; ++r) {
@@ -145,20 +210,33 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
 
     // Pass 2: collect the candidates.
     int* cand = a.cand + (int64_t)sig * a.candcap;
-    for (int j0 = 0; j0 < a.m; j0 += 256) {
-        const int j = j0 + tid;
-        bool take = false;
-        if (j < a.m && !(ex && ((ex[j >> 5] >> (j & 31)) & 1u))) {
-            const double u = (double)fabsf(g[j]) + eps;
-            take = (u > thr) || (u >= thr_max);
+    constexpr int CH = 8;   // loads per thread issued before the first is used
+    for (int b0 = 0; b0 < a.m; b0 += 256 * CH) {
+        float v[CH];
+        uint32_t word[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int j = b0 + 256 * q + tid;
+            const bool in = j < a.m;
+            v[q] = in ? fabsf(g[j]) : 0.f;
+            word[q] = (ex && in) ? ex[j >> 5] : 0u;
         }
-        const unsigned long long bal = __ballot(take);
-        int base = 0;
-        if (lane == 0 && bal) base = atomicAdd(&s_cnt, __popcll(bal));
-        base = __shfl(base, 0);
-        if (take) {
-            const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
-            if (pos < a.candcap) cand[pos] = j;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int j = b0 + 256 * q + tid;
+            bool take = false;
+            if (j < a.m && !((word[q] >> (j & 31)) & 1u)) {
+                const double u = (double)v[q] + eps;
+                take = (u > thr) || (u >= thr_max);
+            }
+            const unsigned long long bal = __ballot(take);
+            int base = 0;
+            if (lane == 0 && bal) base = atomicAdd(&s_cnt, __popcll(bal));
+            base = __shfl(base, 0);
+            if (take) {
+                const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+                if (pos < a.candcap) cand[pos] = j;
+            }
         }
     }
     __syncthreads();
@@ -204,14 +282,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     __syncthreads();
     auto score = [&](int c) {     // by one wave; returns in every lane
         const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)cand[c] * a.lda);
-        const float4* r4 = reinterpret_cast<const float4*>(s_r);
-        double acc = 0.0;
-        for (int q = lane; q < a.kpad / 4; q += 64) {
-            const float4 x = aj[q], y = r4[q];
-            acc += (double)x.x * y.x + (double)x.y * y.y + (double)x.z * y.z + (double)x.w * y.w;
-        }
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        return fabs(acc);
+        return fabs(wave_dot_f64(aj, reinterpret_cast<const float4*>(s_r), a.kpad / 4, lane));
     };
     // Stage 1: the candidates ranked among the first k by |g~| (ties to the lower atom).
     for (int c = wave; c < nc; c += 4) {
@@ -334,13 +405,7 @@ __global__ __launch_bounds__(256) void rank8_kernel(Rank8Args a)
     for (int c = wave; c < nc; c += 4) {
         const int j = a.cand[(int64_t)sig * a.candcap + c];
         const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)j * a.lda);
-        const float4* r4 = reinterpret_cast<const float4*>(r);
-        double acc = 0.0;
-        for (int q = lane; q < a.kpad / 4; q += 64) {
-            const float4 x = aj[q], y = r4[q];
-            acc += (double)x.x * y.x + (double)x.y * y.y + (double)x.z * y.z + (double)x.w * y.w;
-        }
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        const double acc = wave_dot_f64(aj, reinterpret_cast<const float4*>(r), a.kpad / 4, lane);
         if (lane == 0) { s_val[c] = fabs(acc); s_idx[c] = j; }
     }
     __syncthreads();

@@ -3,10 +3,14 @@
 // (the natural stopping condition, Eq. (9), fails exactly for these), at most k
 // of them, largest first, ties to the lower atom index.
 //
-// One 256-thread workgroup per signal streams its row of correlations once
-// (coalesced).  Each thread keeps a sorted top-KMAX list in registers; each
-// wave then merges its 64 lists with k rounds of a wave-wide argmax on the list
-// heads (cross-lane shuffles, no LDS); the four wave lists are ranked in LDS.
+// One 256-thread workgroup per signal streams its row of correlations twice
+// (coalesced, eight 16-byte loads per thread in flight before any is used): the
+// first pass finds each thread's maximum, whose k-th largest over the workgroup
+// bounds the row's k-th largest from below; in the second pass each thread keeps
+// a sorted top-KMAX list in registers of the entries at or above that bound (few,
+// so the list insertions that dominated a single pass are rare).  Each wave then
+// merges its 64 lists with k rounds of a wave-wide argmax on the list heads
+// (cross-lane shuffles, no LDS); the four wave lists are ranked in LDS.
 // On the first pass of the relative lambda rule the row maximum is reduced first
 // and lambda_i = c * ||A^T b_i||_inf is set from it (Section IV-A).
 #include <float.h>
@@ -71,15 +75,79 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     if (tid == 0) s_lam = a.lam[sig];
     __syncthreads();
     const double lam = s_lam;
+    // (double)v > lam  <=>  v > lamf for every float v, with lamf the largest float <= lam
+    float lamf = (float)lam;
+    if ((double)lamf > lam) lamf = nextafterf(lamf, -INFINITY);
 
+    // visit(j, |g_j|) for every atom outside I, in increasing j per thread
+    auto scan = [&](auto&& visit) {
+        constexpr int CH = 8;   // float4 loads per thread issued before the first is used
+        for (int base = 4 * tid; base < m4; base += 1024 * CH) {
+            float4 f[CH];
+            uint32_t word[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int j0 = base + 1024 * q;
+                const bool in = j0 < m4;
+                f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int j0 = base + 1024 * q;
+                if (j0 >= m4) break;
+                if (!(word[q] & 1u)) visit(j0, fabsf(f[q].x));
+                if (!(word[q] & 2u)) visit(j0 + 1, fabsf(f[q].y));
+                if (!(word[q] & 4u)) visit(j0 + 2, fabsf(f[q].z));
+                if (!(word[q] & 8u)) visit(j0 + 3, fabsf(f[q].w));
+            }
+        }
+        for (int j = m4 + tid; j < a.m; j += 256) {
+            if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+            visit(j, fabsf(g[j]));
+        }
+    };
+
+    // Pass A: each thread's largest |g_j|.  The k-th largest of the 256 thread maxima is at most the
+    // k-th largest |g_j| of the row (they are k distinct entries of it), so only entries >= T can be
+    // among the k largest and pass B inserts only those.
+    float tmax = -1.f;
+    scan([&](int, float v) { tmax = fmaxf(tmax, v); });
+    float vmx = fmaxf(tmax, 0.f);
+    {
+        float cur = tmax;
+        for (int r = 0; r < k; ++r) {
+            float b = cur;
+            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            if (lane == 0) s_val[wave * KMAX + r] = b;
+            const unsigned long long owners = __ballot(cur == b);
+            if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float T = INFINITY;                        // k = 0: nothing is admitted
+        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;        // merge the four descending wave lists
+        for (int r = 0; r < k; ++r) {
+            const float v0 = p0 < k ? s_val[p0] : -3.f, v1 = p1 < k ? s_val[KMAX + p1] : -3.f;
+            const float v2 = p2 < k ? s_val[2 * KMAX + p2] : -3.f, v3 = p3 < k ? s_val[3 * KMAX + p3] : -3.f;
+            const float bv = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+            T = bv;
+            if (bv == v0) ++p0; else if (bv == v1) ++p1; else if (bv == v2) ++p2; else ++p3;
+        }
+        s_red[0] = T;
+    }
+    __syncthreads();
+    const float T = s_red[0];
+    __syncthreads();
+
+    // Pass B: per-thread sorted top-KMAX lists of the entries >= T that violate.
     float val[KMAX];
     int idx[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) { val[q] = -1.f; idx[q] = INT_MAX; }
-    float vmx = 0.f;
     auto consider = [&](int j, float v) {
-        vmx = fmaxf(vmx, v);
-        if (!((double)v > lam) || !(v > val[KMAX - 1])) return;
+        if (!(v > lamf) || !(v >= T) || !(v > val[KMAX - 1])) return;
         float cv = v;
         int ci = j;
 #pragma unroll
@@ -93,19 +161,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             ci = sw ? ti : ci;
         }
     };
-#pragma unroll 2
-    for (int j0 = 4 * tid; j0 < m4; j0 += 1024) {
-        const float4 f = *reinterpret_cast<const float4*>(g + j0);
-        const uint32_t word = ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
-        if (!(word & 1u)) consider(j0, fabsf(f.x));
-        if (!(word & 2u)) consider(j0 + 1, fabsf(f.y));
-        if (!(word & 4u)) consider(j0 + 2, fabsf(f.z));
-        if (!(word & 8u)) consider(j0 + 3, fabsf(f.w));
-    }
-    for (int j = m4 + tid; j < a.m; j += 256) {
-        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-        consider(j, fabsf(g[j]));
-    }
+    if (T <= FLT_MAX) scan(consider);
     // vmax over the signal (outside I)
     for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
     __syncthreads();
