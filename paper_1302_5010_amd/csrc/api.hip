@@ -463,17 +463,20 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         (void)hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
         if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, c->device) != hipSuccess)
             optin = 0;
-        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(solve_kernel));
-        if (e == hipSuccess) {
+        // both solve kernels get the largest dynamic LDS the device allows; the budget is the smaller
+        size_t dyn = SIZE_MAX;
+        for (const void* fn : {reinterpret_cast<const void*>(solve_kernel), reinterpret_cast<const void*>(solve_block_kernel)}) {
+            e = hipFuncGetAttributes(&fa, fn);
+            if (e != hipSuccess) break;
             size_t total = (size_t)per_block;
             if (optin > per_block &&
-                hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     optin - (int)fa.sharedSizeBytes) == hipSuccess)
                 total = (size_t)optin;
             (void)hipGetLastError();
-            c->lds_dyn_max = total > fa.sharedSizeBytes + 256 ? total - fa.sharedSizeBytes - 256 : 0;
+            dyn = std::min(dyn, total > fa.sharedSizeBytes + 256 ? total - fa.sharedSizeBytes - 256 : (size_t)0);
         }
+        if (e == hipSuccess) c->lds_dyn_max = dyn;
     }
     if (e != hipSuccess) {
         bmpl_status st = fail(e == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP, "bmpl_create: %s",
@@ -763,7 +766,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     };
 
     // Master problem and residual for the running list act[idx] (steps 4-8 of Algorithm 1),
-    // with the factor held in LDS for capacity kl when it fits.
+    // with the factor held in LDS for capacity kl when it fits.  kl must bound |I| of every
+    // running signal after this master solve (the kernel does not check it).
     // `explore`: the pass before selected omega rho candidates (not a warm-start proposal)
     auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated, bool explore) -> bmpl_status {
         const bool ev = tm && !gated;
@@ -785,7 +789,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;
         if (so.zs_lds) lds += block_scratch_bytes(w.K);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
-        hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
+        if (so.zs_lds)
+            hipLaunchKernelGGL(solve_block_kernel, dim3(n_grid), dim3(256), lds, q, so);
+        else
+            hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
         HIPC(hipGetLastError());
         if (ev) {
             const size_t e1 = mark(c, q);
@@ -834,7 +841,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             st = segment_graph(c, p, cur, need, &ge, [&](hipStream_t q) -> bmpl_status {
                 int cc = cur;
                 for (int d = 0; d < GRAPH_DEPTH; ++d) {
-                    bmpl_status r = enqueue_master(q, cc, p, need, true, true);
+                    // factor capacity for this iteration's |I| (a smaller LDS footprint fits more signals per CU)
+                    bmpl_status r = enqueue_master(q, cc, p, std::min(need, imax + (d + 1) * rho), true, true);
                     if (r != BMPL_OK) return r;
                     r = enqueue_select_pass(q, cc, p, false, false, true);
                     if (r != BMPL_OK) return r;

@@ -85,7 +85,8 @@ struct RestrideArgs {
 __global__ void prep_kernel(PrepArgs a);
 __global__ void status_compact_kernel(StatusArgs a);
 __global__ void warm_select_kernel(WarmArgs a);
-__global__ void solve_kernel(SolveArgs a);
+__global__ void solve_kernel(SolveArgs a);         // single appends only (zs_lds ignored)
+__global__ void solve_block_kernel(SolveArgs a);   // block appends when zs_lds
 __global__ void residual_kernel(ResidualArgs a);
 __global__ void pack_kernel(PackArgs a);
 __global__ void restride_kernel(RestrideArgs a);

@@ -426,45 +426,31 @@ __device__ void append_list(Sig& v, int& nS, const int* list, int nv, const doub
 // Rinv, so Rinv^T Rinv = G^{-1} is unchanged for the remaining positions, and the leading
 // (s-1) x (s-1) block is the new inverse factor (rows may change sign, which no product of the solver
 // sees).  One barrier per row: row j's new values land where no later step reads, and the next step's
-// writes (row j + 1) wait until every thread has read the old row j + 1.  The caller shifts the support
-// order.  Returns false (and changes nothing) when a row is longer than the per-thread register budget.
-constexpr int DROP_CT = 16;   // columns per thread: supports up to 16 * NT positions
-__device__ bool chol_drop(Sig& v, int s, int q)
+// writes (row j + 1) wait until every thread has read the old row j + 1.  The moved column's running
+// entries live in `cbuf` (s doubles of scratch, each entry owned by one thread), so the downdate needs
+// no per-thread arrays whatever |S| is.  The caller shifts the support order.
+__device__ void chol_drop(Sig& v, int s, int q, double* cbuf)
 {
     const int tid = threadIdx.x;
-    if (s > DROP_CT * NT) return false;
-    double carry[DROP_CT];
-#pragma unroll
-    for (int t = 0; t < DROP_CT; ++t) {
-        const int c = tid + NT * t;
-        carry[t] = c < q ? v.R[tri(q) + c] : 0.0;
-    }
+    for (int c = tid; c < s; c += NT) cbuf[c] = c < q ? v.R[tri(q) + c] : 0.0;
     double last = v.R[tri(q) + q];
     __syncthreads();
     for (int j = q; j < s - 1; ++j) {
         const double* nx = v.R + tri(j + 1);
         const double b = nx[q];
-        double nxt[DROP_CT];
-#pragma unroll
-        for (int t = 0; t < DROP_CT; ++t) {
-            const int c = tid + NT * t;
-            nxt[t] = c <= j ? nx[c < q ? c : c + 1] : 0.0;
-        }
         const double r = hypot(last, b);
         const double cs = r > 0.0 ? b / r : 1.0;
         const double sn = r > 0.0 ? -last / r : 0.0;
         double* out = v.R + tri(j);
-#pragma unroll
-        for (int t = 0; t < DROP_CT; ++t) {
-            const int c = tid + NT * t;
-            const double nw = cs * carry[t] + sn * nxt[t];
-            carry[t] = -sn * carry[t] + cs * nxt[t];
-            if (c <= j) out[c] = nw;
+        for (int c = tid; c <= j; c += NT) {     // columns past j stay zero in the moved column
+            const double nxt = nx[c < q ? c : c + 1];
+            const double cv = cbuf[c];
+            out[c] = cs * cv + sn * nxt;
+            cbuf[c] = -sn * cv + cs * nxt;
         }
         last = r;
         __syncthreads();
     }
-    return true;
 }
 
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
@@ -747,8 +733,12 @@ __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
 // Working set: the inverse factor Rinv and the per-slot vectors live in LDS
 // when they fit (copied in at entry, written back at exit), otherwise they are
 // used in place in global memory.  G_II (row-major, stride K) stays global.
+// Two kernels share the body: with block appends (for a factor in global memory)
+// and without them, whose register footprint is half as large, so twice as many
+// workgroups fit on a CU.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
+template <bool BLOCK>
+__device__ __forceinline__ void solve_body(const SolveArgs& a)
 {
     extern __shared__ double s_dyn[];
     __shared__ double red[4];
@@ -807,7 +797,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
         vatom = reinterpret_cast<int*>(d + 4 * K);
     }
     // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
-    double* zs = a.zs_lds ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0)) : nullptr;
+    double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0)) : nullptr;
 
     // 1. Load the state, register the new slots.
     if (a.vec_lds) {
@@ -845,12 +835,28 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
     // 2. Gram rows of the new slots and c = A_J^T b, in float64.
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
     if (a.Q) {
-        for (int e = tid; e < nnew * nI; e += NT) {
-            const int t = e / nI, u = e - t * nI;
-            const int q = nI0 + t;
-            const double val = a.Q[(int64_t)vatom[q] * a.ldq + vatom[u]];
-            s.G[(int64_t)q * K + u] = val;
-            s.G[(int64_t)u * K + q] = val;
+        // four table reads per thread in flight before the symmetric stores
+        const int tot = nnew * nI;
+        for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
+            double val[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = e0 + r * NT;
+                if (e < tot) {
+                    const int t = e / nI, u = e - t * nI;
+                    val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = e0 + r * NT;
+                if (e < tot) {
+                    const int t = e / nI, u = e - t * nI;
+                    const int q = nI0 + t;
+                    s.G[(int64_t)q * K + u] = val[r];
+                    s.G[(int64_t)u * K + q] = val[r];
+                }
+            }
         }
         // c_q = a_q^T b: one wave per new atom, float4 loads, all issued before the sums
         for (int t = wave; t < nnew; t += NT / 64) {
@@ -984,24 +990,11 @@ active_set:
                 s.th[u] = 0;
             }
             __syncthreads();
-            if (chol_drop(s, ns_old, q)) {
-                // factor downdated in place; support positions past q move down by one
-                for (int k = q + 1 + tid; k < ns_old; k += NT) s.so[k - 1] = vatom[k];
-                nS = ns_old - 1;
-                __syncthreads();
-            } else if (zs) {
-                nS = q;
-                append_list(s, nS, vatom + q + 1, ns_old - q - 1, nullptr, w.n, zs, a.phase ? a.phase + 6 : nullptr);
-            } else {
-                nS = q;
-                for (int k = q + 1; k < ns_old; ++k) {
-                    const int u = vatom[k];
-                    if (!chol_append(s, nS, u, s.th[u], vw, vz, red, a.phase ? a.phase + 6 : nullptr)) {
-                        if (tid == 0) s.x[u] = 0.0;
-                        __syncthreads();
-                    }
-                }
-            }
+            // downdate the factor in place (vw is free scratch here); support positions past q move down
+            chol_drop(s, ns_old, q, vw);
+            for (int k = q + 1 + tid; k < ns_old; k += NT) s.so[k - 1] = vatom[k];
+            nS = ns_old - 1;
+            __syncthreads();
         }
         if (inexact) break;
     }
@@ -1036,7 +1029,7 @@ active_set:
             if (u < nI0 || s_keep[u - nI0]) continue;
             for (int q = tid; q < nS; q += NT) vatom[q] = s.so[q];   // vatom is scratch after the Gram phase
             __syncthreads();
-            if (!chol_drop(s, nS, k)) { inexact = true; break; }
+            chol_drop(s, nS, k, vw);
             for (int q = k + 1 + tid; q < nS; q += NT) s.so[q - 1] = vatom[q];
             --nS;
             __syncthreads();
@@ -1113,6 +1106,9 @@ active_set:
     __syncthreads();
     phase_mark(5);
 }
+
+__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) { solve_body<false>(a); }
+__global__ __launch_bounds__(256) void solve_block_kernel(SolveArgs a) { solve_body<true>(a); }
 
 // ---------------------------------------------------------------------------
 // Residual xi = b - A_S x_S (float64 accumulation, stored float32) and the
