@@ -91,9 +91,10 @@ typedef enum {
                                        time instead of in blocks of up to 8 (same factor in exact
                                        arithmetic; a diagnostic and comparison switch) */
 
-/* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning): 128x128, 128x256, 256x128,
- * 64x128, 32x64, 64x64 signals x atoms with 64x64 or 32x32 waves, then 256x256 and 128x256 with
- * 128x128 and 64x128 waves. */
+/* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning), signals x atoms (waves of
+ * 64 lanes, each computing the sub-tile in parentheses): 0 128x128 (64x64), 1 256x256 (64x64, 16 waves),
+ * 2 256x128 (64x64), 3 64x128 (32x64), 4 32x64 (32x32), 5 64x64 (32x32), 6 256x256 (128x128, 4 waves),
+ * 7 256x256 (128x64, 8 waves). */
 #define BMPL_CORR_SHAPES 8
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the

@@ -131,13 +131,13 @@ hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad
     if (kpad % (TILE_ROW_BYTES / (int)sizeof(E))) return hipErrorInvalidValue;
     switch (variant) {
     case 0: return launch_shape<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 1: return launch_shape<E, 128, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 1: return launch_shape<E, 256, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 2: return launch_shape<E, 256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 6: return launch_shape<E, 256, 256, 128, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 7: return launch_shape<E, 128, 256, 64, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 7: return launch_shape<E, 256, 256, 128, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -148,13 +148,13 @@ const char* corr_shape_name(int v)
 {
     switch (v) {
     case 0: return "128x128 (4 waves of 64x64)";
-    case 1: return "128x256 (8 waves of 64x64)";
+    case 1: return "256x256 (16 waves of 64x64)";
     case 2: return "256x128 (8 waves of 64x64)";
     case 3: return "64x128 (4 waves of 32x64)";
     case 4: return "32x64 (2 waves of 32x32)";
     case 5: return "64x64 (4 waves of 32x32)";
     case 6: return "256x256 (4 waves of 128x128)";
-    case 7: return "128x256 (4 waves of 64x128)";
+    case 7: return "256x256 (8 waves of 128x64)";
     default: return "?";
     }
 }
