@@ -28,6 +28,7 @@ using namespace bmpl;
 
 namespace {
 
+constexpr int WARM_KL = 64;        // LDS factor capacity of the master solve right after a warm start
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
 constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 2 rho are used)
 
@@ -191,7 +192,7 @@ void free_signals(bmpl_ctx* c)
     Workspace& w = c->w;
     dfree(w.R); dfree(w.bnorm2); dfree(w.lam); dfree(w.status); dfree(w.iters); dfree(w.nI);
     dfree(w.nS); dfree(w.nsel); dfree(w.sel); dfree(w.vmax); dfree(w.kkt_on); dfree(w.obj);
-    dfree(w.kkt); dfree(w.inI); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
+    dfree(w.kkt); dfree(w.inI); dfree(w.glazy); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
@@ -227,6 +228,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     HIPC(dalloc(&w.g0max, P));
     HIPC(dalloc(&w.kkt, P));
     HIPC(dalloc(&w.inI, P * w.words));
+    HIPC(dalloc(&w.glazy, P));
     HIPC(alloc_slots(w, p, K));
     HIPC(dalloc(&c->Bw, P * c->kpad));
     HIPC(dalloc(&c->Gc, P * (size_t)c->ldg));
@@ -766,8 +768,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     };
 
     // Master problem and residual for the running list act[idx] (steps 4-8 of Algorithm 1),
-    // with the factor held in LDS for capacity kl when it fits.  kl must bound |I| of every
-    // running signal after this master solve (the kernel does not check it).
+    // with the factor held in LDS for capacity kl when it fits.  A signal whose support outgrows kl
+    // moves its factor to global memory inside the kernel and continues there (slower), so kl is
+    // |I|'s bound for ordinary passes, where most of I is in S, and smaller after a warm start.
     // `explore`: the pass before selected omega rho candidates (not a warm-start proposal)
     auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated, bool explore) -> bmpl_status {
         const bool ev = tm && !gated;
@@ -862,7 +865,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         st = grow_to(imax);
         if (st != BMPL_OK) return st;
         c->timing.outer_iters += tm ? 1 : 0;
-        st = enqueue_master(s, cur, n_act, imax, false, !after_warm);
+        // a warm start's proposal is mostly zeros: an LDS factor for WARM_KL support positions
+        st = enqueue_master(s, cur, n_act, after_warm ? std::min(imax, WARM_KL) : imax, false, !after_warm);
         if (st != BMPL_OK) return st;
         st = enqueue_select_pass(s, cur, n_act, false, after_warm, false);
         if (st != BMPL_OK) return st;

@@ -46,6 +46,8 @@ struct Workspace {
     float* g0max;       // [p] ||A^T b_i||_inf from the first correlation pass (Eq. (10))
     double* kkt;        // [p] final certificate (relative to lambda_i)
     uint32_t* inI;      // [p][words] membership bitmap of I
+    int* glazy;         // [p] 1: G holds only the entries against S members (and the diagonal); a slot's
+                        //     column is gathered when it enters S (set once a pass adds many slots)
     int* slot_atom;     // [p][K]
     double* x;          // [p][K] coefficient per slot
     double* c;          // [p][K] a_u^T b per slot

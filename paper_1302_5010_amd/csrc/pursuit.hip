@@ -36,7 +36,8 @@ namespace {
 constexpr int NT = 256;
 constexpr int NB = 16;      // new atoms per Gram pass
 constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
-constexpr int JADD = 16;    // violators added to S per active-set step (the largest ones)
+constexpr int JADD = 8;     // violators added to S per active-set step (the largest ones)
+constexpr int LAZY_MIN = 32;   // new slots in one pass above which the Gram matrix is kept lazily
 constexpr int JB = SOLVE_JB;   // atoms per block factor append
 
 __device__ inline double block_sum(double v, double* red)
@@ -599,6 +600,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.nI[sig] = 0;
         w.nS[sig] = 0;
         w.nsel[sig] = 0;
+        w.glazy[sig] = 0;
         w.vmax[sig] = 0.f;
         w.kkt_on[sig] = 0.0;
         w.kkt[sig] = 0.0;
@@ -772,11 +774,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
 
     Sig s;
     s.K = K;
-    s.r_lds = a.rinv_lds != 0;
+    // The LDS factor holds up to a.kl support positions; a signal whose support outgrows it moves its
+    // factor to the global home and continues there (spill_factor below).
+    s.r_lds = a.rinv_lds != 0 && nS <= a.kl;
     s.G = w.G + (int64_t)sig * K * K;
     char* lp = reinterpret_cast<char*>(s_dyn);
     if (a.rinv_lds) {
-        s.R = reinterpret_cast<double*>(lp);
+        s.R = s.r_lds ? reinterpret_cast<double*>(lp) : g_R;
         lp += sizeof(double) * tri(a.kl);
     } else {
         s.R = g_R;
@@ -806,7 +810,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         }
         for (int k = tid; k < nS; k += NT) s.so[k] = g_so[k];
     }
-    if (a.rinv_lds)
+    if (s.r_lds)
         for (int64_t e = tid; e < tri(nS); e += NT) s.R[e] = g_R[e];
     for (int u = tid; u < nI0; u += NT) vatom[u] = g_atom[u];
     for (int t = tid; t < nnew; t += NT) {
@@ -832,9 +836,40 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     };
     phase_mark(0);
 
-    // 2. Gram rows of the new slots and c = A_J^T b, in float64.
+    // 2. Gram rows of the new slots and c = A_J^T b, in float64.  With many new slots (a warm start)
+    //    the Gram matrix is kept lazily from then on: a new slot's row only against the support
+    //    members and itself, and a slot's whole column when it enters S (gather_cols below), which is
+    //    every entry the solver reads.  Most proposed slots never enter S.
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
-    if (a.Q) {
+    const bool lazy = a.Q && (w.glazy[sig] != 0 || nnew > LAZY_MIN);
+    if (a.Q && lazy) {
+        if (tid == 0) w.glazy[sig] = 1;
+        const int span = nS + 1;                  // support positions, then the diagonal
+        const int tot = nnew * span;
+        for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
+            double val[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = e0 + r * NT;
+                if (e < tot) {
+                    const int t = e / span, k = e - t * span;
+                    const int u = k < nS ? s.so[k] : nI0 + t;
+                    val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = e0 + r * NT;
+                if (e < tot) {
+                    const int t = e / span, k = e - t * span;
+                    const int q = nI0 + t;
+                    const int u = k < nS ? s.so[k] : q;
+                    s.G[(int64_t)q * K + u] = val[r];
+                    s.G[(int64_t)u * K + q] = val[r];
+                }
+            }
+        }
+    } else if (a.Q) {
         // four table reads per thread in flight before the symmetric stores
         const int tot = nnew * nI;
         for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
@@ -858,6 +893,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
                 }
             }
         }
+    }
+    if (a.Q) {
         // c_q = a_q^T b: one wave per new atom, float4 loads, all issued before the sums
         for (int t = wave; t < nnew; t += NT / 64) {
             const float4* aj = reinterpret_cast<const float4*>(a.At + (int64_t)vatom[nI0 + t] * a.lda);
@@ -939,6 +976,39 @@ active_set:
             if (keep) s_list[before + __popcll(bal & ((1ull << lane) - 1ull))] = u;
             __syncthreads();
             nv = JADD;
+        }
+        if (lazy && nv > 0) {
+            // lazy Gram: the columns of the slots about to enter S, against every slot of I
+            const int tot = nv * nI;
+            for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
+                double val[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = e0 + r * NT;
+                    if (e < tot) {
+                        const int t = e / nI, u2 = e - t * nI;
+                        val[r] = a.Q[(int64_t)g_atom[s_list[t]] * a.ldq + g_atom[u2]];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = e0 + r * NT;
+                    if (e < tot) {
+                        const int t = e / nI, u2 = e - t * nI;
+                        const int j = s_list[t];
+                        s.G[(int64_t)j * K + u2] = val[r];
+                        s.G[(int64_t)u2 * K + j] = val[r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (s.r_lds && nS + nv > a.kl) {
+            // the support outgrows the LDS factor: move it to the global home and continue there
+            for (int64_t e = tid; e < tri(nS); e += NT) g_R[e] = s.R[e];
+            __syncthreads();
+            s.R = g_R;
+            s.r_lds = false;
         }
         if (nv == 0) {
             // nothing to append: the pruned problem on I_t is solved from u restricted to it
@@ -1094,7 +1164,7 @@ active_set:
         }
         for (int k = tid; k < nS; k += NT) g_so[k] = s.so[k];
     }
-    if (a.rinv_lds)
+    if (s.r_lds)
         for (int64_t i = tid; i < tri(nS); i += NT) g_R[i] = s.R[i];
     if (tid == 0) {
         w.nI[sig] = nI;

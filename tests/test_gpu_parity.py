@@ -269,6 +269,52 @@ def test_warm_start_proposals_keep_parity():
     assert np.all(st[1::4] & pk.BMPL_SIG_FALLBACK)              # junk proposals needed the pursuit
 
 
+@pytest.mark.parametrize("block_append,graph", [(True, False), (False, True)])
+def test_large_warm_proposals(block_append, graph):
+    """Proposals of 200 atoms: past 32 new slots in one pass the Gram matrix is kept lazily (entries
+    against support members only, a slot's column gathered when it enters S).  Truth plus junk, all junk
+    and truth alone, with block and single factor appends."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=256, m=2000, p=48, k=30, sigma=0.01, seed=91, rho=7)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    rng = np.random.default_rng(11)
+    warm = np.full((P.p, 200), -1, dtype=np.int32)
+    for i in range(P.p):
+        truth = list(P.supports[i])
+        junk = [int(j) for j in rng.permutation(P.m) if j not in truth]
+        prop = {0: truth + junk[:200 - len(truth)], 1: junk[:200], 2: truth}[i % 3]
+        warm[i, :len(prop)] = prop
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, block_append=block_append, graph=graph)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam), warm=to_dev(warm))
+    st = out["status"].cpu().numpy()
+    assert np.all(st & pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+    check_batch(P.At, P.Bt, lam, out, ref)
+    assert np.all(st[1::3] & pk.BMPL_SIG_FALLBACK)
+
+
+def test_warm_start_support_outgrows_the_lds_factor():
+    """A warm start whose support passes the 64 positions the first master solve keeps in LDS: the
+    factor moves to global memory mid-solve and the result keeps parity."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=320, m=3000, p=24, k=90, sigma=0.01, seed=93, lambda_rel=0.01, rho=10)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    rng = np.random.default_rng(12)
+    warm = np.full((P.p, 160), -1, dtype=np.int32)
+    for i in range(P.p):
+        truth = list(P.supports[i])
+        junk = [int(j) for j in rng.permutation(P.m) if j not in truth]
+        prop = truth + junk[:160 - len(truth)]
+        warm[i, :len(prop)] = prop
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam), warm=to_dev(warm))
+    st = out["status"].cpu().numpy()
+    assert np.all(st & pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    assert out["supp_len"].cpu().numpy().max() > 64
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+    check_batch(P.At, P.Bt, lam, out, ref)
+
+
 @pytest.mark.slow
 def test_cs_gaussian_full_size_sampled():
     """2048 x 16384 dictionary, 1024 signals, rho = 10: the benchmark's workload and launch;
