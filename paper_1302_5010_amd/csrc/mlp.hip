@@ -330,9 +330,16 @@ __global__ __launch_bounds__(256) void params_bf16_kernel(const float* __restric
 
 // ---------------------------------------------------------------------------
 // Top-k per row (k <= 256), ties to the lower index, output ascending by atom index,
-// padded with -1 when the row is shorter than k.  One workgroup per row: the row's order
-// keys sit in LDS; four 8-bit radix passes find the k-th largest key T and how many keys
-// equal to T to take; a final pass compacts in index order.
+// padded with -1 when the row is shorter than k.  One workgroup per row.
+//   1. Each thread keeps the two largest order keys of its entries; the k-th largest of
+//      those 512 keys, T, is at most the row's k-th largest key (they are distinct
+//      entries of the row), so every entry of the top k has a key >= T.
+//   2. Each wave compacts, in index order, the entries of its quarter of the row with a
+//      key >= T (typically a few hundred in all) into LDS as (key, index) pairs.
+//   3. A bitonic sort orders the candidates by key, then lower index; the first k are
+//      the answer, whose indices a second bitonic sort puts in ascending order.
+// If a quarter holds more candidates than its LDS share (many equal keys), the row is
+// done by an exact radix select over the keys in global memory instead.
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t order_key(float x)
 {
@@ -356,25 +363,132 @@ __device__ inline int block_excl_count(bool flag, int* s_wave, int& total)
     return before + within;
 }
 
+// In-place bitonic sort of N (a power of two) LDS elements by 256 threads, descending or ascending.
+template <class T, int N, bool DESC>
+__device__ inline void bitonic_sort(T* v)
+{
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < N / 2; t += 256) {
+                const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));   // stride is a power of two
+                const int j = i + stride;
+                const bool first_up = ((i & size) == 0) == DESC;   // this block ends in the final order
+                const T x = v[i], y = v[j];
+                if (first_up ? (x < y) : (x > y)) { v[i] = y; v[j] = x; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int TOPK_CAP = 2048;   // candidates per row in LDS, a quarter per wave
+
 __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, int64_t lds, int L, int k,
                                                    int* __restrict__ out, int64_t ldo)
 {
-    extern __shared__ uint32_t keys[];
+    __shared__ uint32_t s_t[512];
+    __shared__ uint64_t s_c[TOPK_CAP];
+    __shared__ int s_sel[256];
+    __shared__ int s_over;
     __shared__ int hist[256];
     __shared__ int s_digit, s_need;
     __shared__ int s_wave[4];
     const int row = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float* s = S + (int64_t)row * lds;
-    for (int j = tid; j < L; j += 256) keys[j] = order_key(s[j]);
+    int* o = out + (int64_t)row * ldo;
+    const int kk = k < L ? k : L;
+
+    // 1. per-thread two largest keys, then their kk-th largest over the workgroup
+    uint32_t t1 = 0u, t2 = 0u;
+    for (int j0 = tid; j0 < L; j0 += 256 * 4) {
+        uint32_t key[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = j0 + 256 * e;
+            key[e] = j < L ? order_key(s[j]) : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t u = key[e];
+            if (u > t1) { t2 = t1; t1 = u; } else if (u > t2) { t2 = u; }
+        }
+    }
+    s_t[2 * tid] = t1;
+    s_t[2 * tid + 1] = t2;
+    if (tid == 0) s_over = 0;
+    __syncthreads();
+    bitonic_sort<uint32_t, 512, true>(s_t);
+    const uint32_t T = kk > 0 ? s_t[kk - 1] : 0xFFFFFFFFu;
+
+    // 2. per-wave ordered compaction of the keys >= T over the wave's quarter of the row
+    constexpr int CW = TOPK_CAP / 4;
+    const int q4 = (L + 3) / 4;
+    const int lo = wave * q4, hi = lo + q4 < L ? lo + q4 : L;
+    int cnt = 0;
+    uint64_t* mine = s_c + wave * CW;
+    for (int b0 = lo; b0 < hi; b0 += 64 * 4) {
+        uint32_t key[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = b0 + 64 * e + lane;
+            key[e] = j < hi ? order_key(s[j]) : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = b0 + 64 * e + lane;
+            const bool take = j < hi && key[e] >= T && kk > 0;
+            const uint64_t bal = __ballot(take);
+            const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+            if (take && pos < CW) mine[pos] = ((uint64_t)key[e] << 32) | (uint64_t)(~(uint32_t)j);
+            cnt += __popcll(bal);
+        }
+    }
+    if (cnt > CW && lane == 0) s_over = 1;
+    for (int q = cnt + lane; q < CW; q += 64) mine[q] = 0ull;   // below every real (key, index) pair
+    __syncthreads();
+
+    if (!s_over) {
+        // 3. gather the four quarters' candidates to the front (through registers: the moves overlap),
+        //    order them, take the first kk, list their indices ascending
+        if (lane == 0) s_wave[wave] = cnt;
+        __syncthreads();
+        const int off = (wave > 0 ? s_wave[0] : 0) + (wave > 1 ? s_wave[1] : 0) + (wave > 2 ? s_wave[2] : 0);
+        const int c = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        uint64_t mv[CW / 64];
+#pragma unroll
+        for (int q = 0; q < CW / 64; ++q) mv[q] = mine[lane + 64 * q];
+        __syncthreads();
+        int N = 256;
+        while (N < c) N <<= 1;
+#pragma unroll
+        for (int q = 0; q < CW / 64; ++q) {
+            const int e = lane + 64 * q;
+            if (e < cnt) s_c[off + e] = mv[q];
+        }
+        for (int e = c + tid; e < N; e += 256) s_c[e] = 0ull;
+        __syncthreads();
+        if (N == 256) bitonic_sort<uint64_t, 256, true>(s_c);
+        else if (N == 512) bitonic_sort<uint64_t, 512, true>(s_c);
+        else if (N == 1024) bitonic_sort<uint64_t, 1024, true>(s_c);
+        else bitonic_sort<uint64_t, TOPK_CAP, true>(s_c);
+        s_sel[tid] = tid < kk ? (int)(~(uint32_t)(s_c[tid] & 0xFFFFFFFFull)) : 0x7FFFFFFF;
+        __syncthreads();
+        bitonic_sort<int, 256, false>(s_sel);
+        if (tid < k) o[tid] = tid < kk ? s_sel[tid] : -1;
+        return;
+    }
+
+    // Fallback: exact radix select over the keys in global memory.  Four 8-bit passes find the
+    // kk-th largest key P and how many keys equal to P to take; a final pass compacts in index order.
     uint32_t prefix = 0u, mask = 0u;
-    int need = k < L ? k : L;
+    int need = kk;
     if (need > 0) {
         for (int shift = 24; shift >= 0; shift -= 8) {
             hist[tid] = 0;
             __syncthreads();
             for (int j = tid; j < L; j += 256) {
-                const uint32_t u = keys[j];
+                const uint32_t u = order_key(s[j]);
                 if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
             }
             __syncthreads();
@@ -396,21 +510,20 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, 
     }
     // keys > prefix are all taken; `need` keys equal to prefix, the lowest indices first
     int base_out = 0, base_tie = 0;
-    const int kk = k < L ? k : L;
     for (int c0 = 0; c0 < L && kk > 0; c0 += 256) {
         const int j = c0 + tid;
-        const uint32_t u = j < L ? keys[j] : 0u;
+        const uint32_t u = j < L ? order_key(s[j]) : 0u;
         const bool gt = j < L && u > prefix;
         const bool eq = j < L && u == prefix;
         int tot_eq, tot_sel;
         const int tie_rank = base_tie + block_excl_count(eq, s_wave, tot_eq);
         const bool sel = gt || (eq && tie_rank < need);
         const int pos = base_out + block_excl_count(sel, s_wave, tot_sel);
-        if (sel) out[(int64_t)row * ldo + pos] = j;
+        if (sel) o[pos] = j;
         base_tie += tot_eq;
         base_out += tot_sel;
     }
-    for (int q = base_out + tid; q < k; q += 256) out[(int64_t)row * ldo + q] = -1;
+    for (int q = base_out + tid; q < k; q += 256) o[q] = -1;
 }
 
 }  // namespace
@@ -506,14 +619,8 @@ hipError_t mlp_topk(const float* S, int64_t lds, int rows, int L, int k, int* ou
 {
     if (rows <= 0) return hipSuccess;
     if (k < 1 || k > 256 || L < 1 || ldo < k) return hipErrorInvalidValue;
-    const size_t bytes = (size_t)L * 4;
-    if (bytes > TOPK_MAX_LDS) return hipErrorInvalidValue;
-    if (bytes > 65536) {   // raise the kernel's dynamic LDS limit (an attribute of the current device)
-        hipError_t e = hipFuncSetAttribute((const void*)topk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)TOPK_MAX_LDS);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(topk_kernel, dim3(rows), dim3(256), bytes, s, S, lds, L, k, out, ldo);
+    if ((size_t)L * 4 > TOPK_MAX_LDS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(topk_kernel, dim3(rows), dim3(256), 0, s, S, lds, L, k, out, ldo);
     return hipGetLastError();
 }
 
