@@ -135,7 +135,10 @@ hipError_t launch_gemm(const uint16_t* X, int64_t ldx, int M, const uint16_t* W,
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (kpad <= 0 || kpad % 64 || ldx % 8 || ldw % 8 || ldx < kpad || ldw < kpad) return hipErrorInvalidValue;
-    // large outputs: 128 x 128 tiles of four 64 x 64 waves; small ones: 64 x 64 tiles of 32 x 32 waves
+    // very large outputs (four or more rounds of 256 x 256 tiles on 256 CUs): eight 128 x 64 waves per
+    // tile; large ones: 128 x 128 tiles of four 64 x 64 waves; small ones: 64 x 64 tiles of 32 x 32 waves
+    if ((int64_t)((M + 255) / 256) * ((N + 255) / 256) >= 1024)
+        return launch_gemm_shape<256, 256, 128, 64>(X, ldx, M, W, ldw, N, kpad, epi, s);
     if ((int64_t)((M + 127) / 128) * ((N + 127) / 128) >= 512)
         return launch_gemm_shape<128, 128, 64, 64>(X, ldx, M, W, ldw, N, kpad, epi, s);
     return launch_gemm_shape<64, 64, 32, 32>(X, ldx, M, W, ldw, N, kpad, epi, s);
