@@ -36,7 +36,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int NB = 16;      // new atoms per Gram pass
 constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
-constexpr int JADD = 8;     // violators added to S per active-set step (the largest ones)
+constexpr int JADD = 8;     // most violators added to S per active-set step (the largest ones)
 constexpr int LAZY_MIN = 32;   // new slots in one pass above which the Gram matrix is kept lazily
 constexpr int JB = SOLVE_JB;   // atoms per block factor append
 
@@ -930,6 +930,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     bool inexact = false;
     bool explored = false;
     bool resolve = false;   // after the pruning: solve on I_t even if no slot outside S violates
+    // Violators admitted per step, adapted to the dictionary: halved after a step whose move to the
+    // sign-fixed minimiser dropped atoms (correlated atoms enter and leave), doubled (up to JADD) after a
+    // clean one.
+    int jadd = JADD;
 active_set:
     for (;;) {
         grad_slots(s, nI, nS, vg, true);
@@ -951,8 +955,8 @@ active_set:
         int nv = s_cnt;
         if (nv == 0 && !resolve) break;
         resolve = false;
-        if (nv > JADD) {
-            // keep the JADD largest violations (ties to the lower slot), in slot order: adding a few at a
+        if (nv > jadd) {
+            // keep the jadd largest violations (ties to the lower slot), in slot order: adding a few at a
             // time keeps sign changes, and with them drops, rare when many atoms of I violate at once
             int u = -1, rank = 0;
             double gu = 0.0;
@@ -966,7 +970,7 @@ active_set:
                 }
             }
             __syncthreads();
-            const bool keep = tid < nv && rank < JADD;
+            const bool keep = tid < nv && rank < jadd;
             // compact the kept slots in slot order (s_list is in slot order)
             const unsigned long long bal = __ballot(keep);
             if (lane == 0) redi[wave] = __popcll(bal);
@@ -975,7 +979,7 @@ active_set:
             for (int w2 = 0; w2 < wave; ++w2) before += redi[w2];
             if (keep) s_list[before + __popcll(bal & ((1ull << lane) - 1ull))] = u;
             __syncthreads();
-            nv = JADD;
+            nv = jadd;
         }
         if (lazy && nv > 0) {
             // lazy Gram: the columns of the slots about to enter S, against every slot of I
@@ -1027,6 +1031,7 @@ active_set:
             }
         }
         // move toward the sign-fixed minimiser, dropping at zero crossings
+        int dropped = 0;
         for (;;) {
             if (++steps > a.max_steps) { inexact = true; break; }
             sign_fixed_solve(s, nS, lam, vw, vz, vx);
@@ -1049,6 +1054,7 @@ active_set:
             }
             __syncthreads();
             if (q < 0) break;
+            ++dropped;
             // drop position q: downdate the factor (or truncate it and append the later positions again)
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 7), 1ull);
             const int ns_old = nS;
@@ -1067,6 +1073,7 @@ active_set:
             __syncthreads();
         }
         if (inexact) break;
+        jadd = dropped > 0 ? (jadd > 1 ? jadd / 2 : 1) : (jadd < JADD ? jadd * 2 : JADD);
     }
     if (a.smpl_keep > 0 && !explored && !inexact && nnew > a.smpl_keep && nnew <= NT && a.Q) {
         // Subspace exploratory matching (Algorithm 2): keep the smpl_keep new atoms with the largest |u_j|
