@@ -782,11 +782,12 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.smpl_keep = explore ? smpl_keep : 0;
         so.phase = phases ? c->phase_dev : nullptr;
         const size_t vec_bytes = vec_area_bytes(w.K);
-        so.vec_lds = vec_bytes <= c->lds_dyn_max ? 1 : 0;
+        const size_t stage = c->Q ? 0 : GRAM_STAGE_BYTES;   // direct Gram staging, only without the table
+        so.vec_lds = vec_bytes + stage <= c->lds_dyn_max ? 1 : 0;
         so.kl = std::min(kl, w.K);
         const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
-        so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes <= c->lds_dyn_max) ? 1 : 0;
-        size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0);
+        so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes + stage <= c->lds_dyn_max) ? 1 : 0;
+        size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0) + stage;
         // block appends pay off when the factor streams from global memory; with an LDS-resident
         // factor single appends are cheaper and keep the workgroup's LDS (and occupancy) smaller
         so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;

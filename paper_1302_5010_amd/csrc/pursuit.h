@@ -40,6 +40,7 @@ struct WarmArgs {
 constexpr int SOLVE_JB = 8;
 __host__ __device__ inline size_t vec_area_bytes(int K) { return ((size_t)K * 58 + 15) / 16 * 16; }
 __host__ __device__ inline size_t block_scratch_bytes(int K) { return (size_t)K * SOLVE_JB * 8; }
+constexpr size_t GRAM_STAGE_BYTES = 64 * 16 * 8;   // direct Gram rows' atom staging (only without the table)
 
 struct SolveArgs {
     Workspace w;

@@ -502,11 +502,12 @@ __device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outsid
 
 // Gram rows G(q, u) of the new slots q against every slot u, and c_q = a_q^T b,
 // as n-long float64 dot products (used when no Gram table is available).  The
-// new atoms are staged through LDS in chunks; each thread owns one slot u.
+// new atoms are staged through LDS in chunks (s_new: CH x NB doubles of the launch's dynamic
+// LDS, present only when there is no table); each thread owns one slot u.
+static_assert(CH * NB * 8 == GRAM_STAGE_BYTES, "direct Gram staging size");
 __device__ void gram_rows_direct(const SolveArgs& a, Sig& s, const int* g_atom, const float* bw, int nI0,
-                                 int nnew, int nI)
+                                 int nnew, int nI, double* s_new)
 {
-    __shared__ double s_new[CH * NB];
     const int tid = threadIdx.x;
     const int kpad = a.w.kpad;
     const int K = s.K;
@@ -802,6 +803,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     }
     // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
     double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0)) : nullptr;
+    // direct Gram staging (no table) after the vectors and the block scratch
+    double* snew = a.Q ? nullptr
+                       : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0) +
+                                                   (a.zs_lds ? block_scratch_bytes(K) : 0));
 
     // 1. Load the state, register the new slots.
     if (a.vec_lds) {
@@ -918,7 +923,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
             if (lane == 0) s.c[nI0 + t] = acc;
         }
     } else {
-        gram_rows_direct(a, s, g_atom, bw, nI0, nnew, nI);
+        gram_rows_direct(a, s, g_atom, bw, nI0, nnew, nI, snew);
     }
     __syncthreads();
 
