@@ -29,6 +29,7 @@ using namespace bmpl;
 namespace {
 
 constexpr int WARM_KL = 64;        // LDS factor capacity of the master solve right after a warm start
+constexpr int RESCORE_LDS_SMALL = 512;   // candidates per signal in the first re-score pass's LDS
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
 constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 2 rho are used)
 
@@ -50,6 +51,9 @@ struct bmpl_ctx {
     int* cert_act = nullptr;      // [p_cap] compacted list of those signals
     int* n_cert_dev = nullptr;    // its length
     double gamma_amax = 0.0;      // bfloat16 band factor: gamma_n * max_j ||a_j||
+    int* spill = nullptr;         // [p_cap] re-score rows left to the second pass (row + 1, 0 = none)
+    int* spill_act = nullptr;     // [p_cap] their signals
+    int* n_spill_dev = nullptr;   // their count
     int* cand = nullptr;          // [p_cap][CANDCAP] screening candidates
     int* ncand = nullptr;         // [p_cap]
     uint16_t* diag16 = nullptr;   // bfloat16 staging of bmpl_correlate
@@ -198,6 +202,7 @@ void free_signals(bmpl_ctx* c)
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
     dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
     dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
+    dfree(c->spill); dfree(c->spill_act); dfree(c->n_spill_dev);
     dfree(c->beta);
     c->p_cap = 0;
     c->K_cap = 0;
@@ -240,6 +245,9 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
         HIPC(dalloc(&w.rnorm, P));
         HIPC(dalloc(&c->cand, P * CANDCAP_DEF));
         HIPC(dalloc(&c->ncand, P));
+        HIPC(dalloc(&c->spill, P));
+        HIPC(dalloc(&c->spill_act, P));
+        HIPC(dalloc(&c->n_spill_dev, 1));
     }
     if (c->qroute) HIPC(dalloc(&c->beta, P * (size_t)c->ldg));
     if (c->opt.screen == BMPL_PREC_FP8) {
@@ -705,13 +713,24 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.gamma_amax = c->gamma_amax;
             rs.act = lst; rs.n_act_dev = cnt; rs.p_grid = n_grid;
             rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
-            // candidate values (12 bytes each) and the staged residual within 60 KB of LDS
-            rs.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));
             rs.ncand = c->ncand;
             rs.lam = w.lam; rs.lam_rel = sc.lam_rel;
             rs.k = rho; rs.nI = w.nI; rs.max_active = max_active;
             rs.sel = w.sel; rs.selcap = w.selcap; rs.nsel = w.nsel; rs.vmax = w.vmax; rs.status = w.status;
-            return launch_rescore(rs, q);
+            // first pass: up to RESCORE_LDS_SMALL candidate values (12 bytes each) in LDS, so many
+            // workgroups fit a CU; the few signals with more go to a second pass over their list with
+            // candidate values and the staged residual within 60 KB of LDS
+            rs.candcap_lds = RESCORE_LDS_SMALL;
+            rs.spill_row = c->spill; rs.row_of = nullptr;
+            e = launch_rescore(rs, q);
+            if (e != hipSuccess) return e;
+            e = launch_flag_compact(lst, cnt, n_grid, c->spill, c->spill_act, c->n_spill_dev, q);
+            if (e != hipSuccess) return e;
+            RescoreArgs r2 = rs;
+            r2.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));
+            r2.act = c->spill_act; r2.n_act_dev = c->n_spill_dev;
+            r2.spill_row = nullptr; r2.row_of = c->spill;
+            return launch_rescore(r2, q);
         };
         SelectArgs a{};
         a.G = c->Gc; a.ldg = c->ldg; a.m = c->m;

@@ -130,6 +130,10 @@ struct RescoreArgs {
     double* lam; double lam_rel;
     int k; const int* nI; int max_active;
     int* sel; int selcap; int* nsel; float* vmax; int* status;
+    // Two-pass use: a pass with spill_row set leaves the signals whose candidates exceed candcap_lds
+    // (but fit candcap) undecided and records spill_row[sig] = its row + 1 (0 for every other running
+    // signal); a pass over those signals with row_of = spill_row reads the product row recorded there.
+    int* spill_row; const int* row_of;
 };
 // e4m3 ranking (screen.hip): exact re-score of the candidates that the e4m3 product ranked highest,
 // admission of the exact violators among them, and the list of signals left for a certified pass.

@@ -259,11 +259,16 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     const int sig = a.act ? a.act[row] : row;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nc_all = a.ncand[sig];
+    if (a.spill_row) {   // first of two passes: more candidates than this pass's LDS holds are left over
+        const bool over_lds = nc_all > a.candcap_lds && nc_all <= a.candcap;
+        if (tid == 0) a.spill_row[sig] = over_lds ? row + 1 : 0;
+        if (over_lds) return;
+    }
     const bool overflow = nc_all > a.candcap || nc_all > a.candcap_lds;
     const int nc = overflow ? 0 : nc_all;
     const int* cand = a.cand + (int64_t)sig * a.candcap;
     const float* r = a.R + (int64_t)sig * a.ldr;
-    const float* gt = a.G + (int64_t)row * a.ldg;
+    const float* gt = a.G + (int64_t)(a.row_of ? a.row_of[sig] - 1 : row) * a.ldg;
     double* s_val = s_dyn;                                       // [candcap_lds] exact |g|, -1 = unscored
     float* s_gt = reinterpret_cast<float*>(s_dyn + a.candcap_lds);   // [candcap_lds] |g~|
     float* s_r = s_gt + a.candcap_lds;                           // [kpad] residual

@@ -315,6 +315,25 @@ def test_warm_start_support_outgrows_the_lds_factor():
     check_batch(P.At, P.Bt, lam, out, ref)
 
 
+@pytest.mark.parametrize("screen", ["bf16", "fp8"])
+def test_screening_with_many_candidates(screen):
+    """An orthonormal dictionary and flat signals put every atom inside the reduced-precision band of
+    the k-th largest correlation (about 1024 candidates per signal): the exact re-score runs its
+    second, large-LDS pass for them, and the result keeps parity with the oracle."""
+    pk = _lib()
+    n = 1024
+    At = np.eye(n, dtype=np.float32)
+    rng = np.random.default_rng(21)
+    Bt = (np.ones((4, n)) / np.sqrt(n) * (1.0 + 0.01 * rng.standard_normal((4, n)))).astype(np.float32)
+    lam = 0.995 * np.abs(Bt.astype(np.float64)).max(axis=1)
+    s = pk.Solver(to_dev(At), 0.0, rho=10, screen=screen)
+    out = s.solve(to_dev(Bt), lam=to_dev(lam))
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED), st
+    ref = oracle.solve(At, Bt, lam, 10)
+    check_batch(At, Bt, lam, out, ref)
+
+
 @pytest.mark.slow
 def test_cs_gaussian_full_size_sampled():
     """2048 x 16384 dictionary, 1024 signals, rho = 10: the benchmark's workload and launch;
