@@ -196,7 +196,7 @@ void free_signals(bmpl_ctx* c)
     Workspace& w = c->w;
     dfree(w.R); dfree(w.bnorm2); dfree(w.lam); dfree(w.status); dfree(w.iters); dfree(w.nI);
     dfree(w.nS); dfree(w.nsel); dfree(w.sel); dfree(w.vmax); dfree(w.kkt_on); dfree(w.obj);
-    dfree(w.kkt); dfree(w.inI); dfree(w.glazy); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
+    dfree(w.kkt); dfree(w.inI); dfree(w.glazy); dfree(w.jadd); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
     dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
@@ -234,6 +234,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     HIPC(dalloc(&w.kkt, P));
     HIPC(dalloc(&w.inI, P * w.words));
     HIPC(dalloc(&w.glazy, P));
+    HIPC(dalloc(&w.jadd, P));
     HIPC(alloc_slots(w, p, K));
     HIPC(dalloc(&c->Bw, P * c->kpad));
     HIPC(dalloc(&c->Gc, P * (size_t)c->ldg));

@@ -602,6 +602,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.nS[sig] = 0;
         w.nsel[sig] = 0;
         w.glazy[sig] = 0;
+        w.jadd[sig] = JADD;
         w.vmax[sig] = 0.f;
         w.kkt_on[sig] = 0.0;
         w.kkt[sig] = 0.0;
@@ -937,8 +938,9 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     bool resolve = false;   // after the pruning: solve on I_t even if no slot outside S violates
     // Violators admitted per step, adapted to the dictionary: halved after a step whose move to the
     // sign-fixed minimiser dropped atoms (correlated atoms enter and leave), doubled (up to JADD) after a
-    // clean one.
-    int jadd = JADD;
+    // clean one; carried from one outer iteration to the next.
+    int jadd = w.jadd[sig];
+    jadd = jadd >= 1 && jadd <= JADD ? jadd : JADD;
 active_set:
     for (;;) {
         grad_slots(s, nI, nS, vg, true);
@@ -1183,6 +1185,7 @@ active_set:
         w.nS[sig] = nS;
         w.iters[sig] += 1;
         w.kkt_on[sig] = kon > 0.0 ? kon : 0.0;
+        w.jadd[sig] = jadd;
         if (inexact) w.status[sig] |= BMPL_SIG_INEXACT;
     }
     __syncthreads();
