@@ -334,6 +334,21 @@ def test_screening_with_many_candidates(screen):
     check_batch(At, Bt, lam, out, ref)
 
 
+@pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
+def test_odd_shapes(screen):
+    """n, m and p that are multiples of nothing the kernels tile by (97 x 1003, 37 signals): padded
+    k stages, a ragged atom tile, a ragged signal tile and the scalar tails of the selection."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=97, m=1003, p=37, k=9, sigma=0.01, seed=95, rho=3)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, screen=screen)
+    out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+    st = out["status"].cpu().numpy()
+    assert np.all(st == pk.BMPL_SIG_CONVERGED), np.unique(st, return_counts=True)
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+    check_batch(P.At, P.Bt, lam, out, ref)
+
+
 @pytest.mark.slow
 def test_cs_gaussian_full_size_sampled():
     """2048 x 16384 dictionary, 1024 signals, rho = 10: the benchmark's workload and launch;
