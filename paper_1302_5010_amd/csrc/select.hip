@@ -3,12 +3,12 @@
 // (the natural stopping condition, Eq. (9), fails exactly for these), at most k
 // of them, largest first, ties to the lower atom index.
 //
-// One 256-thread workgroup per signal streams its row of correlations twice
-// (coalesced, eight 16-byte loads per thread in flight before any is used): the
-// first pass finds each thread's maximum, whose k-th largest over the workgroup
-// bounds the row's k-th largest from below; in the second pass each thread keeps
-// a sorted top-KMAX list in registers of the entries at or above that bound (few,
-// so the list insertions that dominated a single pass are rare).  Each wave then
+// One 256-thread workgroup per signal reads its row of correlations once
+// (coalesced).  Each thread's first eight 16-byte loads stay in registers; the
+// k-th largest of the threads' maxima over them bounds the row's k-th largest from
+// below, so when each thread then keeps a sorted top-KMAX list in registers, of the
+// registered entries and of the rest of the row as it streams in, only entries at
+// or above that bound are inserted (few, so the list insertions stay rare).  Each wave then
 // merges its 64 lists with k rounds of a wave-wide argmax on the list heads
 // (cross-lane shuffles, no LDS); the four wave lists are ranked in LDS.
 // On the first pass of the relative lambda rule the row maximum is reduced first
@@ -79,40 +79,28 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     float lamf = (float)lam;
     if ((double)lamf > lam) lamf = nextafterf(lamf, -INFINITY);
 
-    // visit(j, |g_j|) for every atom outside I, in increasing j per thread
-    auto scan = [&](auto&& visit) {
-        constexpr int CH = 8;   // float4 loads per thread issued before the first is used
-        for (int base = 4 * tid; base < m4; base += 1024 * CH) {
-            float4 f[CH];
-            uint32_t word[CH];
+    // Each thread's first CH float4 of the row stay in registers; the rest is streamed once later.
+    constexpr int CH = 8;
+    float4 f0[CH];
+    uint32_t w0[CH];
 #pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int j0 = base + 1024 * q;
-                const bool in = j0 < m4;
-                f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-                word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;   // 4 atoms share one word
-            }
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int j0 = base + 1024 * q;
-                if (j0 >= m4) break;
-                if (!(word[q] & 1u)) visit(j0, fabsf(f[q].x));
-                if (!(word[q] & 2u)) visit(j0 + 1, fabsf(f[q].y));
-                if (!(word[q] & 4u)) visit(j0 + 2, fabsf(f[q].z));
-                if (!(word[q] & 8u)) visit(j0 + 3, fabsf(f[q].w));
-            }
-        }
-        for (int j = m4 + tid; j < a.m; j += 256) {
-            if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-            visit(j, fabsf(g[j]));
-        }
-    };
-
-    // Pass A: each thread's largest |g_j|.  The k-th largest of the 256 thread maxima is at most the
-    // k-th largest |g_j| of the row (they are k distinct entries of it), so only entries >= T can be
-    // among the k largest and pass B inserts only those.
+    for (int q = 0; q < CH; ++q) {
+        const int j0 = 4 * tid + 1024 * q;
+        const bool in = j0 < m4;
+        f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        w0[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0xFu;   // 4 atoms share one word; 0xF: absent
+    }
+    // The k-th largest of the 256 threads' maxima over their registered entries is at most the k-th
+    // largest |g_j| of the row (they are k distinct entries of it), so only entries >= T can be among
+    // the k largest: the insertions below skip the rest.
     float tmax = -1.f;
-    scan([&](int, float v) { tmax = fmaxf(tmax, v); });
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        if (!(w0[q] & 1u)) tmax = fmaxf(tmax, fabsf(f0[q].x));
+        if (!(w0[q] & 2u)) tmax = fmaxf(tmax, fabsf(f0[q].y));
+        if (!(w0[q] & 4u)) tmax = fmaxf(tmax, fabsf(f0[q].z));
+        if (!(w0[q] & 8u)) tmax = fmaxf(tmax, fabsf(f0[q].w));
+    }
     float vmx = fmaxf(tmax, 0.f);
     {
         float cur = tmax;
@@ -161,7 +149,44 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             ci = sw ? ti : ci;
         }
     };
-    if (T <= FLT_MAX) scan(consider);
+    // the registered entries, then the rest of the row in one stream (vmax over every entry outside I)
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int j0 = 4 * tid + 1024 * q;
+        if (!(w0[q] & 1u)) consider(j0, fabsf(f0[q].x));
+        if (!(w0[q] & 2u)) consider(j0 + 1, fabsf(f0[q].y));
+        if (!(w0[q] & 4u)) consider(j0 + 2, fabsf(f0[q].z));
+        if (!(w0[q] & 8u)) consider(j0 + 3, fabsf(f0[q].w));
+    }
+    auto visit = [&](int j, float v) {
+        vmx = fmaxf(vmx, v);
+        consider(j, v);
+    };
+    constexpr int CS = 4;   // float4 loads per thread in flight in the stream
+    for (int base = 4 * tid + 1024 * CH; base < m4; base += 1024 * CS) {
+        float4 f[CS];
+        uint32_t word[CS];
+#pragma unroll
+        for (int q = 0; q < CS; ++q) {
+            const int j0 = base + 1024 * q;
+            const bool in = j0 < m4;
+            f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < CS; ++q) {
+            const int j0 = base + 1024 * q;
+            if (j0 >= m4) break;
+            if (!(word[q] & 1u)) visit(j0, fabsf(f[q].x));
+            if (!(word[q] & 2u)) visit(j0 + 1, fabsf(f[q].y));
+            if (!(word[q] & 4u)) visit(j0 + 2, fabsf(f[q].z));
+            if (!(word[q] & 8u)) visit(j0 + 3, fabsf(f[q].w));
+        }
+    }
+    for (int j = m4 + tid; j < a.m; j += 256) {
+        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+        visit(j, fabsf(g[j]));
+    }
     // vmax over the signal (outside I)
     for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
     __syncthreads();
