@@ -6,11 +6,10 @@
 // One 256-thread workgroup per signal reads its row of correlations once
 // (coalesced).  Each thread's first eight 16-byte loads stay in registers; the
 // k-th largest of the threads' maxima over them bounds the row's k-th largest from
-// below, so when each thread then keeps a sorted top-KMAX list in registers, of the
-// registered entries and of the rest of the row as it streams in, only entries at
-// or above that bound are inserted (few, so the list insertions stay rare).  Each wave then
-// merges its 64 lists with k rounds of a wave-wide argmax on the list heads
-// (cross-lane shuffles, no LDS); the four wave lists are ranked in LDS.
+// below (they are k distinct entries of the row).  The registered entries and the
+// rest of the row as it streams in are tested against that bound and lambda; the
+// few that pass are appended to an LDS buffer (one atomic per wave and step) and
+// bitonic-sorted by (|g|, lower index).
 // On the first pass of the relative lambda rule the row maximum is reduced first
 // and lambda_i = c * ||A^T b_i||_inf is set from it (Section IV-A).
 #include <float.h>
@@ -88,7 +87,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
         const int j0 = 4 * tid + 1024 * q;
         const bool in = j0 < m4;
         f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-        w0[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0xFu;   // 4 atoms share one word; 0xF: absent
+        w0[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;   // 4 atoms share one word; 0xF: absent
     }
     // The k-th largest of the 256 threads' maxima over their registered entries is at most the k-th
     // largest |g_j| of the row (they are k distinct entries of it), so only entries >= T can be among
@@ -129,119 +128,143 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     const float T = s_red[0];
     __syncthreads();
 
-    // Pass B: per-thread sorted top-KMAX lists of the entries >= T that violate.
-    float val[KMAX];
-    int idx[KMAX];
+    {
+        // The entries at or above the bound (a few dozen to a few hundred) are appended to an LDS buffer and
+        // bitonic-sorted by (|g|, lower index).  A buffer overflow (many equal values) is resolved by the
+        // exact rounds of argmax below, which need no buffer.
+        constexpr int CAP = 2048;
+        __shared__ float s_cv[CAP];
+        __shared__ int s_ci[CAP];
+        __shared__ int s_n;
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+        auto take = [&](bool t, int j, float v) {   // called by the whole wave
+            const unsigned long long bal = __ballot(t);
+            if (!bal) return;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_n, __popcll(bal));
+            base = __shfl(base, 0);
+            const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+            if (t && pos < CAP) { s_cv[pos] = v; s_ci[pos] = j; }
+        };
+        auto ok = [&](float v) { return v > lamf && v >= T; };
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) { val[q] = -1.f; idx[q] = INT_MAX; }
-    auto consider = [&](int j, float v) {
-        if (!(v > lamf) || !(v >= T) || !(v > val[KMAX - 1])) return;
-        float cv = v;
-        int ci = j;
+        for (int q = 0; q < CH; ++q) {
+            const int j0 = 4 * tid + 1024 * q;
+            take(!(w0[q] & 1u) && ok(fabsf(f0[q].x)), j0, fabsf(f0[q].x));
+            take(!(w0[q] & 2u) && ok(fabsf(f0[q].y)), j0 + 1, fabsf(f0[q].y));
+            take(!(w0[q] & 4u) && ok(fabsf(f0[q].z)), j0 + 2, fabsf(f0[q].z));
+            take(!(w0[q] & 8u) && ok(fabsf(f0[q].w)), j0 + 3, fabsf(f0[q].w));
+        }
+        constexpr int CS = 4;
+        // every lane runs the same number of steps (the ballots need the whole wave)
+        for (int base0 = 1024 * CH; base0 < m4; base0 += 1024 * CS) {
+            const int base = base0 + 4 * tid;
+            float4 f[CS];
+            uint32_t word[CS];
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) {   // stable insertion: equal values keep lower index first
-            bool sw = cv > val[q];
-            float tv = val[q];
-            int ti = idx[q];
-            val[q] = sw ? cv : tv;
-            idx[q] = sw ? ci : ti;
-            cv = sw ? tv : cv;
-            ci = sw ? ti : ci;
-        }
-    };
-    // the registered entries, then the rest of the row in one stream (vmax over every entry outside I)
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int j0 = 4 * tid + 1024 * q;
-        if (!(w0[q] & 1u)) consider(j0, fabsf(f0[q].x));
-        if (!(w0[q] & 2u)) consider(j0 + 1, fabsf(f0[q].y));
-        if (!(w0[q] & 4u)) consider(j0 + 2, fabsf(f0[q].z));
-        if (!(w0[q] & 8u)) consider(j0 + 3, fabsf(f0[q].w));
-    }
-    auto visit = [&](int j, float v) {
-        vmx = fmaxf(vmx, v);
-        consider(j, v);
-    };
-    constexpr int CS = 4;   // float4 loads per thread in flight in the stream
-    for (int base = 4 * tid + 1024 * CH; base < m4; base += 1024 * CS) {
-        float4 f[CS];
-        uint32_t word[CS];
-#pragma unroll
-        for (int q = 0; q < CS; ++q) {
-            const int j0 = base + 1024 * q;
-            const bool in = j0 < m4;
-            f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-            word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < CS; ++q) {
-            const int j0 = base + 1024 * q;
-            if (j0 >= m4) break;
-            if (!(word[q] & 1u)) visit(j0, fabsf(f[q].x));
-            if (!(word[q] & 2u)) visit(j0 + 1, fabsf(f[q].y));
-            if (!(word[q] & 4u)) visit(j0 + 2, fabsf(f[q].z));
-            if (!(word[q] & 8u)) visit(j0 + 3, fabsf(f[q].w));
-        }
-    }
-    for (int j = m4 + tid; j < a.m; j += 256) {
-        if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
-        visit(j, fabsf(g[j]));
-    }
-    // vmax over the signal (outside I)
-    for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
-    __syncthreads();
-    if (lane == 0) s_red[wave] = vmx;
-
-    // Wave merge: k rounds of argmax over the 64 list heads.
-    for (int r = 0; r < k; ++r) {
-        float bv = val[0];
-        int bi = idx[0];
-        for (int o = 32; o > 0; o >>= 1) {
-            float ov = __shfl_xor(bv, o);
-            int oi = __shfl_xor(bi, o);
-            if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { s_val[wave * KMAX + r] = bv; s_idx[wave * KMAX + r] = bi; }
-        if (bv < 0.f) {
-            for (int rr = r + 1; rr < k && lane == 0; ++rr) { s_val[wave * KMAX + rr] = -1.f; s_idx[wave * KMAX + rr] = INT_MAX; }
-            break;
-        }
-        if (idx[0] == bi) {   // the winning lane pops its head
-#pragma unroll
-            for (int q = 0; q < KMAX - 1; ++q) { val[q] = val[q + 1]; idx[q] = idx[q + 1]; }
-            val[KMAX - 1] = -1.f;
-            idx[KMAX - 1] = INT_MAX;
-        }
-    }
-    __syncthreads();
-    // Rank the 4k wave candidates; candidate c lands at its rank if < k.
-    int cnt = 0;
-    if (tid < 4 * k) {
-        const int w = tid / k, r = tid % k;
-        const float v = s_val[w * KMAX + r];
-        const int i = s_idx[w * KMAX + r];
-        if (v >= 0.f) {
-            int rank = 0;
-            for (int c = 0; c < 4 * k; ++c) {
-                const float ov = s_val[(c / k) * KMAX + c % k];
-                const int oi = s_idx[(c / k) * KMAX + c % k];
-                if (ov >= 0.f && better(ov, oi, v, i)) ++rank;
+            for (int q = 0; q < CS; ++q) {
+                const int j0 = base + 1024 * q;
+                const bool in = j0 < m4;
+                f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : (in ? 0u : 0xFu);
             }
-            if (rank < k) a.sel[(int64_t)sig * a.selcap + rank] = i;
+#pragma unroll
+            for (int q = 0; q < CS; ++q) {
+                const int j0 = base + 1024 * q;
+                const float v0 = fabsf(f[q].x), v1 = fabsf(f[q].y), v2 = fabsf(f[q].z), v3 = fabsf(f[q].w);
+                if (!(word[q] & 1u)) vmx = fmaxf(vmx, v0);
+                if (!(word[q] & 2u)) vmx = fmaxf(vmx, v1);
+                if (!(word[q] & 4u)) vmx = fmaxf(vmx, v2);
+                if (!(word[q] & 8u)) vmx = fmaxf(vmx, v3);
+                take(!(word[q] & 1u) && ok(v0), j0, v0);
+                take(!(word[q] & 2u) && ok(v1), j0 + 1, v1);
+                take(!(word[q] & 4u) && ok(v2), j0 + 2, v2);
+                take(!(word[q] & 8u) && ok(v3), j0 + 3, v3);
+            }
         }
+        for (int j0 = m4; j0 < a.m; j0 += 256) {
+            const int j = j0 + tid;
+            const bool in = j < a.m && !(ex && ((ex[j >> 5] >> (j & 31)) & 1u));
+            const float v = in ? fabsf(g[j]) : 0.f;
+            if (in) vmx = fmaxf(vmx, v);
+            take(in && ok(v), j, v);
+        }
+        __syncthreads();
+        const int nc = s_n;
+        if (nc <= CAP) {
+            int N = 64;
+            while (N < nc) N <<= 1;
+            for (int e = nc + tid; e < N; e += 256) { s_cv[e] = -1.f; s_ci[e] = INT_MAX; }
+            __syncthreads();
+            for (int size = 2; size <= N; size <<= 1)
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int t = tid; t < N / 2; t += 256) {
+                        const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1)), j = i + stride;
+                        const float vi = s_cv[i], vj = s_cv[j];
+                        const int ii = s_ci[i], ij = s_ci[j];
+                        const bool i_first = better(vi, ii, vj, ij);
+                        if (((i & size) == 0) ? !i_first : i_first) {   // best first overall
+                            s_cv[i] = vj; s_cv[j] = vi;
+                            s_ci[i] = ij; s_ci[j] = ii;
+                        }
+                    }
+                    __syncthreads();
+                }
+            for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
+            if (lane == 0) s_red[wave] = vmx;
+            __syncthreads();
+            const int nsel = nc < k ? nc : k;
+            for (int q = tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = q < nsel ? s_ci[q] : -1;
+            if (tid == 0) {
+                a.nsel[sig] = nsel;
+                a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+            }
+            return;
+        }
+        // Buffer overflow (more than CAP entries at or above the bound: many equal values): k rounds of
+        // a workgroup argmax over the row, each taking the best (|g|, index) pair after the previous one.
+        for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
+        if (lane == 0) s_red[wave] = vmx;
+        __syncthreads();
+        const float vmax_all = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+        float pv = INFINITY;
+        int pi = -1;
+        int nsel = 0;
+        for (int r = 0; r < k; ++r) {
+            float bv = -1.f;
+            int bi = INT_MAX;
+            for (int j = tid; j < a.m; j += 256) {
+                if (ex && ((ex[j >> 5] >> (j & 31)) & 1u)) continue;
+                const float v = fabsf(g[j]);
+                const bool after = v < pv || (v == pv && j > pi);
+                if (v > lamf && after && better(v, j, bv, bi)) { bv = v; bi = j; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const float ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+            }
+            __syncthreads();
+            if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
+            __syncthreads();
+            bv = s_val[0];
+            bi = s_idx[0];
+            for (int w2 = 1; w2 < 4; ++w2)
+                if (better(s_val[w2], s_idx[w2], bv, bi)) { bv = s_val[w2]; bi = s_idx[w2]; }
+            if (bv < 0.f) break;
+            if (tid == 0) a.sel[(int64_t)sig * a.selcap + r] = bi;
+            pv = bv;
+            pi = bi;
+            ++nsel;
+        }
+        for (int q = nsel + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
+        if (tid == 0) {
+            a.nsel[sig] = nsel;
+            a.vmax[sig] = vmax_all;
+        }
+        return;
     }
-    // count = number of valid candidates, capped at k
-    if (tid == 0) {
-        for (int c = 0; c < 4 * k; ++c) cnt += s_val[(c / k) * KMAX + c % k] >= 0.f;
-        cnt = cnt < k ? cnt : k;
-        a.nsel[sig] = cnt;
-        a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
-    }
-    __syncthreads();
-    if (tid == 0) { s_red[0] = (float)a.nsel[sig]; }
-    __syncthreads();
-    const int nsel = (int)s_red[0];
-    for (int q = nsel + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
 }
 
 }  // namespace
@@ -250,9 +273,7 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t stream)
 {
     if (a.p_grid <= 0) return hipSuccess;
     if (a.k <= 0 || a.k > 64 || a.k > a.selcap) return hipErrorInvalidValue;
-    if (a.k <= 16)
-        hipLaunchKernelGGL(select_kernel<16>, dim3(a.p_grid), dim3(256), 0, stream, a);
-    else if (a.k <= 32)
+    if (a.k <= 32)
         hipLaunchKernelGGL(select_kernel<32>, dim3(a.p_grid), dim3(256), 0, stream, a);
     else
         hipLaunchKernelGGL(select_kernel<64>, dim3(a.p_grid), dim3(256), 0, stream, a);

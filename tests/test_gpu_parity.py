@@ -81,22 +81,28 @@ def test_correlate_every_tile_shape(shape, screen):
         assert np.all(np.abs(G - R64 @ A64.T) <= bound), (shape, p)
 
 
-@pytest.mark.parametrize("k", [1, 10, 33])
-def test_select_matches_cpu_sort(k):
+@pytest.mark.parametrize("with_excl", [True, False])
+@pytest.mark.parametrize("k", [1, 10, 20, 33])
+def test_select_matches_cpu_sort(k, with_excl):
+    """Rows longer than the entries each thread keeps in registers (8192), with a scalar tail."""
     pk = _lib()
     rng = np.random.default_rng(k)
-    p, m = 37, 5000
-    s = pk.Solver(to_dev(np.eye(m, 64, dtype=np.float32)), 0.1)
+    p, m = 37, 20003
+    s = pk.Solver(to_dev(np.eye(m, 64, dtype=np.float32)), 0.1, gram_table=False)
     G = rng.standard_normal((p, m)).astype(np.float32)
     lam = np.quantile(np.abs(G), rng.uniform(0.9, 0.999, p), axis=1).diagonal().astype(np.float64)
     lam[3] = 10.0                                   # a row with no violator
+    G[5, :] = -0.5                                  # every entry tied: more candidates than any buffer
+    lam[5] = 0.1
+    G[6, ::2] = 0.25                                # half the row tied just above lambda
+    lam[6] = 0.2
     words = (m + 31) // 32
-    excl_bits = rng.random((p, m)) < 0.3
+    excl_bits = (rng.random((p, m)) < 0.3) if with_excl else np.zeros((p, m), dtype=bool)
     excl = np.zeros((p, words), dtype=np.uint32)
     for i in range(p):
         for j in np.nonzero(excl_bits[i])[0]:
             excl[i, j >> 5] |= np.uint32(1 << (j & 31))
-    sel, nsel, vmax = s.select(to_dev(G), to_dev(lam), k, excl=to_dev(excl.view(np.int32)))
+    sel, nsel, vmax = s.select(to_dev(G), to_dev(lam), k, excl=to_dev(excl.view(np.int32)) if with_excl else None)
     sel, nsel, vmax = sel.cpu().numpy(), nsel.cpu().numpy(), vmax.cpu().numpy()
     for i in range(p):
         a = np.abs(G[i]).copy()
