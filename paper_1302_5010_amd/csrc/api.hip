@@ -50,7 +50,7 @@ struct bmpl_ctx {
     int* cert = nullptr;          // [p_cap] left for the certified pass
     int* cert_act = nullptr;      // [p_cap] compacted list of those signals
     int* n_cert_dev = nullptr;    // its length
-    double gamma_amax = 0.0;      // bfloat16 band factor: gamma_n * max_j ||a_j||
+    double band_x = 0.0, band_dx = 0.0;   // bfloat16 band: eps_i = band_x ||xi_i|| + band_dx ||bf16(xi_i) - xi_i||
     int* spill = nullptr;         // [p_cap] re-score rows left to the second pass (row + 1, 0 = none)
     int* spill_act = nullptr;     // [p_cap] their signals
     int* n_spill_dev = nullptr;   // their count
@@ -199,7 +199,7 @@ void free_signals(bmpl_ctx* c)
     dfree(w.kkt); dfree(w.inI); dfree(w.glazy); dfree(w.jadd); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
     free_slots(w);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
-    dfree(w.R16); dfree(w.rnorm); dfree(c->cand); dfree(c->ncand);
+    dfree(w.R16); dfree(w.rnorm); dfree(w.dxnorm); dfree(c->cand); dfree(c->ncand);
     dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
     dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
     dfree(c->spill); dfree(c->spill_act); dfree(c->n_spill_dev);
@@ -244,6 +244,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
         HIPC(dalloc(&w.R16, (P + 1) * c->kpad));
         HIPC(hipMemset(w.R16 + P * c->kpad, 0, c->kpad * sizeof(uint16_t)));
         HIPC(dalloc(&w.rnorm, P));
+        HIPC(dalloc(&w.dxnorm, P));
         HIPC(dalloc(&c->cand, P * CANDCAP_DEF));
         HIPC(dalloc(&c->ncand, P));
         HIPC(dalloc(&c->spill, P));
@@ -420,23 +421,29 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
-    // bfloat16 copy of the dictionary and the band factor gamma_n * max_j ||a_j|| for screening.
+    // bfloat16 copy of the dictionary and the factors of the screening band.
     if (e == hipSuccess && opt.screen != BMPL_PREC_FP32) {
         float* norms = nullptr;
         e = dalloc(&c->A16, (size_t)(m + 1) * c->kpad);
         if (e == hipSuccess) e = hipMemsetAsync(c->A16, 0, (size_t)(m + 1) * c->kpad * sizeof(uint16_t), s);
         if (e == hipSuccess) e = launch_to_bf16(c->At, c->kpad, c->A16, c->kpad, m, c->kpad, s);
-        if (e == hipSuccess) e = dalloc(&norms, (size_t)m);
+        if (e == hipSuccess) e = dalloc(&norms, (size_t)3 * m);
         if (e == hipSuccess) e = launch_atom_norms(c->At, c->kpad, c->kpad, norms, m, s);
-        std::vector<float> hn(m);
-        if (e == hipSuccess) e = hipMemcpyAsync(hn.data(), norms, sizeof(float) * m, hipMemcpyDeviceToHost, s);
+        std::vector<float> hn((size_t)3 * m);
+        if (e == hipSuccess) e = hipMemcpyAsync(hn.data(), norms, sizeof(float) * 3 * m, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (norms) (void)hipFree(norms);
         if (e == hipSuccess) {
-            double amax = 0.0;
-            for (float v : hn) amax = std::max(amax, (double)v);
-            const double gamma = (std::ldexp(1.0, -7) + std::ldexp(1.0, -16) + n * std::ldexp(1.0, -24)) * 1.01;
-            c->gamma_amax = gamma * amax;
+            // |g~ - g| <= ||a^||  ||dx|| + ||da|| ||x|| + n 2^-24 ||a^|| (||x|| + ||dx||) with a^ = bf16(a),
+            // da = a^ - a, dx = bf16(x) - x; maxima over the atoms, 1 % margin for the rounding of the norms
+            double ahat = 0.0, da = 0.0;
+            for (int j = 0; j < m; ++j) {
+                ahat = std::max(ahat, (double)hn[(size_t)m + j]);
+                da = std::max(da, (double)hn[(size_t)2 * m + j]);
+            }
+            const double acc = n * std::ldexp(1.0, -24);
+            c->band_x = (da + acc * ahat) * 1.01;
+            c->band_dx = ahat * (1.0 + acc) * 1.01;
         }
     }
     // e4m3 copy with per-atom power-of-two scales for the FP8 ranking product (row m zero, scale 1)
@@ -702,7 +709,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             sc.G = c->Gc; sc.ldg = c->ldg; sc.m = c->m;
             sc.act = lst; sc.n_act_dev = cnt; sc.p_grid = n_grid;
             sc.lam = w.lam; sc.lam_rel = (rel && first) ? c->lambda : 0.0;
-            sc.rnorm = w.rnorm; sc.gamma_amax = c->gamma_amax;
+            sc.rnorm = w.rnorm; sc.dxnorm = w.dxnorm; sc.band_x = c->band_x; sc.band_dx = c->band_dx;
             sc.excl = w.inI; sc.words = w.words;
             sc.k = rho; sc.nI = w.nI; sc.max_active = max_active;
             sc.cand = c->cand; sc.candcap = CANDCAP_DEF; sc.ncand = c->ncand;
@@ -711,7 +718,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             RescoreArgs rs{};
             rs.At = c->At; rs.lda = c->kpad; rs.kpad = c->kpad;
             rs.R = w.R; rs.ldr = c->kpad;
-            rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.gamma_amax = c->gamma_amax;
+            rs.G = c->Gc; rs.ldg = c->ldg; rs.rnorm = w.rnorm; rs.dxnorm = w.dxnorm;
+            rs.band_x = c->band_x; rs.band_dx = c->band_dx;
             rs.act = lst; rs.n_act_dev = cnt; rs.p_grid = n_grid;
             rs.cand = c->cand; rs.candcap = CANDCAP_DEF;
             rs.ncand = c->ncand;

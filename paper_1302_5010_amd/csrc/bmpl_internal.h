@@ -61,6 +61,7 @@ struct Workspace {
     // reduced-precision screening (null in float32 mode)
     uint16_t* R16;      // [p_cap + 1][kpad] bfloat16 copy of R (row p_cap all zero)
     double* rnorm;      // [p] ||xi_i||_2
+    double* dxnorm;     // [p] ||bf16(xi_i) - xi_i||_2 (the residual's own rounding)
     uint8_t* R8;        // [p_cap + 1][kpad] e4m3 copy of R / rscale8 (FP8 ranking only; row p_cap zero)
     float* rscale8;     // [p_cap + 1] power-of-two scale of each R8 row
 };
@@ -116,7 +117,8 @@ struct ScreenArgs {
     const float* G; int64_t ldg; int m;
     const int* act; const int* n_act_dev; int p_grid;
     const double* lam; double lam_rel;       // lam_rel > 0: first pass of the relative rule
-    const double* rnorm; double gamma_amax;  // band eps_i = gamma_amax * rnorm[sig]
+    const double* rnorm; const double* dxnorm;   // band eps_i = band_x rnorm[sig] + band_dx dxnorm[sig]
+    double band_x, band_dx;
     const uint32_t* excl; int words;
     int k; const int* nI; int max_active;
     int* cand; int candcap; int* ncand;
@@ -125,7 +127,7 @@ struct RescoreArgs {
     const float* At; int64_t lda; int kpad;  // float32 atoms
     const float* R; int64_t ldr;             // float32 residuals
     const float* G; int64_t ldg;             // screening product (row per running signal)
-    const double* rnorm; double gamma_amax;  // the band
+    const double* rnorm; const double* dxnorm; double band_x, band_dx;   // the band
     const int* act; const int* n_act_dev; int p_grid;
     const int* cand; int candcap; int candcap_lds; const int* ncand;
     double* lam; double lam_rel;
@@ -157,6 +159,7 @@ hipError_t launch_atoms_fp8(const float* At, int64_t lda, int kpad, uint8_t* A8,
                             hipStream_t stream);
 hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd, int rows, int cols,
                           hipStream_t stream);
+// norms[3 m]: ||a_j||, ||bf16(a_j)|| and ||bf16(a_j) - a_j||, each rounded up
 hipError_t launch_atom_norms(const float* At, int64_t lda, int n, float* norms, int m, hipStream_t stream);
 hipError_t launch_screen(const ScreenArgs& a, hipStream_t stream);
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t stream);
@@ -198,5 +201,8 @@ __device__ inline uint16_t bf16_round(float f)
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+
+// The float32 value of bfloat16 bits.
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 }  // namespace bmpl

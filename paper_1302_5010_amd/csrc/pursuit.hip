@@ -106,21 +106,6 @@ struct Sig {
     int* so;              // slot of each support position
 };
 
-// sum_{k < len} Ri[k] v[k], four independent accumulators (row i of a packed factor).
-__device__ inline double row_dot(const double* Ri, const double* v, int len)
-{
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= len; k += 4) {
-        a0 += Ri[k] * v[k];
-        a1 += Ri[k + 1] * v[k + 1];
-        a2 += Ri[k + 2] * v[k + 2];
-        a3 += Ri[k + 3] * v[k + 3];
-    }
-    for (; k < len; ++k) a0 += Ri[k] * v[k];
-    return (a0 + a1) + (a2 + a3);
-}
-
 // z[i] = sum_{k <= i} R(i, k) w[k] for i < s with the factor in global memory: one row per wave at a
 // time, lanes across the row (coalesced, four loads in flight), a wave reduction per row.
 __device__ inline void rows_matvec_global(const double* R, const double* w, double* z, int s)
@@ -139,6 +124,60 @@ __device__ inline void rows_matvec_global(const double* R, const double* w, doub
         double acc = a0 + a1;
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
         if (lane == 0) z[i] = acc;
+    }
+}
+
+// Lanes per row (or column) of an LDS-resident factor with s support positions: a short support
+// leaves most threads idle, so P consecutive lanes share a row and the serial chain is s / P long.
+__device__ inline int split_lanes(int s) { return s <= NT / 4 ? 4 : (s <= NT / 2 ? 2 : 1); }
+
+// z[i] = sum_{k <= i} R(i, k) v[k] for i < s (packed lower factor in LDS), split_lanes(s) lanes per
+// row combined by shuffles inside the group.  Returns this lane's share of sum_i z_i^2.
+__device__ inline double rows_matvec_lds(const double* R, const double* v, double* z, int s)
+{
+    const int P = split_lanes(s);
+    const int sub = threadIdx.x & (P - 1);
+    double part = 0.0;
+    for (int i = threadIdx.x / P; i < s; i += NT / P) {   // the P lanes of a group share i
+        const double* Ri = R + tri(i);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = sub;
+        for (; k + 3 * P <= i; k += 4 * P) {
+            a0 += Ri[k] * v[k];
+            a1 += Ri[k + P] * v[k + P];
+            a2 += Ri[k + 2 * P] * v[k + 2 * P];
+            a3 += Ri[k + 3 * P] * v[k + 3 * P];
+        }
+        for (; k <= i; k += P) a0 += Ri[k] * v[k];
+        double acc = (a0 + a1) + (a2 + a3);
+        for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (sub == 0) {
+            z[i] = acc;
+            part += acc * acc;
+        }
+    }
+    return part;
+}
+
+// out[k] = (sum_{i = k}^{s-1} v[i] R(i, k)) / div for k < s (packed lower factor in LDS),
+// split_lanes(s) lanes per column.
+__device__ inline void cols_matvec_lds(const double* R, const double* v, double* out, int s, double div)
+{
+    const int P = split_lanes(s);
+    const int sub = threadIdx.x & (P - 1);
+    for (int k = threadIdx.x / P; k < s; k += NT / P) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = k + sub;
+        for (; i + 3 * P < s; i += 4 * P) {
+            a0 += v[i] * R[tri(i) + k];
+            a1 += v[i + P] * R[tri(i + P) + k];
+            a2 += v[i + 2 * P] * R[tri(i + 2 * P) + k];
+            a3 += v[i + 3 * P] * R[tri(i + 3 * P) + k];
+        }
+        for (; i < s; i += P) a0 += v[i] * R[tri(i) + k];
+        double acc = (a0 + a1) + (a2 + a3);
+        for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (sub == 0) out[k] = acc / div;
     }
 }
 
@@ -198,11 +237,7 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     __syncthreads();
     double part = 0.0;
     if (v.r_lds) {
-        for (int i = tid; i < s; i += NT) {      // z = Rinv w
-            const double acc = row_dot(v.R + tri(i), vw, i + 1);
-            vz[i] = acc;
-            part += acc * acc;
-        }
+        part = rows_matvec_lds(v.R, vw, vz, s);    // z = Rinv w
     } else {
         rows_matvec_global(v.R, vw, vz, s);
         __syncthreads();
@@ -220,8 +255,10 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     }
     const double d = sqrt(dd);
     double* Rs = v.R + tri(s);
-    for (int k = tid; k < s; k += NT)        // new row: -(z^T Rinv)_k / d
-        Rs[k] = -col_dot(v, vz, k, s) / d;
+    if (v.r_lds)                             // new row: -(z^T Rinv)_k / d
+        cols_matvec_lds(v.R, vz, Rs, s, -d);
+    else
+        for (int k = tid; k < s; k += NT) Rs[k] = -col_dot(v, vz, k, s) / d;
     if (tid == 0) {
         Rs[s] = 1.0 / d;
         v.so[s] = j;
@@ -464,12 +501,15 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
     }
     __syncthreads();
     if (v.r_lds) {
-        for (int i = tid; i < nS; i += NT) vz[i] = row_dot(v.R + tri(i), vw, i + 1);
+        rows_matvec_lds(v.R, vw, vz, nS);
     } else {
         rows_matvec_global(v.R, vw, vz, nS);
     }
     __syncthreads();
-    for (int k = tid; k < nS; k += NT) vx[k] = col_dot(v, vz, k, nS);
+    if (v.r_lds)
+        cols_matvec_lds(v.R, vz, vx, nS, 1.0);
+    else
+        for (int k = tid; k < nS; k += NT) vx[k] = col_dot(v, vz, k, nS);
     __syncthreads();
 }
 
@@ -577,19 +617,25 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
     const float* b = a.B + (int64_t)sig * a.ldb;
     float* Bw = a.Bw + (int64_t)sig * w.kpad;
     float* R = w.R + (int64_t)sig * w.kpad;
-    double part = 0.0;
+    double part = 0.0, dpart = 0.0;
     int bad = 0;
     for (int r = threadIdx.x; r < w.kpad; r += 256) {
         float v = r < w.n ? b[r] : 0.f;
         if (!isfinite(v)) bad = 1;
         Bw[r] = v;
         R[r] = v;
-        if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round(v);
+        if (w.R16) {
+            const uint16_t h = bf16_round(v);
+            w.R16[(int64_t)sig * w.kpad + r] = h;
+            const double d = (double)bf16_value(h) - (double)v;
+            dpart += d * d;
+        }
         part += (double)v * (double)v;
     }
     if (bad) atomicOr(&s_bad, 1);
     for (int q = threadIdx.x; q < w.words; q += 256) w.inI[(int64_t)sig * w.words + q] = 0u;
     const double bb = block_sum(part, red);
+    const double bd = w.R16 ? block_sum(dpart, red) : 0.0;
     if (threadIdx.x == 0) {
         double lam = a.lambda_dev ? a.lambda_dev[sig] : a.lambda_abs;
         int st = 0;
@@ -611,6 +657,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.rr2[sig] = bb;
         w.g0max[sig] = 0.f;
         if (w.rnorm) w.rnorm[sig] = sqrt(bb);
+        if (w.dxnorm) w.dxnorm[sig] = sqrt(bd);
     }
     if (w.R8) write_residual_fp8(w, sig, red);
 }
@@ -816,8 +863,17 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         }
         for (int k = tid; k < nS; k += NT) s.so[k] = g_so[k];
     }
-    if (s.r_lds)
-        for (int64_t e = tid; e < tri(nS); e += NT) s.R[e] = g_R[e];
+    if (s.r_lds) {   // four loads in flight per thread
+        const int64_t T = tri(nS);
+        for (int64_t e0 = tid; e0 < T; e0 += 4 * NT) {
+            double r[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = e0 + q * NT < T ? g_R[e0 + q * NT] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (e0 + q * NT < T) s.R[e0 + q * NT] = r[q];
+        }
+    }
     for (int u = tid; u < nI0; u += NT) vatom[u] = g_atom[u];
     for (int t = tid; t < nnew; t += NT) {
         const int q = nI0 + t;
@@ -1229,7 +1285,7 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     const double xl1 = block_sum(l1, red);    // also orders the LDS writes above
     const float* bw = a.Bw + (int64_t)sig * w.kpad;
     float* Rres = w.R + (int64_t)sig * w.kpad;
-    double rr = 0.0;
+    double rr = 0.0, dr = 0.0;
     // rows 4 q .. 4 q + 3 per step (kpad and lda are multiples of 4)
     const int n4 = w.kpad / 4;
     const int64_t lda4 = a.lda / 4;
@@ -1267,17 +1323,24 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
             const int r = 4 * q + e;
             if (r >= w.n) acc[e] = 0.0;
             o[e] = (float)acc[e];
-            if (w.R16) w.R16[(int64_t)sig * w.kpad + r] = bf16_round(o[e]);
+            if (w.R16) {
+                const uint16_t h = bf16_round(o[e]);
+                w.R16[(int64_t)sig * w.kpad + r] = h;
+                const double d = (double)bf16_value(h) - (double)o[e];
+                dr += d * d;
+            }
             rr += acc[e] * acc[e];
         }
         reinterpret_cast<float4*>(Rres)[q] = out;
     }
     const double rn = block_sum(rr, red);
+    const double rd = w.R16 ? block_sum(dr, red) : 0.0;
     if (tid == 0) {
         w.obj_prev[sig] = w.obj[sig];
         w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
         w.rr2[sig] = rn;
         if (w.rnorm) w.rnorm[sig] = sqrt(rn);
+        if (w.dxnorm) w.dxnorm[sig] = sqrt(rd);
     }
     if (w.R8) write_residual_fp8(w, sig, red);
 }

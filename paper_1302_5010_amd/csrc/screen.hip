@@ -1,12 +1,17 @@
 // Reduced-precision screening of the worst-case analysis (Algorithm 1, step 3).
 //
 // With a bfloat16 correlation product g~ = bf16(A)^T bf16(xi) (float32
-// accumulation) every entry is within a certified band of the float32 value:
-//     |g~_j - g_j| <= eps_i = gamma_n * max_j ||a_j|| * ||xi_i||,
-//     gamma_n = (2^-7 + 2^-16 + n 2^-24) * 1.01,
-// (each operand rounds with relative error 2^-8, the products are exact, the
-// float32 accumulation adds n 2^-24 of sum |a_j||xi|, and sum |a_j||xi| <=
-// ||a_j|| ||xi|| by Cauchy-Schwarz).  The screen keeps every atom whose band
+// accumulation) every entry is within a certified band of the float32 value.
+// With a^ = bf16(a_j), da = a^ - a_j, x^ = bf16(xi), dx = x^ - xi, the products
+// a^_k x^_k are exact in float32 and
+//     a^ . x^ - a_j . xi = a^ . dx + da . xi             (exactly),
+// so by Cauchy-Schwarz, with the float32 accumulation's n 2^-24 sum |a^_k x^_k|,
+//     |g~_j - g_j| <= ||a^|| ||dx|| + ||da|| ||xi|| + n 2^-24 ||a^|| (||xi|| + ||dx||)
+//                  <= eps_i = band_x ||xi_i|| + band_dx ||dx_i||
+// with the maxima of ||a^|| and ||da|| over the atoms (set up once) and ||dx_i||
+// measured where the residual is rounded.  Rounding errors of random data are
+// about a third of their worst case, so this is two to three times narrower than
+// the worst-case 2^-7 max_j ||a_j|| ||xi_i||.  The screen keeps every atom whose band
 // could reach the selection threshold, the candidates are re-scored exactly
 // (float32 data, float64 accumulation), and only re-scored values decide which
 // atoms enter I and whether the natural stopping condition Eq. (9) holds.  So
@@ -37,66 +42,76 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ 
     for (int c = threadIdx.x; c < cols; c += 256) dst[(int64_t)r * ldd + c] = bf16_round(src[(int64_t)r * lds + c]);
 }
 
+// ||a_j||, ||bf16(a_j)|| and ||bf16(a_j) - a_j|| into norms[j], norms[m + j], norms[2m + j], rounded up.
 __global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict__ At, int64_t lda, int n,
                                                         float* __restrict__ norms, int m)
 {
-    __shared__ double red[4];
+    __shared__ double red[3][4];
     const int j = blockIdx.x;
     if (j >= m) return;
-    double s = 0.0;
+    double s = 0.0, sh = 0.0, sd = 0.0;
     for (int k = threadIdx.x; k < n; k += 256) {
-        const double v = At[(int64_t)j * lda + k];
+        const float f = At[(int64_t)j * lda + k];
+        const float h = bf16_value(bf16_round(f));
+        const double v = f, vh = h, d = (double)h - (double)f;
         s += v * v;
+        sh += vh * vh;
+        sd += d * d;
     }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        sh += __shfl_xor(sh, o);
+        sd += __shfl_xor(sd, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s;
+        red[1][threadIdx.x >> 6] = sh;
+        red[2][threadIdx.x >> 6] = sd;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) norms[j] = (float)sqrt(red[0] + red[1] + red[2] + red[3]) * (1.0f + 1e-6f);
+    if (threadIdx.x < 3) {
+        const double* r = red[threadIdx.x];
+        norms[(int64_t)threadIdx.x * m + j] = (float)sqrt(r[0] + r[1] + r[2] + r[3]) * (1.0f + 1e-6f);
+    }
 }
 
 // x . y over n4 float4 (float32 data, float64 accumulation) by one wave; every lane gets the sum.
-// Eight 16-byte loads of each operand per lane are in flight before the first is used.
+// Six 16-byte loads of x per lane are in flight before the first is used (eight would cost the
+// re-score kernel a quarter of its workgroups per CU).
 __device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4* __restrict__ y, int n4, int lane)
 {
-    constexpr int CH = 8;
+    constexpr int CH = 6;   // six float4 per lane in flight: 122 VGPRs, four workgroups per CU
     double acc = 0.0;
     for (int q0 = lane; q0 < n4; q0 += 64 * CH) {
-        float4 fx[CH], fy[CH];
+        float4 fx[CH];
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = q0 + 64 * e;
             fx[e] = q < n4 ? x[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            fy[e] = q < n4 ? y[q] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int e = 0; e < CH; ++e)
-            acc += (double)fx[e].x * fy[e].x + (double)fx[e].y * fy[e].y + (double)fx[e].z * fy[e].z +
-                   (double)fx[e].w * fy[e].w;
+        for (int e = 0; e < CH; ++e) {    // y is read as the sums need it (LDS in the re-score)
+            const int q = q0 + 64 * e;
+            const float4 fy = q < n4 ? y[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            acc += (double)fx[e].x * fy.x + (double)fx[e].y * fy.y + (double)fx[e].z * fy.z + (double)fx[e].w * fy.w;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     return acc;
 }
 
+// The candidate rule by sweeps over the row (used when many equal values overflow the candidate buffer
+// of screen_select_kernel): the thread maxima, then per-thread lists of the entries at or above their
+// k-th largest, then the candidates.
 template <int KMAX>
-__global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
+__device__ void screen_sweeps(const ScreenArgs& a, int row, int sig, int k, float eps)
 {
     __shared__ float s_top[4][KMAX];
     __shared__ float s_red[8];
     __shared__ int s_cnt;
-    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
-    const int row = blockIdx.x;
-    if (row >= n_act) return;
-    const int sig = a.act ? a.act[row] : row;
     const float* g = a.G + (int64_t)row * a.ldg;
     const uint32_t* ex = a.excl ? a.excl + (int64_t)sig * a.words : nullptr;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float eps = (float)(a.gamma_amax * a.rnorm[sig]);
-
-    int k = a.k;
-    if (a.nI && a.max_active > 0) {
-        const int room = a.max_active - a.nI[sig];
-        k = room < k ? (room > 0 ? room : 0) : k;
-    }
     // Pass 1: the k largest |g~| outside I (values only) and the largest |g~| overall, in two sweeps:
     // each thread's maximum first (the k-th largest of the 256 thread maxima bounds the k-th largest
     // entry from below), then per-thread sorted lists of only the entries at or above that bound.
@@ -243,6 +258,213 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
     if (tid == 0) a.ncand[sig] = s_cnt;
 }
 
+// Candidates of one signal from a single read of its row.  Each thread's first eight float4 stay in
+// registers; the k-th largest T of the threads' maxima over them (outside I) bounds the k-th largest
+// |g~| outside I from below, so tau = that value - eps >= T - eps, and every candidate (U_j > thr >= tau,
+// or U_j >= max|g~| - eps >= T - eps) has |g~_j| + eps >= T - eps; with a fixed lambda it also has
+// |g~_j| + eps > lambda.  The entries that pass these tests (computed in the same double arithmetic as the
+// rule itself) are appended to an LDS buffer as the row streams in.  The buffer holds every entry at or
+// above the k-th largest whenever it holds k entries, so the k-th largest, tau and thr follow from it, and
+// the candidates are the buffered entries that pass the rule.  When it holds fewer than k (fixed lambda),
+// the k-th largest has U <= lambda, so tau <= lambda = thr.  A buffer overflow falls back to the sweeps.
+template <int KMAX>
+__global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
+{
+    constexpr int CH = 8;       // float4 per thread held in registers
+    constexpr int CAP = 2048;   // buffered entries
+    __shared__ float s_cv[CAP];
+    __shared__ int s_ci[CAP];
+    __shared__ float s_tw[4 * KMAX];
+    __shared__ float s_r[4];
+    __shared__ float s_T, s_kth;
+    __shared__ int s_n, s_cnt;
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    const float* g = a.G + (int64_t)row * a.ldg;
+    const uint32_t* ex = a.excl ? a.excl + (int64_t)sig * a.words : nullptr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float eps = (float)(a.band_x * a.rnorm[sig] + a.band_dx * a.dxnorm[sig]);
+
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        const int room = a.max_active - a.nI[sig];
+        k = room < k ? (room > 0 ? room : 0) : k;
+    }
+    const bool rel = a.lam_rel > 0.0;
+    const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
+    const int m4 = vec4 ? (a.m & ~3) : 0;
+
+    float4 f0[CH];
+    uint32_t w0[CH];     // bit set: in I or past the row
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int j0 = 4 * tid + 1024 * q;
+        const bool in = j0 < m4;
+        f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        w0[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;
+    }
+    float gall = 0.f, tmax = -1.f;   // largest |g~| over every atom; over the registered atoms outside I
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        gall = fmaxf(gall, fmaxf(fmaxf(fabsf(f0[q].x), fabsf(f0[q].y)), fmaxf(fabsf(f0[q].z), fabsf(f0[q].w))));
+        if (!(w0[q] & 1u)) tmax = fmaxf(tmax, fabsf(f0[q].x));
+        if (!(w0[q] & 2u)) tmax = fmaxf(tmax, fabsf(f0[q].y));
+        if (!(w0[q] & 4u)) tmax = fmaxf(tmax, fabsf(f0[q].z));
+        if (!(w0[q] & 8u)) tmax = fmaxf(tmax, fabsf(f0[q].w));
+    }
+    {
+        float cur = tmax;
+        for (int r = 0; r < k; ++r) {
+            float b = cur;
+            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            if (lane == 0) s_tw[wave * KMAX + r] = b;
+            const unsigned long long owners = __ballot(cur == b);
+            if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
+        }
+    }
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    if (tid == 0) {
+        float T = INFINITY;
+        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;        // merge the four descending wave lists
+        for (int r = 0; r < k; ++r) {
+            const float v0 = p0 < k ? s_tw[p0] : -3.f, v1 = p1 < k ? s_tw[KMAX + p1] : -3.f;
+            const float v2 = p2 < k ? s_tw[2 * KMAX + p2] : -3.f, v3 = p3 < k ? s_tw[3 * KMAX + p3] : -3.f;
+            const float bv = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+            T = bv;
+            if (bv == v0) ++p0; else if (bv == v1) ++p1; else if (bv == v2) ++p2; else ++p3;
+        }
+        s_T = T;
+    }
+    __syncthreads();
+    // admission test on u = |g~| + eps: u >= T - eps (k > 0), and u > lambda for a fixed lambda
+    const double pre = k > 0 ? (double)s_T - eps : -DBL_MAX;
+    const double lam_fix = rel ? -DBL_MAX : a.lam[sig];
+    auto ok = [&](float v) {
+        const double u = (double)v + eps;
+        return u >= pre && u > lam_fix;
+    };
+    auto take = [&](bool t, int j, float v) {   // called by the whole wave
+        const unsigned long long bal = __ballot(t);
+        if (!bal) return;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_n, __popcll(bal));
+        base = __shfl(base, 0);
+        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+        if (t && pos < CAP) { s_cv[pos] = v; s_ci[pos] = j; }
+    };
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int j0 = 4 * tid + 1024 * q;
+        take(!(w0[q] & 1u) && ok(fabsf(f0[q].x)), j0, fabsf(f0[q].x));
+        take(!(w0[q] & 2u) && ok(fabsf(f0[q].y)), j0 + 1, fabsf(f0[q].y));
+        take(!(w0[q] & 4u) && ok(fabsf(f0[q].z)), j0 + 2, fabsf(f0[q].z));
+        take(!(w0[q] & 8u) && ok(fabsf(f0[q].w)), j0 + 3, fabsf(f0[q].w));
+    }
+    constexpr int CS = 4;
+    for (int base0 = 1024 * CH; base0 < m4; base0 += 1024 * CS) {   // the same trip count in every lane
+        const int base = base0 + 4 * tid;
+        float4 f[CS];
+        uint32_t word[CS];
+#pragma unroll
+        for (int q = 0; q < CS; ++q) {
+            const int j0 = base + 1024 * q;
+            const bool in = j0 < m4;
+            f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            word[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;
+        }
+#pragma unroll
+        for (int q = 0; q < CS; ++q) {
+            const int j0 = base + 1024 * q;
+            const float v0 = fabsf(f[q].x), v1 = fabsf(f[q].y), v2 = fabsf(f[q].z), v3 = fabsf(f[q].w);
+            gall = fmaxf(gall, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
+            take(!(word[q] & 1u) && ok(v0), j0, v0);
+            take(!(word[q] & 2u) && ok(v1), j0 + 1, v1);
+            take(!(word[q] & 4u) && ok(v2), j0 + 2, v2);
+            take(!(word[q] & 8u) && ok(v3), j0 + 3, v3);
+        }
+    }
+    for (int j0 = m4; j0 < a.m; j0 += 256) {
+        const int j = j0 + tid;
+        const bool in = j < a.m;
+        const float v = in ? fabsf(g[j]) : 0.f;
+        gall = fmaxf(gall, v);
+        const bool out = in && !(ex && ((ex[j >> 5] >> (j & 31)) & 1u));
+        take(out && ok(v), j, v);
+    }
+    for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
+    if (lane == 0) s_r[wave] = gall;
+    if (tid == 0) { s_cnt = 0; s_kth = -1.f; }
+    __syncthreads();
+    const int nc = s_n;
+    if (nc > CAP) {
+        screen_sweeps<KMAX>(a, row, sig, k, eps);
+        return;
+    }
+    const float gmax = fmaxf(fmaxf(s_r[0], s_r[1]), fmaxf(s_r[2], s_r[3]));
+    if (k > 0 && nc >= k) {
+        if (nc <= 2 * 256) {
+            // k-th largest buffered value: the entry with fewer than k larger values and at least k at or above
+            for (int e = tid; e < nc; e += 256) {
+                const float v = s_cv[e];
+                int gt = 0, ge = 0;
+                for (int d = 0; d < nc; ++d) {
+                    const float w = s_cv[d];
+                    gt += w > v;
+                    ge += w >= v;
+                }
+                if (gt < k && ge >= k) s_kth = v;   // every writer stores the same value
+            }
+        } else {
+            int N = 64;
+            while (N < nc) N <<= 1;
+            for (int e = nc + tid; e < N; e += 256) { s_cv[e] = -1.f; s_ci[e] = -1; }
+            __syncthreads();
+            for (int size = 2; size <= N; size <<= 1)       // descending by value (the indices ride along)
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int t = tid; t < N / 2; t += 256) {
+                        const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1)), j = i + stride;
+                        const float vi = s_cv[i], vj = s_cv[j];
+                        if (((i & size) == 0) ? (vi < vj) : (vi > vj)) {
+                            const int ii = s_ci[i];
+                            s_cv[i] = vj; s_cv[j] = vi;
+                            s_ci[i] = s_ci[j]; s_ci[j] = ii;
+                        }
+                    }
+                    __syncthreads();
+                }
+            if (tid == 0) s_kth = s_cv[k - 1];
+        }
+    }
+    __syncthreads();
+    const float kth = s_kth;
+    const double lam_lo = rel ? a.lam_rel * ((double)gmax - eps) : a.lam[sig];
+    const double tau = kth >= 0.f ? (double)kth - eps : -1.0;
+    const double thr = lam_lo > tau ? lam_lo : tau;
+    const double thr_max = rel ? (double)gmax - eps : DBL_MAX;   // U_j >= this: may attain the max
+    int* cand = a.cand + (int64_t)sig * a.candcap;
+    for (int e0 = 0; e0 < nc; e0 += 256) {
+        const int e = e0 + tid;
+        bool t = false;
+        if (e < nc) {
+            const double u = (double)s_cv[e] + eps;
+            t = (u > thr) || (u >= thr_max);
+        }
+        const unsigned long long bal = __ballot(t);
+        int base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&s_cnt, __popcll(bal));
+        base = __shfl(base, 0);
+        if (t) {
+            const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+            if (pos < a.candcap) cand[pos] = s_ci[e];
+        }
+    }
+    __syncthreads();
+    if (tid == 0) a.ncand[sig] = s_cnt;
+}
+
 // Exact re-score of the candidates (float32 data, float64 accumulation), then the
 // selection itself.  Scored in two stages: first the k candidates with the largest
 // |g~| (their k-th exact value v_k bounds the true k-th largest from below), then only
@@ -250,7 +472,7 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
 // top k nor violate.  The residual is staged in LDS once per signal.
 __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
 {
-    extern __shared__ double s_dyn[];
+    extern __shared__ __align__(16) double s_dyn[];
     __shared__ double red[8];
     __shared__ int s_lim;
     const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
@@ -272,14 +494,28 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     double* s_val = s_dyn;                                       // [candcap_lds] exact |g|, -1 = unscored
     float* s_gt = reinterpret_cast<float*>(s_dyn + a.candcap_lds);   // [candcap_lds] |g~|
     float* s_r = s_gt + a.candcap_lds;                           // [kpad] residual
-    const double eps = a.gamma_amax * a.rnorm[sig];
+    const double eps = a.band_x * a.rnorm[sig] + a.band_dx * a.dxnorm[sig];
 
     int k = a.k;
     if (a.nI && a.max_active > 0) {
         const int room = a.max_active - a.nI[sig];
         k = room < k ? (room > 0 ? room : 0) : k;
     }
-    for (int q = tid; q < a.kpad; q += 256) s_r[q] = r[q];
+    if ((a.kpad & 3) == 0 && (a.ldr & 3) == 0 && (reinterpret_cast<uintptr_t>(a.R) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(s_r) & 15) == 0) {
+        // the residual in two batches of float4 loads per thread at most (n <= 2048: one round trip)
+        const float4* r4 = reinterpret_cast<const float4*>(r);
+        float4* s_r4 = reinterpret_cast<float4*>(s_r);
+        const int n4 = a.kpad / 4;
+        for (int q0 = tid; q0 < n4; q0 += 2 * 256) {
+            const float4 v0 = r4[q0];
+            const float4 v1 = q0 + 256 < n4 ? r4[q0 + 256] : make_float4(0.f, 0.f, 0.f, 0.f);
+            s_r4[q0] = v0;
+            if (q0 + 256 < n4) s_r4[q0 + 256] = v1;
+        }
+    } else {
+        for (int q = tid; q < a.kpad; q += 256) s_r[q] = r[q];
+    }
     for (int c = tid; c < nc; c += 256) {
         s_val[c] = -1.0;
         s_gt[c] = fabsf(gt[cand[c]]);

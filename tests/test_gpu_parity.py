@@ -321,13 +321,15 @@ def test_warm_start_support_outgrows_the_lds_factor():
     check_batch(P.At, P.Bt, lam, out, ref)
 
 
+@pytest.mark.parametrize("n", [1024, 3000])
 @pytest.mark.parametrize("screen", ["bf16", "fp8"])
-def test_screening_with_many_candidates(screen):
+def test_screening_with_many_candidates(screen, n):
     """An orthonormal dictionary and flat signals put every atom inside the reduced-precision band of
-    the k-th largest correlation (about 1024 candidates per signal): the exact re-score runs its
-    second, large-LDS pass for them, and the result keeps parity with the oracle."""
+    the k-th largest correlation (n candidates per signal): the exact re-score runs its second,
+    large-LDS pass for them, and the result keeps parity with the oracle.  With 3000 atoms the band
+    holds more entries than the single-read screen buffers (2048), so the bfloat16 screen takes its
+    sweep fallback and the e4m3 ranking's selection its rounds of argmax."""
     pk = _lib()
-    n = 1024
     At = np.eye(n, dtype=np.float32)
     rng = np.random.default_rng(21)
     Bt = (np.ones((4, n)) / np.sqrt(n) * (1.0 + 0.01 * rng.standard_normal((4, n)))).astype(np.float32)
@@ -433,6 +435,45 @@ def test_bf16_correlate_within_band(n, m, p):
     assert np.all(np.abs(G - ref) <= band)
     # and it is a bfloat16 product, not a float32 one: errors well above float32's
     assert np.max(np.abs(G - ref)) > 1e-4 * np.max(np.abs(ref))
+
+
+def bf16_rne(x):
+    """float32 -> nearest bfloat16 (ties to even), as float32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def bf16_rounding_band(At, Rt):
+    """Per-entry band from the operands' own rounding: with a^ = bf16(a), x^ = bf16(r),
+    a^ . x^ - a . r = a^ . (x^ - r) + (a^ - a) . r exactly, bounded by Cauchy-Schwarz, plus the
+    float32 accumulation's n 2^-24 ||a^|| ||x^||."""
+    n = At.shape[1]
+    A64, R64 = At.astype(np.float64), Rt.astype(np.float64)
+    Ah, Rh = bf16_rne(At).astype(np.float64), bf16_rne(Rt).astype(np.float64)
+    nah = np.linalg.norm(Ah, axis=1)
+    nda = np.linalg.norm(Ah - A64, axis=1)
+    nr = np.linalg.norm(R64, axis=1)
+    ndr = np.linalg.norm(Rh - R64, axis=1)
+    nrh = np.linalg.norm(Rh, axis=1)
+    return np.outer(ndr, nah) + np.outer(nr, nda) + n * 2.0 ** -24 * np.outer(nrh, nah)
+
+
+@pytest.mark.parametrize("n,m,p", [(128, 700, 33), (2048, 4100, 130)])
+def test_bf16_rounding_band_holds_and_is_tighter(n, m, p):
+    """The band the screen uses (operand rounding measured, not assumed worst-case) holds entry by entry
+    for the MFMA product and is well inside the worst-case band."""
+    pk = _lib()
+    rng = np.random.default_rng(7 * n + p)
+    At = rng.standard_normal((m, n)).astype(np.float32)
+    At /= np.linalg.norm(At, axis=1, keepdims=True)
+    Rt = rng.standard_normal((p, n)).astype(np.float32)
+    s = pk.Solver(to_dev(At), 0.1, screen="bf16")
+    G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
+    ref = Rt.astype(np.float64) @ At.astype(np.float64).T
+    tight = bf16_rounding_band(At, Rt)
+    assert np.all(np.abs(G - ref) <= tight)
+    assert np.max(tight / bf16_band(At, Rt)) < 0.6
 
 
 @pytest.mark.parametrize("graph", [False, True])
