@@ -800,7 +800,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     // moves its factor to global memory inside the kernel and continues there (slower), so kl is
     // |I|'s bound for ordinary passes, where most of I is in S, and smaller after a warm start.
     // `explore`: the pass before selected omega rho candidates (not a warm-start proposal)
-    auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, bool gated, bool explore) -> bmpl_status {
+    // `ibound`: |I| after this pass's selection is at most this (the LDS vectors are sized by it)
+    auto enqueue_master = [&](hipStream_t q, int idx, int n_grid, int kl, int ibound, bool gated,
+                              bool explore) -> bmpl_status {
         const bool ev = tm && !gated;
         size_t e0 = ev ? mark(c, q) : 0;
         SolveArgs so{};
@@ -809,7 +811,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.max_steps = 16 * w.K + 256;
         so.smpl_keep = explore ? smpl_keep : 0;
         so.phase = phases ? c->phase_dev : nullptr;
-        const size_t vec_bytes = vec_area_bytes(w.K);
+        // the exploratory pass of SMPL briefly holds omega rho new slots: the full capacity then
+        so.kv = so.smpl_keep > 0 ? w.K : std::min(w.K, std::max(1, ibound));
+        const size_t vec_bytes = vec_area_bytes(so.kv);
         const size_t stage = c->Q ? 0 : GRAM_STAGE_BYTES;   // direct Gram staging, only without the table
         so.vec_lds = vec_bytes + stage <= c->lds_dyn_max ? 1 : 0;
         so.kl = std::min(kl, w.K);
@@ -874,7 +878,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
                 int cc = cur;
                 for (int d = 0; d < GRAPH_DEPTH; ++d) {
                     // factor capacity for this iteration's |I| (a smaller LDS footprint fits more signals per CU)
-                    bmpl_status r = enqueue_master(q, cc, p, std::min(need, imax + (d + 1) * rho), true, true);
+                    const int ib = std::min(need, imax + (d + 1) * rho);
+                    bmpl_status r = enqueue_master(q, cc, p, ib, ib, true, true);
                     if (r != BMPL_OK) return r;
                     r = enqueue_select_pass(q, cc, p, false, false, true);
                     if (r != BMPL_OK) return r;
@@ -895,7 +900,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         if (st != BMPL_OK) return st;
         c->timing.outer_iters += tm ? 1 : 0;
         // a warm start's proposal is mostly zeros: an LDS factor for WARM_KL support positions
-        st = enqueue_master(s, cur, n_act, after_warm ? std::min(imax, WARM_KL) : imax, false, !after_warm);
+        st = enqueue_master(s, cur, n_act, after_warm ? std::min(imax, WARM_KL) : imax, imax, false, !after_warm);
         if (st != BMPL_OK) return st;
         st = enqueue_select_pass(s, cur, n_act, false, after_warm, false);
         if (st != BMPL_OK) return st;

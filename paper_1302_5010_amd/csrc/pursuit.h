@@ -52,6 +52,7 @@ struct SolveArgs {
     int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
+    int kv;                         // their stride: a bound on |I| during the launch (<= w.K)
     int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
     int smpl_keep;                  // > 0: subspace exploratory matching keeps this many of the new atoms
     uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,

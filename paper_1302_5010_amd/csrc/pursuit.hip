@@ -836,13 +836,14 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     }
     double *vw, *vz, *vx, *vg;
     int* vatom;
+    const int KV = a.kv;   // LDS vectors: stride KV >= |I| during this launch
     if (a.vec_lds) {
         double* d = reinterpret_cast<double*>(lp);
-        s.x = d; s.c = d + K; vw = d + 2 * K; vz = d + 3 * K; vx = d + 4 * K; vg = d + 5 * K;
-        int* ip = reinterpret_cast<int*>(d + 6 * K);
-        s.so = ip; vatom = ip + K;
-        s.th = reinterpret_cast<signed char*>(ip + 2 * K);
-        s.ex = reinterpret_cast<unsigned char*>(s.th + K);
+        s.x = d; s.c = d + KV; vw = d + 2 * KV; vz = d + 3 * KV; vx = d + 4 * KV; vg = d + 5 * KV;
+        int* ip = reinterpret_cast<int*>(d + 6 * KV);
+        s.so = ip; vatom = ip + KV;
+        s.th = reinterpret_cast<signed char*>(ip + 2 * KV);
+        s.ex = reinterpret_cast<unsigned char*>(s.th + KV);
     } else {
         double* d = w.vscratch + (int64_t)sig * 8 * K;
         s.x = g_x; s.c = g_c; s.th = g_th; s.ex = g_ex; s.so = g_so;
@@ -850,10 +851,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         vatom = reinterpret_cast<int*>(d + 4 * K);
     }
     // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
-    double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0)) : nullptr;
+    double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV) : 0)) : nullptr;
     // direct Gram staging (no table) after the vectors and the block scratch
     double* snew = a.Q ? nullptr
-                       : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(K) : 0) +
+                       : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV) : 0) +
                                                    (a.zs_lds ? block_scratch_bytes(K) : 0));
 
     // 1. Load the state, register the new slots.
@@ -1143,8 +1144,8 @@ active_set:
         // (ties to the lower atom index); the others leave S (downdates) and I, the kept slots move down
         // to nI0.., and the master problem continues on I_t from u restricted to it.
         explored = true;
-        __shared__ int s_keep[NT];
-        __shared__ int s_newpos[NT];
+        int* s_keep = reinterpret_cast<int*>(vx);     // [nnew] (vx and vg are free once the step ends)
+        int* s_newpos = reinterpret_cast<int*>(vg);   // [nnew]
         if (tid < nnew) {
             const int u = nI0 + tid;
             const double xu = fabs(s.x[u]);
