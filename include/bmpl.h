@@ -283,7 +283,8 @@ typedef struct {
     double corr_ms; int64_t corr_launches; double corr_flops; double corr_bytes;
     double select_ms; int64_t select_launches;
     double solve_ms; int64_t solve_launches;
-    double residual_ms;     /* residual xi = b - A_S x_S and objective */
+    double residual_ms;     /* 0: the residual xi = b - A_S x_S and objective are the last step of the
+                               master-problem kernel and count in solve_ms */
     double other_ms;        /* set-up, compaction, packing */
     double wall_ms;         /* first to last event of each solve, summed */
     int64_t solves;

@@ -112,7 +112,7 @@ struct bmpl_ctx {
 
 namespace {
 
-enum { K_CORR = 0, K_SELECT = 1, K_SOLVE = 2, K_OTHER = 3, K_RESID = 4 };
+enum { K_CORR = 0, K_SELECT = 1, K_SOLVE = 2, K_OTHER = 3 };
 
 bool timing_on(const bmpl_ctx* c) { return (c->opt.flags & BMPL_FLAG_TIMING) != 0; }
 
@@ -147,7 +147,6 @@ void fold_timing(bmpl_ctx* c, size_t first, size_t last)
             break;
         case K_SELECT: c->timing.select_ms += ms; c->timing.select_launches++; break;
         case K_SOLVE: c->timing.solve_ms += ms; c->timing.solve_launches++; break;
-        case K_RESID: c->timing.residual_ms += ms; break;
         default: c->timing.other_ms += ms; break;
         }
     }
@@ -830,15 +829,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         else
             hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
         HIPC(hipGetLastError());
-        if (ev) {
-            const size_t e1 = mark(c, q);
-            span(c, e0, e1, K_SOLVE);
-            e0 = e1;
-        }
-        ResidualArgs ra{w, c->At, c->kpad, c->Bw, c->act[idx], c->n_act_dev + idx};
-        hipLaunchKernelGGL(residual_kernel, dim3(n_grid), dim3(256), (size_t)w.K * 12, q, ra);
-        HIPC(hipGetLastError());
-        if (ev) span(c, e0, mark(c, q), K_RESID);
+        if (ev) span(c, e0, mark(c, q), K_SOLVE);   // the residual is the solve kernel's last step
         return BMPL_OK;
     };
     auto grow_to = [&](int need) -> bmpl_status {

@@ -59,12 +59,6 @@ struct SolveArgs {
                                     // then counts of factor appends, drops and solves; or null
 };
 
-struct ResidualArgs {
-    Workspace w;
-    const float* At; int64_t lda;
-    const float* Bw;
-    const int* act; const int* n_act_dev;
-};
 
 struct PackArgs {
     Workspace w;
@@ -89,7 +83,6 @@ __global__ void status_compact_kernel(StatusArgs a);
 __global__ void warm_select_kernel(WarmArgs a);
 __global__ void solve_kernel(SolveArgs a);         // single appends only (zs_lds ignored)
 __global__ void solve_block_kernel(SolveArgs a);   // block appends when zs_lds
-__global__ void residual_kernel(ResidualArgs a);
 __global__ void pack_kernel(PackArgs a);
 __global__ void restride_kernel(RestrideArgs a);
 

@@ -788,6 +788,78 @@ __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
 // and without them, whose register footprint is half as large, so twice as many
 // workgroups fit on a CU.
 // ---------------------------------------------------------------------------
+// Residual xi = b - A_S x_S (float64 accumulation, stored float32) and the objective
+// lambda ||x||_1 + 1/2 ||xi||^2 of a signal that was just solved (step 7 of Algorithm 1), with the
+// norms and reduced-precision copies the next product and its screening band use.  Run by the solve
+// workgroup after its write-back: sx / satom hold the support's values and atoms (LDS), xl1 = ||x||_1.
+// Four rows per thread, eight atoms' loads in flight, straight from the atom-major dictionary; a
+// workgroup that finishes its master problem early computes its residual while others still solve.
+__device__ void residual_tail(const Workspace& w, int sig, const float* At, int64_t lda, const float* Bw,
+                              const double* sx, const int* satom, int nS, double xl1, double* red)
+{
+    const int tid = threadIdx.x;
+    const float* bw = Bw + (int64_t)sig * w.kpad;
+    float* Rres = w.R + (int64_t)sig * w.kpad;
+    double rr = 0.0, dr = 0.0;
+    // rows 4 q .. 4 q + 3 per step (kpad and lda are multiples of 4)
+    const int n4 = w.kpad / 4;
+    const int64_t lda4 = lda / 4;
+    const float4* At4 = reinterpret_cast<const float4*>(At);
+    constexpr int CH = 8;
+    for (int q = tid; q < n4; q += NT) {
+        const float4 bv = reinterpret_cast<const float4*>(bw)[q];
+        double acc[4] = {(double)bv.x, (double)bv.y, (double)bv.z, (double)bv.w};
+        int k = 0;
+        for (; k + CH <= nS; k += CH) {
+            float4 f[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) f[e] = At4[(int64_t)satom[k + e] * lda4 + q];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const double xv = sx[k + e];
+                acc[0] -= (double)f[e].x * xv;
+                acc[1] -= (double)f[e].y * xv;
+                acc[2] -= (double)f[e].z * xv;
+                acc[3] -= (double)f[e].w * xv;
+            }
+        }
+        for (; k < nS; ++k) {
+            const float4 f = At4[(int64_t)satom[k] * lda4 + q];
+            const double xv = sx[k];
+            acc[0] -= (double)f.x * xv;
+            acc[1] -= (double)f.y * xv;
+            acc[2] -= (double)f.z * xv;
+            acc[3] -= (double)f.w * xv;
+        }
+        float4 out;
+        float* o = reinterpret_cast<float*>(&out);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 4 * q + e;
+            if (r >= w.n) acc[e] = 0.0;
+            o[e] = (float)acc[e];
+            if (w.R16) {
+                const uint16_t h = bf16_round(o[e]);
+                w.R16[(int64_t)sig * w.kpad + r] = h;
+                const double d = (double)bf16_value(h) - (double)o[e];
+                dr += d * d;
+            }
+            rr += acc[e] * acc[e];
+        }
+        reinterpret_cast<float4*>(Rres)[q] = out;
+    }
+    const double rn = block_sum(rr, red);
+    const double rd = w.R16 ? block_sum(dr, red) : 0.0;
+    if (tid == 0) {
+        w.obj_prev[sig] = w.obj[sig];
+        w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
+        w.rr2[sig] = rn;
+        if (w.rnorm) w.rnorm[sig] = sqrt(rn);
+        if (w.dxnorm) w.dxnorm[sig] = sqrt(rd);
+    }
+    if (w.R8) write_residual_fp8(w, sig, red);
+}
+
 template <bool BLOCK>
 __device__ __forceinline__ void solve_body(const SolveArgs& a)
 {
@@ -1215,7 +1287,7 @@ active_set:
 
     phase_mark(2);
 
-    // 4. Certificate on I (float64).  The residual and objective follow in residual_kernel.
+    // 4. Certificate on I (float64).
     grad_slots(s, nI, nS, vg, false);
     double e = 0.0;
     for (int u = tid; u < nI; u += NT) {
@@ -1245,106 +1317,28 @@ active_set:
         w.jadd[sig] = jadd;
         if (inexact) w.status[sig] |= BMPL_SIG_INEXACT;
     }
-    __syncthreads();
     phase_mark(5);
+
+    // 6. Residual and objective (step 7), from the support's values and atoms gathered into vw / vz
+    //    (free after the certificate).
+    {
+        double* sx = vw;
+        int* satom = reinterpret_cast<int*>(vz);
+        double l1 = 0.0;
+        for (int k = tid; k < nS; k += NT) {
+            const int u = s.so[k];
+            const double xv = s.x[u];
+            sx[k] = xv;
+            satom[k] = g_atom[u];
+            l1 += fabs(xv);
+        }
+        const double xl1 = block_sum(l1, red);    // also orders the writes above
+        residual_tail(w, sig, a.At, a.lda, a.Bw, sx, satom, nS, xl1, red);
+    }
 }
 
-__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) { solve_body<false>(a); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void solve_kernel(SolveArgs a) { solve_body<false>(a); }
 __global__ __launch_bounds__(256) void solve_block_kernel(SolveArgs a) { solve_body<true>(a); }
-
-// ---------------------------------------------------------------------------
-// Residual xi = b - A_S x_S (float64 accumulation, stored float32) and the
-// objective lambda ||x||_1 + 1/2 ||xi||^2 of every signal that was just solved
-// (step 7 of Algorithm 1).  One workgroup per signal reads its support's atom
-// columns straight from the atom-major dictionary, four rows per thread and eight
-// atoms' loads in flight; little LDS, so every signal of the batch can be
-// resident at once.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
-{
-    extern __shared__ double s_dyn[];
-    __shared__ double red[4];
-    const int n_act = *a.n_act_dev;
-    const int row = blockIdx.x;
-    if (row >= n_act) return;
-    const Workspace& w = a.w;
-    const int sig = a.act[row];
-    if (w.nsel[sig] <= 0) return;
-    const int tid = threadIdx.x;
-    const int64_t K = w.K;
-    const int nS = w.nS[sig];
-    double* sx = s_dyn;
-    int* satom = reinterpret_cast<int*>(s_dyn + K);
-    double l1 = 0.0;
-    for (int k = tid; k < nS; k += NT) {
-        const int u = w.sord[sig * K + k];
-        const double xv = w.x[sig * K + u];
-        sx[k] = xv;
-        satom[k] = w.slot_atom[sig * K + u];
-        l1 += fabs(xv);
-    }
-    const double xl1 = block_sum(l1, red);    // also orders the LDS writes above
-    const float* bw = a.Bw + (int64_t)sig * w.kpad;
-    float* Rres = w.R + (int64_t)sig * w.kpad;
-    double rr = 0.0, dr = 0.0;
-    // rows 4 q .. 4 q + 3 per step (kpad and lda are multiples of 4)
-    const int n4 = w.kpad / 4;
-    const int64_t lda4 = a.lda / 4;
-    const float4* At4 = reinterpret_cast<const float4*>(a.At);
-    constexpr int CH = 8;
-    for (int q = tid; q < n4; q += NT) {
-        const float4 bv = reinterpret_cast<const float4*>(bw)[q];
-        double acc[4] = {(double)bv.x, (double)bv.y, (double)bv.z, (double)bv.w};
-        int k = 0;
-        for (; k + CH <= nS; k += CH) {
-            float4 f[CH];
-#pragma unroll
-            for (int e = 0; e < CH; ++e) f[e] = At4[(int64_t)satom[k + e] * lda4 + q];
-#pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const double xv = sx[k + e];
-                acc[0] -= (double)f[e].x * xv;
-                acc[1] -= (double)f[e].y * xv;
-                acc[2] -= (double)f[e].z * xv;
-                acc[3] -= (double)f[e].w * xv;
-            }
-        }
-        for (; k < nS; ++k) {
-            const float4 f = At4[(int64_t)satom[k] * lda4 + q];
-            const double xv = sx[k];
-            acc[0] -= (double)f.x * xv;
-            acc[1] -= (double)f.y * xv;
-            acc[2] -= (double)f.z * xv;
-            acc[3] -= (double)f.w * xv;
-        }
-        float4 out;
-        float* o = reinterpret_cast<float*>(&out);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = 4 * q + e;
-            if (r >= w.n) acc[e] = 0.0;
-            o[e] = (float)acc[e];
-            if (w.R16) {
-                const uint16_t h = bf16_round(o[e]);
-                w.R16[(int64_t)sig * w.kpad + r] = h;
-                const double d = (double)bf16_value(h) - (double)o[e];
-                dr += d * d;
-            }
-            rr += acc[e] * acc[e];
-        }
-        reinterpret_cast<float4*>(Rres)[q] = out;
-    }
-    const double rn = block_sum(rr, red);
-    const double rd = w.R16 ? block_sum(dr, red) : 0.0;
-    if (tid == 0) {
-        w.obj_prev[sig] = w.obj[sig];
-        w.obj[sig] = 0.5 * rn + w.lam[sig] * xl1;
-        w.rr2[sig] = rn;
-        if (w.rnorm) w.rnorm[sig] = sqrt(rn);
-        if (w.dxnorm) w.dxnorm[sig] = sqrt(rd);
-    }
-    if (w.R8) write_residual_fp8(w, sig, red);
-}
 
 // ---------------------------------------------------------------------------
 // Results: support sorted by atom index, float32 values, per-signal scalars.
