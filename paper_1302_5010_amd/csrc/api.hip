@@ -646,9 +646,15 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     sa.rho = c->opt.rho;
     hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    int n_act = *c->h_count;
+    // In graph mode the host does not wait for the running count until the first captured segment has
+    // been launched: every kernel reads the count on the device, p bounds it, and the GPU runs set-up,
+    // the first pass and the first segment back to back.
+    int n_act = p;
+    if (!graph) {
+        HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        n_act = *c->h_count;
+    }
     if (tm) span(c, ev_first, mark(c, s), K_OTHER);
 
     // One pass of the worst-case analysis on the running list act[cur] (n_grid bounds its
@@ -851,8 +857,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         st = enqueue_select_pass(s, 0, n_act, true, false, false);
         if (st != BMPL_OK) return st;
         cur = 1;
-        st = read_count(cur);
-        if (st != BMPL_OK) return st;
+        if (!graph || warm) {
+            st = read_count(cur);
+            if (st != BMPL_OK) return st;
+        }
     }
     // Then per iteration: master problem on I_t, next selection pass.
     int imax = 0;
