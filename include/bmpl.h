@@ -131,7 +131,8 @@ typedef struct {
 /*
  * Caller-owned device result buffers, filled by bmpl_solve.  For signal i:
  * x_idx[i*ld_x + s], x_val[i*ld_x + s] for s < supp_len[i] hold the nonzero
- * coefficients sorted by atom index; ld_x >= min(max_active, n).
+ * coefficients sorted by atom index, and -1 / 0 for supp_len[i] <= s < ld_x (every entry is
+ * written, so the caller need not clear the buffers); ld_x >= min(max_active, n).
  * kkt[i] = max( max_{j not in S}(|a_j^T xi| - lambda)_+ , max_{j in S}|a_j^T xi - lambda sign x_j| ) / lambda,
  * computed in float64 on I and from the float32 correlation product outside I.
  * objective[i] = lambda ||x||_1 + 1/2 ||b - A x||^2 in float64.

@@ -203,14 +203,15 @@ class Solver:
         ld = ld_x if ld_x is not None else min(self.max_active, self.n)
         dev = Bt.device
         out = {
-            "x_val": torch.zeros((p, ld), dtype=torch.float32, device=dev),
-            "x_idx": torch.full((p, ld), -1, dtype=torch.int32, device=dev),
-            "supp_len": torch.zeros(p, dtype=torch.int32, device=dev),
-            "iters": torch.zeros(p, dtype=torch.int32, device=dev),
-            "kkt": torch.zeros(p, dtype=torch.float64, device=dev),
-            "lambda": torch.zeros(p, dtype=torch.float64, device=dev),
-            "objective": torch.zeros(p, dtype=torch.float64, device=dev),
-            "status": torch.zeros(p, dtype=torch.int32, device=dev),
+            # the library writes every entry (rows padded with -1 / 0 past supp_len)
+            "x_val": torch.empty((p, ld), dtype=torch.float32, device=dev),
+            "x_idx": torch.empty((p, ld), dtype=torch.int32, device=dev),
+            "supp_len": torch.empty(p, dtype=torch.int32, device=dev),
+            "iters": torch.empty(p, dtype=torch.int32, device=dev),
+            "kkt": torch.empty(p, dtype=torch.float64, device=dev),
+            "lambda": torch.empty(p, dtype=torch.float64, device=dev),
+            "objective": torch.empty(p, dtype=torch.float64, device=dev),
+            "status": torch.empty(p, dtype=torch.int32, device=dev),
         }
         r = _Result(out["x_val"].data_ptr(), out["x_idx"].data_ptr(), out["supp_len"].data_ptr(),
                     out["iters"].data_ptr(), out["kkt"].data_ptr(), out["lambda"].data_ptr(),

@@ -1374,8 +1374,12 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a)
     __shared__ int s_c[4];
     if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = cnt;
     __syncthreads();
+    const int tot = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    for (int s = tot + threadIdx.x; s < a.ld_x; s += 256) {   // the rest of the row: -1 / 0
+        a.x_idx[(int64_t)sig * a.ld_x + s] = -1;
+        a.x_val[(int64_t)sig * a.ld_x + s] = 0.f;
+    }
     if (threadIdx.x == 0) {
-        const int tot = s_c[0] + s_c[1] + s_c[2] + s_c[3];
         a.supp_len[sig] = tot;
         const bool bad = w.status[sig] & BMPL_SIG_NONFINITE;
         if (a.iters) a.iters[sig] = w.iters[sig];
