@@ -100,10 +100,11 @@ struct bmpl_ctx {
     struct GraphKey {
         int p, cur, kl, K, shapes[3];
         long gen;
+        int merged;   // the large tile also covers the middle bucket of running counts
         bool operator==(const GraphKey& o) const
         {
             return p == o.p && cur == o.cur && kl == o.kl && K == o.K && gen == o.gen && shapes[0] == o.shapes[0] &&
-                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2];
+                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] && merged == o.merged;
         }
     };
     struct GraphEntry { GraphKey key; hipGraph_t g; hipGraphExec_t ge; };
@@ -315,9 +316,10 @@ void drop_graphs(bmpl_ctx* c)
 // The instantiated graph of one segment for this configuration, captured on first use by
 // `enqueue(stream)` on the context's capture stream.
 template <class F>
-bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, hipGraphExec_t* out, F&& enqueue)
+bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, int merged, hipGraphExec_t* out, F&& enqueue)
 {
-    bmpl_ctx::GraphKey key{p, cur, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen};
+    bmpl_ctx::GraphKey key{p, cur, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen,
+                           merged};
     for (auto& e : c->graphs)
         if (e.key == key) {
             *out = e.ge;
@@ -657,6 +659,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     }
     if (tm) span(c, ev_first, mark(c, s), K_OTHER);
 
+    bool merge_mid = false;   // graph segments: see the gated product below
     // One pass of the worst-case analysis on the running list act[cur] (n_grid bounds its
     // size): correlation, selection, stop test and compaction into act[nxt].  With `gated`
     // every correlation tile shape is enqueued and each runs only for its own bucket of the
@@ -683,8 +686,12 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
                                             c->Gc, c->ldg, c->p_cap, lo, hi, q);
             };
             if (gate) {
-                const int lo[3] = {512, 64, 1}, hi[3] = {1 << 30, 512, 64};
+                // count buckets of the three tile shapes; in a segment that starts with 512 or more running
+                // signals the large tile also takes the middle bucket (one launch less per iteration: the
+                // count rarely falls that far within four iterations)
+                const int lo[3] = {merge_mid ? 64 : 512, 64, 1}, hi[3] = {1 << 30, 512, 64};
                 for (int b = 0; b < 3; ++b) {
+                    if (b == 1 && merge_mid) continue;
                     const int grid = std::min(n_grid, hi[b] - 1);
                     if (grid < lo[b]) continue;
                     const hipError_t e = gemm(c->corr_shape[b], grid, lo[b], hi[b]);
@@ -873,7 +880,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             st = grow_to(need);
             if (st != BMPL_OK) return st;
             hipGraphExec_t ge = nullptr;
-            st = segment_graph(c, p, cur, need, &ge, [&](hipStream_t q) -> bmpl_status {
+            merge_mid = n_act >= 512;
+            st = segment_graph(c, p, cur, need, merge_mid ? 1 : 0, &ge, [&](hipStream_t q) -> bmpl_status {
                 int cc = cur;
                 for (int d = 0; d < GRAPH_DEPTH; ++d) {
                     // factor capacity for this iteration's |I| (a smaller LDS footprint fits more signals per CU)

@@ -408,6 +408,24 @@ def test_graph_mode_matches_host_loop():
         check_batch(P.At, P.Bt, lam, out, ref)
 
 
+def test_graph_mode_large_batch_buckets():
+    """A batch of 700 signals: graph segments that start with 512 or more running signals let the large
+    correlation tile serve the middle bucket of counts too, so while signals converge the count passes
+    through [64, 512) inside a segment.  Parity with the oracle, and the cached graphs replay exactly."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=256, m=2000, p=700, k=30, sigma=0.01, seed=79, rho=7)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True)
+    outs = [s.solve(to_dev(P.Bt), lam=to_dev(lam)) for _ in range(2)]
+    torch.cuda.synchronize()
+    for key in ("x_idx", "x_val", "supp_len", "iters", "status"):
+        assert torch.equal(outs[0][key], outs[1][key]), key
+    it = outs[0]["iters"].cpu().numpy()
+    assert it.min() < it.max()                    # the count falls during the solve
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho)
+    check_batch(P.At, P.Bt, lam, outs[1], ref)
+
+
 # ---------------------------------------------------------------------------
 # Reduced-precision screening (bfloat16 product, exact re-score)
 # ---------------------------------------------------------------------------
