@@ -29,6 +29,7 @@
 #include "../../include/bmpl.h"
 #include "bmpl_internal.h"
 #include "pursuit.h"
+#include "wave_ops.h"
 
 namespace bmpl {
 namespace {
@@ -43,7 +44,7 @@ constexpr int JB = SOLVE_JB;   // atoms per block factor append
 __device__ inline double block_sum(double v, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v = wave_sum(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
@@ -53,7 +54,7 @@ __device__ inline double block_sum(double v, double* red)
 __device__ inline double block_max(double v, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    v = wave_max(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
@@ -78,10 +79,19 @@ __device__ inline void write_residual_fp8(const Workspace& w, int sig, double* r
 __device__ inline void block_argmin(double& a, int& q, double* red, int* redi)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) {
-        double oa = __shfl_xor(a, o);
-        int oq = __shfl_xor(q, o);
+    auto take = [&](double oa, int oq) {
         if (oa < a || (oa == a && (unsigned)oq < (unsigned)q)) { a = oa; q = oq; }
+    };
+    take(lane_move<DPP_XOR1>(a), lane_move<DPP_XOR1>(q));
+    take(lane_move<DPP_XOR2>(a), lane_move<DPP_XOR2>(q));
+    take(lane_move<DPP_HALF_MIRROR>(a), lane_move<DPP_HALF_MIRROR>(q));
+    take(lane_move<DPP_MIRROR>(a), lane_move<DPP_MIRROR>(q));
+    take(lane_move<-1>(a), lane_move<-1>(q));
+    {
+        const double a0 = read_lane(a, 0), a1 = read_lane(a, 32);
+        const int q0 = __builtin_amdgcn_readlane(q, 0), q1 = __builtin_amdgcn_readlane(q, 32);
+        a = a0; q = q0;
+        take(a1, q1);
     }
     __syncthreads();
     if (lane == 0) { red[wave] = a; redi[wave] = q; }
@@ -121,8 +131,7 @@ __device__ inline void rows_matvec_global(const double* R, const double* w, doub
             a1 += r1 * w[k + 64] + r3 * w[k + 192];
         }
         for (; k <= i; k += 64) a0 += Ri[k] * w[k];
-        double acc = a0 + a1;
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        const double acc = wave_sum(a0 + a1);
         if (lane == 0) z[i] = acc;
     }
 }
@@ -149,8 +158,7 @@ __device__ inline double rows_matvec_lds(const double* R, const double* v, doubl
             a3 += Ri[k + 3 * P] * v[k + 3 * P];
         }
         for (; k <= i; k += P) a0 += Ri[k] * v[k];
-        double acc = (a0 + a1) + (a2 + a3);
-        for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        const double acc = group_sum((a0 + a1) + (a2 + a3), P);
         if (sub == 0) {
             z[i] = acc;
             part += acc * acc;
@@ -175,8 +183,7 @@ __device__ inline void cols_matvec_lds(const double* R, const double* v, double*
             a3 += v[i + 3 * P] * R[tri(i + 3 * P) + k];
         }
         for (; i < s; i += P) a0 += v[i] * R[tri(i) + k];
-        double acc = (a0 + a1) + (a2 + a3);
-        for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        const double acc = group_sum((a0 + a1) + (a2 + a3), P);
         if (sub == 0) out[k] = acc / div;
     }
 }
@@ -1049,7 +1056,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
                     acc += (double)fa[e].x * fb[e].x + (double)fa[e].y * fb[e].y + (double)fa[e].z * fb[e].z +
                            (double)fa[e].w * fb[e].w;
             }
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            acc = wave_sum(acc);
             if (lane == 0) s.c[nI0 + t] = acc;
         }
     } else {

@@ -30,6 +30,7 @@
 
 #include "../../include/bmpl.h"
 #include "bmpl_internal.h"
+#include "wave_ops.h"
 
 namespace bmpl {
 namespace {
@@ -58,11 +59,9 @@ __global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict_
         sh += vh * vh;
         sd += d * d;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        s += __shfl_xor(s, o);
-        sh += __shfl_xor(sh, o);
-        sd += __shfl_xor(sd, o);
-    }
+    s = wave_sum(s);
+    sh = wave_sum(sh);
+    sd = wave_sum(sd);
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = s;
         red[1][threadIdx.x >> 6] = sh;
@@ -96,8 +95,7 @@ __device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4
             acc += (double)fx[e].x * fy.x + (double)fx[e].y * fy.y + (double)fx[e].z * fy.z + (double)fx[e].w * fy.w;
         }
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return acc;
+    return wave_sum(acc);
 }
 
 // The candidate rule by sweeps over the row (used when many equal values overflow the candidate buffer
@@ -150,8 +148,7 @@ __device__ void screen_sweeps(const ScreenArgs& a, int row, int sig, int k, floa
     {
         float cur = tmax;
         for (int r = 0; r < k; ++r) {
-            float b = cur;
-            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            const float b = wave_max(cur);
             if (lane == 0) s_top[wave][r] = b;
             const unsigned long long owners = __ballot(cur == b);
             if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
@@ -188,11 +185,10 @@ __device__ void screen_sweeps(const ScreenArgs& a, int row, int sig, int k, floa
         }
     };
     if (T <= FLT_MAX) scan(consider);
-    for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
+    gall = wave_max(gall);
     // wave merge of the per-thread lists: k rounds of a wave max on the heads
     for (int r = 0; r < k; ++r) {
-        float b = top[0];
-        for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+        const float b = wave_max(top[0]);
         if (lane == 0) s_top[wave][r] = b;
         // the first lane holding the head value pops it
         const unsigned long long owners = __ballot(top[0] == b);
@@ -317,8 +313,7 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
     {
         float cur = tmax;
         for (int r = 0; r < k; ++r) {
-            float b = cur;
-            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            const float b = wave_max(cur);
             if (lane == 0) s_tw[wave * KMAX + r] = b;
             const unsigned long long owners = __ballot(cur == b);
             if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
@@ -394,7 +389,7 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
         const bool out = in && !(ex && ((ex[j >> 5] >> (j & 31)) & 1u));
         take(out && ok(v), j, v);
     }
-    for (int o = 32; o > 0; o >>= 1) gall = fmaxf(gall, __shfl_xor(gall, o));
+    gall = wave_max(gall);
     if (lane == 0) s_r[wave] = gall;
     if (tid == 0) { s_cnt = 0; s_kth = -1.f; }
     __syncthreads();
@@ -557,7 +552,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
         }
         if (k > 0 && gt < k && ge >= k) red[0] = v;   // every writer stores the same value
     }
-    for (int o = 32; o > 0; o >>= 1) e1 = fmax(e1, __shfl_xor(e1, o));
+    e1 = wave_max(e1);
     __syncthreads();
     if (lane == 0) red[2 + wave] = e1;   // red[0] = v_k, red[2..5] = per-wave maxima
     __syncthreads();
@@ -578,7 +573,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     __syncthreads();
     double mx = 0.0;
     for (int c = tid; c < nc; c += 256) mx = fmax(mx, s_val[c]);
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    mx = wave_max(mx);
     if (lane == 0) red[wave] = mx;
     __syncthreads();
     mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));

@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "bmpl_internal.h"
+#include "wave_ops.h"
 
 namespace bmpl {
 namespace {
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             mx = fmaxf(mx, fmaxf(fmaxf(fabsf(f.x), fabsf(f.y)), fmaxf(fabsf(f.z), fabsf(f.w))));
         }
         for (int j = m4 + tid; j < a.m; j += 256) mx = fmaxf(mx, fabsf(g[j]));
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        mx = wave_max(mx);
         if (lane == 0) s_red[wave] = mx;
         __syncthreads();
         if (tid == 0) {
@@ -104,8 +105,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     {
         float cur = tmax;
         for (int r = 0; r < k; ++r) {
-            float b = cur;
-            for (int o = 32; o > 0; o >>= 1) b = fmaxf(b, __shfl_xor(b, o));
+            const float b = wave_max(cur);
             if (lane == 0) s_val[wave * KMAX + r] = b;
             const unsigned long long owners = __ballot(cur == b);
             if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
                     }
                     __syncthreads();
                 }
-            for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
+            vmx = wave_max(vmx);
             if (lane == 0) s_red[wave] = vmx;
             __syncthreads();
             const int nsel = nc < k ? nc : k;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
         }
         // Buffer overflow (more than CAP entries at or above the bound: many equal values): k rounds of
         // a workgroup argmax over the row, each taking the best (|g|, index) pair after the previous one.
-        for (int o = 32; o > 0; o >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, o));
+        vmx = wave_max(vmx);
         if (lane == 0) s_red[wave] = vmx;
         __syncthreads();
         const float vmax_all = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
