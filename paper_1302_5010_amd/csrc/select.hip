@@ -9,7 +9,7 @@
 // below (they are k distinct entries of the row).  The registered entries and the
 // rest of the row as it streams in are tested against that bound and lambda; the
 // few that pass are appended to an LDS buffer (one atomic per wave and step) and
-// bitonic-sorted by (|g|, lower index).
+// ranked by (|g|, lower index): by counting for up to 256 entries, else by a bitonic sort.
 // On the first pass of the relative lambda rule the row maximum is reduced first
 // and lambda_i = c * ||A^T b_i||_inf is set from it (Section IV-A).
 #include <float.h>
@@ -192,6 +192,27 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
         }
         __syncthreads();
         const int nc = s_n;
+        if (nc <= 256) {
+            // few entries: each thread ranks one by counting the better ones (entries are distinct
+            // atoms, so the ranks are a permutation), no sort and one barrier
+            const int nsel = nc < k ? nc : k;
+            if (tid < nc) {
+                const float v = s_cv[tid];
+                const int j = s_ci[tid];
+                int rank = 0;
+                for (int d = 0; d < nc; ++d) rank += better(s_cv[d], s_ci[d], v, j) ? 1 : 0;
+                if (rank < nsel) a.sel[(int64_t)sig * a.selcap + rank] = j;
+            }
+            for (int q = nsel + tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = -1;
+            vmx = wave_max(vmx);
+            if (lane == 0) s_red[wave] = vmx;
+            __syncthreads();
+            if (tid == 0) {
+                a.nsel[sig] = nsel;
+                a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+            }
+            return;
+        }
         if (nc <= CAP) {
             int N = 64;
             while (N < nc) N <<= 1;
