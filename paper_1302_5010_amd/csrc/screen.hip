@@ -319,19 +319,19 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
             if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
         }
     }
-    if (tid == 0) s_n = 0;
+    if (tid == 0) { s_n = 0; s_T = INFINITY; }
     __syncthreads();
-    if (tid == 0) {
-        float T = INFINITY;
-        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;        // merge the four descending wave lists
-        for (int r = 0; r < k; ++r) {
-            const float v0 = p0 < k ? s_tw[p0] : -3.f, v1 = p1 < k ? s_tw[KMAX + p1] : -3.f;
-            const float v2 = p2 < k ? s_tw[2 * KMAX + p2] : -3.f, v3 = p3 < k ? s_tw[3 * KMAX + p3] : -3.f;
-            const float bv = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
-            T = bv;
-            if (bv == v0) ++p0; else if (bv == v1) ++p1; else if (bv == v2) ++p2; else ++p3;
-        }
-        s_T = T;
+    if (tid < 4 * k) {   // T = the k-th largest of the 4k listed maxima (equal values write the same T)
+        const int tw = tid / k;
+        const float v = s_tw[tw * KMAX + (tid - tw * k)];
+        int gt = 0, ge = 0;
+        for (int w2 = 0; w2 < 4; ++w2)
+            for (int r = 0; r < k; ++r) {
+                const float w = s_tw[w2 * KMAX + r];
+                gt += w > v;
+                ge += w >= v;
+            }
+        if (gt < k && ge >= k) s_T = v;
     }
     __syncthreads();
     // admission test on u = |g~| + eps: u >= T - eps (k > 0), and u > lambda for a fixed lambda

@@ -54,6 +54,19 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     const bool vec4 = ((a.ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(a.G) & 15) == 0);
     const int m4 = vec4 ? (a.m & ~3) : 0;
 
+    // Each thread's first CH float4 of the row stay in registers (issued before lambda is read, so the
+    // loads are in flight meanwhile); the rest is streamed once later.
+    constexpr int CH = 8;
+    float4 f0[CH];
+    uint32_t w0[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int j0 = 4 * tid + 1024 * q;
+        const bool in = j0 < m4;
+        f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        w0[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;   // 4 atoms share one word; 0xF: absent
+    }
+
     // Pass 1 (relative lambda rule only): lambda_i = c * max_j |g_j|.
     if (a.lam_rel > 0.0) {
         float mx = 0.f;
@@ -79,17 +92,6 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     float lamf = (float)lam;
     if ((double)lamf > lam) lamf = nextafterf(lamf, -INFINITY);
 
-    // Each thread's first CH float4 of the row stay in registers; the rest is streamed once later.
-    constexpr int CH = 8;
-    float4 f0[CH];
-    uint32_t w0[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int j0 = 4 * tid + 1024 * q;
-        const bool in = j0 < m4;
-        f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-        w0[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;   // 4 atoms share one word; 0xF: absent
-    }
     // The k-th largest of the 256 threads' maxima over their registered entries is at most the k-th
     // largest |g_j| of the row (they are k distinct entries of it), so only entries >= T can be among
     // the k largest: the insertions below skip the rest.
@@ -111,18 +113,21 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             if (lane == __ffsll((long long)owners) - 1) cur = -2.f;   // pop one holder
         }
     }
+    if (tid == 0) s_red[0] = INFINITY;           // k = 0: nothing is admitted
     __syncthreads();
-    if (tid == 0) {
-        float T = INFINITY;                        // k = 0: nothing is admitted
-        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;        // merge the four descending wave lists
-        for (int r = 0; r < k; ++r) {
-            const float v0 = p0 < k ? s_val[p0] : -3.f, v1 = p1 < k ? s_val[KMAX + p1] : -3.f;
-            const float v2 = p2 < k ? s_val[2 * KMAX + p2] : -3.f, v3 = p3 < k ? s_val[3 * KMAX + p3] : -3.f;
-            const float bv = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
-            T = bv;
-            if (bv == v0) ++p0; else if (bv == v1) ++p1; else if (bv == v2) ++p2; else ++p3;
-        }
-        s_red[0] = T;
+    if (tid < 4 * k) {
+        // T = the k-th largest of the 4k listed maxima: the value with fewer than k larger ones and at
+        // least k at or above it (equal values write the same T)
+        const int tw = tid / k;
+        const float v = s_val[tw * KMAX + (tid - tw * k)];
+        int gt = 0, ge = 0;
+        for (int w2 = 0; w2 < 4; ++w2)
+            for (int r = 0; r < k; ++r) {
+                const float w = s_val[w2 * KMAX + r];
+                gt += w > v;
+                ge += w >= v;
+            }
+        if (gt < k && ge >= k) s_red[0] = v;
     }
     __syncthreads();
     const float T = s_red[0];
