@@ -51,6 +51,16 @@ __device__ inline double block_sum(double v, double* red)
     return red[0] + red[1] + red[2] + red[3];
 }
 
+// block_sum for a caller that has passed a barrier since the last read of red (saves the first one).
+__device__ inline double block_sum_fenced(double v, double* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
 __device__ inline double block_max(double v, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -250,7 +260,7 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
         __syncthreads();
         for (int i = tid; i < s; i += NT) part += vz[i] * vz[i];
     }
-    const double zz = block_sum(part, red);
+    const double zz = block_sum_fenced(part, red);   // the barrier after the gather fences red
     const double gjj = s_gjj;
     const double dd = gjj - zz;
     if (!(dd > 1e-11 * gjj)) {
