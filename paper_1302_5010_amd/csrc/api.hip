@@ -725,6 +725,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             sc.excl = w.inI; sc.words = w.words;
             sc.k = rho; sc.nI = w.nI; sc.max_active = max_active;
             sc.cand = c->cand; sc.candcap = CANDCAP_DEF; sc.ncand = c->ncand;
+            sc.clear_count = c->n_spill_dev;
             hipError_t e = launch_screen(sc, q);
             if (e != hipSuccess) return e;
             RescoreArgs rs{};
@@ -743,9 +744,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             // candidate values and the staged residual within 60 KB of LDS
             rs.candcap_lds = RESCORE_LDS_SMALL;
             rs.spill_row = c->spill; rs.row_of = nullptr;
+            rs.spill_act = c->spill_act; rs.n_spill = c->n_spill_dev;   // appended in any order
             e = launch_rescore(rs, q);
-            if (e != hipSuccess) return e;
-            e = launch_flag_compact(lst, cnt, n_grid, c->spill, c->spill_act, c->n_spill_dev, q);
             if (e != hipSuccess) return e;
             RescoreArgs r2 = rs;
             r2.candcap_lds = std::max(64, std::min(CANDCAP_DEF, (61440 - 4 * c->kpad) / 12 / 4 * 4));

@@ -122,6 +122,7 @@ struct ScreenArgs {
     const uint32_t* excl; int words;
     int k; const int* nI; int max_active;
     int* cand; int candcap; int* ncand;
+    int* clear_count;                         // set to 0 by workgroup 0 before anything else (or null)
 };
 struct RescoreArgs {
     const float* At; int64_t lda; int kpad;  // float32 atoms
@@ -137,6 +138,7 @@ struct RescoreArgs {
     // (but fit candcap) undecided and records spill_row[sig] = its row + 1 (0 for every other running
     // signal); a pass over those signals with row_of = spill_row reads the product row recorded there.
     int* spill_row; const int* row_of;
+    int* spill_act; int* n_spill;   // first pass: the left-over signals are appended here (n_spill starts at 0)
 };
 // e4m3 ranking (screen.hip): exact re-score of the candidates that the e4m3 product ranked highest,
 // admission of the exact violators among them, and the list of signals left for a certified pass.

@@ -274,6 +274,7 @@ __global__ __launch_bounds__(256) void screen_select_kernel(ScreenArgs a)
     __shared__ float s_r[4];
     __shared__ float s_T, s_kth;
     __shared__ int s_n, s_cnt;
+    if (a.clear_count && blockIdx.x == 0 && threadIdx.x == 0) *a.clear_count = 0;   // the re-score's spill list
     const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
     const int row = blockIdx.x;
     if (row >= n_act) return;
@@ -478,7 +479,10 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
     const int nc_all = a.ncand[sig];
     if (a.spill_row) {   // first of two passes: more candidates than this pass's LDS holds are left over
         const bool over_lds = nc_all > a.candcap_lds && nc_all <= a.candcap;
-        if (tid == 0) a.spill_row[sig] = over_lds ? row + 1 : 0;
+        if (tid == 0) {
+            a.spill_row[sig] = over_lds ? row + 1 : 0;
+            if (over_lds) a.spill_act[atomicAdd(a.n_spill, 1)] = sig;
+        }
         if (over_lds) return;
     }
     const bool overflow = nc_all > a.candcap || nc_all > a.candcap_lds;
