@@ -766,6 +766,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             r8.lam = c->zeros; r8.lam_rel = 0.0;
             r8.k = std::min(CAND8, 2 * rho); r8.sel = c->cand8; r8.selcap = CAND8; r8.nsel = c->ncand8;
             r8.vmax = c->vmax8;
+            r8.clear_count = c->n_cert_dev;
             HIPC(launch_select(r8, q));
             // ... re-scored exactly; the exact violators among them are admitted
             Rank8Args rk{};
@@ -774,10 +775,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             rk.cand = c->cand8; rk.candcap = CAND8; rk.ncand = c->ncand8;
             rk.lam = w.lam; rk.k = rho; rk.nI = w.nI; rk.max_active = max_active;
             rk.sel = w.sel; rk.selcap = w.selcap; rk.nsel = w.nsel; rk.vmax = w.vmax; rk.cert = c->cert;
+            // signals with no exact violator among their candidates go to cert_act (any order): the
+            // certified bfloat16 pass decides them
+            rk.cert_act = c->cert_act; rk.n_cert = c->n_cert_dev;
             HIPC(launch_rank8(rk, q));
-            // signals with no exact violator among their candidates: the certified bfloat16 pass decides
-            HIPC(launch_flag_compact(c->act[cur], c->n_act_dev + cur, n_grid, c->cert, c->cert_act, c->n_cert_dev,
-                                     q));
             HIPC(product(1, c->cert_act, c->n_cert_dev, true));
             HIPC(screen_pass(c->cert_act, c->n_cert_dev));
         } else if (c->A16) {

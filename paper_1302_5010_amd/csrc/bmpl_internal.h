@@ -109,6 +109,7 @@ struct SelectArgs {
     int* sel; int selcap; int* nsel; float* vmax;
     // pursuit bookkeeping (may be null in the diagnostic entry point)
     const int* nI; int max_active;
+    int* clear_count;      // set to 0 by workgroup 0 before anything else (or null)
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
 
@@ -151,11 +152,9 @@ struct Rank8Args {
     int k; const int* nI; int max_active;
     int* sel; int selcap; int* nsel; float* vmax;
     int* cert;                               // [p] 1: no exact violator among the candidates
+    int* cert_act; int* n_cert;              // those signals, appended in any order (n_cert starts at 0)
 };
 hipError_t launch_rank8(const Rank8Args& a, hipStream_t stream);
-// act_out = the signals of act_in (device count n_in_dev) with flag[sig] != 0, in order; count to n_out_dev.
-hipError_t launch_flag_compact(const int* act_in, const int* n_in_dev, int n_in, const int* flag, int* act_out,
-                               int* n_out_dev, hipStream_t stream);
 // A8[j] = e4m3(a_j / ascale[j]), ascale[j] the power of two that brings max |a_j| to at most 448.
 hipError_t launch_atoms_fp8(const float* At, int64_t lda, int kpad, uint8_t* A8, float* ascale, int m,
                             hipStream_t stream);

@@ -674,38 +674,8 @@ __global__ __launch_bounds__(256) void rank8_kernel(Rank8Args a)
         a.nsel[sig] = nsel;
         a.vmax[sig] = (float)vmx;
         a.cert[sig] = nsel == 0 ? 1 : 0;
+        if (nsel == 0 && a.cert_act) a.cert_act[atomicAdd(a.n_cert, 1)] = sig;
     }
-}
-
-// One workgroup: stable compaction of the flagged signals of a running list.
-__global__ __launch_bounds__(1024) void flag_compact_kernel(const int* act_in, const int* n_in_dev, int n_in,
-                                                            const int* flag, int* act_out, int* n_out_dev)
-{
-    __shared__ int s_wave[16];
-    __shared__ int s_base;
-    const int n = n_in_dev ? *n_in_dev : n_in;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_base = 0;
-    __syncthreads();
-    for (int r0 = 0; r0 < n; r0 += 1024) {
-        const int r = r0 + tid;
-        const int sig = r < n ? (act_in ? act_in[r] : r) : -1;
-        const bool keep = sig >= 0 && flag[sig] != 0;
-        const unsigned long long bal = __ballot(keep);
-        if (lane == 0) s_wave[wave] = __popcll(bal);
-        __syncthreads();
-        int before = s_base;
-        for (int w2 = 0; w2 < wave; ++w2) before += s_wave[w2];
-        if (keep) act_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = sig;
-        __syncthreads();
-        if (tid == 0) {
-            int t = 0;
-            for (int w2 = 0; w2 < 16; ++w2) t += s_wave[w2];
-            s_base += t;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) *n_out_dev = s_base;
 }
 
 __global__ __launch_bounds__(256) void atoms_fp8_kernel(const float* __restrict__ At, int64_t lda, int kpad,
@@ -768,14 +738,6 @@ hipError_t launch_rank8(const Rank8Args& a, hipStream_t stream)
     if (a.p_grid <= 0) return hipSuccess;
     if (a.kpad % 4 || a.lda % 4 || a.ldr % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(rank8_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_flag_compact(const int* act_in, const int* n_in_dev, int n_in, const int* flag, int* act_out,
-                               int* n_out_dev, hipStream_t stream)
-{
-    hipLaunchKernelGGL(flag_compact_kernel, dim3(1), dim3(1024), 0, stream, act_in, n_in_dev, n_in, flag, act_out,
-                       n_out_dev);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ __device__ inline bool better(float v, int i, float w, int j)
 template <int KMAX>
 __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
 {
+    if (a.clear_count && blockIdx.x == 0 && threadIdx.x == 0) *a.clear_count = 0;   // a later kernel's list
     const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
     const int row = blockIdx.x;
     if (row >= n_act) return;
