@@ -918,9 +918,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         if (st != BMPL_OK) return st;
     }
     const size_t e_pack = tm ? mark(c, s) : 0;
+    const size_t pack_lds = (size_t)w.K * 12;
     PackArgs pk{w, out->x_val_dev, out->x_idx_dev, out->supp_len_dev, out->iters_dev, out->kkt_dev,
-                out->lambda_dev, out->objective_dev, out->sig_status_dev, out->ld_x};
-    hipLaunchKernelGGL(pack_kernel, dim3(p), dim3(256), 0, s, pk);
+                out->lambda_dev, out->objective_dev, out->sig_status_dev, out->ld_x, pack_lds <= 48 * 1024 ? 1 : 0};
+    hipLaunchKernelGGL(pack_kernel, dim3(p), dim3(256), pk.stage ? pack_lds : 0, s, pk);
     HIPC(hipGetLastError());
     if (tm) {
         const size_t e_last = mark(c, s);

@@ -65,6 +65,7 @@ struct PackArgs {
     float* x_val; int32_t* x_idx; int32_t* supp_len; int32_t* iters;
     double* kkt; double* lambda; double* objective; int32_t* status;
     int ld_x;
+    int stage;          // the support's atoms and values are staged in dynamic LDS (12 w.K bytes)
 };
 
 struct SlotArrays {

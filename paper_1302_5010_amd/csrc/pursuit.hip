@@ -25,6 +25,7 @@
 //
 // One 256-thread workgroup per signal; signals are independent.
 #include <float.h>
+#include <limits.h>
 
 #include "../../include/bmpl.h"
 #include "bmpl_internal.h"
@@ -1370,20 +1371,43 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a)
     const int* at = w.slot_atom + sig * K;
     const int nS = (w.status[sig] & BMPL_SIG_NONFINITE) ? 0 : w.nS[sig];
     int cnt = 0;
-    // rank by atom index among the support positions with a nonzero value
-    for (int k = threadIdx.x; k < nS; k += 256) {
-        const int u = so[k];
-        const double xu = xs[u];
-        if (xu == 0.0) continue;
-        const int atom = at[u];
-        int rank = 0;
-        for (int k2 = 0; k2 < nS; ++k2) {
-            const int u2 = so[k2];
-            if (xs[u2] != 0.0 && at[u2] < atom) ++rank;
+    if (a.stage) {
+        // the support's values and atoms (INT_MAX for a zero value) in LDS, then ranks from LDS
+        extern __shared__ double s_px[];
+        int* s_pa = reinterpret_cast<int*>(s_px + K);
+        for (int k = threadIdx.x; k < nS; k += 256) {
+            const int u = so[k];
+            const double xu = xs[u];
+            s_px[k] = xu;
+            s_pa[k] = xu != 0.0 ? at[u] : INT_MAX;
         }
-        if (rank < a.ld_x) {
-            a.x_idx[(int64_t)sig * a.ld_x + rank] = atom;
-            a.x_val[(int64_t)sig * a.ld_x + rank] = (float)xu;
+        __syncthreads();
+        for (int k = threadIdx.x; k < nS; k += 256) {
+            const int atom = s_pa[k];
+            if (atom == INT_MAX) continue;
+            int rank = 0;
+            for (int k2 = 0; k2 < nS; ++k2) rank += s_pa[k2] < atom;
+            if (rank < a.ld_x) {
+                a.x_idx[(int64_t)sig * a.ld_x + rank] = atom;
+                a.x_val[(int64_t)sig * a.ld_x + rank] = (float)s_px[k];
+            }
+        }
+    } else {
+        // rank by atom index among the support positions with a nonzero value
+        for (int k = threadIdx.x; k < nS; k += 256) {
+            const int u = so[k];
+            const double xu = xs[u];
+            if (xu == 0.0) continue;
+            const int atom = at[u];
+            int rank = 0;
+            for (int k2 = 0; k2 < nS; ++k2) {
+                const int u2 = so[k2];
+                if (xs[u2] != 0.0 && at[u2] < atom) ++rank;
+            }
+            if (rank < a.ld_x) {
+                a.x_idx[(int64_t)sig * a.ld_x + rank] = atom;
+                a.x_val[(int64_t)sig * a.ld_x + rank] = (float)xu;
+            }
         }
     }
     for (int k = threadIdx.x; k < nS; k += 256) cnt += xs[so[k]] != 0.0;
