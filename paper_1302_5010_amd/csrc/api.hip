@@ -100,11 +100,11 @@ struct bmpl_ctx {
     struct GraphKey {
         int p, cur, kl, K, shapes[3];
         long gen;
-        int merged;   // the large tile also covers the middle bucket of running counts
+        int variant;  // bit 0: the large tile also covers the middle count bucket; bit 1: a 2-iteration segment
         bool operator==(const GraphKey& o) const
         {
             return p == o.p && cur == o.cur && kl == o.kl && K == o.K && gen == o.gen && shapes[0] == o.shapes[0] &&
-                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] && merged == o.merged;
+                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] && variant == o.variant;
         }
     };
     struct GraphEntry { GraphKey key; hipGraph_t g; hipGraphExec_t ge; };
@@ -316,10 +316,10 @@ void drop_graphs(bmpl_ctx* c)
 // The instantiated graph of one segment for this configuration, captured on first use by
 // `enqueue(stream)` on the context's capture stream.
 template <class F>
-bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, int merged, hipGraphExec_t* out, F&& enqueue)
+bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, int variant, hipGraphExec_t* out, F&& enqueue)
 {
     bmpl_ctx::GraphKey key{p, cur, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen,
-                           merged};
+                           variant};
     for (auto& e : c->graphs)
         if (e.key == key) {
             *out = e.ge;
@@ -875,16 +875,19 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     bool after_warm = warm;
     while (n_act > 0) {
         if (graph && !after_warm) {
-            // GRAPH_DEPTH iterations as one captured graph launch.  The kernels read the running
-            // count on the device, so iterations past the last signal's stop are empty launches.
-            const int need = std::min(max_active, imax + GRAPH_DEPTH * rho);
+            // GRAPH_DEPTH iterations as one captured graph launch (two once fewer than 64 signals run: the
+            // last few usually stop within two).  The kernels read the running count on the device, so
+            // iterations past the last signal's stop are empty launches.
+            const int depth = n_act < 64 ? 2 : GRAPH_DEPTH;
+            const int need = std::min(max_active, imax + depth * rho);
             st = grow_to(need);
             if (st != BMPL_OK) return st;
             hipGraphExec_t ge = nullptr;
             merge_mid = n_act >= 512;
-            st = segment_graph(c, p, cur, need, merge_mid ? 1 : 0, &ge, [&](hipStream_t q) -> bmpl_status {
+            st = segment_graph(c, p, cur, need, (merge_mid ? 1 : 0) | (depth == 2 ? 2 : 0), &ge,
+                               [&](hipStream_t q) -> bmpl_status {
                 int cc = cur;
-                for (int d = 0; d < GRAPH_DEPTH; ++d) {
+                for (int d = 0; d < depth; ++d) {
                     // factor capacity for this iteration's |I| (a smaller LDS footprint fits more signals per CU)
                     const int ib = std::min(need, imax + (d + 1) * rho);
                     bmpl_status r = enqueue_master(q, cc, p, ib, ib, true, true);
@@ -898,7 +901,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             if (st != BMPL_OK) return st;
             HIPC(hipGraphLaunch(ge, s));
             imax = need;
-            st = read_count(cur);    // GRAPH_DEPTH is even: the running list is back in act[cur]
+            st = read_count(cur);    // the depth is even: the running list is back in act[cur]
             if (st != BMPL_OK) return st;
             continue;
         }
