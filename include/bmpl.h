@@ -78,8 +78,9 @@ typedef enum {
 /* bmpl_options.flags bits. */
 #define BMPL_FLAG_TIMING 1          /* time every kernel launch with HIP events (see bmpl_get_timing) */
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
-#define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each,
-                                       one launch and one read-back per segment (ignored with TIMING) */
+#define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each
+                                       (2 once fewer than 64 signals run), one launch and one read-back per
+                                       segment (ignored with TIMING) */
 #define BMPL_FLAG_Q_ROUTE 32        /* Section III's batch correlation, Eq. (12): after the first pass,
                                        g = beta - Q_{:,S} x_S with beta = A^T b (float64, computed once
                                        per solve) and the float64 Gram table, instead of the MFMA product
