@@ -532,28 +532,43 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
 }
 
 // g_u = c_u - G_uS x_S for the slots u < nI (all of them, or only those outside S
-// that may still enter it), one thread per slot streaming its own row of G.
+// that may still enter it).  A row of 16 lanes takes two slots at a time and splits their support
+// entries (G is global, so a slot costs one round trip with its loads in flight rather than a chain of
+// |S| / 8), then sums each row by DPP moves inside the row.
 __device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outside_only)
 {
-    for (int u = threadIdx.x; u < nI; u += NT) {
-        if (outside_only && (v.th[u] != 0 || v.ex[u])) continue;
-        const double* Gu = v.G + (int64_t)u * v.K;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int k = 0;
-        for (; k + 8 <= nS; k += 8) {
-            double gv[8];
+    constexpr int GL = 16, NG = NT / GL, DEPTH = 4;
+    const int sub = threadIdx.x & (GL - 1), grp = threadIdx.x / GL;
+    for (int u0 = grp; u0 < nI; u0 += 2 * NG) {
+        const int u1 = u0 + NG;
+        const bool d0 = !(outside_only && (v.th[u0] != 0 || v.ex[u0]));
+        const bool d1 = u1 < nI && !(outside_only && (v.th[u1] != 0 || v.ex[u1]));
+        if (!d0 && !d1) continue;       // the same decision for the whole row of lanes
+        const double* G0 = v.G + (int64_t)u0 * v.K;
+        const double* G1 = v.G + (int64_t)(d1 ? u1 : u0) * v.K;
+        double a0 = 0.0, a1 = 0.0;
+        for (int k0 = sub; k0 < nS; k0 += GL * DEPTH) {
+            double g0[DEPTH], g1[DEPTH], xv[DEPTH];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) gv[e] = Gu[v.so[k + e]];
-            a0 += gv[0] * v.x[v.so[k]] + gv[4] * v.x[v.so[k + 4]];
-            a1 += gv[1] * v.x[v.so[k + 1]] + gv[5] * v.x[v.so[k + 5]];
-            a2 += gv[2] * v.x[v.so[k + 2]] + gv[6] * v.x[v.so[k + 6]];
-            a3 += gv[3] * v.x[v.so[k + 3]] + gv[7] * v.x[v.so[k + 7]];
+            for (int e = 0; e < DEPTH; ++e) {
+                const int k = k0 + GL * e;
+                const int sk = k < nS ? v.so[k] : 0;
+                g0[e] = (k < nS && d0) ? G0[sk] : 0.0;
+                g1[e] = (k < nS && d1) ? G1[sk] : 0.0;
+                xv[e] = k < nS ? v.x[sk] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < DEPTH; ++e) {
+                a0 += g0[e] * xv[e];
+                a1 += g1[e] * xv[e];
+            }
         }
-        for (; k < nS; ++k) {
-            const int s0 = v.so[k];
-            a0 += Gu[s0] * v.x[s0];
+        a0 = row16_sum(a0);
+        a1 = row16_sum(a1);
+        if (sub == 0) {
+            if (d0) vg[u0] = v.c[u0] - a0;
+            if (d1) vg[u1] = v.c[u1] - a1;
         }
-        vg[u] = v.c[u] - ((a0 + a1) + (a2 + a3));
     }
     __syncthreads();
 }

@@ -100,4 +100,14 @@ __device__ inline double group_sum(double v, int P)
     return v;
 }
 
+// Sum over each row of 16 lanes (every lane of the row gets it; the row's lanes active together).
+__device__ inline double row16_sum(double v)
+{
+    v += lane_move<DPP_XOR1>(v);
+    v += lane_move<DPP_XOR2>(v);
+    v += lane_move<DPP_HALF_MIRROR>(v);
+    v += lane_move<DPP_MIRROR>(v);
+    return v;
+}
+
 }  // namespace bmpl
