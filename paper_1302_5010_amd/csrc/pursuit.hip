@@ -969,14 +969,14 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         }
         for (int k = tid; k < nS; k += NT) s.so[k] = g_so[k];
     }
-    if (s.r_lds) {   // four loads in flight per thread
+    if (s.r_lds) {   // eight loads in flight per thread
         const int64_t T = tri(nS);
-        for (int64_t e0 = tid; e0 < T; e0 += 4 * NT) {
-            double r[4];
+        for (int64_t e0 = tid; e0 < T; e0 += 8 * NT) {
+            double r[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r[q] = e0 + q * NT < T ? g_R[e0 + q * NT] : 0.0;
+            for (int q = 0; q < 8; ++q) r[q] = e0 + q * NT < T ? g_R[e0 + q * NT] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 8; ++q)
                 if (e0 + q * NT < T) s.R[e0 + q * NT] = r[q];
         }
     }
