@@ -230,11 +230,14 @@ def test_edge_cases(screen):
     assert out0["status"].numel() == 0
 
 
-def test_caps_match_oracle_caps():
+@pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
+def test_caps_match_oracle_caps(screen):
+    """Iteration and active-set caps; with max_active = 4 the selection is asked for k = 0 atoms once I is
+    full (the screening kernels' stop-test-only path)."""
     pk = _lib()
     P = bi.small_gaussian()
     lam = lam_rel(P.At, P.Bt, P.lambda_rel)
-    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_outer=2)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_outer=2, screen=screen)
     out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
     st = out["status"].cpu().numpy()
     ref = oracle.solve(P.At, P.Bt, lam, P.rho, max_outer=2)
@@ -243,7 +246,7 @@ def test_caps_match_oracle_caps():
     # the capped iterate is the exact master solution on the same active sets
     Xg = dense_from_gpu(out, P.m)
     np.testing.assert_allclose(Xg, ref["X"], atol=1e-5)
-    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_active=4)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_active=4, screen=screen)
     out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
     st = out["status"].cpu().numpy()
     ref = oracle.solve(P.At, P.Bt, lam, P.rho, max_active=4)
