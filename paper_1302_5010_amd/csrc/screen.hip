@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
             const float w = s_gt[d];
             rank += (w > v || (w == v && cand[d] < j)) ? 1 : 0;
         }
-        for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o);
+        rank = wave_sum(rank);
         if (rank < (k > 0 ? k : 1)) {
             const double e = score(c);
             if (lane == 0) s_val[c] = e;
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs a)
         if (rank < k) a.sel[(int64_t)sig * a.selcap + rank] = j;
         ++cnt;
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    cnt = wave_sum(cnt);
     if (lane == 0) red[wave] = (double)cnt;
     __syncthreads();
     if (tid == 0) {

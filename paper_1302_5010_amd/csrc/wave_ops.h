@@ -80,6 +80,12 @@ __device__ inline double wave_sum(double v)
     return read_lane(v, 0) + read_lane(v, 32);
 }
 
+__device__ inline int wave_sum(int v)
+{
+    v = half_reduce(v, [](int a, int b) { return a + b; });
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
+}
+
 __device__ inline double wave_max(double v)
 {
     v = half_reduce(v, [](double a, double b) { return fmax(a, b); });
