@@ -343,8 +343,7 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
                 for (int e = 0; e < JB; ++e) acc[e] += r * wk[e];
             }
 #pragma unroll
-            for (int e = 0; e < JB; ++e)
-                for (int o = 32; o > 0; o >>= 1) acc[e] += __shfl_xor(acc[e], o);
+            for (int e = 0; e < JB; ++e) acc[e] = wave_sum(acc[e]);
         }
         __syncthreads();
         if (i >= 0 && lane < JB) {
