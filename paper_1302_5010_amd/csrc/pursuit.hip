@@ -128,20 +128,21 @@ struct Sig {
 };
 
 // z[i] = sum_{k <= i} R(i, k) w[k] for i < s with the factor in global memory: one row per wave at a
-// time, lanes across the row (coalesced, four loads in flight), a wave reduction per row.
+// time, lanes across the row (coalesced, eight loads in flight), a wave reduction per row.
 __device__ inline void rows_matvec_global(const double* R, const double* w, double* z, int s)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = wave; i < s; i += NT / 64) {
         const double* Ri = R + tri(i);
         double a0 = 0.0, a1 = 0.0;
-        int k = lane;
-        for (; k + 192 <= i; k += 256) {
-            const double r0 = Ri[k], r1 = Ri[k + 64], r2 = Ri[k + 128], r3 = Ri[k + 192];
-            a0 += r0 * w[k] + r2 * w[k + 128];
-            a1 += r1 * w[k + 64] + r3 * w[k + 192];
+        for (int k0 = lane; k0 <= i; k0 += 512) {   // eight loads in flight per lane
+            double r[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r[e] = k0 + 64 * e <= i ? Ri[k0 + 64 * e] : 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (k0 + 64 * e <= i) (e & 1 ? a1 : a0) += r[e] * w[k0 + 64 * e];
         }
-        for (; k <= i; k += 64) a0 += Ri[k] * w[k];
         const double acc = wave_sum(a0 + a1);
         if (lane == 0) z[i] = acc;
     }
@@ -219,18 +220,17 @@ __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
             o += i + 1;
         }
     } else {
-        // global factor: rows in lockstep across the wave so loads of one row coalesce; four rows'
+        // global factor: rows in lockstep across the wave so loads of one row coalesce; eight rows'
         // loads in flight
         int i = k & ~63;
-        for (; i + 4 <= s; i += 4) {
-            const double r0 = i >= k ? f.R[tri(i) + k] : 0.0;
-            const double r1 = i + 1 >= k ? f.R[tri(i + 1) + k] : 0.0;
-            const double r2 = i + 2 >= k ? f.R[tri(i + 2) + k] : 0.0;
-            const double r3 = i + 3 >= k ? f.R[tri(i + 3) + k] : 0.0;
-            a0 += v[i] * r0;
-            a1 += v[i + 1] * r1;
-            a2 += v[i + 2] * r2;
-            a3 += v[i + 3] * r3;
+        for (; i + 8 <= s; i += 8) {
+            double r[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r[e] = i + e >= k ? f.R[tri(i + e) + k] : 0.0;
+            a0 += v[i] * r[0] + v[i + 4] * r[4];
+            a1 += v[i + 1] * r[1] + v[i + 5] * r[5];
+            a2 += v[i + 2] * r[2] + v[i + 6] * r[6];
+            a3 += v[i + 3] * r[3] + v[i + 7] * r[7];
         }
         for (; i < s; ++i)
             if (i >= k) a0 += v[i] * f.R[tri(i) + k];
