@@ -325,12 +325,12 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
         if (i >= 0) {
             const double* Ri = v.R + tri(i);
             int k = lane;
-            for (; k + 192 <= i; k += 256) {      // four loads in flight per lane
-                double r[4];
+            for (; k + 448 <= i; k += 512) {      // eight loads in flight per lane
+                double r[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) r[q] = Ri[k + 64 * q];
+                for (int q = 0; q < 8; ++q) r[q] = Ri[k + 64 * q];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     const double* wk = zs + (k + 64 * q) * JB;
 #pragma unroll
                     for (int e = 0; e < JB; ++e) acc[e] += r[q] * wk[e];
@@ -412,12 +412,12 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
 #pragma unroll
         for (int b = 0; b < JB; ++b) acc[b] = 0.0;
         int i = kb + wave * 64;
-        for (; i + 4 <= s0; i += 4) {              // four rows' loads in flight
-            double r[4];
+        for (; i + 8 <= s0; i += 8) {              // eight rows' loads in flight
+            double r[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r[q] = (i + q >= k) ? v.R[tri(i + q) + k] : 0.0;
+            for (int q = 0; q < 8; ++q) r[q] = (i + q >= k) ? v.R[tri(i + q) + k] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const double* zi = zs + (i + q) * JB;
 #pragma unroll
                 for (int b = 0; b < JB; ++b) acc[b] += r[q] * zi[b];
