@@ -29,7 +29,7 @@
  *    (NULL = the null stream) and may return before it finishes; outputs are
  *    valid once the stream is synchronised.  bmpl_solve synchronises the stream
  *    once per outer iteration to read back how many signals are still running.
- *  - Every call returns a bmpl_status; on failure bmpl_last_error() describes
+ *  - Every call returns a bmpl_status; on failure bmpl_last_error(ctx) describes
  *    it.  A context is not re-entrant: one call in flight per context.
  */
 #ifndef BMPL_H
@@ -135,7 +135,10 @@ typedef struct {
  * coefficients sorted by atom index, and -1 / 0 for supp_len[i] <= s < ld_x (every entry is
  * written, so the caller need not clear the buffers); ld_x >= min(max_active, n).
  * kkt[i] = max( max_{j not in S}(|a_j^T xi| - lambda)_+ , max_{j in S}|a_j^T xi - lambda sign x_j| ) / lambda,
- * computed in float64 on I and from the float32 correlation product outside I.
+ * computed in float64 on I; outside I from the correlation product with its rounding bounded: atoms
+ * whose reduced-precision or float32 |g~_j| lies within the product's error bound of lambda are re-scored
+ * exactly (float32 data, float64 sums) before the natural stop is accepted, so a signal is never reported
+ * CONVERGED while an atom outside I has an exact |a_j^T xi| > lambda.
  * objective[i] = lambda ||x||_1 + 1/2 ||b - A x||^2 in float64.
  * lambda[i] = the lambda_i actually used.  iters[i] = outer iterations that added atoms.
  * Any pointer except x_idx/x_val/supp_len may be NULL to skip that output.
@@ -191,8 +194,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p,
 /* Release the context and all its device memory.  NULL is accepted. */
 bmpl_status bmpl_destroy(bmpl_ctx* c);
 
-/* Message describing the last failure on this thread; valid until the next call. */
-const char* bmpl_last_error(void);
+/* Message describing the last failure of a call made on this thread (kept per thread, so it also
+ * covers a bmpl_create that returned no context; c may be NULL); valid until the next call. */
+const char* bmpl_last_error(const bmpl_ctx* c);
 
 /*
  * Diagnostic entry points (one step of the pursuit each, used by the kernel

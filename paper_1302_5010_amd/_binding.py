@@ -84,7 +84,7 @@ def _load():
     lib.bmpl_solve.argtypes = [vp, vp, i64, i32, vp, vp, i32, ctypes.POINTER(_Result), vp]
     lib.bmpl_destroy.argtypes = [vp]
     lib.bmpl_last_error.restype = ctypes.c_char_p
-    lib.bmpl_last_error.argtypes = []
+    lib.bmpl_last_error.argtypes = [ctypes.c_void_p]
     lib.bmpl_correlate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
     lib.bmpl_select.argtypes = [vp, vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.bmpl_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
@@ -119,7 +119,7 @@ _lib = _load()
 
 def _check(rc: int, what: str):
     if rc != 0:
-        msg = _lib.bmpl_last_error().decode(errors="replace")
+        msg = _lib.bmpl_last_error(None).decode(errors="replace")
         raise BmplError(f"{what} failed ({rc}): {msg}")
 
 

@@ -51,6 +51,7 @@ struct bmpl_ctx {
     int* cert_act = nullptr;      // [p_cap] compacted list of those signals
     int* n_cert_dev = nullptr;    // its length
     double band_x = 0.0, band_dx = 0.0;   // bfloat16 band: eps_i = band_x ||xi_i|| + band_dx ||bf16(xi_i) - xi_i||
+    double band32 = 0.0;          // float32 product: |g~_j - g_j| <= band32 ||xi_i|| (2 n 2^-24 max_j ||a_j||)
     int* spill = nullptr;         // [p_cap] re-score rows left to the second pass (row + 1, 0 = none)
     int* spill_act = nullptr;     // [p_cap] their signals
     int* n_spill_dev = nullptr;   // their count
@@ -97,14 +98,17 @@ struct bmpl_ctx {
     // graph capture of iteration segments (BMPL_FLAG_GRAPH)
     hipStream_t cap_stream = nullptr;
     long ws_gen = 0;                   // bumped whenever workspace buffers move
+    // A segment's kernels bake in the bounds on |I| of each of its iterations, which follow from the
+    // bound at the segment's start (i0) and its end (kl, clamped to max_active): both are in the key.
     struct GraphKey {
-        int p, cur, kl, K, shapes[3];
+        int p, cur, i0, kl, K, shapes[3];
         long gen;
         int variant;  // bit 0: the large tile also covers the middle count bucket; bit 1: a 2-iteration segment
         bool operator==(const GraphKey& o) const
         {
-            return p == o.p && cur == o.cur && kl == o.kl && K == o.K && gen == o.gen && shapes[0] == o.shapes[0] &&
-                   shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] && variant == o.variant;
+            return p == o.p && cur == o.cur && i0 == o.i0 && kl == o.kl && K == o.K && gen == o.gen &&
+                   shapes[0] == o.shapes[0] && shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] &&
+                   variant == o.variant;
         }
     };
     struct GraphEntry { GraphKey key; hipGraph_t g; hipGraphExec_t ge; };
@@ -316,10 +320,11 @@ void drop_graphs(bmpl_ctx* c)
 // The instantiated graph of one segment for this configuration, captured on first use by
 // `enqueue(stream)` on the context's capture stream.
 template <class F>
-bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int kl, int variant, hipGraphExec_t* out, F&& enqueue)
+bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int i0, int kl, int variant, hipGraphExec_t* out,
+                          F&& enqueue)
 {
-    bmpl_ctx::GraphKey key{p, cur, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen,
-                           variant};
+    bmpl_ctx::GraphKey key{p, cur, i0, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]},
+                           c->ws_gen, variant};
     for (auto& e : c->graphs)
         if (e.key == key) {
             *out = e.ge;
@@ -372,7 +377,11 @@ bmpl_status bmpl_options_default(bmpl_options* o)
     return BMPL_OK;
 }
 
-const char* bmpl_last_error(void) { return g_err.c_str(); }
+const char* bmpl_last_error(const bmpl_ctx* c)
+{
+    (void)c;   // the message is per thread: it also describes failures that left no context (bmpl_create)
+    return g_err.c_str();
+}
 
 bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, bmpl_lambda_mode mode,
                         double lambda, const bmpl_options* o, void* hip_stream, bmpl_ctx** out)
@@ -422,6 +431,20 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
                              hipMemcpyDeviceToDevice, s);
+    // float32 product band: the deterministic bound 2 n 2^-24 ||a_j|| ||xi|| of an n-term float32 dot
+    // product (products and sums rounded), with the largest atom norm and a 1 % margin
+    if (e == hipSuccess) {
+        float* norms = nullptr;
+        e = dalloc(&norms, (size_t)3 * m);
+        if (e == hipSuccess) e = launch_atom_norms(c->At, c->kpad, c->kpad, norms, m, s);
+        std::vector<float> hn((size_t)m);
+        if (e == hipSuccess) e = hipMemcpyAsync(hn.data(), norms, sizeof(float) * m, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (norms) (void)hipFree(norms);
+        double amax = 0.0;
+        for (int j = 0; j < m; ++j) amax = std::max(amax, (double)hn[j]);
+        c->band32 = 2.0 * n * std::ldexp(1.0, -24) * amax * 1.01;
+    }
     // bfloat16 copy of the dictionary and the factors of the screening band.
     if (e == hipSuccess && opt.screen != BMPL_PREC_FP32) {
         float* norms = nullptr;
@@ -785,6 +808,18 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             HIPC(screen_pass(c->act[cur], c->n_act_dev + cur));
         } else {
             HIPC(launch_select(a, q));
+            // the natural stop certified against the float32 product's rounding (exact re-score of the
+            // atoms within the band of lambda when nothing was admitted)
+            CertifyArgs cf{};
+            cf.G = c->Gc; cf.ldg = c->ldg; cf.m = c->m;
+            cf.act = c->act[cur]; cf.n_act_dev = c->n_act_dev + cur; cf.p_grid = n_grid;
+            cf.lam = w.lam; cf.rr2 = w.rr2; cf.band = c->band32;
+            cf.excl = w.inI; cf.words = w.words;
+            cf.At = c->At; cf.lda = c->kpad; cf.n = c->n;
+            cf.R = w.R; cf.ldr = c->kpad;
+            cf.k = rho; cf.nI = w.nI; cf.max_active = max_active;
+            cf.sel = w.sel; cf.selcap = w.selcap; cf.nsel = w.nsel; cf.vmax = w.vmax;
+            HIPC(launch_certify(cf, q));
         }
         if (ev) {
             const size_t e1 = mark(c, q);
@@ -884,7 +919,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             if (st != BMPL_OK) return st;
             hipGraphExec_t ge = nullptr;
             merge_mid = n_act >= 512;
-            st = segment_graph(c, p, cur, need, (merge_mid ? 1 : 0) | (depth == 2 ? 2 : 0), &ge,
+            st = segment_graph(c, p, cur, imax, need, (merge_mid ? 1 : 0) | (depth == 2 ? 2 : 0), &ge,
                                [&](hipStream_t q) -> bmpl_status {
                 int cc = cur;
                 for (int d = 0; d < depth; ++d) {

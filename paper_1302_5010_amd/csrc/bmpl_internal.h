@@ -113,6 +113,23 @@ struct SelectArgs {
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
 
+// Certification of the natural stop under the float32 product (select.hip): for running signals whose
+// selection admitted nothing, the atoms whose float32 |g~| lies within eps_i = band sqrt(rr2[sig]) of
+// lambda are re-scored exactly (float32 data, float64 sums); exact violators are admitted (sel, nsel),
+// otherwise vmax becomes the exact maximum over them.
+struct CertifyArgs {
+    const float* G; int64_t ldg; int m;     // the float32 product, one row per running signal
+    const int* act; const int* n_act_dev; int p_grid;
+    const double* lam; const double* rr2;   // lambda_i and ||xi_i||^2
+    double band;                            // eps_i = band ||xi_i||
+    const uint32_t* excl; int words;        // I bitmaps
+    const float* At; int64_t lda; int n;    // float32 atoms
+    const float* R; int64_t ldr;            // float32 residuals (row per signal)
+    int k; const int* nI; int max_active;
+    int* sel; int selcap; int* nsel; float* vmax;
+};
+hipError_t launch_certify(const CertifyArgs& a, hipStream_t stream);
+
 // Reduced-precision screening (screen.hip).
 struct ScreenArgs {
     const float* G; int64_t ldg; int m;

@@ -35,6 +35,10 @@ struct WarmArgs {
     int max_active;
 };
 
+// Internal status bit (never returned): the solve kernel could not run this signal's master problem
+// and the next stop test ends it.
+constexpr int ST_HALT = 1 << 20;
+
 // Atoms per block append of the inverse factor, and the LDS layout of the solve kernel's per-slot
 // vectors (x, c, w, z, x_new, g as float64; support order and atoms as int; theta and exclusion bytes).
 constexpr int SOLVE_JB = 8;

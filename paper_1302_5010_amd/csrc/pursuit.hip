@@ -735,14 +735,18 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                              fabs(w.obj_prev[sig] - w.obj[sig]) <= a.eps_early * a.rho * bb)
                         early = true;                                             // Eq. (13)
                 }
-                if (ns == 0 || it >= a.max_outer || early) {
+                const bool halt = (st & ST_HALT) != 0;   // the solve kernel stopped it (reported inexact)
+                st &= ~ST_HALT;
+                if (ns == 0 || it >= a.max_outer || early || halt) {
                     double off = vm - lam;
                     off = off > 0.0 ? off : 0.0;
                     double kk = fmax(off, w.kkt_on[sig]);
                     kk = lam > 0.0 ? kk / lam : kk;
                     w.kkt[sig] = kk;
                     if (a.warm_check && ns != 0) st |= BMPL_SIG_FALLBACK;
-                    if (natural) {
+                    if (halt) {
+                        // INEXACT is set already
+                    } else if (natural) {
                         if (kk <= a.kkt_tol) st |= BMPL_SIG_CONVERGED;
                     } else if (early) {
                         st |= BMPL_SIG_EARLY;
@@ -914,6 +918,12 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     int nS = w.nS[sig];
     const double lam = w.lam[sig];
     int nI = nI0 + nnew;
+    if (nI > K || (a.vec_lds && nI > a.kv)) {
+        // the launch was sized for a smaller |I| (a host-side bound that does not hold): stop the signal
+        // at its current iterate, reported inexact, rather than overrun the LDS vectors
+        if (tid == 0) w.status[sig] |= BMPL_SIG_INEXACT | ST_HALT;
+        return;
+    }
     uint64_t tick = a.phase ? wall_clock64() : 0;
 
     // global homes of this signal's state

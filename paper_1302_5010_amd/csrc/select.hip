@@ -294,7 +294,116 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     }
 }
 
+// Certification of the natural stop under the float32 product.  For a running signal whose selection
+// admitted nothing although it had room, every float32 |g~_j| outside I is at most lambda, but the
+// exact |g_j| may exceed it by up to the product's rounding error eps_i = band ||xi_i||.  If the
+// largest |g~_j| is within eps_i of lambda, the atoms with |g~_j| >= lambda - eps_i (the only ones whose
+// exact correlation can exceed lambda) are re-scored exactly: float32 data, float64 sums.  The exact
+// violators among them are admitted, largest first (ties to the lower index), and the signal goes on;
+// with none, vmax becomes the largest exact value (<= lambda), so the stop and the certificate's
+// off-I term are exact.  The row is swept in chunks of the LDS buffer, so any number of atoms in the
+// band is handled; at most EXB exact violators are kept (the lowest-indexed ones, all of them violators).
+__global__ __launch_bounds__(256) void certify_kernel(CertifyArgs a)
+{
+    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
+    const int row = blockIdx.x;
+    if (row >= n_act) return;
+    const int sig = a.act ? a.act[row] : row;
+    if (a.nsel[sig] != 0) return;
+    int k = a.k;
+    if (a.nI && a.max_active > 0) {
+        const int room = a.max_active - a.nI[sig];
+        k = room < k ? room : k;
+    }
+    if (k <= 0) return;                            // I is full: the active-set cap decides
+    const double lam = a.lam[sig];
+    const double eps = a.band * sqrt(a.rr2[sig]);
+    if ((double)a.vmax[sig] + eps <= lam) return;   // every exact |g_j| <= |g~_j| + eps <= lambda
+    const double lo = lam - eps;
+    const float* g = a.G + (int64_t)row * a.ldg;
+    const uint32_t* ex = a.excl + (int64_t)sig * a.words;
+    const float* r = a.R + (int64_t)sig * a.ldr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int CB = 256, EXB = 256;
+    __shared__ int s_c[CB];
+    __shared__ int s_n, s_next;
+    __shared__ float s_ev[EXB];
+    __shared__ int s_ei[EXB];
+    __shared__ int s_ne;
+    __shared__ int s_wc[4];
+    __shared__ double s_mx[4];
+    if (tid == 0) s_ne = 0;
+    double emax = 0.0;
+    int start = 0;
+    for (;;) {
+        // collect up to CB atoms of the band with index >= start, in index order
+        if (tid == 0) { s_n = 0; s_next = a.m; }
+        __syncthreads();
+        for (int j0 = start; j0 < a.m; j0 += 256) {
+            const int j = j0 + tid;
+            const bool t = j < a.m && !((ex[j >> 5] >> (j & 31)) & 1u) && (double)fabsf(g[j]) >= lo;
+            const unsigned long long bal = __ballot(t);
+            if (lane == 0) s_wc[wave] = __popcll(bal);
+            __syncthreads();
+            const int before = (wave > 0 ? s_wc[0] : 0) + (wave > 1 ? s_wc[1] : 0) + (wave > 2 ? s_wc[2] : 0);
+            const int tot = s_wc[0] + s_wc[1] + s_wc[2] + s_wc[3];
+            const int base = s_n;
+            const int pos = base + before + __popcll(bal & ((1ull << lane) - 1ull));
+            if (t && pos < CB) s_c[pos] = j;
+            if (t && pos == CB) s_next = j;          // the first atom that did not fit
+            __syncthreads();
+            if (tid == 0) s_n = base + tot;
+            __syncthreads();
+            if (base + tot > CB) break;              // uniform: every thread read the same s_n
+        }
+        const int nc = s_n < CB ? s_n : CB;
+        // exact re-score, one wave per atom: float32 products summed in float64
+        for (int c = wave; c < nc; c += 4) {
+            const int j = s_c[c];
+            const float* aj = a.At + (int64_t)j * a.lda;
+            double acc = 0.0;
+            for (int q = lane; q < a.n; q += 64) acc += (double)aj[q] * (double)r[q];
+            acc = fabs(wave_sum(acc));
+            emax = fmax(emax, acc);
+            if (lane == 0 && acc > lam) {
+                const int pos = atomicAdd(&s_ne, 1);
+                if (pos < EXB) { s_ev[pos] = (float)acc; s_ei[pos] = j; }
+            }
+        }
+        __syncthreads();
+        if (s_n <= CB) break;
+        start = s_next;
+        __syncthreads();
+    }
+    emax = wave_max(emax);
+    if (lane == 0) s_mx[wave] = emax;
+    __syncthreads();
+    const double vmx = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+    const int ne = s_ne < EXB ? s_ne : EXB;
+    const int nsel = ne < k ? ne : k;
+    if (tid < ne) {
+        const float v = s_ev[tid];
+        const int j = s_ei[tid];
+        int rank = 0;
+        for (int d = 0; d < ne; ++d) rank += better(s_ev[d], s_ei[d], v, j) ? 1 : 0;
+        if (rank < nsel) a.sel[(int64_t)sig * a.selcap + rank] = j;
+    }
+    if (tid == 0) {
+        a.nsel[sig] = nsel;
+        // with no violator every exact |g_j| is <= lambda: round down, so the stop test in float64 holds
+        a.vmax[sig] = nsel > 0 ? (float)vmx : __double2float_rd(vmx);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_certify(const CertifyArgs& a, hipStream_t stream)
+{
+    if (a.p_grid <= 0) return hipSuccess;
+    if (a.k <= 0 || a.k > a.selcap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(certify_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream)
 {

@@ -3,7 +3,7 @@
 For each signal, with the GPU's sparse result expanded to a dense float64 x
 and the objective recomputed here in float64 from it (never taken from the
 GPU):
-  * relative objective error (F_gpu - F_or) / F_or <= 1e-5;
+  * relative objective error |F_gpu - F_or| / F_or <= 1e-5 (either side lower fails);
   * relative l2 error ||x_gpu - x_or|| / ||x_or|| <= 1e-4;
   * where the oracle's margin exceeds 1e-3 lambda: identical supports and signs;
   * per atom: every j with lambda - |g_j| > 1e-3 lambda is absent and every j
@@ -42,7 +42,7 @@ def check_signal(A64, b, lam, x_gpu, x_or, tag=""):
     """Assert the parity rules for one signal; returns a dict of the measured errors."""
     F_or = objective(A64, b, x_or, lam)
     F_gpu = objective(A64, b, x_gpu, lam)
-    rel_obj = (F_gpu - F_or) / F_or if F_or > 0 else abs(F_gpu)
+    rel_obj = abs(F_gpu - F_or) / F_or if F_or > 0 else abs(F_gpu)
     nx = np.linalg.norm(x_or)
     rel_x = np.linalg.norm(x_gpu - x_or) / nx if nx > 0 else np.linalg.norm(x_gpu)
     g = A64.T @ (b - A64 @ x_or)

@@ -43,13 +43,14 @@ def test_options_default(lib):
 
 def test_argument_errors_without_gpu(lib):
     lib.bmpl_last_error.restype = ctypes.c_char_p
+    lib.bmpl_last_error.argtypes = [ctypes.c_void_p]
     vp = ctypes.c_void_p
     lib.bmpl_create.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
                                 vp, vp, ctypes.POINTER(vp)]
     h = vp()
     fake = ctypes.c_void_p(0x1000)
     assert lib.bmpl_create(None, 4, 4, 4, 0, 0.1, None, None, ctypes.byref(h)) == -1
-    assert b"NULL A" in lib.bmpl_last_error()
+    assert b"NULL A" in lib.bmpl_last_error(None)
     assert lib.bmpl_create(fake, 2, 4, 4, 0, 0.1, None, None, ctypes.byref(h)) == -1     # lda < n
     assert lib.bmpl_create(fake, 4, 4, 0, 0, 0.1, None, None, ctypes.byref(h)) == -1     # m = 0
     assert lib.bmpl_create(fake, 4, 4, 4, 0, -1.0, None, None, ctypes.byref(h)) == -1    # lambda < 0
@@ -69,7 +70,7 @@ def test_argument_errors_without_gpu(lib):
         for bad in (-1e-3, float("nan"), float("inf")):
             setattr(o, field, bad)
             assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -1
-            assert b"eps_early" in lib.bmpl_last_error()
+            assert b"eps_early" in lib.bmpl_last_error(None)
         setattr(o, field, 0.0)
     o.screen = 9
     assert lib.bmpl_create(fake, 4, 4, 4, 0, 0.1, ctypes.byref(o), None, ctypes.byref(h)) == -4
@@ -89,6 +90,7 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def test_proposal_argument_errors_without_gpu(lib):
     lib.bmpl_last_error.restype = ctypes.c_char_p
+    lib.bmpl_last_error.argtypes = [ctypes.c_void_p]
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.bmpl_mlp_param_count.restype = i64
     lib.bmpl_mlp_param_count.argtypes = [i32, i32, i32]
@@ -98,11 +100,11 @@ def test_proposal_argument_errors_without_gpu(lib):
     h = vp()
     fake = ctypes.c_void_p(0x1000)
     assert lib.bmpl_mlp_create(None, 4, 4, 4, fake, 64, 64, 8, None, ctypes.byref(h)) == -1
-    assert b"NULL A or P" in lib.bmpl_last_error()
+    assert b"NULL A or P" in lib.bmpl_last_error(None)
     assert lib.bmpl_mlp_create(fake, 4, 4, 4, fake, 100, 64, 8, None, ctypes.byref(h)) == -1   # d_in % 64
     assert lib.bmpl_mlp_create(fake, 4, 4, 4, fake, 64, 0, 8, None, ctypes.byref(h)) == -1    # d_hidden
     assert lib.bmpl_mlp_create(fake, 4, 4, 40000, fake, 64, 64, 8, None, ctypes.byref(h)) == -1   # m too wide
-    assert b"exceeds" in lib.bmpl_last_error()
+    assert b"exceeds" in lib.bmpl_last_error(None)
     assert lib.bmpl_mlp_create(fake, 2, 4, 4, fake, 64, 64, 8, None, ctypes.byref(h)) == -1   # lda < n
     assert h.value is None
     assert lib.bmpl_mlp_destroy(None) == 0

@@ -136,6 +136,81 @@ def test_loss_and_gradient_against_reference(seed, p):
         assert rel(gb[name], rb[name]) <= 16 * U, (name, rel(gb[name], rb[name]))
 
 
+def mlp_tile(M: int, N: int) -> int:
+    """Edge of the square output tile the network's matrix products use for an M x N output (the size rule
+    of the library's launcher: 256 when there are at least 1024 such tiles, 128 when there are at least 512
+    of 128, else 64)."""
+    if -(-M // 256) * -(-N // 256) >= 1024:
+        return 256
+    if -(-M // 128) * -(-N // 128) >= 512:
+        return 128
+    return 64
+
+
+def _full_width(p, seed):
+    """The benchmark's network shape: n = 1024, m = 20000 atoms, d = h = 2048, random initial weights with
+    perturbed biases (a non-trivial operating point)."""
+    n, m, d, h = 1024, 20000, 2048, 2048
+    P = bi.tiny_gaussian(n, m, p, 10, 0.01, seed=seed)
+    Pm = bi.projection(m, d, seed=seed)
+    params = bi.mlp_init(d, h, m, seed=seed, prior=10.0 / m)
+    rng = np.random.default_rng(seed)
+    params = params + (0.3 * rng.standard_normal(params.size)).astype(np.float32) * (np.abs(params) == 0)
+    return P, Pm, params.astype(np.float32), (d, h, m)
+
+
+def test_forward_large_tiles_full_width():
+    """Inference as the benchmark runs it: chunks of 4096 signals through the 2048 / 2048 / 20000 network.
+    A 4096-row chunk runs the hidden layers (bias + GELU epilogue) on 128 x 128 tiles and the output layer
+    (bias epilogue, 20000 = 78 x 256 + 32: a ragged edge tile) on 256 x 256 tiles; the 96-row tail chunk on
+    64 x 64 tiles.  Sampled rows (tile edges of both chunks) against the float64 reference, 8 u row-wise."""
+    pk = _lib()
+    p = 4096 + 96
+    P, Pm, params, (d, h, m) = _full_width(p, seed=11)
+    assert mlp_tile(4096, h) == 128 and mlp_tile(4096, m) == 256
+    assert mlp_tile(96, h) == 64 and mlp_tile(96, m) == 64
+    net = pk.ProposalNet(to_dev(P.At), to_dev(Pm), h, max_batch=4096)
+    net.set_params(to_dev(params))
+    S = net.forward(to_dev(P.Bt))
+    torch.cuda.synchronize()
+    rows = [0, 1, 127, 128, 255, 256, 1000, 2047, 2048, 3839, 3840, 4095, 4096, 4150, p - 1]
+    S = S[rows].cpu().numpy().astype(np.float64)
+    Zr = mo.embed(mo.projected_dictionary(P.At, Pm), P.Bt[rows])
+    Sr = mo.forward(oracle_params(params, d, h, m), Zr, d, h, m)["S"]
+    errs = [rel(S[q], Sr[q]) for q in range(len(rows))]
+    assert max(errs) <= 8 * U, errs
+    # the ragged last output tile (atoms 19968 .. 19999) on its own
+    assert max(rel(S[q, 19968:], Sr[q, 19968:]) for q in range(len(rows))) <= 8 * U
+
+
+def test_loss_and_gradient_training_shape():
+    """One training batch as the benchmark runs it: 1024 signals, the 2048 / 2048 / 20000 network.  The
+    output layer's forward product and dW3 = dS^T H2 run on 128 x 128 tiles (the other products on
+    64 x 64); loss within 8 u and every gradient block within 16 u norm-wise of the float64 reference."""
+    pk = _lib()
+    p = 1024
+    P, Pm, params, (d, h, m) = _full_width(p, seed=12)
+    assert mlp_tile(p, m) == 128 and mlp_tile(m, h) == 128
+    assert mlp_tile(p, h) == 64 and mlp_tile(h, h) == 64
+    net = pk.ProposalNet(to_dev(P.At), to_dev(Pm), h, max_batch=p)
+    net.set_params(to_dev(params))
+    supp = np.full((p, 12), -1, dtype=np.int32)
+    lens = np.zeros(p, dtype=np.int32)
+    for i, sp in enumerate(P.supports):
+        supp[i, :len(sp)] = sp
+        lens[i] = len(sp)
+    pw = 20.0
+    loss, g = net.loss_grad(to_dev(P.Bt), to_dev(supp), to_dev(lens), pw)
+    loss = float(loss.item())
+    g = g.cpu().numpy().astype(np.float64)
+    Zr = mo.embed(mo.projected_dictionary(P.At, Pm), P.Bt)
+    loss_r, g_r = mo.loss_and_grad(oracle_params(params, d, h, m), Zr, mo.labels(P.supports, m), pw, d, h, m)
+    assert abs(loss - loss_r) <= 8 * U * loss_r
+    gb, rb = mo.unpack(g, d, h, m), mo.unpack(g_r, d, h, m)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert rel(gb[name], rb[name]) <= 16 * U, (name, rel(gb[name], rb[name]))
+
+
 def test_adam_step_against_reference():
     pk = _lib()
     P, Pm, params, (d, h, m) = _small(5, p=32)

@@ -254,6 +254,74 @@ def test_caps_match_oracle_caps(screen):
     np.testing.assert_allclose(dense_from_gpu(out, P.m), ref["X"], atol=1e-5)
 
 
+@pytest.mark.parametrize("max_active", [60, 70])
+def test_graph_mode_active_cap_inside_a_segment(max_active):
+    """Graph segments whose bound on |I| reaches the max_active cap inside the segment (rho = 10, four
+    iterations per segment: the cap of 60 or 70 is first reached in the second segment and every later
+    segment starts at it).  Each segment's kernels are sized by its own bounds, so results equal the host
+    loop's bit for bit, no signal is reported inexact, and the capped results match the oracle's."""
+    pk = _lib()
+    P = bi.tiny_gaussian(n=256, m=2000, p=160, k=40, sigma=0.01, seed=91, lambda_rel=0.05, rho=10)
+    lam = lam_rel(P.At, P.Bt, P.lambda_rel)
+    host = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_active=max_active).solve(to_dev(P.Bt), lam=to_dev(lam))
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, max_active=max_active, graph=True)
+    for rep in range(2):                            # the second solve replays the cached segments
+        out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
+        torch.cuda.synchronize()
+        for key in ("x_idx", "x_val", "supp_len", "iters", "status"):
+            assert torch.equal(out[key], host[key]), (rep, key)
+    st = out["status"].cpu().numpy()
+    assert not np.any(st & pk.BMPL_SIG_INEXACT)
+    assert np.any(st & pk.BMPL_SIG_CAP_ACTIVE) and np.any(st & pk.BMPL_SIG_CONVERGED)
+    ref = oracle.solve(P.At, P.Bt, lam, P.rho, max_active=max_active)
+    assert np.array_equal((st & pk.BMPL_SIG_CAP_ACTIVE) > 0, (ref["status"] & oracle.ST_CAP_ACTIVE) > 0)
+    np.testing.assert_allclose(dense_from_gpu(out, P.m), ref["X"], atol=1e-5)
+
+
+def test_fp32_stop_certified_within_rounding_band():
+    """The natural stop under the float32 product is certified: an atom whose float32 correlation lies
+    below lambda while its exact correlation exceeds lambda (1 + 2e-4) is re-scored and admitted.
+    The signal is b = a_J + v with v orthogonal to a_J and ||v|| = 1000, so a_J^T b = 1 is a sum of
+    far larger products and its float32 value carries a rounding error of about 1e-3; the other atoms
+    live on the coordinates where b is zero (their correlations are exactly 0).  Among seeded v, one
+    whose float32 product (the library's own kernel and tile shape, as in the solve's first pass) falls
+    at least 3e-4 below the exact value is kept, and lambda is set between the two."""
+    pk = _lib()
+    n, m, h, J = 2048, 256, 1024, 0
+    rng = np.random.default_rng(1302)
+    A = np.zeros((m, n))
+    A[J, :h] = rng.standard_normal(h)
+    A[1:, h:] = rng.standard_normal((m - 1, n - h))
+    At = (A / np.linalg.norm(A, axis=1, keepdims=True)).astype(np.float32)
+    aJ = At[J].astype(np.float64)
+    s = pk.Solver(to_dev(At), 1.0, rho=4)
+    for _ in range(64):
+        v = np.zeros(n)
+        v[:h] = rng.standard_normal(h)
+        v -= (v @ aJ) / (aJ @ aJ) * aJ
+        v *= 1e3 / np.linalg.norm(v)
+        b = (aJ + v).astype(np.float32)
+        g = At.astype(np.float64) @ b.astype(np.float64)
+        g32 = s.correlate(to_dev(b[None, :]))[0, :m].cpu().numpy()
+        if g[J] > 0 and g32[J] < g[J] * (1 - 3e-4):
+            break
+    else:
+        pytest.fail("no seeded signal with a float32 rounding error of 3e-4")
+    assert np.all(g[1:] == 0)
+    lam = np.array([g[J] / (1 + 2e-4)])
+    assert g32[J] <= lam[0] < g[J]
+    out = s.solve(to_dev(b[None, :]), lam=to_dev(lam))
+    torch.cuda.synchronize()
+    assert out["status"].cpu().numpy()[0] == pk.BMPL_SIG_CONVERGED
+    assert out["supp_len"].cpu().numpy()[0] == 1 and out["x_idx"].cpu().numpy()[0, 0] == J
+    x = dense_from_gpu(out, m)[0]
+    r = b.astype(np.float64) - At.astype(np.float64).T @ x
+    kkt = np.max(np.maximum(np.abs(At.astype(np.float64) @ r) - lam[0], 0.0)) / lam[0]
+    assert kkt <= 1e-4 and out["kkt"].cpu().numpy()[0] <= 1e-4
+    ref = oracle.solve(At, b[None, :], lam, 4)
+    check_batch(At, b[None, :], lam, out, ref)
+
+
 def test_warm_start_proposals_keep_parity():
     pk = _lib()
     P = bi.small_gaussian()

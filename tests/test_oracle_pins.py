@@ -369,6 +369,44 @@ def test_smpl_keeps_the_atom_with_the_largest_restricted_coefficient():
     assert checked >= 4
 
 
+def test_early_stop_eq13_orthonormal_closed_form():
+    """Eq. (13) pinned by a closed form.  With orthonormal atoms, g_j = z_j = a_j^T b for every j outside I,
+    the master problem on I is soft thresholding, and the objective after iteration t is
+    F_t = ||b||^2 / 2 - sum_{j in I_t} (|z_j| - lambda)^2 / 2, so iteration t lowers it by
+    delta_t = sum_{j in J_t} (|z_j| - lambda)^2 / 2, J_t the t-th block of rho atoms in decreasing |z_j|.
+    For every t, a tolerance just above delta_t / (rho ||b||^2) must stop the solver right after iteration
+    t (status early, x = soft thresholding on the first t blocks) and one just below it one iteration
+    later.  This fixes which decrease is tested, the normaliser rho ||b||^2 and the direction of the test."""
+    rng = np.random.default_rng(13)
+    n, m = 96, 60
+    Q, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    At = np.ascontiguousarray(Q.T.astype(np.float32))
+    b = (Q[:, :40] @ (rng.uniform(0.5, 3.0, 40) * rng.choice([-1, 1], 40))
+         + 0.05 * rng.standard_normal(n)).astype(np.float32)
+    b64 = b.astype(np.float64)
+    bb = float(b64 @ b64)
+    z = At.astype(np.float64) @ b64
+    lam = 0.3
+    order = np.argsort(-np.abs(z), kind="stable")
+    viol = order[np.abs(z[order]) > lam]
+    for rho in (3, 5):
+        blocks = [viol[i:i + rho] for i in range(0, len(viol), rho)]
+        delta = np.array([0.5 * np.sum((np.abs(z[J]) - lam) ** 2) for J in blocks])
+        assert np.all(delta[:-1] > delta[1:] * 1.01)     # strictly decreasing: each threshold has one answer
+        for t in range(1, len(blocks) - 1):
+            for factor, T in ((1 + 1e-3, t), (1 - 1e-3, t + 1)):
+                eps = factor * delta[t - 1] / (rho * bb)
+                tr = oracle.trace(At, b, lam, rho, eps_early=eps)
+                assert tr["status"] & oracle.ST_EARLY, (rho, t, factor)
+                assert tr["iters"] == T, (rho, t, factor, tr["iters"])
+                keep = np.concatenate(blocks[:T])
+                expect = np.zeros(m)
+                expect[keep] = np.sign(z[keep]) * (np.abs(z[keep]) - lam)
+                np.testing.assert_allclose(tr["x"], expect, atol=2e-5)
+                F = 0.5 * bb - np.concatenate([[0.0], np.cumsum(delta[:T])])
+                np.testing.assert_allclose(tr["obj_trace"][:T + 1], F, rtol=1e-6)
+
+
 def test_early_stop_rule_eq13():
     """The objective-decrease stop of Eq. (13): the solver stops at the first outer iteration whose
     decrease is at most eps * rho * ||b||^2, not before; with eps = 0 it runs to the natural stop."""
