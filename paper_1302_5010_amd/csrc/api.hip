@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -48,6 +49,10 @@ struct bmpl_ctx {
     float* vmax8 = nullptr;       // [p_cap] scratch of the ranking pass
     double* zeros = nullptr;      // [p_cap] zero thresholds for the ranking pass
     int* cert = nullptr;          // [p_cap] left for the certified pass
+    int* cert32 = nullptr;        // [p_cap] float32 product: rows whose stop needs the exact re-score
+    int* n_cert32 = nullptr;      // their count
+    int* grow_list = nullptr;     // [p_cap] signals whose slot block grows before the next master problem
+    int* n_grow = nullptr;        // their count
     int* cert_act = nullptr;      // [p_cap] compacted list of those signals
     int* n_cert_dev = nullptr;    // its length
     double band_x = 0.0, band_dx = 0.0;   // bfloat16 band: eps_i = band_x ||xi_i|| + band_dx ||bf16(xi_i) - xi_i||
@@ -69,13 +74,17 @@ struct bmpl_ctx {
     // per-signal workspace
     Workspace w{};
     int p_cap = 0;
-    int K_cap = 0;
     int selcap = 0;
+    // arena of the per-signal slot blocks (device state, its chunks, and pinned host views)
+    Arena* arena_dev = nullptr;
+    Arena* h_arena = nullptr;     // pinned: the chunk list as the host last wrote it
+    Arena* h_arena_rd = nullptr;  // pinned: top / starved / reserve read back with the running count
+    unsigned long long arena_total = 0;   // doubles over all chunks
     float* Bw = nullptr;          // [p_cap][kpad]
     float* Gc = nullptr;          // [p_cap][ldg] correlations
     int64_t ldg = 0;
     int* act[2] = {nullptr, nullptr};
-    int* n_act_dev = nullptr;     // [2]
+    int* n_act_dev = nullptr;     // [2] running counts (inside the arena header)
     int* h_count = nullptr;       // pinned host int
 
     // correlation tile shape per running-signal bucket (>= 512, 64..511, < 64), set by bmpl_autotune
@@ -101,12 +110,12 @@ struct bmpl_ctx {
     // A segment's kernels bake in the bounds on |I| of each of its iterations, which follow from the
     // bound at the segment's start (i0) and its end (kl, clamped to max_active): both are in the key.
     struct GraphKey {
-        int p, cur, i0, kl, K, shapes[3];
+        int p, cur, i0, kl, shapes[3];
         long gen;
         int variant;  // bit 0: the large tile also covers the middle count bucket; bit 1: a 2-iteration segment
         bool operator==(const GraphKey& o) const
         {
-            return p == o.p && cur == o.cur && i0 == o.i0 && kl == o.kl && K == o.K && gen == o.gen &&
+            return p == o.p && cur == o.cur && i0 == o.i0 && kl == o.kl && gen == o.gen &&
                    shapes[0] == o.shapes[0] && shapes[1] == o.shapes[1] && shapes[2] == o.shapes[2] &&
                    variant == o.variant;
         }
@@ -168,54 +177,84 @@ void fold_timing(bmpl_ctx* c, size_t first, size_t last)
 
 namespace {
 
-SlotArrays slots_of(const Workspace& w)
-{
-    return SlotArrays{w.slot_atom, w.x, w.c, w.theta, w.excl, w.sord, w.G, w.Rinv};
-}
-
-void free_slots(Workspace& w)
-{
-    dfree(w.slot_atom); dfree(w.x); dfree(w.c); dfree(w.theta); dfree(w.excl);
-    dfree(w.sord); dfree(w.G); dfree(w.Rinv); dfree(w.vscratch);
-}
-
-hipError_t alloc_slots(Workspace& w, int p, int K)
-{
-    const size_t pk = (size_t)p * K, pt = (size_t)p * (size_t)tri(K), pkk = (size_t)p * K * K;
-    hipError_t e;
-    if ((e = dalloc(&w.slot_atom, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.x, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.c, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.theta, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.excl, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.sord, pk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.G, pkk)) != hipSuccess) return e;
-    if ((e = dalloc(&w.Rinv, pt)) != hipSuccess) return e;
-    if ((e = dalloc(&w.vscratch, pk * 8)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
 void free_signals(bmpl_ctx* c)
 {
     Workspace& w = c->w;
     dfree(w.R); dfree(w.bnorm2); dfree(w.lam); dfree(w.status); dfree(w.iters); dfree(w.nI);
     dfree(w.nS); dfree(w.nsel); dfree(w.sel); dfree(w.vmax); dfree(w.kkt_on); dfree(w.obj);
     dfree(w.kkt); dfree(w.inI); dfree(w.glazy); dfree(w.jadd); dfree(w.obj_prev); dfree(w.rr2); dfree(w.g0max);
-    free_slots(w);
+    dfree(w.cap); dfree(w.blk);
     dfree(c->Bw); dfree(c->Gc); dfree(c->act[0]); dfree(c->act[1]);
     dfree(w.R16); dfree(w.rnorm); dfree(w.dxnorm); dfree(c->cand); dfree(c->ncand);
     dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
     dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
     dfree(c->spill); dfree(c->spill_act); dfree(c->n_spill_dev);
+    dfree(c->cert32); dfree(c->n_cert32); dfree(c->grow_list); dfree(c->n_grow);
     dfree(c->beta);
     c->p_cap = 0;
-    c->K_cap = 0;
 }
 
-// Size the per-signal workspace for p signals, slot capacity K, selection capacity selcap.
-bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
+// Add a chunk of at least `min_doubles` (preferably `want_doubles`) to the slot-block arena; the
+// device sees the new chunk list from the next kernel on `s` on.
+bmpl_status arena_add(bmpl_ctx* c, unsigned long long min_doubles, unsigned long long want_doubles, hipStream_t s)
 {
-    if (p <= c->p_cap && K <= c->K_cap && selcap <= c->selcap) return BMPL_OK;
+    Arena& H = *c->h_arena;
+    if (H.nchunks >= ARENA_CHUNKS)
+        return fail(BMPL_E_NOMEM, "slot-block arena: all %d chunks in use", ARENA_CHUNKS);
+    double* p = nullptr;
+    unsigned long long sz = std::max(want_doubles, min_doubles);
+    hipError_t e = dalloc(&p, (size_t)sz);
+    if (e != hipSuccess && sz > min_doubles) {
+        (void)hipGetLastError();
+        sz = min_doubles;
+        e = dalloc(&p, (size_t)sz);
+    }
+    if (e != hipSuccess)
+        return fail(BMPL_E_NOMEM, "slot-block arena: allocating %.3g GB failed: %s", 8.0 * sz / 1e9,
+                    hipGetErrorString(e));
+    const int k = H.nchunks;
+    H.base[k] = p;
+    H.start[k] = k ? H.start[k - 1] + H.size[k - 1] : 0;
+    H.size[k] = sz;
+    H.nchunks = k + 1;
+    c->arena_total += sz;
+    // the chunk list only (top, starved and reserve stay as the device has them)
+    const size_t off = offsetof(Arena, nchunks);
+    HIPC(hipMemcpyAsync(reinterpret_cast<char*>(c->arena_dev) + off, reinterpret_cast<char*>(c->h_arena) + off,
+                        sizeof(Arena) - off, hipMemcpyHostToDevice, s));
+    return BMPL_OK;
+}
+
+// Make sure `need` doubles of slot blocks (with a margin for chunk tails) can be handed out after the
+// first `used` doubles of this solve.
+bmpl_status arena_ensure(bmpl_ctx* c, unsigned long long used, unsigned long long need, hipStream_t s)
+{
+    const unsigned long long want = need + need / 8 + (1ull << 20);
+    if (c->arena_total >= used && c->arena_total - used >= want) return BMPL_OK;
+    const unsigned long long missing = want - (c->arena_total > used ? c->arena_total - used : 0);
+    return arena_add(c, missing, std::max(missing, c->arena_total / 4), s);
+}
+
+// Doubles of slot blocks one signal may take while |I| grows from nI (capacity K) by `iters` passes of
+// up to `rho_pass` atoms (the first of them adding `first` atoms): the growth steps of the solve kernel.
+unsigned long long block_reserve(int K, int nI, int first, int iters, int rho_pass, int slack, int kcap, int n)
+{
+    unsigned long long r = 0;
+    int need = std::min(kcap, nI + first);
+    for (int t = 0; t < iters; ++t) {
+        while (K < need) {
+            K = grow_capacity(K, std::min(need, K + std::max(1, rho_pass)), slack, kcap);
+            r += (unsigned long long)block_doubles(K, n);
+        }
+        need = std::min(kcap, need + rho_pass);
+    }
+    return r;
+}
+
+// Size the per-signal workspace for p signals and selection capacity selcap.
+bmpl_status ensure_workspace(bmpl_ctx* c, int p, int selcap)
+{
+    if (p <= c->p_cap && selcap <= c->selcap) return BMPL_OK;
     free_signals(c);
     Workspace& w = c->w;
     const size_t P = p;
@@ -239,11 +278,19 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
     HIPC(dalloc(&w.inI, P * w.words));
     HIPC(dalloc(&w.glazy, P));
     HIPC(dalloc(&w.jadd, P));
-    HIPC(alloc_slots(w, p, K));
+    HIPC(dalloc(&w.cap, P));
+    HIPC(dalloc(&w.blk, P));
+    w.arena = c->arena_dev;
     HIPC(dalloc(&c->Bw, P * c->kpad));
     HIPC(dalloc(&c->Gc, P * (size_t)c->ldg));
     HIPC(dalloc(&c->act[0], P));
     HIPC(dalloc(&c->act[1], P));
+    HIPC(dalloc(&c->cert32, P));
+    HIPC(dalloc(&c->n_cert32, 1));
+    HIPC(dalloc(&c->grow_list, P));
+    HIPC(dalloc(&c->n_grow, 1));
+    HIPC(hipMemset(c->n_grow, 0, sizeof(int)));
+    HIPC(hipMemset(c->n_cert32, 0, sizeof(int)));
     if (c->opt.screen != BMPL_PREC_FP32) {
         HIPC(dalloc(&w.R16, (P + 1) * c->kpad));
         HIPC(hipMemset(w.R16 + P * c->kpad, 0, c->kpad * sizeof(uint16_t)));
@@ -272,36 +319,8 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int K, int selcap)
         HIPC(dalloc(&c->n_cert_dev, 1));
     }
     c->p_cap = p;
-    c->K_cap = K;
     c->selcap = selcap;
-    w.K = K;
     w.selcap = selcap;
-    c->ws_gen++;
-    return BMPL_OK;
-}
-
-// Grow the slot capacity in the middle of a solve, keeping every signal's state.
-bmpl_status grow_slots(bmpl_ctx* c, int K_new, hipStream_t s)
-{
-    Workspace& w = c->w;
-    Workspace nw = w;
-    nw.slot_atom = nullptr; nw.x = nullptr; nw.c = nullptr; nw.theta = nullptr; nw.excl = nullptr;
-    nw.sord = nullptr; nw.G = nullptr; nw.Rinv = nullptr; nw.vscratch = nullptr;
-    hipError_t e = alloc_slots(nw, c->p_cap, K_new);
-    if (e != hipSuccess) {
-        free_slots(nw);
-        return fail(e == hipErrorOutOfMemory ? BMPL_E_NOMEM : BMPL_E_HIP,
-                    "growing the active-set capacity to %d failed: %s", K_new, hipGetErrorString(e));
-    }
-    RestrideArgs ra{slots_of(w), slots_of(nw), w.nI, w.nS, c->K_cap, K_new};
-    hipLaunchKernelGGL(restride_kernel, dim3(w.p), dim3(256), 0, s, ra);
-    HIPC(hipGetLastError());
-    HIPC(hipStreamSynchronize(s));
-    free_slots(w);
-    w.slot_atom = nw.slot_atom; w.x = nw.x; w.c = nw.c; w.theta = nw.theta; w.excl = nw.excl;
-    w.sord = nw.sord; w.G = nw.G; w.Rinv = nw.Rinv; w.vscratch = nw.vscratch;
-    w.K = K_new;
-    c->K_cap = K_new;
     c->ws_gen++;
     return BMPL_OK;
 }
@@ -323,8 +342,8 @@ template <class F>
 bmpl_status segment_graph(bmpl_ctx* c, int p, int cur, int i0, int kl, int variant, hipGraphExec_t* out,
                           F&& enqueue)
 {
-    bmpl_ctx::GraphKey key{p, cur, i0, kl, c->K_cap, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]},
-                           c->ws_gen, variant};
+    bmpl_ctx::GraphKey key{p, cur, i0, kl, {c->corr_shape[0], c->corr_shape[1], c->corr_shape[2]}, c->ws_gen,
+                           variant};
     for (auto& e : c->graphs)
         if (e.key == key) {
             *out = e.ge;
@@ -425,8 +444,17 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     c->w.m = m;
     c->w.words = (m + 31) / 32;
     e = dalloc(&c->At, (size_t)(m + 1) * c->kpad);   // row m stays zero
-    if (e == hipSuccess) e = dalloc(&c->n_act_dev, 2);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_count), sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_arena), sizeof(Arena), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_arena_rd), sizeof(Arena), hipHostMallocDefault);
+    if (e == hipSuccess) e = dalloc(reinterpret_cast<char**>(&c->arena_dev), sizeof(Arena));
+    if (e == hipSuccess)   // the running counts live in the arena header: one read-back holds both
+        c->n_act_dev = reinterpret_cast<int*>(reinterpret_cast<char*>(c->arena_dev) + offsetof(Arena, n_act));
+    if (e == hipSuccess) {
+        std::memset(c->h_arena, 0, sizeof(Arena));
+        std::memset(c->h_arena_rd, 0, sizeof(Arena));
+        e = hipMemcpyAsync(c->arena_dev, c->h_arena, sizeof(Arena), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(c->At, 0, (size_t)(m + 1) * c->kpad * sizeof(float), s);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->At, c->kpad * sizeof(float), A_dev, lda * sizeof(float), n * sizeof(float), m,
@@ -540,13 +568,18 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     dfree(c->A8);
     dfree(c->ascale8);
     dfree(c->diag16);
-    dfree(c->n_act_dev);
     dfree(c->diagR);
     dfree(c->phase_dev);
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->h_count) (void)hipHostFree(c->h_count);
+    if (c->h_arena) {
+        for (int k = 0; k < c->h_arena->nchunks; ++k) (void)hipFree(c->h_arena->base[k]);
+        (void)hipHostFree(c->h_arena);
+    }
+    if (c->h_arena_rd) (void)hipHostFree(c->h_arena_rd);
+    if (c->arena_dev) (void)hipFree(c->arena_dev);
     delete c;
     return BMPL_OK;
 }
@@ -638,11 +671,14 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const bool graph = (c->opt.flags & BMPL_FLAG_GRAPH) != 0 && !timing_on(c);
 
     const int first_add = warm ? std::max(warm_k, rho) : rho;
-    // slot capacity for the first iterations: a proposal's atoms plus a few iterations of growth
-    const int grow0 = (graph ? GRAPH_DEPTH * rho : 0) + (warm ? 2 * rho : first_add);
-    int K0 = std::min(max_active, std::max(64, round_up(first_add + grow0, 32)));
-    K0 = std::max(K0, std::min(max_active, c->K_cap));
-    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), K0, std::max(rho, warm ? warm_k : 0));
+    const int slack = 2 * rho;   // slot-block growth: room for two more passes past the need
+    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), std::max(rho, warm ? warm_k : 0));
+    if (st != BMPL_OK) return st;
+    // Slot blocks for every signal up to the first host read-back: the first master problem (a
+    // proposal's atoms or rho) and, in graph mode, the iterations of the first segment.
+    const int iters0 = (graph && !warm) ? 1 + GRAPH_DEPTH : 1;
+    st = arena_ensure(c, 0, (unsigned long long)p *
+                               block_reserve(0, 0, first_add, iters0, rho, slack, max_active, c->n), s);
     if (st != BMPL_OK) return st;
     Workspace& w = c->w;
     w.p = p;
@@ -669,6 +705,10 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     sa.max_outer = max_outer; sa.kkt_tol = c->opt.kkt_tol; sa.warm_check = 0;
     sa.eps_early = c->opt.eps_early; sa.r_inf_rel = c->opt.r_inf_rel; sa.r2_rel = c->opt.r2_rel;
     sa.rho = c->opt.rho;
+    // slot-block reserve for the iterations up to the next read-back (a graph segment at most)
+    sa.reserve_iters = graph ? GRAPH_DEPTH : 1; sa.rho_pass = rho; sa.slack = slack; sa.kcap = max_active;
+    sa.clear_cert = c->n_cert32;
+    sa.grow_list = c->grow_list; sa.n_grow = c->n_grow;
     hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
     HIPC(hipGetLastError());
     // In graph mode the host does not wait for the running count until the first captured segment has
@@ -807,6 +847,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         } else if (c->A16) {
             HIPC(screen_pass(c->act[cur], c->n_act_dev + cur));
         } else {
+            a.rr2 = w.rr2; a.band = c->band32; a.cert_list = c->cert32; a.n_cert = c->n_cert32;
             HIPC(launch_select(a, q));
             // the natural stop certified against the float32 product's rounding (exact re-score of the
             // atoms within the band of lambda when nothing was admitted)
@@ -819,6 +860,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             cf.R = w.R; cf.ldr = c->kpad;
             cf.k = rho; cf.nI = w.nI; cf.max_active = max_active;
             cf.sel = w.sel; cf.selcap = w.selcap; cf.nsel = w.nsel; cf.vmax = w.vmax;
+            cf.cert_list = c->cert32; cf.n_cert = c->n_cert32;
             HIPC(launch_certify(cf, q));
         }
         if (ev) {
@@ -856,23 +898,26 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         SolveArgs so{};
         so.w = w; so.At = c->At; so.lda = c->kpad; so.Bw = c->Bw;
         so.Q = c->Q; so.ldq = c->m;
-        so.max_steps = 16 * w.K + 256;
+        so.max_steps_per_slot = 16;
         so.smpl_keep = explore ? smpl_keep : 0;
         so.phase = phases ? c->phase_dev : nullptr;
         // the exploratory pass of SMPL briefly holds omega rho new slots: the full capacity then
-        so.kv = so.smpl_keep > 0 ? w.K : std::min(w.K, std::max(1, ibound));
+        so.kv = std::min(max_active, std::max(1, ibound));
         const size_t vec_bytes = vec_area_bytes(so.kv);
         const size_t stage = c->Q ? 0 : GRAM_STAGE_BYTES;   // direct Gram staging, only without the table
         so.vec_lds = vec_bytes + stage <= c->lds_dyn_max ? 1 : 0;
-        so.kl = std::min(kl, w.K);
+        so.kl = std::min(kl, so.kv);
         const size_t rinv_bytes = 8 * (size_t)tri(so.kl);
         so.rinv_lds = (so.vec_lds && vec_bytes + rinv_bytes + stage <= c->lds_dyn_max) ? 1 : 0;
         size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0) + stage;
         // block appends pay off when the factor streams from global memory; with an LDS-resident
         // factor single appends are cheaper and keep the workgroup's LDS (and occupancy) smaller
-        so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(w.K) <= c->lds_dyn_max) ? 1 : 0;
-        if (so.zs_lds) lds += block_scratch_bytes(w.K);
+        so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(so.kv) <= c->lds_dyn_max) ? 1 : 0;
+        if (so.zs_lds) lds += block_scratch_bytes(so.kv);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
+        GrowArgs ga{w, c->grow_list, c->n_grow, slack, max_active};
+        hipLaunchKernelGGL(grow_kernel, dim3(std::min(n_grid, 512)), dim3(256), 0, q, ga);
+        HIPC(hipGetLastError());
         if (so.zs_lds)
             hipLaunchKernelGGL(solve_block_kernel, dim3(n_grid), dim3(256), lds, q, so);
         else
@@ -881,16 +926,23 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         if (ev) span(c, e0, mark(c, q), K_SOLVE);   // the residual is the solve kernel's last step
         return BMPL_OK;
     };
-    auto grow_to = [&](int need) -> bmpl_status {
-        if (need <= c->K_cap) return BMPL_OK;
-        const int K_new = std::min(max_active, round_up(std::max(need + 4 * rho, c->K_cap + c->K_cap / 4), 32));
-        return grow_slots(c, K_new, s);
-    };
+    // The running count and the arena's state (blocks handed out, failed requests, the reserve the
+    // running signals may need before the next read-back), then arena space for that reserve.
     auto read_count = [&](int idx) -> bmpl_status {
-        HIPC(hipMemcpyAsync(c->h_count, c->n_act_dev + idx, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(c->h_arena_rd, c->arena_dev, offsetof(Arena, nchunks), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
-        n_act = *c->h_count;
-        return BMPL_OK;
+        n_act = c->h_arena_rd->n_act[idx];
+        const Arena& R = *c->h_arena_rd;
+        if (R.starved) HIPC(hipMemsetAsync(&c->arena_dev->starved, 0, sizeof(unsigned long long), s));
+        if (n_act == 0) return BMPL_OK;
+        if (R.top > c->arena_total) {
+            // failed requests moved the offset past the last chunk: nothing lies beyond the chunks, so
+            // the offset returns to their end (the stream is idle here)
+            const unsigned long long t = c->arena_total;
+            HIPC(hipMemcpyAsync(&c->arena_dev->top, &t, sizeof t, hipMemcpyHostToDevice, s));
+            HIPC(hipStreamSynchronize(s));
+        }
+        return arena_ensure(c, std::min(R.top, c->arena_total), R.reserve, s);
     };
 
     // Iteration 0: lambda rule and the first selection (or the warm-start proposal).
@@ -915,8 +967,6 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
             // iterations past the last signal's stop are empty launches.
             const int depth = n_act < 64 ? 2 : GRAPH_DEPTH;
             const int need = std::min(max_active, imax + depth * rho);
-            st = grow_to(need);
-            if (st != BMPL_OK) return st;
             hipGraphExec_t ge = nullptr;
             merge_mid = n_act >= 512;
             st = segment_graph(c, p, cur, imax, need, (merge_mid ? 1 : 0) | (depth == 2 ? 2 : 0), &ge,
@@ -942,8 +992,6 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         }
         const int add = after_warm ? std::max(warm_k, rho) : rho;
         imax = std::min(max_active, imax + add);
-        st = grow_to(imax);
-        if (st != BMPL_OK) return st;
         c->timing.outer_iters += tm ? 1 : 0;
         // a warm start's proposal is mostly zeros: an LDS factor for WARM_KL support positions
         st = enqueue_master(s, cur, n_act, after_warm ? std::min(imax, WARM_KL) : imax, imax, false, !after_warm);
@@ -956,9 +1004,11 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         if (st != BMPL_OK) return st;
     }
     const size_t e_pack = tm ? mark(c, s) : 0;
-    const size_t pack_lds = (size_t)w.K * 12;
+    const int stage_max = std::min(max_active, c->n);   // |S| <= min(|I|, n)
+    const size_t pack_lds = (size_t)stage_max * 12;
     PackArgs pk{w, out->x_val_dev, out->x_idx_dev, out->supp_len_dev, out->iters_dev, out->kkt_dev,
-                out->lambda_dev, out->objective_dev, out->sig_status_dev, out->ld_x, pack_lds <= 48 * 1024 ? 1 : 0};
+                out->lambda_dev, out->objective_dev, out->sig_status_dev, out->ld_x, pack_lds <= 48 * 1024 ? 1 : 0,
+                stage_max};
     hipLaunchKernelGGL(pack_kernel, dim3(p), dim3(256), pk.stage ? pack_lds : 0, s, pk);
     HIPC(hipGetLastError());
     if (tm) {
@@ -995,7 +1045,7 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
     if (p < 1) return fail(BMPL_E_INVALID, "bmpl_autotune: p must be >= 1");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int rho = c->opt.rho;
-    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), std::max(c->K_cap, 64), std::max(c->selcap, rho));
+    bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), std::max(c->selcap, rho));
     if (st != BMPL_OK) return st;
     Workspace& w = c->w;
     HIPC(hipMemsetAsync(w.R, 0, (size_t)p * c->kpad * sizeof(float), s));

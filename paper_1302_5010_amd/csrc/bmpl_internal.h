@@ -17,6 +17,65 @@ __device__ inline double sym_at(const double* P, int u, int v)
     return u >= v ? P[tri(u) + v] : P[tri(v) + u];
 }
 
+// Device arena of the per-signal slot blocks: a list of chunks viewed as one range of doubles.  Blocks
+// are handed out by bumping `top` (a block never straddles two chunks); a signal whose active set
+// outgrows its block takes a larger one and copies its state over.  The arena is reset for every solve.
+constexpr int ARENA_CHUNKS = 32;
+struct Arena {
+    int n_act[2];                 // running-signal counts of the two running lists (read back with the rest)
+    unsigned long long top;       // doubles handed out in this solve (offset in the chunk list)
+    unsigned long long starved;   // block requests that found no room (the host adds a chunk)
+    unsigned long long reserve;   // doubles the running signals may request during the next iterations
+    int nchunks;
+    int pad_;
+    double* base[ARENA_CHUNKS];
+    unsigned long long start[ARENA_CHUNKS];   // offset of each chunk in the list (start[c+1] = start[c] + size[c])
+    unsigned long long size[ARENA_CHUNKS];    // doubles
+};
+
+// One signal's slot block for capacity K (slots of I) and signal length n:
+//   G [K][K] float64 (Gram of I, row-major by slot) | Rinv [tri(min(K, n))] float64 (inverse Cholesky
+//   factor of G_SS, packed by support position; |S| <= n) | x [K] | c [K] | vs [8K] float64 scratch |
+//   atom [K] int | sord [K] int | theta [K] int8 | excl [K] uint8, padded to 256 bytes.
+__host__ __device__ inline int64_t block_doubles(int K, int n)
+{
+    const int64_t F = K < n ? K : n;
+    const int64_t d = (int64_t)K * K + tri(F) + 10 * (int64_t)K + (10 * (int64_t)K + 7) / 8;
+    return (d + 31) / 32 * 32;
+}
+
+struct SlotBlock {
+    double* G; double* Rinv; double* x; double* c; double* vs;
+    int* atom; int* sord; signed char* theta; unsigned char* excl;
+};
+
+__host__ __device__ inline SlotBlock slot_block(double* base, int K, int n)
+{
+    SlotBlock b;
+    const int64_t F = K < n ? K : n;
+    b.G = base;
+    b.Rinv = b.G + (int64_t)K * K;
+    b.x = b.Rinv + tri(F);
+    b.c = b.x + K;
+    b.vs = b.c + K;
+    b.atom = reinterpret_cast<int*>(b.vs + 8 * (int64_t)K);
+    b.sord = b.atom + K;
+    b.theta = reinterpret_cast<signed char*>(b.sord + K);
+    b.excl = reinterpret_cast<unsigned char*>(b.theta + K);
+    return b;
+}
+
+// Capacity a block grows to when it must hold `need` slots: at least twice the current capacity and
+// `need + slack`, a multiple of 32 (64 at least), at most kcap (>= need).
+__host__ __device__ inline int grow_capacity(int K, int need, int slack, int kcap)
+{
+    int a = need + slack, b = 2 * K;
+    int t = a > b ? a : b;
+    t = t < 64 ? 64 : t;
+    t = (t + 31) / 32 * 32;
+    return t < kcap ? (t > need ? t : need) : (kcap > need ? kcap : need);
+}
+
 // Per-signal state of the batched pursuit.  Arrays indexed [signal * stride + ...].
 // "slot" = position in the active set I (insertion order, never removed);
 // "position" = position in the support S (order of entry into S).
@@ -25,7 +84,6 @@ struct Workspace {
     int kpad;       // n rounded up to a multiple of 32 (rows of the residual buffer)
     int m;          // atoms
     int words;      // ceil(m / 32): bitmap words per signal
-    int K;          // slot capacity per signal
     int p;          // signals in the current solve
 
     float* R;           // [p_cap + 1][kpad] float32 residuals xi_i (zero rows past n; row p_cap all zero)
@@ -49,15 +107,9 @@ struct Workspace {
     int* jadd;          // [p] violators the next active-set step admits (adapted per signal, 1..8)
     int* glazy;         // [p] 1: G holds only the entries against S members (and the diagonal); a slot's
                         //     column is gathered when it enters S (set once a pass adds many slots)
-    int* slot_atom;     // [p][K]
-    double* x;          // [p][K] coefficient per slot
-    double* c;          // [p][K] a_u^T b per slot
-    signed char* theta; // [p][K] sign per slot (0 = not in S)
-    unsigned char* excl;// [p][K] slot excluded from S (linearly dependent)
-    int* sord;          // [p][K] slot of each support position
-    double* G;          // [p][K*K] Gram of I, row-major by slot
-    double* Rinv;       // [p][tri(K)] inverse Cholesky factor of G_SS, packed by position
-    double* vscratch;   // [p][8K] vectors when they do not fit LDS
+    int* cap;           // [p] slot capacity of the signal's block (0: none yet)
+    double** blk;       // [p] the signal's slot block in the arena (layout: slot_block)
+    Arena* arena;       // allocator of the blocks
     // reduced-precision screening (null in float32 mode)
     uint16_t* R16;      // [p_cap + 1][kpad] bfloat16 copy of R (row p_cap all zero)
     double* rnorm;      // [p] ||xi_i||_2
@@ -110,6 +162,8 @@ struct SelectArgs {
     // pursuit bookkeeping (may be null in the diagnostic entry point)
     const int* nI; int max_active;
     int* clear_count;      // set to 0 by workgroup 0 before anything else (or null)
+    // float32 band (0 = off): signals whose stop needs the exact re-score are appended (their rows)
+    const double* rr2; double band; int* cert_list; int* n_cert;
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
 
@@ -127,6 +181,7 @@ struct CertifyArgs {
     const float* R; int64_t ldr;            // float32 residuals (row per signal)
     int k; const int* nI; int max_active;
     int* sel; int selcap; int* nsel; float* vmax;
+    const int* cert_list; const int* n_cert;   // the rows the selection listed
 };
 hipError_t launch_certify(const CertifyArgs& a, hipStream_t stream);
 

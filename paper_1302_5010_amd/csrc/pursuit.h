@@ -26,6 +26,11 @@ struct StatusArgs {
     double r_inf_rel;   // Eq. (10) correlation radius relative to ||A^T b_i||_inf, 0 = off
     double r2_rel;      // Eq. (10) residual radius relative to ||b_i||, 0 = off
     int rho;            // atoms per outer iteration in the Eq. (13) normalisation
+    // slot-block reserve: the doubles the kept signals may request from the arena during the next
+    // reserve_iters outer iterations (rho_pass slots each at most), written to arena->reserve
+    int reserve_iters; int rho_pass; int slack; int kcap;
+    int* clear_cert;    // the selection's certification list count, set to 0 at the end (or null)
+    int* grow_list; int* n_grow;   // kept signals whose block must grow for this pass's selection
 };
 
 struct WarmArgs {
@@ -52,11 +57,11 @@ struct SolveArgs {
     const float* Bw;
     const double* Q; int64_t ldq;   // Gram table A^T A (float64) or null
     const int* act; const int* n_act_dev;
-    int max_steps;
+    int max_steps_per_slot;         // active-set step cap: max_steps_per_slot * capacity + 256
     int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
-    int kv;                         // their stride: a bound on |I| during the launch (<= w.K)
+    int kv;                         // their stride: a bound on |I| during the launch
     int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
     int smpl_keep;                  // > 0: subspace exploratory matching keeps this many of the new atoms
     uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,
@@ -64,23 +69,19 @@ struct SolveArgs {
 };
 
 
+struct GrowArgs {
+    Workspace w;
+    const int* list; const int* n_list;   // the signals to grow (written by the stop test)
+    int slack, kcap;                // grow_capacity's parameters; kcap = max_active
+};
+
 struct PackArgs {
     Workspace w;
     float* x_val; int32_t* x_idx; int32_t* supp_len; int32_t* iters;
     double* kkt; double* lambda; double* objective; int32_t* status;
     int ld_x;
-    int stage;          // the support's atoms and values are staged in dynamic LDS (12 w.K bytes)
-};
-
-struct SlotArrays {
-    int* slot_atom; double* x; double* c; signed char* theta; unsigned char* excl;
-    int* sord; double* G; double* Rinv;
-};
-
-struct RestrideArgs {
-    SlotArrays src, dst;
-    const int* nI; const int* nS;
-    int K_old, K_new;
+    int stage;          // the support's atoms and values are staged in dynamic LDS (12 bytes per position)
+    int stage_max;      // positions that fit that staging
 };
 
 __global__ void prep_kernel(PrepArgs a);
@@ -89,6 +90,6 @@ __global__ void warm_select_kernel(WarmArgs a);
 __global__ void solve_kernel(SolveArgs a);         // single appends only (zs_lds ignored)
 __global__ void solve_block_kernel(SolveArgs a);   // block appends when zs_lds
 __global__ void pack_kernel(PackArgs a);
-__global__ void restride_kernel(RestrideArgs a);
+__global__ void grow_kernel(GrowArgs a);
 
 }  // namespace bmpl

@@ -113,6 +113,23 @@ __device__ inline void block_argmin(double& a, int& q, double* red, int* redi)
         if (red[w] < a || (red[w] == a && (unsigned)redi[w] < (unsigned)q)) { a = red[w]; q = redi[w]; }
 }
 
+// A block of `sz` doubles from the arena (one thread calls it), or null when no chunk has room.  The
+// offset `top` only grows (one fetch-and-add per request, so many workgroups allocate at once without
+// retry loops); a range that would straddle the end of a chunk is abandoned and the request is made
+// again, which lands past that end.  The chunk list is constant while kernels run.
+__device__ double* arena_alloc(Arena* A, unsigned long long sz)
+{
+    const int nc = A->nchunks;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        const unsigned long long off = atomicAdd(&A->top, sz);
+        int c = 0;
+        while (c < nc && off >= A->start[c] + A->size[c]) ++c;
+        if (c == nc) return nullptr;
+        if (off + sz <= A->start[c] + A->size[c]) return A->base[c] + (off - A->start[c]);
+    }
+    return nullptr;
+}
+
 // Per-signal working view inside the solve kernel.  G is global (row-major,
 // stride K); the rest points into LDS or into the global homes.
 struct Sig {
@@ -688,6 +705,12 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.obj_prev[sig] = 0.5 * bb;
         w.rr2[sig] = bb;
         w.g0max[sig] = 0.f;
+        w.cap[sig] = 0;
+        w.blk[sig] = nullptr;
+        if (sig == 0) {   // a new solve hands out slot blocks from the start of the arena
+            w.arena->top = 0;
+            w.arena->starved = 0;
+        }
         if (w.rnorm) w.rnorm[sig] = sqrt(bb);
         if (w.dxnorm) w.dxnorm[sig] = sqrt(bd);
     }
@@ -707,8 +730,11 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
     const int n_in = a.n_in_dev ? *a.n_in_dev : a.n_in;
     __shared__ int s_scan[1024];
     __shared__ int s_base;
-    if (threadIdx.x == 0) s_base = 0;
+    __shared__ unsigned long long s_res[16];
+    __shared__ int s_ng;
+    if (threadIdx.x == 0) { s_base = 0; s_ng = 0; }
     __syncthreads();
+    unsigned long long res = 0;   // this thread's share of the slot-block reserve
     for (int r0 = 0; r0 < n_in; r0 += 1024) {
         const int r = r0 + threadIdx.x;
         int keep = 0, sig = -1;
@@ -763,6 +789,17 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                 }
             }
         }
+        if (keep && a.grow_list && w.nI[sig] + w.nsel[sig] > w.cap[sig])
+            a.grow_list[atomicAdd(&s_ng, 1)] = sig;   // its block grows before the master problem
+        if (keep && a.reserve_iters > 0) {
+            // the blocks this signal may take while its |I| grows by up to reserve_iters * rho_pass slots
+            int Kc = w.cap[sig];
+            const int target = min(a.kcap, w.nI[sig] + a.reserve_iters * a.rho_pass);
+            while (Kc < target) {
+                Kc = grow_capacity(Kc, min(target, Kc + a.rho_pass), a.slack, a.kcap);
+                res += (unsigned long long)block_doubles(Kc, w.n);
+            }
+        }
         s_scan[threadIdx.x] = keep;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {           // inclusive Hillis-Steele scan
@@ -776,7 +813,21 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
         if (threadIdx.x == 1023) s_base += s_scan[1023];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *a.n_out_dev = s_base;
+    if (threadIdx.x == 0) {
+        *a.n_out_dev = s_base;
+        if (a.n_grow) *a.n_grow = s_ng;
+        if (a.clear_cert) *a.clear_cert = 0;   // this pass's certification list is consumed
+    }
+    if (a.reserve_iters > 0) {
+        for (int o = 32; o > 0; o >>= 1) res += __shfl_xor(res, o);
+        if ((threadIdx.x & 63) == 0) s_res[threadIdx.x >> 6] = res;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int q = 0; q < 16; ++q) t += s_res[q];
+            w.arena->reserve = t;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -811,6 +862,71 @@ __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
     if (total > 0) {
         if (keep && pos < cap) w.sel[(int64_t)sig * w.selcap + pos] = j;
         if (tid == 0) w.nsel[sig] = total < cap ? total : cap;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Slot-block growth: a running signal whose active set, with this pass's selection, outgrows its block
+// takes a larger one from the arena (grow_capacity) and copies its state over: slots, support order,
+// the inverse factor and the Gram matrix of I (restrided).  A request that finds no room is counted in
+// the arena's `starved` and leaves the signal as it is (the master-problem kernel then skips it).
+// ---------------------------------------------------------------------------
+// The stop test lists the signals that need it; a grid of at most a few hundred workgroups loops over
+// the list.
+__global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
+{
+    const int n_list = *a.n_list;
+    const Workspace& w = a.w;
+    const int tid = threadIdx.x;
+    __shared__ double* s_blk;
+    for (int li = blockIdx.x; li < n_list; li += gridDim.x) {
+        const int sig = a.list[li];
+        const int nI0 = w.nI[sig], nS = w.nS[sig];
+        const int nI = nI0 + w.nsel[sig];
+        const int K = w.cap[sig];
+        const int K2 = grow_capacity(K, nI, a.slack, a.kcap);
+        if (tid == 0) {
+            s_blk = arena_alloc(w.arena, (unsigned long long)block_doubles(K2, w.n));
+            if (!s_blk) atomicAdd(&w.arena->starved, 1ull);
+        }
+        __syncthreads();
+        double* nb = s_blk;
+        __syncthreads();   // s_blk is rewritten for the next signal
+        if (!nb) continue;
+        if (K > 0) {
+            const SlotBlock o = slot_block(w.blk[sig], K, w.n), d = slot_block(nb, K2, w.n);
+            for (int u = tid; u < nI0; u += 256) {
+                d.x[u] = o.x[u]; d.c[u] = o.c[u]; d.atom[u] = o.atom[u]; d.theta[u] = o.theta[u];
+                d.excl[u] = o.excl[u];
+            }
+            for (int k = tid; k < nS; k += 256) d.sord[k] = o.sord[k];
+            const int tr = (int)tri(nS), tot = nI0 * nI0;
+            for (int e0 = tid; e0 < tr; e0 += 8 * 256) {   // eight loads in flight per thread
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = e0 + q * 256 < tr ? o.Rinv[e0 + q * 256] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (e0 + q * 256 < tr) d.Rinv[e0 + q * 256] = v[q];
+            }
+            for (int e0 = tid; e0 < tot; e0 += 8 * 256) {   // G restrided from K to K2
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int e = e0 + q * 256, u = e / nI0;
+                    v[q] = e < tot ? o.G[(int64_t)u * K + (e - u * nI0)] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int e = e0 + q * 256, u = e / nI0;
+                    if (e < tot) d.G[(int64_t)u * K2 + (e - u * nI0)] = v[q];
+                }
+            }
+        }
+        if (tid == 0) {
+            w.blk[sig] = nb;
+            w.cap[sig] = K2;
+        }
     }
 }
 
@@ -913,34 +1029,42 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nnew = w.nsel[sig];
     if (nnew <= 0) return;
-    const int K = w.K;
     const int nI0 = w.nI[sig];
     int nS = w.nS[sig];
     const double lam = w.lam[sig];
     int nI = nI0 + nnew;
-    if (nI > K || (a.vec_lds && nI > a.kv)) {
+    if (a.vec_lds && nI > a.kv) {
         // the launch was sized for a smaller |I| (a host-side bound that does not hold): stop the signal
         // at its current iterate, reported inexact, rather than overrun the LDS vectors
         if (tid == 0) w.status[sig] |= BMPL_SIG_INEXACT | ST_HALT;
         return;
     }
+
+    // The signal's slot block (grown by grow_kernel before this launch); a block that could not grow
+    // (no arena room) leaves the signal untouched: the host adds room and the next outer iteration
+    // selects the same atoms again.
+    const int K = w.cap[sig];
+    if (nI > K) return;
+    double* base = w.blk[sig];
+    const SlotBlock hb = slot_block(base, K, w.n);
+    const int max_steps = a.max_steps_per_slot * K + 256;
     uint64_t tick = a.phase ? wall_clock64() : 0;
 
     // global homes of this signal's state
-    int* g_atom = w.slot_atom + (int64_t)sig * K;
-    double* g_x = w.x + (int64_t)sig * K;
-    double* g_c = w.c + (int64_t)sig * K;
-    signed char* g_th = w.theta + (int64_t)sig * K;
-    unsigned char* g_ex = w.excl + (int64_t)sig * K;
-    int* g_so = w.sord + (int64_t)sig * K;
-    double* g_R = w.Rinv + (int64_t)sig * tri(K);
+    int* g_atom = hb.atom;
+    double* g_x = hb.x;
+    double* g_c = hb.c;
+    signed char* g_th = hb.theta;
+    unsigned char* g_ex = hb.excl;
+    int* g_so = hb.sord;
+    double* g_R = hb.Rinv;
 
     Sig s;
     s.K = K;
     // The LDS factor holds up to a.kl support positions; a signal whose support outgrows it moves its
     // factor to the global home and continues there (spill_factor below).
     s.r_lds = a.rinv_lds != 0 && nS <= a.kl;
-    s.G = w.G + (int64_t)sig * K * K;
+    s.G = hb.G;
     char* lp = reinterpret_cast<char*>(s_dyn);
     if (a.rinv_lds) {
         s.R = s.r_lds ? reinterpret_cast<double*>(lp) : g_R;
@@ -959,7 +1083,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         s.th = reinterpret_cast<signed char*>(ip + 2 * KV);
         s.ex = reinterpret_cast<unsigned char*>(s.th + KV);
     } else {
-        double* d = w.vscratch + (int64_t)sig * 8 * K;
+        double* d = hb.vs;
         s.x = g_x; s.c = g_c; s.th = g_th; s.ex = g_ex; s.so = g_so;
         vw = d; vz = d + K; vx = d + 2 * K; vg = d + 3 * K;
         vatom = reinterpret_cast<int*>(d + 4 * K);
@@ -969,7 +1093,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     // direct Gram staging (no table) after the vectors and the block scratch
     double* snew = a.Q ? nullptr
                        : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV) : 0) +
-                                                   (a.zs_lds ? block_scratch_bytes(K) : 0));
+                                                   (a.zs_lds ? block_scratch_bytes(KV) : 0));
 
     // 1. Load the state, register the new slots.
     if (a.vec_lds) {
@@ -1211,7 +1335,7 @@ active_set:
         // move toward the sign-fixed minimiser, dropping at zero crossings
         int dropped = 0;
         for (;;) {
-            if (++steps > a.max_steps) { inexact = true; break; }
+            if (++steps > max_steps) { inexact = true; break; }
             sign_fixed_solve(s, nS, lam, vw, vz, vx);
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 8), 1ull);
             double alpha = 1.0;
@@ -1389,13 +1513,14 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a)
 {
     const int sig = blockIdx.x;
     const Workspace& w = a.w;
-    const int64_t K = w.K;
-    const int* so = w.sord + sig * K;
-    const double* xs = w.x + sig * K;
-    const int* at = w.slot_atom + sig * K;
-    const int nS = (w.status[sig] & BMPL_SIG_NONFINITE) ? 0 : w.nS[sig];
+    const int nS = (w.status[sig] & BMPL_SIG_NONFINITE) || !w.blk[sig] ? 0 : w.nS[sig];
+    const SlotBlock b = slot_block(w.blk[sig], w.cap[sig], w.n);   // only read when nS > 0
+    const int* so = b.sord;
+    const double* xs = b.x;
+    const int* at = b.atom;
+    const int64_t K = a.stage_max;
     int cnt = 0;
-    if (a.stage) {
+    if (a.stage && nS <= a.stage_max) {
         // the support's values and atoms (INT_MAX for a zero value) in LDS, then ranks from LDS
         extern __shared__ double s_px[];
         int* s_pa = reinterpret_cast<int*>(s_px + K);
@@ -1453,32 +1578,6 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a)
         if (a.objective) a.objective[sig] = bad ? NAN : w.obj[sig];
         if (a.status) a.status[sig] = w.status[sig];
     }
-}
-
-// ---------------------------------------------------------------------------
-// Capacity growth: copy the per-signal state from stride K_old to stride K_new.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void restride_kernel(RestrideArgs a)
-{
-    const int sig = blockIdx.x;
-    const int nI = min(a.nI[sig], a.K_old);
-    const int nS = min(a.nS[sig], a.K_old);
-    const int64_t o1 = (int64_t)sig * a.K_old, n1 = (int64_t)sig * a.K_new;
-    for (int u = threadIdx.x; u < nI; u += 256) {
-        a.dst.slot_atom[n1 + u] = a.src.slot_atom[o1 + u];
-        a.dst.x[n1 + u] = a.src.x[o1 + u];
-        a.dst.c[n1 + u] = a.src.c[o1 + u];
-        a.dst.theta[n1 + u] = a.src.theta[o1 + u];
-        a.dst.excl[n1 + u] = a.src.excl[o1 + u];
-    }
-    for (int k = threadIdx.x; k < nS; k += 256) a.dst.sord[n1 + k] = a.src.sord[o1 + k];
-    const int64_t go = (int64_t)sig * a.K_old * a.K_old, gn = (int64_t)sig * a.K_new * a.K_new;
-    for (int64_t e = threadIdx.x; e < (int64_t)nI * nI; e += 256) {
-        const int64_t u = e / nI, v = e % nI;
-        a.dst.G[gn + u * a.K_new + v] = a.src.G[go + u * a.K_old + v];
-    }
-    const int64_t ro = (int64_t)sig * tri(a.K_old), rn = (int64_t)sig * tri(a.K_new);
-    for (int64_t e = threadIdx.x; e < tri(nS); e += 256) a.dst.Rinv[rn + e] = a.src.Rinv[ro + e];
 }
 
 }  // namespace bmpl

@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256) void q_corr_kernel(QCorrArgs a)
     const int j0 = blockIdx.x * QCHUNK;
     const int tid = threadIdx.x;
     const Workspace& w = a.w;
-    const int64_t K = w.K;
-    const int nS = w.nS[sig];
+    const int nS = w.blk[sig] ? w.nS[sig] : 0;
+    const SlotBlock b = slot_block(w.blk[sig], w.cap[sig], w.n);   // only read when nS > 0
     double g[QCHUNK / 256];
 #pragma unroll
     for (int t = 0; t < QCHUNK / 256; ++t) {
@@ -85,9 +85,9 @@ __global__ __launch_bounds__(256) void q_corr_kernel(QCorrArgs a)
         const int nk = nS - k0 < QSTAGE ? nS - k0 : QSTAGE;
         __syncthreads();
         for (int k = tid; k < nk; k += 256) {
-            const int u = w.sord[sig * K + k0 + k];
-            s_atom[k] = w.slot_atom[sig * K + u];
-            s_x[k] = w.x[sig * K + u];
+            const int u = b.sord[k0 + k];
+            s_atom[k] = b.atom[u];
+            s_x[k] = b.x[u];
         }
         __syncthreads();
         for (int k = 0; k < nk; ++k) {

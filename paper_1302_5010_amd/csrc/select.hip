@@ -27,6 +27,15 @@ __device__ inline bool better(float v, int i, float w, int j)
     return v > w || (v == w && i < j);
 }
 
+// With a float32 band: a signal that admitted nothing although it had room, and whose largest |g~| is
+// within its band eps_i of lambda, is listed for the exact re-score of certify_kernel.
+__device__ inline void list_for_certification(const SelectArgs& a, int row, int sig, int k, int nsel, float vmax,
+                                              double lam)
+{
+    if (a.band > 0.0 && nsel == 0 && k > 0 && (double)vmax + a.band * sqrt(a.rr2[sig]) > lam)
+        a.cert_list[atomicAdd(a.n_cert, 1)] = row;
+}
+
 template <int KMAX>
 __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
 {
@@ -214,8 +223,10 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             if (lane == 0) s_red[wave] = vmx;
             __syncthreads();
             if (tid == 0) {
+                const float vm = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
                 a.nsel[sig] = nsel;
-                a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+                a.vmax[sig] = vm;
+                list_for_certification(a, row, sig, k, nsel, vm, lam);
             }
             return;
         }
@@ -244,8 +255,10 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             const int nsel = nc < k ? nc : k;
             for (int q = tid; q < a.selcap && q < k; q += 256) a.sel[(int64_t)sig * a.selcap + q] = q < nsel ? s_ci[q] : -1;
             if (tid == 0) {
+                const float vm = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
                 a.nsel[sig] = nsel;
-                a.vmax[sig] = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+                a.vmax[sig] = vm;
+                list_for_certification(a, row, sig, k, nsel, vm, lam);
             }
             return;
         }
@@ -289,6 +302,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
         if (tid == 0) {
             a.nsel[sig] = nsel;
             a.vmax[sig] = vmax_all;
+            list_for_certification(a, row, sig, k, nsel, vmax_all, lam);
         }
         return;
     }
@@ -303,22 +317,28 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
 // with none, vmax becomes the largest exact value (<= lambda), so the stop and the certificate's
 // off-I term are exact.  The row is swept in chunks of the LDS buffer, so any number of atoms in the
 // band is handled; at most EXB exact violators are kept (the lowest-indexed ones, all of them violators).
+// The signals come from the list the selection kernel wrote (usually empty or a handful), so a fixed
+// small grid loops over it.
+__device__ void certify_row(const CertifyArgs& a, int row, int sig);
+
 __global__ __launch_bounds__(256) void certify_kernel(CertifyArgs a)
 {
-    const int n_act = a.n_act_dev ? *a.n_act_dev : a.p_grid;
-    const int row = blockIdx.x;
-    if (row >= n_act) return;
-    const int sig = a.act ? a.act[row] : row;
-    if (a.nsel[sig] != 0) return;
+    const int n_list = *a.n_cert;
+    for (int li = blockIdx.x; li < n_list; li += gridDim.x) {
+        const int row = a.cert_list[li];
+        certify_row(a, row, a.act ? a.act[row] : row);
+    }
+}
+
+__device__ void certify_row(const CertifyArgs& a, int row, int sig)
+{
     int k = a.k;
     if (a.nI && a.max_active > 0) {
         const int room = a.max_active - a.nI[sig];
         k = room < k ? room : k;
     }
-    if (k <= 0) return;                            // I is full: the active-set cap decides
     const double lam = a.lam[sig];
     const double eps = a.band * sqrt(a.rr2[sig]);
-    if ((double)a.vmax[sig] + eps <= lam) return;   // every exact |g_j| <= |g~_j| + eps <= lambda
     const double lo = lam - eps;
     const float* g = a.G + (int64_t)row * a.ldg;
     const uint32_t* ex = a.excl + (int64_t)sig * a.words;
@@ -393,6 +413,7 @@ __global__ __launch_bounds__(256) void certify_kernel(CertifyArgs a)
         // with no violator every exact |g_j| is <= lambda: round down, so the stop test in float64 holds
         a.vmax[sig] = nsel > 0 ? (float)vmx : __double2float_rd(vmx);
     }
+    __syncthreads();   // the shared buffers are reused for the next listed signal
 }
 
 }  // namespace
@@ -401,7 +422,7 @@ hipError_t launch_certify(const CertifyArgs& a, hipStream_t stream)
 {
     if (a.p_grid <= 0) return hipSuccess;
     if (a.k <= 0 || a.k > a.selcap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(certify_kernel, dim3(a.p_grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(certify_kernel, dim3(a.p_grid < 64 ? a.p_grid : 64), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
