@@ -215,6 +215,22 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
                            float* G_dev, int64_t ldg, void* hip_stream);
 
 /*
+ * bmpl_correlate for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, layouts and result (the same kernels,
+ * so bit-identical to bmpl_correlate), but it allocates nothing and never synchronises: the residuals
+ * are staged in a library-owned device array of BMPL_NOALLOC_SCRATCH_BYTES per GPU (held until the
+ * process ends), and every launch is asynchronous on hip_stream (kernels only: no memset or memcpy
+ * nodes).  The staging needs (p + 1) * kpad * 4 bytes, kpad = n rounded up to 64 (128 with e4m3
+ * ranking), plus (p + 1) * kpad * 2 with bfloat16 screening or (p + 1) * (kpad + 4) with e4m3 ranking,
+ * each part rounded up to 256 bytes; a larger p returns BMPL_E_INVALID.  Every call on one GPU shares
+ * that GPU's array (it keeps the last call's contents; nothing needs clearing): calls that overlap in
+ * time on one GPU (different streams, threads or contexts) race and must be ordered by the caller.
+ */
+#define BMPL_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+bmpl_status bmpl_correlate_noalloc(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t p, float* G_dev,
+                                   int64_t ldg, void* hip_stream);
+
+/*
  * The worst-case analysis of Algorithm 1, step 3, on given correlations:
  * for each row i of G (p rows, leading dimension ldg >= m) pick up to k atoms j
  * with |G[i,j]| > lambda_dev[i] and mask bit j of excl_dev clear, largest

@@ -86,6 +86,7 @@ def _load():
     lib.bmpl_last_error.restype = ctypes.c_char_p
     lib.bmpl_last_error.argtypes = [ctypes.c_void_p]
     lib.bmpl_correlate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    lib.bmpl_correlate_noalloc.argtypes = [vp, vp, i64, i32, vp, i64, vp]
     lib.bmpl_select.argtypes = [vp, vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.bmpl_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.bmpl_gram_table.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64)]
@@ -106,6 +107,7 @@ def _load():
     lib.bmpl_mlp_propose.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp]
     lib.bmpl_topk.argtypes = [vp, i64, i32, i32, i32, vp, i32, vp]
     for f in ("bmpl_options_default", "bmpl_create", "bmpl_solve", "bmpl_destroy", "bmpl_correlate",
+              "bmpl_correlate_noalloc",
               "bmpl_select", "bmpl_get_timing", "bmpl_reset_timing", "bmpl_gram_table", "bmpl_autotune",
               "bmpl_set_tuning", "bmpl_mlp_create", "bmpl_mlp_destroy", "bmpl_mlp_set_params",
               "bmpl_mlp_get_params", "bmpl_mlp_embed", "bmpl_mlp_forward", "bmpl_mlp_loss_grad",
@@ -294,6 +296,18 @@ class Solver:
         with torch.cuda.device(Rt.device):
             _check(_lib.bmpl_correlate(self._h, Rt.data_ptr(), self.n, p, G.data_ptr(), self.m,
                                        _stream_ptr(stream)), "bmpl_correlate")
+        return G
+
+    def correlate_noalloc(self, Rt: torch.Tensor, G: torch.Tensor, stream=None) -> torch.Tensor:
+        """bmpl_correlate_noalloc into the caller's G ((p, m) float32): the library allocates nothing and
+        does not synchronise, so the call can be captured in a graph."""
+        Rt = _dev(Rt, torch.float32, "Rt")
+        p = Rt.shape[0]
+        if G.dtype != torch.float32 or G.shape != (p, self.m) or not G.is_contiguous() or G.device != Rt.device:
+            raise BmplError("G must be a contiguous (p, m) float32 tensor on the residuals' device")
+        with torch.cuda.device(Rt.device):
+            _check(_lib.bmpl_correlate_noalloc(self._h, Rt.data_ptr(), self.n, p, G.data_ptr(), self.m,
+                                               _stream_ptr(stream)), "bmpl_correlate_noalloc")
         return G
 
     def select(self, G: torch.Tensor, lam: torch.Tensor, k: int, excl: torch.Tensor | None = None, stream=None):

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,39 @@ constexpr int WARM_KL = 64;        // LDS factor capacity of the master solve ri
 constexpr int RESCORE_LDS_SMALL = 512;   // candidates per signal in the first re-score pass's LDS
 constexpr int CANDCAP_DEF = 4096;  // screening candidates per signal
 constexpr int CAND8 = 64;          // e4m3-ranked candidates re-scored per signal (at most; 2 rho are used)
+
+// Device scratch of bmpl_correlate_noalloc (staged residuals and their reduced-precision copies).  Each
+// device holds its own copy; host code uses the per-device address from hipGetSymbolAddress, never the
+// array's name.
+static __device__ __align__(256) unsigned char scratch[BMPL_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {};   // per device, looked up once
+
+// The current device's address of `scratch` (looked up on first use per device; the device is current).
+bmpl_status scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= 64) return fail(BMPL_E_UNSUPPORTED, "device %d out of the supported range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BMPL_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return BMPL_OK;
+}
+
+// Rows 0..p-1 of dst = the residuals r_i = R + i ldr (n values, zeros up to kpad); row p all zero.
+__global__ __launch_bounds__(256) void stage_rows_kernel(const float* __restrict__ R, int64_t ldr, int n, int p,
+                                                         float* __restrict__ dst, int kpad)
+{
+    const int i = blockIdx.x;
+    float* d = dst + (int64_t)i * kpad;
+    for (int r = threadIdx.x; r < kpad; r += 256) d[r] = (i < p && r < n) ? R[(int64_t)i * ldr + r] : 0.0f;
+}
 
 }  // namespace
 
@@ -94,6 +128,7 @@ struct bmpl_ctx {
     // diagnostic correlate staging
     float* diagR = nullptr;
     int diag_cap = 0;
+    unsigned char* scratch = nullptr;   // this device's address of the no-allocation scratch
 
     // kernel timing (BMPL_FLAG_TIMING)
     bmpl_timing timing{};
@@ -448,6 +483,15 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_arena), sizeof(Arena), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_arena_rd), sizeof(Arena), hipHostMallocDefault);
     if (e == hipSuccess) e = dalloc(reinterpret_cast<char**>(&c->arena_dev), sizeof(Arena));
+    if (e == hipSuccess) {   // the no-allocation entry point's scratch: its address on this device
+        void* sp = nullptr;
+        if (scratch_address(c->device, &sp) != BMPL_OK) {
+            const std::string msg = g_err;
+            bmpl_destroy(c);
+            return fail(BMPL_E_HIP, "bmpl_create: %s", msg.c_str());
+        }
+        c->scratch = static_cast<unsigned char*>(sp);
+    }
     if (e == hipSuccess)   // the running counts live in the arena header: one read-back holds both
         c->n_act_dev = reinterpret_cast<int*>(reinterpret_cast<char*>(c->arena_dev) + offsetof(Arena, n_act));
     if (e == hipSuccess) {
@@ -624,6 +668,48 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
         return BMPL_OK;
     }
     HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, c->diagR, c->kpad, nullptr, nullptr, p, G_dev, ldg, p, 0, 1 << 30, s));
+    return BMPL_OK;
+}
+
+bmpl_status bmpl_correlate_noalloc(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t p, float* G_dev,
+                                   int64_t ldg, void* hip_stream)
+{
+    if (!c || !R_dev || !G_dev) return fail(BMPL_E_INVALID, "bmpl_correlate_noalloc: NULL argument");
+    if (p < 0 || ldr < c->n || ldg < c->m) return fail(BMPL_E_INVALID, "bmpl_correlate_noalloc: bad shape");
+    if (p == 0) return BMPL_OK;
+    // scratch layout: float32 rows [p + 1][kpad] | bfloat16 rows [p + 1][kpad] (bfloat16 screening) |
+    // e4m3 rows [p + 1][kpad] and their scales [p + 1] (e4m3 ranking), each part 256-byte aligned
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t rows = (size_t)p + 1, kp = (size_t)c->kpad;
+    const size_t o16 = al(rows * kp * sizeof(float));
+    const size_t o8 = o16 + (c->A16 && !c->A8 ? al(rows * kp * sizeof(uint16_t)) : 0);
+    const size_t os = o8 + (c->A8 ? al(rows * kp) : 0);
+    const size_t need = os + (c->A8 ? al(rows * sizeof(float)) : 0);
+    if (need > (size_t)BMPL_NOALLOC_SCRATCH_BYTES)
+        return fail(BMPL_E_INVALID, "bmpl_correlate_noalloc: %d residuals of %d values need %zu bytes of scratch, "
+                                    "more than BMPL_NOALLOC_SCRATCH_BYTES (%zu)", p, c->n, need,
+                    (size_t)BMPL_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    float* stage = reinterpret_cast<float*>(c->scratch);
+    hipLaunchKernelGGL(stage_rows_kernel, dim3(p + 1), dim3(256), 0, s, R_dev, ldr, c->n, p, stage, c->kpad);
+    HIPC(hipGetLastError());
+    if (c->A8) {
+        uint8_t* r8 = c->scratch + o8;
+        float* sc8 = reinterpret_cast<float*>(c->scratch + os);
+        HIPC(launch_atoms_fp8(stage, c->kpad, c->kpad, r8, sc8, p + 1, s));
+        HIPC(launch_corr_gemm_fp8(c->corr_variant(p), c->A8, c->kpad, c->m, c->kpad, r8, c->kpad, nullptr, nullptr, p,
+                                  G_dev, ldg, p, 0, 1 << 30, c->ascale8, sc8, s));
+        return BMPL_OK;
+    }
+    if (c->A16) {
+        uint16_t* r16 = reinterpret_cast<uint16_t*>(c->scratch + o16);
+        HIPC(launch_to_bf16(stage, c->kpad, r16, c->kpad, p + 1, c->kpad, s));
+        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->kpad, c->m, c->kpad, r16, c->kpad, nullptr, nullptr,
+                                   p, G_dev, ldg, p, 0, 1 << 30, s));
+        return BMPL_OK;
+    }
+    HIPC(launch_corr_gemm_f32(c->corr_variant(p), c->At, c->kpad, c->m, c->kpad, stage, c->kpad, nullptr, nullptr, p,
+                              G_dev, ldg, p, 0, 1 << 30, s));
     return BMPL_OK;
 }
 
