@@ -13,6 +13,12 @@ Printed: one JSON line with the throughput, the correlation kernel's
 roofline (HIP-event times of every launch in the timed steps, algorithmic
 flops 2 m n p_running per launch), and the FP64 CPU oracle timed on a sample
 of the same workload (with its parity against the GPU on that sample).
+Further lines in the same object, each with its errors against the FP64
+oracle (the lambda the line used): bfloat16 screening, e4m3 ranking, the
+paper's Q-route and SMPL on the same workload; the ragged 1024 x 32768 batch of
+4096 signals in one solve (against stored oracle rows); the face-like
+dictionary with plain FP32 / e4m3 / bfloat16 and bfloat16 + learned proposal at
+rho = 10 and rho = 1 (512 sampled signals); the paper's own figures as context.
 """
 from __future__ import annotations
 
@@ -26,6 +32,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from tests.parity import objective  # noqa: E402
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
 PEAK_HBM_GBS = 8000.0
@@ -56,136 +64,256 @@ def load_traffic(path: str):
         return None
 
 
-def screened_measurement(args, pk, torch, At, Bt, P, screen: str) -> dict:
-    """Throughput in graph mode and the instrumented kernel breakdown of one screening precision."""
-    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=screen)
-    shapes = s.autotune(P.p)["shapes"]
-    for _ in range(args.warmup):
-        s.solve(Bt)
+def host_info() -> dict:
+    """The host the CPU baseline ran on: usable threads and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def parity_stats(At, Bt, lam, X_gpu, X_or) -> dict:
+    """Errors of GPU solutions against the float64 oracle's (rows aligned), by the parity rules of the test
+    suite but counted instead of asserted: relative objective error |F_gpu - F_or| / F_or and relative l2
+    error of x (maxima), signals whose support or signs differ where the oracle's margin exceeds
+    1e-3 lambda, and per-atom rule violations."""
+    A64 = At.astype(np.float64).T
+    worst_obj = worst_x = 0.0
+    supp_mismatch = atom_viol = 0
+    for q in range(X_or.shape[0]):
+        b = Bt[q].astype(np.float64)
+        xo, xg, lm = X_or[q], X_gpu[q], float(lam[q])
+        Fo, Fg = objective(A64, b, xo, lm), objective(A64, b, xg, lm)
+        worst_obj = max(worst_obj, abs(Fg - Fo) / Fo if Fo > 0 else abs(Fg))
+        nx = np.linalg.norm(xo)
+        worst_x = max(worst_x, np.linalg.norm(xg - xo) / nx if nx > 0 else np.linalg.norm(xg))
+        g = A64.T @ (b - A64 @ xo)
+        So, Sg = xo != 0, xg != 0
+        mu = min(np.min(lm - np.abs(g[~So]), initial=np.inf), np.min(np.abs(xo[So]), initial=np.inf))
+        if mu > 1e-3 * lm and (not np.array_equal(So, Sg) or not np.array_equal(np.sign(xg[So]), np.sign(xo[So]))):
+            supp_mismatch += 1
+        atom_viol += int(np.sum(Sg & ((lm - np.abs(g)) > 1e-3 * lm)) + np.sum(~Sg & (np.abs(xo) > 1e-3 * lm)))
+    return {"signals": int(X_or.shape[0]), "max_rel_obj": float(worst_obj), "max_rel_x": float(worst_x),
+            "support_mismatches": int(supp_mismatch), "atom_rule_violations": int(atom_viol)}
+
+
+class OracleCache:
+    """FP64 oracle solutions of sampled rows, keyed by the exact lambda values (the lambda the GPU used,
+    so both sides solve the identical problem), rho and omega; also records the oracle's time."""
+
+    def __init__(self, P, rows):
+        self.P, self.rows = P, list(rows)
+        self.runs = {}
+
+    def solve(self, lam_rows, rho=None, omega=1):
+        import oracle
+        rho = self.P.rho if rho is None else rho
+        key = (np.asarray(lam_rows, dtype=np.float64).tobytes(), rho, omega)
+        if key not in self.runs:
+            threads = min(oracle.max_threads(), len(self.rows))
+            t0 = time.perf_counter()
+            ref = oracle.solve(self.P.At, self.P.Bt[self.rows], lam_rows, rho, nthreads=threads, omega=omega)
+            self.runs[key] = (ref, time.perf_counter() - t0, threads)
+        return self.runs[key]
+
+    def parity(self, out):
+        lam = out["lambda"][self.rows].cpu().numpy()
+        ref, _, _ = self.solve(lam)
+        return parity_stats(self.P.At, self.P.Bt[self.rows], lam, sparse_rows(out, self.rows, self.P.m), ref["X"])
+
+
+def timed_steps(args, torch, fn, steps=None, warmup=None):
+    """`warmup` untimed calls, then `steps` timed ones bracketed by device synchronisations."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
-    solved = []
+    outs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solved.append(s.solve(Bt)["status"])
+    for _ in range(steps):
+        outs.append(fn())
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    conv = [int(((st & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for st in solved]
-    del s
-    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen=screen)
+    return outs, (time.perf_counter() - t0) / steps
+
+
+def instrumented(pk, torch, At, P, screen, shapes, fn_solve, rho=None, **kw):
+    """One solve with every kernel bracketed by HIP events (host loop, same tile shapes): the kernel
+    breakdown and the correlation product's achieved fraction of its matrix peak."""
+    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho if rho is None else rho, kkt_tol=1e-4, timing=True,
+                   screen=screen, **kw)
     st.set_tuning(shapes)
-    st.solve(Bt)
+    fn_solve(st)
     torch.cuda.synchronize()
     st.reset_timing()
-    for _ in range(args.steps):
-        st.solve(Bt)
+    fn_solve(st)
     torch.cuda.synchronize()
     tb = st.timing()
+    st.close()
     ach = tb["corr_flops"] / (tb["corr_ms"] * 1e-3) / 1e12 if tb["corr_ms"] > 0 else 0.0
-    peak = PEAK_TFLOPS[screen]
-    return {
-        "value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
-        "converged_per_step": conv,
-        "main_product": {"dtype": screen, "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
-                         "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"]),
-                         "note": "first pass (lambda rule) in bfloat16 for fp8" if screen == "fp8" else ""},
-        "kernel_ms_per_step": {k: tb[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms",
-                                                                "other_ms", "wall_ms")},
-    }
+    return {"main_product": {"dtype": screen, "achieved_tflops": ach, "peak_tflops": PEAK_TFLOPS[screen],
+                             "frac": ach / PEAK_TFLOPS[screen],
+                             "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"]),
+                             "launches": tb["corr_launches"]},
+            "kernel_ms_per_step": {k: tb[k] for k in ("corr_ms", "select_ms", "solve_ms", "other_ms", "wall_ms")}}
 
 
-def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma) -> dict:
+def converged_count(pk, out) -> int:
+    return int(((out["status"] & pk.BMPL_SIG_CONVERGED) > 0).sum().item())
+
+
+def screened_measurement(args, pk, torch, At, Bt, P, screen: str, orc: OracleCache) -> dict:
+    """Throughput in graph mode, the instrumented kernel breakdown and the oracle errors of one screening
+    precision."""
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=screen)
+    shapes = s.autotune(P.p)["shapes"]
+    outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
+    s.close()
+    rec = {"value": converged_count(pk, outs[-1]) / dt, "unit": "signals/s", "ms_per_step": dt * 1e3,
+           "converged_per_step": [converged_count(pk, o) for o in outs]}
+    rec.update(instrumented(pk, torch, At, P, screen, shapes, lambda st: st.solve(Bt)))
+    if screen == "fp8":
+        rec["main_product"]["note"] = "first pass (lambda rule) in bfloat16 for fp8"
+    rec["parity_on_sample"] = orc.parity(outs[-1])
+    return rec
+
+
+def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma, orc: OracleCache) -> dict:
     """Section III's correlation (g = beta - Q_{:,S} x_S, float64, HBM-bound on Q's rows) in place of the
     MFMA product, same workload: throughput and the correlation time per step against the MFMA's."""
     s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, q_route=True)
-    for _ in range(args.warmup):
-        s.solve(Bt)
-    torch.cuda.synchronize()
-    solved = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solved.append(s.solve(Bt)["status"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    conv = [int(((st & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for st in solved]
-    del s
+    outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
+    s.close()
     st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, q_route=True)
     st.solve(Bt)
     torch.cuda.synchronize()
     st.reset_timing()
-    for _ in range(args.steps):
-        st.solve(Bt)
+    st.solve(Bt)
     torch.cuda.synchronize()
     tq = st.timing()
-    return {"value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
-            "converged_per_step": conv,
-            "correlation_ms_per_step": tq["corr_ms"] / args.steps,
+    st.close()
+    return {"value": converged_count(pk, outs[-1]) / dt, "unit": "signals/s", "ms_per_step": dt * 1e3,
+            "converged_per_step": [converged_count(pk, o) for o in outs],
+            "correlation_ms_per_step": tq["corr_ms"],
             "mfma_correlation_ms_per_step": tm_mfma["corr_ms"] / args.steps,
             "note": "the first pass (lambda rule) stays the MFMA product in both; the Q-route adds the float64 "
                     "beta = A^T b at set-up (in other_ms)",
-            "kernel_ms_per_step": {k: tq[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms",
-                                                                    "other_ms", "wall_ms")}}
+            "kernel_ms_per_step": {k: tq[k] for k in ("corr_ms", "select_ms", "solve_ms", "other_ms", "wall_ms")},
+            "parity_on_sample": orc.parity(outs[-1])}
 
 
-def smpl_measurement(args, pk, torch, At, Bt, P, out_mpl) -> dict:
+def smpl_measurement(args, pk, torch, At, Bt, P, out_mpl, orc: OracleCache) -> dict:
     """Subspace exploratory matching (Algorithm 2, omega = 3) on the same workload: throughput and
-    outer iterations against plain MPL's."""
+    outer iterations against plain MPL's; errors against the oracle's SMPL (omega = 3)."""
     s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, omega=3)
     s.autotune(P.p)
-    for _ in range(args.warmup):
-        s.solve(Bt)
-    torch.cuda.synchronize()
-    solved = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solved.append(s.solve(Bt))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    conv = [int(((o["status"] & pk.BMPL_SIG_CONVERGED) > 0).sum().item()) for o in solved]
-    return {"omega": 3, "value": sum(conv) / (t1 - t0), "unit": "signals/s", "ms_per_step": (t1 - t0) / args.steps * 1e3,
-            "converged_per_step": conv,
-            "iters_mean": float(solved[-1]["iters"].float().mean().item()),
-            "mpl_iters_mean": float(out_mpl["iters"].float().mean().item())}
+    outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
+    s.close()
+    out = outs[-1]
+    lam = out["lambda"][orc.rows].cpu().numpy()
+    ref, _, _ = orc.solve(lam, omega=3)
+    return {"omega": 3, "value": converged_count(pk, out) / dt, "unit": "signals/s", "ms_per_step": dt * 1e3,
+            "converged_per_step": [converged_count(pk, o) for o in outs],
+            "iters_mean": float(out["iters"].float().mean().item()),
+            "mpl_iters_mean": float(out_mpl["iters"].float().mean().item()),
+            "oracle_iters_mean_on_sample": float(np.mean(ref["iters"])),
+            "parity_on_sample": parity_stats(P.At, P.Bt[orc.rows], lam, sparse_rows(out, orc.rows, P.m), ref["X"])}
+
+
+def ragged_measurement(args, pk, torch) -> dict:
+    """The ragged batch: A 1024 x 32768, 4096 signals with k ~ U{10..400}, in ONE bmpl_solve (graph
+    segments; each signal's slot block follows its own |I|).  lambda_i = 0.03 ||A^T b_i||_inf is computed
+    in float64 on the host and passed in (the stored oracle rows used the same values), so the oracle and
+    the GPU solve identical problems.  One warm-up solve (after autotuning), then one timed solve.  Errors
+    against the stored FP64 oracle results of the 64-signal stratified subset (32 with k >= 200, 32 with
+    k <= 150); the CPU baseline is that oracle run's recorded time (too long to repeat here)."""
+    import json as _json
+
+    import bmpl_inputs as bi
+    P = bi.ragged_gaussian()
+    dev = torch.device("cuda:0")
+    with open(os.path.join(ROOT, "tests", "golden", "ragged1024x32768_oracle.json")) as f:
+        g = _json.load(f)
+    rows = [int(r) for r in g["rows"]]
+    lam = P.lambda_rel * np.abs(P.At.astype(np.float64) @ P.Bt.astype(np.float64).T).max(axis=0)
+    lam[rows] = [float.fromhex(v) for v in g["lam"]]
+    At, Bt, lam_d = (torch.from_numpy(P.At).to(dev), torch.from_numpy(P.Bt).to(dev), torch.from_numpy(lam).to(dev))
+    s = pk.Solver(At, 0.0, rho=P.rho, kkt_tol=1e-4, graph=True)
+    tune = s.autotune(P.p)
+    outs, dt = timed_steps(args, torch, lambda: s.solve(Bt, lam=lam_d), steps=1, warmup=1)
+    out = outs[-1]
+    s.close()
+    X = np.zeros((len(rows), P.m))
+    val = [float.fromhex(v) for v in g["val"]]
+    off = 0
+    for q, ln in enumerate(g["supp_len"]):
+        X[q, g["idx"][off:off + ln]] = val[off:off + ln]
+        off += ln
+    it = out["iters"].cpu().numpy()
+    supp = out["supp_len"].cpu().numpy()
+    k = np.array([len(sp) for sp in P.supports])
+    return {"workload": "ragged1024x32768 (p = 4096, one solve)", "value": converged_count(pk, out) / dt,
+            "unit": "signals/s", "ms_per_step": dt * 1e3, "steps": 1, "warmup": 1,
+            "converged": converged_count(pk, out), "autotune": tune["shapes"],
+            "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+            "support_mean_k_le_150": float(supp[k <= 150].mean()), "support_mean_k_ge_200": float(supp[k >= 200].mean()),
+            "parity_on_stored_subset": parity_stats(P.At, P.Bt[rows], lam[rows], sparse_rows(out, rows, P.m), X),
+            "iters_equal_to_oracle_on_subset": float(np.mean(it[rows] == np.array(g["iters"]))),
+            "cpu_baseline": {"value": len(rows) / g["seconds"], "unit": "signals/s", "cores": g["threads"],
+                             "kind": "oracle", "sample": "the stored 64-signal stratified subset (32 with k >= 200, "
+                             "32 with k <= 150), FP64 C oracle, one signal per thread; time recorded when the "
+                             "stored results were written (tests/golden/make_golden.py), not in this run"}}
 
 
 def learned_comparison(args, pk, torch) -> dict:
-    """Plain FP32, plain BF16-screened and BF16-screened + learned warm start on the face-like
-    dictionary (1024 x 20000, 200 classes of rank-8 subspaces), lambda_i = 0.01 ||A^T b_i||_inf,
-    rho = 10.  The proposal network (2048 -> 2048 -> 2048 -> 20000) is trained on supports that
-    BMPL returned for signals of a distinct seed stream (not timed); the timed learned step is
-    proposal (embedding, network, top-256) + warm-started solve."""
+    """Plain FP32, FP8-ranked, BF16-screened and BF16-screened + learned warm start on the face-like
+    dictionary (1024 x 20000, 200 classes of rank-8 subspaces), lambda_i = 0.01 ||A^T b_i||_inf, at
+    rho = 10 and rho = 1.  The proposal network (2048 -> 2048 -> 2048 -> 20000) is trained on supports that
+    BMPL returned for signals of a distinct seed stream (not timed); a timed learned step is proposal
+    (embedding, network, top-k) + warm-started solve, for k in {32, 64, 256}.  Every line's errors against
+    the float64 oracle on 512 sampled signals (every 32nd), with the lambda that line used."""
     import bmpl_inputs as bi
     from paper_1302_5010_amd import learned as ln
     dev = torch.device("cuda:0")
     P = bi.face_like(p=args.learned_signals)
     At = torch.from_numpy(P.At).to(dev)
     Bt = torch.from_numpy(P.Bt).to(dev)
+    rows = list(range(0, P.p, max(1, P.p // 512)))[:512]
+    orc = OracleCache(P, rows)
     rec = {"workload": f"face20000 (p = {P.p})", "train_signals": args.train_signals, "epochs": args.epochs}
 
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        outs = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            outs.append(fn())
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        conv = int(ln.converged(outs[-1]).sum().item())
-        return outs[-1], {"value": conv / dt, "unit": "signals/s", "ms_per_step": dt * 1e3, "converged": conv,
-                          "iters_mean": float(outs[-1]["iters"].float().mean().item())}
+    def line(fn, solver=None):
+        outs, dt = timed_steps(args, torch, fn)
+        o = outs[-1]
+        r = {"value": converged_count(pk, o) / dt, "unit": "signals/s", "ms_per_step": dt * 1e3,
+             "converged": converged_count(pk, o), "iters_mean": float(o["iters"].float().mean().item()),
+             "parity_on_sample": orc.parity(o)}
+        return o, r
 
-    plain32 = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="fp32")
-    plain32.autotune(P.p)
-    out32, rec["plain_fp32"] = timed(lambda: plain32.solve(Bt))
-    del plain32
-    f8 = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="fp8")
-    f8.autotune(P.p)
-    _, rec["plain_fp8"] = timed(lambda: f8.solve(Bt))
-    del f8
-    bf = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen="bf16")
-    bf.autotune(P.p)
-    outbf, rec["plain_bf16"] = timed(lambda: bf.solve(Bt))
+    def solver(screen, rho):
+        s = pk.Solver(At, P.lambda_rel, mode="rel", rho=rho, kkt_tol=1e-4, graph=True, screen=screen)
+        return s, s.autotune(P.p)["shapes"]
+
+    s32, shapes32 = solver("fp32", P.rho)
+    out32, rec["plain_fp32"] = line(lambda: s32.solve(Bt))
+    rec["plain_fp32"].update(instrumented(pk, torch, At, P, "fp32", shapes32, lambda st: st.solve(Bt)))
+    s32.close()
+    f8, _ = solver("fp8", P.rho)
+    _, rec["plain_fp8"] = line(lambda: f8.solve(Bt))
+    f8.close()
+    bf, shapes16 = solver("bf16", P.rho)
+    outbf, rec["plain_bf16"] = line(lambda: bf.solve(Bt))
+    rec["plain_bf16"].update(instrumented(pk, torch, At, P, "bf16", shapes16, lambda st: st.solve(Bt)))
     # the face application: class-residual classification of the codes (synthetic classes)
     cls = torch.from_numpy(P.meta["class_of_atom"].astype(np.int32)).to(dev)
     labels, _ = bf.classify(Bt, outbf, cls)
@@ -217,19 +345,45 @@ def learned_comparison(args, pk, torch) -> dict:
                        "labelled_converged": int(ln.converged(lab).sum().item()),
                        "loss_every_50_steps": [float(v.item()) for v in losses]}
     del Bt_tr, lab
-    outl, rec["bf16_learned"] = timed(lambda: ln.solve_with_proposal(bf, net, Bt, 256))
-    xi, sl, pr = outbf["x_idx"].cpu().numpy(), outbf["supp_len"].cpu().numpy(), outl["proposal"].cpu().numpy()
-    rec["bf16_learned"]["recall_at_256"] = float(np.mean([np.isin(xi[i, :sl[i]], pr[i]).mean()
-                                                          for i in range(P.p) if sl[i] > 0]))
-    rec["bf16_learned"]["fallback_fraction"] = float(((outl["status"] & pk.BMPL_SIG_FALLBACK) > 0).float().mean())
+    xi, sl = outbf["x_idx"].cpu().numpy(), outbf["supp_len"].cpu().numpy()
+
+    def learned_lines(s, plain_value, rho_tag, shapes, rho):
+        res = {}
+        for k in (32, 64, 256):
+            outl, r = line(lambda: ln.solve_with_proposal(s, net, Bt, k))
+            pr = outl["proposal"].cpu().numpy()
+            r["warm_k"] = k
+            r["recall_at_k"] = float(np.mean([np.isin(xi[i, :sl[i]], pr[i]).mean() for i in range(P.p) if sl[i] > 0]))
+            r["fallback_fraction"] = float(((outl["status"] & pk.BMPL_SIG_FALLBACK) > 0).float().mean())
+            r["speedup_learned_vs_plain_bf16"] = r["value"] / plain_value
+            r["speedup_learned_vs_plain_fp32"] = r["value"] / rec["plain_fp32"]["value"]
+            res[k] = r
+        best = max(res, key=lambda k: res[k]["value"])
+        out = dict(res[best])
+        out["best_of_warm_k"] = {str(k): {"value": res[k]["value"], "iters_mean": res[k]["iters_mean"],
+                                          "speedup_learned_vs_plain_bf16": res[k]["speedup_learned_vs_plain_bf16"]}
+                                 for k in res}
+        prop = net.propose(Bt, best)
+        out.update(instrumented(pk, torch, At, P, "bf16", shapes, lambda st: st.solve(Bt, warm=prop), rho=rho))
+        return out
+
+    rec["bf16_learned"] = learned_lines(bf, rec["plain_bf16"]["value"], "rho10", shapes16, P.rho)
     rec["speedup_learned_vs_plain_fp32"] = rec["bf16_learned"]["value"] / rec["plain_fp32"]["value"]
     rec["speedup_learned_vs_plain_bf16"] = rec["bf16_learned"]["value"] / rec["plain_bf16"]["value"]
-    # the learned run against the plain FP32 run on a sample of signals
-    rows = list(range(0, P.p, max(1, P.p // 32)))
-    X32, Xl = sparse_rows(out32, rows, P.m), sparse_rows(outl, rows, P.m)
-    rec["max_rel_x_learned_vs_fp32_sample"] = float(max(
-        np.linalg.norm(Xl[q] - X32[q]) / max(np.linalg.norm(X32[q]), 1e-300) for q in range(len(rows))))
-    del bf, net
+    bf.close()
+    # rho = 1: one atom per outer iteration (the paper's OMP-like end of the range), where a warm start
+    # saves the most iterations
+    bf1, shapes1 = solver("bf16", 1)
+    _, rec["plain_bf16_rho1"] = line(lambda: bf1.solve(Bt))
+    rec["bf16_learned_rho1"] = learned_lines(bf1, rec["plain_bf16_rho1"]["value"], "rho1", shapes1, 1)
+    bf1.close()
+    # CPU baseline on this workload: the oracle's time on the 512 sampled signals (rho = 10)
+    runs = [v for key, v in orc.runs.items() if key[1] == P.rho and key[2] == 1]
+    ref, secs, threads = runs[0]
+    rec["cpu_baseline"] = {"value": len(rows) / secs, "unit": "signals/s", "cores": threads, "kind": "oracle",
+                           "sample": f"{len(rows)} signals (every {max(1, P.p // 512)}th) of the same workload, "
+                                     "FP64 C oracle, rho = 10, one signal per thread"}
+    del net
     return rec
 
 
@@ -240,6 +394,19 @@ def sparse_rows(out: dict, rows, m: int) -> np.ndarray:
     for q in range(len(rows)):
         X[q, idx[q, :ln[q]]] = val[q, :ln[q]]
     return X
+
+
+# The paper's own figures for batch-mode MPL (context, not the target; another machine)
+PAPER_CONTEXT = {
+    "hardware": "Intel Core i7 PC, C++ on a single core, 64-bit Windows (clock, compiler and precision not stated)",
+    "table4_bmpl_200_signals": {
+        "workload": "A 2^12 x 2^14 Gaussian, k = 400 / 450 / 500 / 550 / 600 sparse Gaussian signals",
+        "seconds": [55.06, 55.79, 56.79, 59.51, 59.91],
+        "signals_per_s": [3.63, 3.58, 3.52, 3.36, 3.34],
+        "speedup_over_batch_omp": [7.89, 9.80, 11.99, 14.04, 16.94],
+        "gram_precompute_s": 46.27},
+    "faces_speedup_over_pgh_l1": "62.0 to 366.0 (Extended YaleB and AR, Table 6)",
+}
 
 
 def main():
@@ -255,6 +422,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the bf16-screened and fp8-ranked measurements")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal comparison on the face-like dictionary")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the one-solve ragged batch (4096 signals)")
     ap.add_argument("--learned-signals", type=int, default=16384, help="inference signals of the learned comparison")
     ap.add_argument("--train-signals", type=int, default=200000, help="BMPL-labelled training signals")
     ap.add_argument("--epochs", type=int, default=2)
@@ -370,39 +538,36 @@ def main():
                     "support_mean": float(np.mean(supp))},
     }
 
+    solver.close()
+    timed.close()
+    # oracle errors on a sample of this workload (the lambda each line used), and the CPU baseline
+    orc = OracleCache(P, range(min(args.cpu_sample, P.p)))
+    if not args.no_cpu and args.cpu_sample > 0:
+        lam_gpu = out["lambda"][orc.rows].cpu().numpy()
+        ref, secs, threads = orc.solve(lam_gpu)
+        result["cpu_baseline"] = {
+            "value": len(orc.rows) / secs, "unit": "signals/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(orc.rows)} signals of the same workload, FP64 C oracle, OpenMP one signal per "
+                      "thread, lambda as the GPU used it",
+            "host": host_info(),
+        }
+        result["parity_on_sample"] = orc.parity(out)
+
     if args.screen == "fp32" and not args.no_extra:
         # The same workload with the reduced-precision products: bfloat16 screening (certified band +
         # exact re-score) and e4m3 ranking (exact re-score of the top candidates, bfloat16 certification).
-        result["bf16_screened"] = screened_measurement(args, pk, torch, At, Bt, P, "bf16")
-        result["fp8_ranked"] = screened_measurement(args, pk, torch, At, Bt, P, "fp8")
-        result["q_route"] = q_route_measurement(args, pk, torch, At, Bt, P, tm)
-        result["smpl"] = smpl_measurement(args, pk, torch, At, Bt, P, out)
+        result["bf16_screened"] = screened_measurement(args, pk, torch, At, Bt, P, "bf16", orc)
+        result["fp8_ranked"] = screened_measurement(args, pk, torch, At, Bt, P, "fp8", orc)
+        result["q_route"] = q_route_measurement(args, pk, torch, At, Bt, P, tm, orc)
+        result["smpl"] = smpl_measurement(args, pk, torch, At, Bt, P, out, orc)
+
+    if not args.no_ragged:
+        result["ragged"] = ragged_measurement(args, pk, torch)
 
     if not args.no_learned:
         result["learned"] = learned_comparison(args, pk, torch)
 
-    if not args.no_cpu and args.cpu_sample > 0:
-        import oracle
-        from tests.parity import check_batch
-        q = min(args.cpu_sample, P.p)
-        rows = list(range(q))
-        lam_gpu = out["lambda"].cpu().numpy()
-        A64 = P.At.astype(np.float64)
-        lam_or = P.lambda_rel * np.abs(A64 @ P.Bt[rows].astype(np.float64).T).max(axis=0)
-        threads = min(oracle.max_threads(), q)
-        c0 = time.perf_counter()
-        ref = oracle.solve(P.At, P.Bt[rows], lam_or, P.rho, nthreads=threads)
-        c1 = time.perf_counter()
-        errs = check_batch(P.At, P.Bt, lam_or, out, ref, rows=range(q), gpu_rows=rows)
-        result["cpu_baseline"] = {
-            "value": q / (c1 - c0), "unit": "signals/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {q} signals of the same workload, FP64 C oracle, OpenMP one signal per thread",
-        }
-        result["parity_on_sample"] = {
-            "signals": q, "max_rel_obj": float(max(e["rel_obj"] for e in errs)),
-            "max_rel_x": float(max(e["rel_x"] for e in errs)),
-            "max_rel_lambda": float(np.max(np.abs(lam_gpu[rows] - lam_or) / lam_or)),
-        }
+    result["paper_context"] = PAPER_CONTEXT
     print(json.dumps(result), flush=True)
 
 
