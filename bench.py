@@ -163,6 +163,7 @@ def instrumented(pk, torch, At, P, screen, shapes, fn_solve, rho=None, **kw):
     ach = tb["corr_flops"] / (tb["corr_ms"] * 1e-3) / 1e12 if tb["corr_ms"] > 0 else 0.0
     return {"main_product": {"dtype": screen, "achieved_tflops": ach, "peak_tflops": PEAK_TFLOPS[screen],
                              "frac": ach / PEAK_TFLOPS[screen],
+                             "roofline_frac": tb["corr_roof_ms"] / tb["corr_ms"] if tb["corr_ms"] > 0 else 0.0,
                              "avg_launch_ms": tb["corr_ms"] / max(1, tb["corr_launches"]),
                              "launches": tb["corr_launches"]},
             "kernel_ms_per_step": {k: tb[k] for k in ("corr_ms", "select_ms", "solve_ms", "other_ms", "wall_ms")}}
@@ -522,6 +523,7 @@ def main():
             "avg_launch_ms": corr_avg_s * 1e3,
             "launches": tm["corr_launches"],
             "algorithmic_gflop_per_step": tm["corr_flops"] / args.steps / 1e9,
+            "per_launch_roofline_frac": tm["corr_roof_ms"] / tm["corr_ms"] if tm["corr_ms"] > 0 else 0.0,
         },
         "timed_run_ms_per_step": (t3 - t2) / args.steps * 1e3,
         "kernel_ms_per_step": {k: tm[k] / args.steps for k in ("corr_ms", "select_ms", "solve_ms",

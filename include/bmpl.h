@@ -95,8 +95,11 @@ typedef enum {
 /* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning), signals x atoms (waves of
  * 64 lanes, each computing the sub-tile in parentheses): 0 128x128 (64x64), 1 256x256 (64x64, 16 waves),
  * 2 256x128 (64x64), 3 64x128 (32x64), 4 32x64 (32x32), 5 64x64 (32x32), 6 256x256 (128x128, 4 waves),
- * 7 256x256 (128x64, 8 waves). */
-#define BMPL_CORR_SHAPES 8
+ * 7 256x256 (128x64, 8 waves); bfloat16 screening only (the dictionary's fragments read from global
+ * memory in the matrix instruction's order, the residual tile through LDS): 8 256x256 (128x64, 8 waves),
+ * 9 128x256 (64x64, 8 waves), 10 256x128 (128x64, 4 waves).  A shape a precision lacks is rejected by
+ * bmpl_set_tuning and not timed by bmpl_autotune. */
+#define BMPL_CORR_SHAPES 11
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
  * precomputed Q of Section III, Eq. (12)) when it is at most this large. */
@@ -296,8 +299,12 @@ bmpl_status bmpl_gram_table(const bmpl_ctx* c, const double** Q_dev, int64_t* ld
  * with HIP events on the solve's stream when the context was created with
  * BMPL_FLAG_TIMING (all zero otherwise).  corr_flops counts the algorithmic
  * 2 * m * n * p_running flops of every correlation launch (no padding);
- * corr_bytes the algorithmic bytes 4 * (m * n + n * p_running + m * p_running)
- * (dictionary and residuals read once, correlations written once).  Times are
+ * corr_bytes the algorithmic bytes e * (m * n + n * p_running) + 4 * m * p_running
+ * (dictionary and residuals read once in the product's precision, e = 4, 2 or 1 bytes, correlations
+ * written once in float32); corr_roof_ms the sum over those launches of their roofline time on MI355X,
+ * max(flops / matrix peak of the precision (157.3 / 2500 / 5000 TFLOP/s), bytes / 8 TB/s), so
+ * corr_roof_ms / corr_ms is the achieved fraction of the roofline, HBM-bound launches (few running
+ * signals) included.  Times are
  * milliseconds.  With timing on, bmpl_solve synchronises its stream before
  * returning.
  */
@@ -319,6 +326,7 @@ typedef struct {
     int64_t factor_appends;     /* Cholesky row appends (including re-appends after drops) */
     int64_t factor_drops;       /* support positions removed at a zero crossing */
     int64_t sign_fixed_solves;  /* sign-fixed minimiser evaluations */
+    double corr_roof_ms;        /* roofline time of the correlation launches (see above) */
 } bmpl_timing;
 
 /* Copy the accumulated timing into *t.  Errors: BMPL_E_INVALID for NULL. */

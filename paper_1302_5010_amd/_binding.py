@@ -39,7 +39,8 @@ class Timing(ctypes.Structure):
                 ("solve_launches", ctypes.c_int64), ("residual_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
                 ("wall_ms", ctypes.c_double), ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
                 ("solve_phase_us", ctypes.c_double * 6), ("factor_appends", ctypes.c_int64),
-                ("factor_drops", ctypes.c_int64), ("sign_fixed_solves", ctypes.c_int64)]
+                ("factor_drops", ctypes.c_int64), ("sign_fixed_solves", ctypes.c_int64),
+                ("corr_roof_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -53,7 +54,7 @@ BMPL_FLAG_GRAPH = 4
 BMPL_FLAG_SINGLE_APPEND = 8
 BMPL_FLAG_PHASES = 16
 BMPL_FLAG_Q_ROUTE = 32
-CORR_SHAPES = 8        # BMPL_CORR_SHAPES
+CORR_SHAPES = 11       # BMPL_CORR_SHAPES
 
 
 class _Result(ctypes.Structure):

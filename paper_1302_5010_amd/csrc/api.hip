@@ -76,6 +76,7 @@ struct bmpl_ctx {
     float* At = nullptr;          // [m][kpad] float32 dictionary, atom-major
     double* Q = nullptr;          // [m][m] float64 Gram table A^T A, or null
     uint16_t* A16 = nullptr;      // [m + 1][kpad] bfloat16 dictionary (screening), row m zero
+    uint16_t* A16p = nullptr;     // the same in the matrix instruction's fragment order (packed_bf16_elems)
     uint8_t* A8 = nullptr;        // [m + 1][kpad] e4m3 dictionary (FP8 ranking), row m zero
     float* ascale8 = nullptr;     // [m + 1] power-of-two scale per e4m3 atom
     int* cand8 = nullptr;         // [p_cap][CAND8] e4m3-ranked candidates
@@ -134,7 +135,7 @@ struct bmpl_ctx {
     bmpl_timing timing{};
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    struct Span { size_t a, b; int kind; double flops, bytes; };
+    struct Span { size_t a, b; int kind; double flops, bytes, roof_ms; };
     std::vector<Span> spans;
     uint64_t* phase_dev = nullptr;     // [9] solve-kernel phase ticks and counters
     int wall_khz = 0;
@@ -178,9 +179,9 @@ size_t mark(bmpl_ctx* c, hipStream_t s)
     return i;
 }
 
-void span(bmpl_ctx* c, size_t a, size_t b, int kind, double flops = 0.0, double bytes = 0.0)
+void span(bmpl_ctx* c, size_t a, size_t b, int kind, double flops = 0.0, double bytes = 0.0, double roof_ms = 0.0)
 {
-    if (a != (size_t)-1 && b != (size_t)-1) c->spans.push_back({a, b, kind, flops, bytes});
+    if (a != (size_t)-1 && b != (size_t)-1) c->spans.push_back({a, b, kind, flops, bytes, roof_ms});
 }
 
 // Fold the recorded spans of one solve into the totals (the stream must be idle).
@@ -193,6 +194,7 @@ void fold_timing(bmpl_ctx* c, size_t first, size_t last)
         case K_CORR:
             c->timing.corr_ms += ms; c->timing.corr_launches++;
             c->timing.corr_flops += sp.flops; c->timing.corr_bytes += sp.bytes;
+            c->timing.corr_roof_ms += sp.roof_ms;
             break;
         case K_SELECT: c->timing.select_ms += ms; c->timing.select_launches++; break;
         case K_SOLVE: c->timing.solve_ms += ms; c->timing.solve_launches++; break;
@@ -523,6 +525,8 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         e = dalloc(&c->A16, (size_t)(m + 1) * c->kpad);
         if (e == hipSuccess) e = hipMemsetAsync(c->A16, 0, (size_t)(m + 1) * c->kpad * sizeof(uint16_t), s);
         if (e == hipSuccess) e = launch_to_bf16(c->At, c->kpad, c->A16, c->kpad, m, c->kpad, s);
+        if (e == hipSuccess) e = dalloc(&c->A16p, packed_bf16_elems(m, c->kpad));
+        if (e == hipSuccess) e = launch_pack_bf16(c->A16, c->kpad, m, c->kpad, c->A16p, s);
         if (e == hipSuccess) e = dalloc(&norms, (size_t)3 * m);
         if (e == hipSuccess) e = launch_atom_norms(c->At, c->kpad, c->kpad, norms, m, s);
         std::vector<float> hn((size_t)3 * m);
@@ -609,6 +613,7 @@ bmpl_status bmpl_destroy(bmpl_ctx* c)
     dfree(c->At);
     dfree(c->Q);
     dfree(c->A16);
+    dfree(c->A16p);
     dfree(c->A8);
     dfree(c->ascale8);
     dfree(c->diag16);
@@ -662,7 +667,7 @@ bmpl_status bmpl_correlate(bmpl_ctx* c, const float* R_dev, int64_t ldr, int32_t
         dfree(c->diag16);
         HIPC(dalloc(&c->diag16, (size_t)(p + 1) * c->kpad));
         HIPC(launch_to_bf16(c->diagR, c->kpad, c->diag16, c->kpad, p + 1, c->kpad, s));
-        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->kpad, c->m, c->kpad, c->diag16, c->kpad, nullptr,
+        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->A16p, c->kpad, c->m, c->kpad, c->diag16, c->kpad, nullptr,
                                    nullptr, p, G_dev, ldg, p, 0, 1 << 30, s));
         HIPC(hipStreamSynchronize(s));
         return BMPL_OK;
@@ -704,7 +709,7 @@ bmpl_status bmpl_correlate_noalloc(bmpl_ctx* c, const float* R_dev, int64_t ldr,
     if (c->A16) {
         uint16_t* r16 = reinterpret_cast<uint16_t*>(c->scratch + o16);
         HIPC(launch_to_bf16(stage, c->kpad, r16, c->kpad, p + 1, c->kpad, s));
-        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->kpad, c->m, c->kpad, r16, c->kpad, nullptr, nullptr,
+        HIPC(launch_corr_gemm_bf16(c->corr_variant(p), c->A16, c->A16p, c->kpad, c->m, c->kpad, r16, c->kpad, nullptr, nullptr,
                                    p, G_dev, ldg, p, 0, 1 << 30, s));
         return BMPL_OK;
     }
@@ -829,7 +834,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
                     return launch_corr_gemm_fp8(shape, c->A8, c->kpad, c->m, c->kpad, w.R8, c->kpad, lst, cnt, grid,
                                                 c->Gc, c->ldg, c->p_cap, lo, hi, c->ascale8, w.rscale8, q);
                 if (prec == 1)
-                    return launch_corr_gemm_bf16(shape, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, lst, cnt,
+                    return launch_corr_gemm_bf16(shape, c->A16, c->A16p, c->kpad, c->m, c->kpad, w.R16, c->kpad, lst, cnt,
                                                  grid, c->Gc, c->ldg, c->p_cap, lo, hi, q);
                 return launch_corr_gemm_f32(shape, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, lst, cnt, grid,
                                             c->Gc, c->ldg, c->p_cap, lo, hi, q);
@@ -860,8 +865,14 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         if (ev) {
             const double mm = c->m, nn = c->n, pp = n_grid;
             const size_t e1 = mark(c, q);
+            // algorithmic work of this launch: operands read once in their precision, correlations written
+            // once in float32; its roofline time on MI355X (matrix peak of the precision, 8 TB/s HBM)
+            const double eb = fp8 ? 1.0 : (c->A16 ? 2.0 : 4.0);
+            const double peak = fp8 ? 5.0e15 : (c->A16 ? 2.5e15 : 157.3e12);
+            const double fl = 2.0 * mm * nn * pp, by = eb * (mm * nn + nn * pp) + 4.0 * mm * pp;
+            const double roof = std::max(fl / peak, by / 8.0e12) * 1e3;
             // the Q-route's work depends on the supports: its time is kept, its flops are not counted
-            span(c, e0, e1, K_CORR, qr ? 0.0 : 2.0 * mm * nn * pp, qr ? 0.0 : 4.0 * (mm * nn + nn * pp + mm * pp));
+            span(c, e0, e1, K_CORR, qr ? 0.0 : fl, qr ? 0.0 : by, qr ? 0.0 : roof);
             e0 = e1;
         }
         // certified bfloat16 screening of a list: band test, candidates, exact re-score and selection
@@ -1147,7 +1158,7 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
             return launch_corr_gemm_fp8(v, c->A8, c->kpad, c->m, c->kpad, w.R8, c->kpad, nullptr, nullptr, nb,
                                         c->Gc, c->ldg, c->p_cap, 0, 1 << 30, c->ascale8, w.rscale8, s);
         if (c->A16)
-            return launch_corr_gemm_bf16(v, c->A16, c->kpad, c->m, c->kpad, w.R16, c->kpad, nullptr, nullptr, nb,
+            return launch_corr_gemm_bf16(v, c->A16, c->A16p, c->kpad, c->m, c->kpad, w.R16, c->kpad, nullptr, nullptr, nb,
                                          c->Gc, c->ldg, c->p_cap, 0, 1 << 30, s);
         return launch_corr_gemm_f32(v, c->At, c->kpad, c->m, c->kpad, w.R, c->kpad, nullptr, nullptr, nb, c->Gc,
                                     c->ldg, c->p_cap, 0, 1 << 30, s);
@@ -1190,9 +1201,10 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
 bmpl_status bmpl_set_tuning(bmpl_ctx* c, const int32_t* shapes)
 {
     if (!c || !shapes) return fail(BMPL_E_INVALID, "bmpl_set_tuning: NULL argument");
+    const int nvar = (c->A16 && !c->A8) ? CORR_VARIANTS : 8;   // shapes 8.. exist for bfloat16 only
     for (int b = 0; b < 3; ++b)
-        if (shapes[b] < 0 || shapes[b] >= CORR_VARIANTS)
-            return fail(BMPL_E_INVALID, "bmpl_set_tuning: shape %d out of range", shapes[b]);
+        if (shapes[b] < 0 || shapes[b] >= nvar)
+            return fail(BMPL_E_INVALID, "bmpl_set_tuning: shape %d out of range for this precision", shapes[b]);
     for (int b = 0; b < 3; ++b) c->corr_shape[b] = shapes[b];
     return BMPL_OK;
 }

@@ -126,7 +126,7 @@ struct Workspace {
 // act == nullptr means the identity map.  If n_act_dev != nullptr the active count is
 // read on the device and `p_grid` only sizes the grid.
 // `variant` selects the tile shape (0..7, see corr_shape_name).
-constexpr int CORR_VARIANTS = 8;   // == BMPL_CORR_SHAPES
+constexpr int CORR_VARIANTS = 11;  // == BMPL_CORR_SHAPES (8..10: bfloat16 only)
 const char* corr_shape_name(int variant);
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,
@@ -137,8 +137,12 @@ hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m
 hipError_t launch_gram_table(const float* At, int64_t lda, int m, int kpad, double* Q, int64_t ldq,
                              hipStream_t stream);
 
-// The same product with bfloat16 operands (raw 16-bit storage), float32 accumulation.
-hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, int m, int kpad,
+// The same product with bfloat16 operands (raw 16-bit storage), float32 accumulation.  Variants 8 and
+// up read the dictionary from Apk, its copy in the matrix instruction's fragment order
+// (launch_pack_bf16, packed_bf16_elems uint16 values); the others from At.
+size_t packed_bf16_elems(int m, int kpad);
+hipError_t launch_pack_bf16(const uint16_t* A16, int64_t lda, int m, int kpad, uint16_t* Apk, hipStream_t stream);
+hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, const uint16_t* Apk, int64_t lda, int m, int kpad,
                                  const uint16_t* Rbuf, int64_t ldr, const int* act,
                                  const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                  int n_lo, int n_hi, hipStream_t stream);

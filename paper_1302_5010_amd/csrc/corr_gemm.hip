@@ -18,6 +18,8 @@
 // number of running signals (autotuned, see bmpl_autotune).  The large-wave shapes
 // (128 x 128 and 64 x 128 per wave) issue more matrix instructions per LDS fragment
 // read, which the short bfloat16 and e4m3 instructions need.
+#include <algorithm>
+
 #include "bmpl_internal.h"
 #include "gemm_tile.h"
 
@@ -106,6 +108,170 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     }
 }
 
+// ---------------------------------------------------------------------------------------------------
+// bfloat16 product with the dictionary operand read straight from global memory into registers.
+//
+// The dictionary is fixed for a context, so its bfloat16 copy is also stored in the matrix
+// instruction's fragment order (pack_bf16_fragments_kernel): for a block of 32 atoms and a chunk of 16
+// k, the 64 lanes' 16-byte B fragments are one contiguous kilobyte (lane l: atom 32 jb + l % 32,
+// k = 16 c + 8 (l / 32) .. + 8).  A wave loads its fragments with fully coalesced 16-byte loads, a
+// whole stage (four chunks) ahead, and only the residual tile goes through LDS; this removes the
+// dictionary's LDS stores and fragment reads, which bound the all-LDS loop for 16-bit operands.
+// Atoms are padded to a multiple of 256 with zero fragments, so no load is predicated.
+// ---------------------------------------------------------------------------------------------------
+constexpr int PACK_ATOMS = 256;   // atom padding of the packed copy
+
+__global__ __launch_bounds__(256) void pack_bf16_fragments_kernel(const uint16_t* __restrict__ A16, int64_t lda,
+                                                                  int m, int kpad, uint4* __restrict__ Apk,
+                                                                  int m_pad)
+{
+    const int nkc = kpad / 16;
+    const int64_t total = (int64_t)(m_pad / 32) * nkc * 64;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int lane = (int)(e & 63);
+        const int64_t fc = e >> 6;             // fragment index = jb * nkc + c
+        const int c = (int)(fc % nkc);
+        const int jb = (int)(fc / nkc);
+        const int atom = 32 * jb + (lane & 31);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (atom < m) v = *reinterpret_cast<const uint4*>(A16 + (int64_t)atom * lda + 16 * c + 8 * (lane >> 5));
+        Apk[e] = v;
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gemm_direct_kernel(
+    const uint4* __restrict__ Apk, int m, int kpad, const __bf16* __restrict__ Rbuf, int64_t ldr,
+    const int* __restrict__ act, const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G,
+    int64_t ldg, int tiles_n, int zero_row, int n_lo, int n_hi)
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    constexpr int TI = S::TI, TJ = S::TJ;
+    constexpr int LR = BM * 8 / S::THREADS;            // 16-byte residual loads per thread and stage
+    static_assert(LR * S::THREADS == BM * 8, "residual staging");
+    const int n_act = n_act_dev ? *n_act_dev : p_grid;
+    if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
+    const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
+    const int tiles_m = (p_grid + BM - 1) / BM;
+    const int tm = tile % tiles_m;
+    const int tn = tile / tiles_m;
+    if (tn >= tiles_n) return;
+    const int sig0 = tm * BM;
+    const int atom0 = tn * BN;
+    if (sig0 >= n_act) return;
+
+    __shared__ __attribute__((aligned(16))) char ldsR[2][BM * TILE_LDS_ROW];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int c4 = tile_c4(tid);
+    const int r0 = tile_r0(tid);
+    int64_t oR[LR];
+#pragma unroll
+    for (int q = 0; q < LR; ++q) {
+        const int a = sig0 + r0 + S::RSTEP * q;
+        const int sg = a < n_act ? (act ? act[a] : a) : zero_row;
+        oR[q] = (int64_t)sg * ldr + 8 * c4;
+    }
+    const int ws = (wave % S::WAVES_M) * WM;
+    const int wa = (wave / S::WAVES_M) * WN;
+    const int l32 = lane & 31;
+    const int h = lane >> 5;
+    const int nkc = kpad / 16;
+    const uint4* aP[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) aP[j] = Apk + ((int64_t)((atom0 + wa) / 32 + j) * nkc) * 64 + lane;
+
+    floatx16 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    float4 gR[LR];
+    uint4 aC[4][TJ], aN[4][TJ];
+#pragma unroll
+    for (int q = 0; q < LR; ++q) gR[q] = *reinterpret_cast<const float4*>(Rbuf + oR[q]);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) aC[kb][j] = aP[j][64 * kb];
+#pragma unroll
+    for (int q = 0; q < LR; ++q)
+        *reinterpret_cast<float4*>(&ldsR[0][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gR[q];
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kpad; k0 += 64) {
+        // next stage: residual slice into registers, dictionary fragments (the last stage re-reads itself)
+        const int kn = k0 + 64 < kpad ? k0 + 64 : k0;
+        const int cn = kn / 16;
+#pragma unroll
+        for (int q = 0; q < LR; ++q) gR[q] = *reinterpret_cast<const float4*>(Rbuf + oR[q] + kn);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) aN[kb][j] = aP[j][64 * (cn + kb)];
+        asm volatile("" ::: "memory");
+        const char* cR = ldsR[cur];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            float4 fx[TI];
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+                fx[i] = *reinterpret_cast<const float4*>(&cR[(ws + 32 * i + l32) * TILE_LDS_ROW + kb * 32 + 16 * h]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fx[i]),
+                                                                       __builtin_bit_cast(bf16x8, aC[kb][j]),
+                                                                       acc[i][j], 0, 0, 0);
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < LR; ++q)
+            *reinterpret_cast<float4*>(&ldsR[cur ^ 1][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gR[q];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) aC[kb][j] = aN[kb][j];
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int atom = atom0 + wa + 32 * j + l32;
+            if (atom >= m) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r];
+            }
+        }
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_direct(const uint16_t* Apk, int m, int kpad, const uint16_t* Rbuf, int64_t ldr, const int* act,
+                         const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row, int n_lo, int n_hi,
+                         hipStream_t stream)
+{
+    static_assert(PACK_ATOMS % BN == 0, "atom tiles must lie inside the packed padding");
+    const int tiles_m = (p_grid + BM - 1) / BM;
+    const int tiles_n = (m + BN - 1) / BN;
+    const int64_t nwg = (int64_t)tiles_m * tiles_n;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((corr_gemm_direct_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg),
+                       dim3(TileShape<BM, BN, WM, WN>::THREADS), 0, stream, reinterpret_cast<const uint4*>(Apk), m,
+                       kpad, reinterpret_cast<const __bf16*>(Rbuf), ldr, act, n_act_dev, p_grid, G, ldg, tiles_n,
+                       zero_row, n_lo, n_hi);
+    return hipGetLastError();
+}
+
 template <class E, int BM, int BN, int WM, int WN>
 hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                         const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
@@ -147,6 +313,9 @@ hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad
 const char* corr_shape_name(int v)
 {
     switch (v) {
+    case 8: return "256x256 (8 waves of 128x64), dictionary fragments from global memory";
+    case 9: return "128x256 (8 waves of 64x64), dictionary fragments from global memory";
+    case 10: return "256x128 (4 waves of 128x64), dictionary fragments from global memory";
     case 0: return "128x128 (4 waves of 64x64)";
     case 1: return "256x256 (16 waves of 64x64)";
     case 2: return "256x128 (8 waves of 64x64)";
@@ -178,11 +347,37 @@ hipError_t launch_corr_gemm_fp8(int variant, const uint8_t* A8, int64_t lda, int
                                    n_lo, n_hi, stream, ascale, rscale);
 }
 
-hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, int64_t lda, int m, int kpad,
+size_t packed_bf16_elems(int m, int kpad)
+{
+    return (size_t)((m + PACK_ATOMS - 1) / PACK_ATOMS * PACK_ATOMS) * (size_t)kpad;
+}
+
+hipError_t launch_pack_bf16(const uint16_t* A16, int64_t lda, int m, int kpad, uint16_t* Apk, hipStream_t stream)
+{
+    if (kpad % 64) return hipErrorInvalidValue;
+    const int m_pad = (m + PACK_ATOMS - 1) / PACK_ATOMS * PACK_ATOMS;
+    const int64_t total = (int64_t)(m_pad / 32) * (kpad / 16) * 64;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_bf16_fragments_kernel, dim3(grid), dim3(256), 0, stream, A16, lda, m, kpad,
+                       reinterpret_cast<uint4*>(Apk), m_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, const uint16_t* Apk, int64_t lda, int m, int kpad,
                                  const uint16_t* Rbuf, int64_t ldr, const int* act,
                                  const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                  int n_lo, int n_hi, hipStream_t stream)
 {
+    if (variant >= 8) {
+        if (!Apk || p_grid <= 0 || m <= 0) return Apk ? hipSuccess : hipErrorInvalidValue;
+        if (kpad % 64) return hipErrorInvalidValue;
+        switch (variant) {
+        case 8: return launch_direct<256, 256, 128, 64>(Apk, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+        case 9: return launch_direct<128, 256, 64, 64>(Apk, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+        case 10: return launch_direct<256, 128, 128, 64>(Apk, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
     return launch_variant<__bf16>(variant, reinterpret_cast<const __bf16*>(At), lda, m, kpad,
                                   reinterpret_cast<const __bf16*>(Rbuf), ldr, act, n_act_dev, p_grid, G, ldg,
                                   zero_row, n_lo, n_hi, stream);

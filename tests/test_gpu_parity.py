@@ -61,18 +61,29 @@ def test_correlate_within_float32_bound(n, m, p):
 
 
 @pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
-@pytest.mark.parametrize("shape", range(8))
+@pytest.mark.parametrize("shape", range(11))
 def test_correlate_every_tile_shape(shape, screen):
+    """Every tile shape within the precision's bound, entry by entry, and bit-identical to shape 0 (every
+    shape feeds each output's accumulator the same k chunks in the same order; shapes 8-10, bfloat16
+    only, read the dictionary from its fragment-ordered copy)."""
     pk = _lib()
     rng = np.random.default_rng(shape)
     n, m = 160, 1500
     At = rng.standard_normal((m, n)).astype(np.float32)
     s = pk.Solver(to_dev(At), 0.1, screen=screen)
+    if shape >= 8 and screen != "bf16":
+        with pytest.raises(pk.BmplError):
+            s.set_tuning([shape, shape, shape])
+        return
+    s0 = pk.Solver(to_dev(At), 0.1, screen=screen)
+    s0.set_tuning([0, 0, 0])
     s.set_tuning([shape, shape, shape])
     A64 = At.astype(np.float64)
     for p in (1, 37, 600):                 # one row, a ragged tile, several tiles in the >= 512 bucket
         Rt = rng.standard_normal((p, n)).astype(np.float32)
-        G = s.correlate(to_dev(Rt)).cpu().numpy().astype(np.float64)
+        Gd = s.correlate(to_dev(Rt))
+        assert torch.equal(Gd, s0.correlate(to_dev(Rt))), (shape, p)
+        G = Gd.cpu().numpy().astype(np.float64)
         R64 = Rt.astype(np.float64)
         if screen == "fp32":
             bound = 2 * n * 2.0 ** -24 * (np.abs(R64) @ np.abs(A64).T)
