@@ -416,6 +416,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cs2048x16384")
+    ap.add_argument("--signals", type=int, default=0,
+                    help="signals of the face-like workload (default: its 8192; 16384 is the learned comparison's)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="signals the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--screen", default="fp32", choices=("fp32", "bf16", "fp8"),
@@ -441,7 +443,7 @@ def main():
     import paper_1302_5010_amd as pk
 
     gen = bi.WORKLOADS[args.workload]
-    P = gen()
+    P = gen(p=args.signals) if args.signals > 0 and args.workload == "face20000" else gen()
     dev = torch.device("cuda:0")
     At = torch.from_numpy(P.At).to(dev)
     Bt = torch.from_numpy(P.Bt).to(dev)

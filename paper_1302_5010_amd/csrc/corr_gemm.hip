@@ -38,8 +38,8 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
     const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
     const int tiles_m = (p_grid + BM - 1) / BM;
-    const int tm = tile % tiles_m;          // signal tile (signal tiles inner: an XCD's run shares atom rows)
-    const int tn = tile / tiles_m;          // atom tile
+    int tm, tn;                             // signal tile, atom tile (grouped order, see grouped_tile)
+    grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
     if (tn >= tiles_n) return;
     const int sig0 = tm * BM;
     const int atom0 = tn * BN;
@@ -153,8 +153,8 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
     const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
     const int tiles_m = (p_grid + BM - 1) / BM;
-    const int tm = tile % tiles_m;
-    const int tn = tile / tiles_m;
+    int tm, tn;
+    grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
     if (tn >= tiles_n) return;
     const int sig0 = tm * BM;
     const int atom0 = tn * BN;

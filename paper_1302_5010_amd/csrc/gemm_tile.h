@@ -196,4 +196,19 @@ __device__ __forceinline__ int xcd_tile_index(int wid, int nwg)
     return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
 }
 
+// Grouped tile order: consecutive tile indices walk GM tiles along the first dimension (signals / rows
+// of X), then the next tile along the second (atoms / rows of W).  The workgroups an XCD runs at the
+// same time then cover a GM x (concurrent / GM) block of tiles, so both operands' tiles are shared in
+// that XCD's L2, instead of every workgroup streaming its own X tile when the X operand is large.
+template <int GM>
+__device__ __forceinline__ void grouped_tile(int tile, int tiles_m, int tiles_n, int& tm, int& tn)
+{
+    const int group = tile / (GM * tiles_n);
+    const int first = group * GM;
+    const int gm = tiles_m - first < GM ? tiles_m - first : GM;
+    const int in = tile - group * GM * tiles_n;
+    tm = first + in % gm;
+    tn = in / gm;
+}
+
 }  // namespace bmpl

@@ -73,8 +73,8 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void mlp_gemm
 {
     using S = TileShape<BM, BN, WM, WN>;
     const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
-    const int tm = tile % tiles_m;           // X-row tiles inner: an XCD's run shares W rows
-    const int tn = tile / tiles_m;
+    int tm, tn;                              // grouped order: an XCD's concurrent tiles share X and W rows
+    grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
     if (tn >= tiles_n) return;
     const int row0 = tm * BM, col0 = tn * BN;
 
