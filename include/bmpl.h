@@ -327,6 +327,9 @@ typedef struct {
     int64_t factor_drops;       /* support positions removed at a zero crossing */
     int64_t sign_fixed_solves;  /* sign-fixed minimiser evaluations */
     double corr_roof_ms;        /* roofline time of the correlation launches (see above) */
+    double solve_step_us[3];    /* with BMPL_FLAG_PHASES: time inside the active-set iterations spent in
+                                   [0] factor downdates (drops), [1] sign-fixed minimiser evaluations,
+                                   [2] gradients outside S, summed over workgroups (microseconds) */
 } bmpl_timing;
 
 /* Copy the accumulated timing into *t.  Errors: BMPL_E_INVALID for NULL. */

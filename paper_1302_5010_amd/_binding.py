@@ -40,11 +40,12 @@ class Timing(ctypes.Structure):
                 ("wall_ms", ctypes.c_double), ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
                 ("solve_phase_us", ctypes.c_double * 6), ("factor_appends", ctypes.c_int64),
                 ("factor_drops", ctypes.c_int64), ("sign_fixed_solves", ctypes.c_int64),
-                ("corr_roof_ms", ctypes.c_double)]
+                ("corr_roof_ms", ctypes.c_double), ("solve_step_us", ctypes.c_double * 3)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["solve_phase_us"] = list(self.solve_phase_us)
+        d["solve_step_us"] = list(self.solve_step_us)
         return d
 
 

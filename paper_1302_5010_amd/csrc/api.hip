@@ -137,7 +137,7 @@ struct bmpl_ctx {
     size_t ev_used = 0;
     struct Span { size_t a, b; int kind; double flops, bytes, roof_ms; };
     std::vector<Span> spans;
-    uint64_t* phase_dev = nullptr;     // [9] solve-kernel phase ticks and counters
+    uint64_t* phase_dev = nullptr;     // [12] solve-kernel phase ticks and counters
     int wall_khz = 0;
 
     // graph capture of iteration segments (BMPL_FLAG_GRAPH)
@@ -780,8 +780,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     c->ev_used = 0;
     const bool phases = tm && (c->opt.flags & BMPL_FLAG_PHASES);
     if (phases && !c->phase_dev) {
-        HIPC(dalloc(&c->phase_dev, 9));
-        HIPC(hipMemsetAsync(c->phase_dev, 0, 9 * sizeof(uint64_t), s));
+        HIPC(dalloc(&c->phase_dev, 12));
+        HIPC(hipMemsetAsync(c->phase_dev, 0, 12 * sizeof(uint64_t), s));
         HIPC(hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, c->device));
     }
     const size_t ev_first = tm ? mark(c, s) : (size_t)-1;
@@ -1000,7 +1000,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.phase = phases ? c->phase_dev : nullptr;
         // the exploratory pass of SMPL briefly holds omega rho new slots: the full capacity then
         so.kv = std::min(max_active, std::max(1, ibound));
-        const size_t vec_bytes = vec_area_bytes(so.kv);
+        const int kp = std::max(std::min(so.kv, c->n), so.smpl_keep > 0 ? rho : 1);   // |S| <= n
+        so.kp = kp;
+        const size_t vec_bytes = vec_area_bytes(so.kv, kp);
         const size_t stage = c->Q ? 0 : GRAM_STAGE_BYTES;   // direct Gram staging, only without the table
         so.vec_lds = vec_bytes + stage <= c->lds_dyn_max ? 1 : 0;
         so.kl = std::min(kl, so.kv);
@@ -1009,8 +1011,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         size_t lds = (so.rinv_lds ? rinv_bytes : 0) + (so.vec_lds ? vec_bytes : 0) + stage;
         // block appends pay off when the factor streams from global memory; with an LDS-resident
         // factor single appends are cheaper and keep the workgroup's LDS (and occupancy) smaller
-        so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(so.kv) <= c->lds_dyn_max) ? 1 : 0;
-        if (so.zs_lds) lds += block_scratch_bytes(so.kv);
+        so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(kp) <= c->lds_dyn_max) ? 1 : 0;
+        if (so.zs_lds) lds += block_scratch_bytes(kp);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
         GrowArgs ga{w, c->grow_list, c->n_grow, slack, max_active};
         hipLaunchKernelGGL(grow_kernel, dim3(std::min(n_grid, 512)), dim3(256), 0, q, ga);
@@ -1222,9 +1224,10 @@ bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t)
     if (!c || !t) return fail(BMPL_E_INVALID, "bmpl_get_timing: NULL argument");
     *t = c->timing;
     if (c->phase_dev && c->wall_khz > 0) {
-        uint64_t ticks[9];
+        uint64_t ticks[12];
         HIPC(hipMemcpy(ticks, c->phase_dev, sizeof ticks, hipMemcpyDeviceToHost));
         for (int i = 0; i < 6; ++i) t->solve_phase_us[i] = (double)ticks[i] * 1e3 / c->wall_khz;
+        for (int i = 0; i < 3; ++i) t->solve_step_us[i] = (double)ticks[9 + i] * 1e3 / c->wall_khz;
         t->factor_appends = (int64_t)ticks[6];
         t->factor_drops = (int64_t)ticks[7];
         t->sign_fixed_solves = (int64_t)ticks[8];
@@ -1236,7 +1239,7 @@ bmpl_status bmpl_reset_timing(bmpl_ctx* c)
 {
     if (!c) return fail(BMPL_E_INVALID, "bmpl_reset_timing: NULL context");
     c->timing = bmpl_timing{};
-    if (c->phase_dev) HIPC(hipMemset(c->phase_dev, 0, 9 * sizeof(uint64_t)));
+    if (c->phase_dev) HIPC(hipMemset(c->phase_dev, 0, 12 * sizeof(uint64_t)));
     return BMPL_OK;
 }
 

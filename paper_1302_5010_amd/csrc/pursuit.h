@@ -44,10 +44,11 @@ struct WarmArgs {
 // and the next stop test ends it.
 constexpr int ST_HALT = 1 << 20;
 
-// Atoms per block append of the inverse factor, and the LDS layout of the solve kernel's per-slot
-// vectors (x, c, w, z, x_new, g as float64; support order and atoms as int; theta and exclusion bytes).
+// Atoms per block append of the inverse factor, and the LDS layout of the solve kernel's vectors: by
+// slot (K of them: x, c, g as float64, atoms as int, theta and exclusion bytes) and by support position
+// (P = min(K, n) of them, since |S| <= n: w, z, x_new and the cached z as float64, support order as int).
 constexpr int SOLVE_JB = 8;
-__host__ __device__ inline size_t vec_area_bytes(int K) { return ((size_t)K * 58 + 15) / 16 * 16; }
+__host__ __device__ inline size_t vec_area_bytes(int K, int P) { return ((size_t)K * 30 + (size_t)P * 36 + 15) / 16 * 16; }
 __host__ __device__ inline size_t block_scratch_bytes(int K) { return (size_t)K * SOLVE_JB * 8; }
 constexpr size_t GRAM_STAGE_BYTES = 64 * 16 * 8;   // direct Gram rows' atom staging (only without the table)
 
@@ -61,7 +62,9 @@ struct SolveArgs {
     int rinv_lds;                   // inverse factor in LDS (capacity kl positions)
     int kl;
     int vec_lds;                    // per-slot vectors in LDS
-    int kv;                         // their stride: a bound on |I| during the launch
+    int kv;                         // their stride by slot: a bound on |I| during the launch
+    int kp;                         // by support position: >= min(kv, n) (and >= the candidates of an
+                                    // exploratory pass, whose scratch lists live there)
     int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
     int smpl_keep;                  // > 0: subspace exploratory matching keeps this many of the new atoms
     uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,

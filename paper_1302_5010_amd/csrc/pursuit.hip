@@ -341,34 +341,23 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
         for (int e = 0; e < JB; ++e) acc[e] = 0.0;
         if (i >= 0) {
             const double* Ri = v.R + tri(i);
-            int k = lane;
-            for (; k + 448 <= i; k += 512) {      // eight loads in flight per lane
+            for (int k = lane; k <= i; k += 512) {   // eight loads in flight per lane, the row's tail too
                 double r[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) r[q] = Ri[k + 64 * q];
+                for (int q = 0; q < 8; ++q) r[q] = k + 64 * q <= i ? Ri[k + 64 * q] : 0.0;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
+                    if (k + 64 * q > i) break;
                     const double* wk = zs + (k + 64 * q) * JB;
 #pragma unroll
                     for (int e = 0; e < JB; ++e) acc[e] += r[q] * wk[e];
                 }
             }
-            for (; k <= i; k += 64) {
-                const double r = Ri[k];
-                const double* wk = zs + k * JB;
-#pragma unroll
-                for (int e = 0; e < JB; ++e) acc[e] += r * wk[e];
-            }
-#pragma unroll
-            for (int e = 0; e < JB; ++e) acc[e] = wave_sum(acc[e]);
         }
+        static_assert(JB == 8, "the eight-way wave sum");
+        const double val = wave_sum8(acc);   // uniform per wave: every lane takes part
         __syncthreads();
-        if (i >= 0 && lane < JB) {
-            double val = 0.0;
-#pragma unroll
-            for (int e = 0; e < JB; ++e) val = lane == e ? acc[e] : val;
-            zs[i * JB + lane] = val;
-        }
+        if (i >= 0 && lane < JB) zs[i * JB + wave_sum8_index(lane)] = val;
     }
     __syncthreads();
     // 3. C = G(list, list) - Z^T Z, lower triangle
@@ -501,11 +490,77 @@ __device__ void append_list(Sig& v, int& nS, const int* list, int nv, const doub
 // writes (row j + 1) wait until every thread has read the old row j + 1.  The moved column's running
 // entries live in `cbuf` (s doubles of scratch, each entry owned by one thread), so the downdate needs
 // no per-thread arrays whatever |S| is.  The caller shifts the support order.
-__device__ void chol_drop(Sig& v, int s, int q, double* cbuf)
+//
+// zc (or null): the cached z = Rinv w of the sign-fixed solve (by position).  Rotating rows rotates z's
+// entries the same way (the moved column's w entry moves with it, so every row's product with w is
+// unchanged); thread 0 carries them along, and zc[s-1] receives the last (removed) row's value.  On
+// return cbuf[0..s-2] holds that last row's entries.
+//
+// Up to DROP_COLS * 256 positions, each thread keeps its columns' running entries in registers and
+// loads the next row's entries one iteration ahead, so the global factor's load latency overlaps the
+// barrier; the next row is only read, never written, during an iteration, and the barrier per row keeps
+// every read of a row before the iteration that writes it.  (The kernel capped at 128 registers uses a
+// narrower register window.)
+template <int DROP_COLS>
+__device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
 {
     const int tid = threadIdx.x;
+    if (s <= DROP_COLS * NT) {
+        double cv[DROP_COLS], nx[DROP_COLS];
+#pragma unroll
+        for (int t = 0; t < DROP_COLS; ++t) {
+            const int c = tid + NT * t;
+            cv[t] = c < q ? v.R[tri(q) + c] : 0.0;
+            nx[t] = (q + 1 < s && c <= q) ? v.R[tri(q + 1) + (c < q ? c : c + 1)] : 0.0;
+        }
+        double last = v.R[tri(q) + q];
+        double b = q + 1 < s ? v.R[tri(q + 1) + q] : 0.0;
+        double zcar = (zc && tid == 0) ? zc[q] : 0.0;
+        for (int j = q; j < s - 1; ++j) {
+            // prefetch row j + 2 (the next iteration's row), columns shifted past the moved one
+            double nn[DROP_COLS];
+            const bool more = j + 2 < s;
+            const double* r2 = v.R + tri(j + 2);
+#pragma unroll
+            for (int t = 0; t < DROP_COLS; ++t) {
+                const int c = tid + NT * t;
+                nn[t] = (more && c <= j + 1) ? r2[c < q ? c : c + 1] : 0.0;
+            }
+            const double bn = more ? r2[q] : 0.0;
+            const double r = hypot(last, b);
+            const double cs = r > 0.0 ? b / r : 1.0;
+            const double sn = r > 0.0 ? -last / r : 0.0;
+            double* out = v.R + tri(j);
+#pragma unroll
+            for (int t = 0; t < DROP_COLS; ++t) {
+                const int c = tid + NT * t;
+                if (c <= j) {                    // columns past j stay zero in the moved column
+                    out[c] = cs * cv[t] + sn * nx[t];
+                    cv[t] = -sn * cv[t] + cs * nx[t];
+                }
+                nx[t] = nn[t];
+            }
+            if (zc && tid == 0) {
+                const double zn = zc[j + 1];
+                zc[j] = cs * zcar + sn * zn;
+                zcar = -sn * zcar + cs * zn;
+            }
+            last = r;
+            b = bn;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < DROP_COLS; ++t) {
+            const int c = tid + NT * t;
+            if (c < s) cbuf[c] = cv[t];
+        }
+        if (zc && tid == 0) zc[s - 1] = zcar;
+        __syncthreads();
+        return;
+    }
     for (int c = tid; c < s; c += NT) cbuf[c] = c < q ? v.R[tri(q) + c] : 0.0;
     double last = v.R[tri(q) + q];
+    double zcar = (zc && tid == 0) ? zc[q] : 0.0;
     __syncthreads();
     for (int j = q; j < s - 1; ++j) {
         const double* nx = v.R + tri(j + 1);
@@ -520,9 +575,46 @@ __device__ void chol_drop(Sig& v, int s, int q, double* cbuf)
             out[c] = cs * cv + sn * nxt;
             cbuf[c] = -sn * cv + cs * nxt;
         }
+        if (zc && tid == 0) {
+            const double zn = zc[j + 1];
+            zc[j] = cs * zcar + sn * zn;
+            zcar = -sn * zcar + cs * zn;
+        }
         last = r;
         __syncthreads();
     }
+    if (zc && tid == 0) zc[s - 1] = zcar;
+    __syncthreads();
+}
+
+// The sign-fixed minimiser after support positions s0..s1-1 were appended to the factor, from the cached
+// z = Rinv w and x* = Rinv^T z of the positions before: the new factor is Rinv with rows s0..s1-1 added
+// (its earlier rows unchanged), and w only gains the entries of the new positions (a member's sign does
+// not change while it stays in S), so z gains the new rows' products with w and x* gains those rows'
+// contributions: O((s1 - s0) s1) work instead of two passes over the factor.  vw: scratch.
+__device__ void xstar_after_append(const Sig& v, int s0, int s1, double lam, double* vw, double* vzc, double* vx,
+                                   double* red)
+{
+    const int tid = threadIdx.x;
+    for (int k = tid; k < s1; k += NT) {
+        const int u = v.so[k];
+        vw[k] = v.c[u] - lam * (double)v.th[u];
+    }
+    __syncthreads();
+    for (int p = s0; p < s1; ++p) {
+        const double* Rp = v.R + tri(p);
+        double part = 0.0;
+        for (int k = tid; k <= p; k += NT) part += Rp[k] * vw[k];
+        const double zp = block_sum(part, red);
+        if (tid == 0) vzc[p] = zp;
+    }
+    __syncthreads();
+    for (int k = tid; k < s1; k += NT) {
+        double acc = k < s0 ? vx[k] : 0.0;
+        for (int p = k > s0 ? k : s0; p < s1; ++p) acc += v.R[tri(p) + k] * vzc[p];
+        vx[k] = acc;
+    }
+    __syncthreads();
 }
 
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
@@ -550,10 +642,13 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
 // g_u = c_u - G_uS x_S for the slots u < nI (all of them, or only those outside S
 // that may still enter it).  A row of 16 lanes takes two slots at a time and splits their support
 // entries (G is global, so a slot costs one round trip with its loads in flight rather than a chain of
-// |S| / 8), then sums each row by DPP moves inside the row.
+// |S| / 8), then sums each row by DPP moves inside the row.  (Reading the rows contiguously over all
+// slots of I against x by slot was measured slower on large active sets: |I| / |S| times the entries.)
+// DEPTH support entries per lane and slot are in flight at once (8 in the kernel without a register cap).
+template <int DEPTH>
 __device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outside_only)
 {
-    constexpr int GL = 16, NG = NT / GL, DEPTH = 4;
+    constexpr int GL = 16, NG = NT / GL;
     const int sub = threadIdx.x & (GL - 1), grp = threadIdx.x / GL;
     for (int u0 = grp; u0 < nI; u0 += 2 * NG) {
         const int u1 = u0 + NG;
@@ -1073,27 +1168,31 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         s.R = g_R;
     }
     double *vw, *vz, *vx, *vg;
+    double* vzc;   // cached z = Rinv w of the sign-fixed solve, by position (x* is in vx)
     int* vatom;
-    const int KV = a.kv;   // LDS vectors: stride KV >= |I| during this launch
+    const int KV = a.kv;                      // LDS vectors by slot: KV >= |I| during this launch
+    const int KP = a.kp;                      // by support position: |S| <= min(|I|, n) <= KP
     if (a.vec_lds) {
         double* d = reinterpret_cast<double*>(lp);
-        s.x = d; s.c = d + KV; vw = d + 2 * KV; vz = d + 3 * KV; vx = d + 4 * KV; vg = d + 5 * KV;
-        int* ip = reinterpret_cast<int*>(d + 6 * KV);
-        s.so = ip; vatom = ip + KV;
-        s.th = reinterpret_cast<signed char*>(ip + 2 * KV);
+        s.x = d; s.c = d + KV; vg = d + 2 * KV;
+        vw = d + 3 * KV; vz = vw + KP; vx = vz + KP; vzc = vx + KP;
+        int* ip = reinterpret_cast<int*>(vzc + KP);
+        s.so = ip; vatom = ip + KP;
+        s.th = reinterpret_cast<signed char*>(vatom + KV);
         s.ex = reinterpret_cast<unsigned char*>(s.th + KV);
     } else {
         double* d = hb.vs;
         s.x = g_x; s.c = g_c; s.th = g_th; s.ex = g_ex; s.so = g_so;
         vw = d; vz = d + K; vx = d + 2 * K; vg = d + 3 * K;
         vatom = reinterpret_cast<int*>(d + 4 * K);
+        vzc = d + 5 * K;
     }
     // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
-    double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV) : 0)) : nullptr;
+    double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV, KP) : 0)) : nullptr;
     // direct Gram staging (no table) after the vectors and the block scratch
     double* snew = a.Q ? nullptr
-                       : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV) : 0) +
-                                                   (a.zs_lds ? block_scratch_bytes(KV) : 0));
+                       : reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV, KP) : 0) +
+                                                   (a.zs_lds ? block_scratch_bytes(KP) : 0));
 
     // 1. Load the state, register the new slots.
     if (a.vec_lds) {
@@ -1136,6 +1235,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         }
     };
     phase_mark(0);
+    // time spent in one call of a step of the active-set loop, summed into phase slot `slot`
+    auto sub_ticks = [&](int slot, uint64_t t0) {
+        if (a.phase && tid == 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + slot), (unsigned long long)(wall_clock64() - t0));
+    };
 
     // 2. Gram rows of the new slots and c = A_J^T b, in float64.  With many new slots (a warm start)
     //    the Gram matrix is kept lazily from then on: a new slot's row only against the support
@@ -1236,9 +1340,14 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     // clean one; carried from one outer iteration to the next.
     int jadd = w.jadd[sig];
     jadd = jadd >= 1 && jadd <= JADD ? jadd : JADD;
+    // the sign-fixed minimiser x* (vx) and z = Rinv w (vzc) are computed in full once, then kept current
+    // through appends (xstar_after_append) and drops (rotated z, and x* from the removed row)
+    bool xs_ok = false;
 active_set:
     for (;;) {
-        grad_slots(s, nI, nS, vg, true);
+        const uint64_t tg = a.phase ? wall_clock64() : 0;
+        grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, true);
+        sub_ticks(11, tg);
         if (wave == 0) {    // violators outside S, in slot order
             int base = 0;
             for (int u0 = 0; u0 < nI && base < NT; u0 += 64) {
@@ -1316,6 +1425,7 @@ active_set:
             s.R = g_R;
             s.r_lds = false;
         }
+        const int nS_before = nS;
         if (nv == 0) {
             // nothing to append: the pruned problem on I_t is solved from u restricted to it
         } else if (zs) {
@@ -1332,11 +1442,21 @@ active_set:
                 chol_append(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
             }
         }
+        if (xs_ok && nS > nS_before) {
+            const uint64_t tsf = a.phase ? wall_clock64() : 0;
+            xstar_after_append(s, nS_before, nS, lam, vw, vzc, vx, red);
+            sub_ticks(10, tsf);
+        }
         // move toward the sign-fixed minimiser, dropping at zero crossings
         int dropped = 0;
         for (;;) {
             if (++steps > max_steps) { inexact = true; break; }
-            sign_fixed_solve(s, nS, lam, vw, vz, vx);
+            if (!xs_ok) {
+                const uint64_t tsf = a.phase ? wall_clock64() : 0;
+                sign_fixed_solve(s, nS, lam, vw, vzc, vx);
+                sub_ticks(10, tsf);
+                xs_ok = true;
+            }
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 8), 1ull);
             double alpha = 1.0;
             int q = -1;
@@ -1369,7 +1489,16 @@ active_set:
             }
             __syncthreads();
             // downdate the factor in place (vw is free scratch here); support positions past q move down
-            chol_drop(s, ns_old, q, vw);
+            const uint64_t td = a.phase ? wall_clock64() : 0;
+            chol_drop<BLOCK ? 8 : 2>(s, ns_old, q, vw, vzc);
+            // x* on S \ q: with the removed row b (vw) and its z entry zl, x*_new[k] = x*[k'] - b_k zl
+            // (k' the position before the shift)
+            {
+                const double zl = vzc[ns_old - 1];
+                for (int k = tid; k < ns_old - 1; k += NT) vz[k] = vx[k < q ? k : k + 1] - vw[k] * zl;
+                double* t = vx; vx = vz; vz = t;
+            }
+            sub_ticks(9, td);
             for (int k = q + 1 + tid; k < ns_old; k += NT) s.so[k - 1] = vatom[k];
             nS = ns_old - 1;
             __syncthreads();
@@ -1408,7 +1537,7 @@ active_set:
             if (u < nI0 || s_keep[u - nI0]) continue;
             for (int q = tid; q < nS; q += NT) vatom[q] = s.so[q];   // vatom is scratch after the Gram phase
             __syncthreads();
-            chol_drop(s, nS, k, vw);
+            chol_drop<BLOCK ? 8 : 2>(s, nS, k, vw, nullptr);
             for (int q = k + 1 + tid; q < nS; q += NT) s.so[q - 1] = vatom[q];
             --nS;
             __syncthreads();
@@ -1447,6 +1576,7 @@ active_set:
             }
             __syncthreads();
             resolve = true;
+            xs_ok = false;
             goto active_set;
         }
     }
@@ -1454,7 +1584,7 @@ active_set:
     phase_mark(2);
 
     // 4. Certificate on I (float64).
-    grad_slots(s, nI, nS, vg, false);
+    grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, false);
     double e = 0.0;
     for (int u = tid; u < nI; u += NT) {
         const double gu = vg[u];

@@ -98,6 +98,35 @@ __device__ inline float wave_max(float v)
     return fmaxf(read_lane(v, 0), read_lane(v, 32));
 }
 
+// Eight sums over the wave at once: a[e] summed over all 64 lanes for e = 0..7.  Each exchange halves
+// the values a lane carries (lane ^ 1 and lane ^ 2 by DPP, lane ^ 4 by a permute), then the lanes that
+// carry the same index are summed (lane ^ 8, ^ 16, ^ 32): 10 exchanges instead of 8 full reductions.
+// Lane l returns the sum for e = 4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1) (wave_sum8_index).
+__device__ inline int wave_sum8_index(int lane) { return 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1); }
+
+__device__ inline double wave_sum8(const double (&a)[8])
+{
+    const int lane = threadIdx.x & 63;
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1;
+    double s4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double recv = lane_move<DPP_XOR1>(b0 ? a[i] : a[i + 4]);
+        s4[i] = (b0 ? a[i + 4] : a[i]) + recv;
+    }
+    double s2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double recv = lane_move<DPP_XOR2>(b1 ? s4[i] : s4[i + 2]);
+        s2[i] = (b1 ? s4[i + 2] : s4[i]) + recv;
+    }
+    double s1 = (b2 ? s2[1] : s2[0]) + __shfl_xor(b2 ? s2[0] : s2[1], 4);
+    s1 += __shfl_xor(s1, 8);
+    s1 += lane_move<-1>(s1);
+    s1 += __shfl_xor(s1, 32);
+    return s1;
+}
+
 // Sum over groups of P consecutive lanes (P = 1, 2 or 4; the group's lanes active together).
 __device__ inline double group_sum(double v, int P)
 {
