@@ -36,8 +36,12 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     using S = TileShape<BM, BN, WM, WN>;
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
     if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
-    const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
-    const int tiles_m = (p_grid + BM - 1) / BM;
+    // Only the signal tiles that hold running signals are numbered (the grid is sized for p_grid, the
+    // count at capture time), so the working tiles are dealt evenly to the XCDs at every running count.
+    const int tiles_m = ((n_act < p_grid ? n_act : p_grid) + BM - 1) / BM;
+    const int nwg = tiles_m * tiles_n;
+    if ((int)blockIdx.x >= nwg) return;
+    const int tile = xcd_tile_index(blockIdx.x, nwg);
     int tm, tn;                             // signal tile, atom tile (grouped order, see grouped_tile)
     grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
     if (tn >= tiles_n) return;
@@ -151,8 +155,10 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     static_assert(LR * S::THREADS == BM * 8, "residual staging");
     const int n_act = n_act_dev ? *n_act_dev : p_grid;
     if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
-    const int tile = xcd_tile_index(blockIdx.x, gridDim.x);
-    const int tiles_m = (p_grid + BM - 1) / BM;
+    const int tiles_m = ((n_act < p_grid ? n_act : p_grid) + BM - 1) / BM;   // as in corr_gemm_kernel
+    const int nwg = tiles_m * tiles_n;
+    if ((int)blockIdx.x >= nwg) return;
+    const int tile = xcd_tile_index(blockIdx.x, nwg);
     int tm, tn;
     grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
     if (tn >= tiles_n) return;
