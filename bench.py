@@ -31,6 +31,9 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# Iteration caps of the face-like solves, by rho (each solve then runs as one captured graph with no host
+# read-back): above the batch's need (at most 6 outer iterations at rho = 10, a few dozen at rho = 1).
+FACE_MAX_OUTER = {10: 8, 1: 64}
 sys.path.insert(0, ROOT)
 
 from tests.parity import objective  # noqa: E402
@@ -176,13 +179,14 @@ def converged_count(pk, out) -> int:
 def screened_measurement(args, pk, torch, At, Bt, P, screen: str, orc: OracleCache) -> dict:
     """Throughput in graph mode, the instrumented kernel breakdown and the oracle errors of one screening
     precision."""
-    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=screen)
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, screen=screen,
+                  max_outer=args.max_outer)
     shapes = s.autotune(P.p)["shapes"]
     outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
     s.close()
     rec = {"value": converged_count(pk, outs[-1]) / dt, "unit": "signals/s", "ms_per_step": dt * 1e3,
            "converged_per_step": [converged_count(pk, o) for o in outs]}
-    rec.update(instrumented(pk, torch, At, P, screen, shapes, lambda st: st.solve(Bt)))
+    rec.update(instrumented(pk, torch, At, P, screen, shapes, lambda st: st.solve(Bt), max_outer=args.max_outer))
     if screen == "fp8":
         rec["main_product"]["note"] = "first pass (lambda rule) in bfloat16 for fp8"
     rec["parity_on_sample"] = orc.parity(outs[-1])
@@ -192,10 +196,12 @@ def screened_measurement(args, pk, torch, At, Bt, P, screen: str, orc: OracleCac
 def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma, orc: OracleCache) -> dict:
     """Section III's correlation (g = beta - Q_{:,S} x_S, float64, HBM-bound on Q's rows) in place of the
     MFMA product, same workload: throughput and the correlation time per step against the MFMA's."""
-    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, q_route=True)
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, q_route=True,
+                  max_outer=args.max_outer)
     outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
     s.close()
-    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, q_route=True)
+    st = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, q_route=True,
+                   max_outer=args.max_outer)
     st.solve(Bt)
     torch.cuda.synchronize()
     st.reset_timing()
@@ -216,7 +222,8 @@ def q_route_measurement(args, pk, torch, At, Bt, P, tm_mfma, orc: OracleCache) -
 def smpl_measurement(args, pk, torch, At, Bt, P, out_mpl, orc: OracleCache) -> dict:
     """Subspace exploratory matching (Algorithm 2, omega = 3) on the same workload: throughput and
     outer iterations against plain MPL's; errors against the oracle's SMPL (omega = 3)."""
-    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, omega=3)
+    s = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=True, omega=3,
+                  max_outer=args.max_outer)
     s.autotune(P.p)
     outs, dt = timed_steps(args, torch, lambda: s.solve(Bt))
     s.close()
@@ -302,19 +309,22 @@ def learned_comparison(args, pk, torch) -> dict:
         return o, r
 
     def solver(screen, rho):
-        s = pk.Solver(At, P.lambda_rel, mode="rel", rho=rho, kkt_tol=1e-4, graph=True, screen=screen)
+        s = pk.Solver(At, P.lambda_rel, mode="rel", rho=rho, kkt_tol=1e-4, graph=True, screen=screen,
+                      max_outer=FACE_MAX_OUTER[rho])
         return s, s.autotune(P.p)["shapes"]
 
     s32, shapes32 = solver("fp32", P.rho)
     out32, rec["plain_fp32"] = line(lambda: s32.solve(Bt))
-    rec["plain_fp32"].update(instrumented(pk, torch, At, P, "fp32", shapes32, lambda st: st.solve(Bt)))
+    rec["plain_fp32"].update(instrumented(pk, torch, At, P, "fp32", shapes32, lambda st: st.solve(Bt),
+                                          max_outer=FACE_MAX_OUTER[P.rho]))
     s32.close()
     f8, _ = solver("fp8", P.rho)
     _, rec["plain_fp8"] = line(lambda: f8.solve(Bt))
     f8.close()
     bf, shapes16 = solver("bf16", P.rho)
     outbf, rec["plain_bf16"] = line(lambda: bf.solve(Bt))
-    rec["plain_bf16"].update(instrumented(pk, torch, At, P, "bf16", shapes16, lambda st: st.solve(Bt)))
+    rec["plain_bf16"].update(instrumented(pk, torch, At, P, "bf16", shapes16, lambda st: st.solve(Bt),
+                                          max_outer=FACE_MAX_OUTER[P.rho]))
     # the face application: class-residual classification of the codes (synthetic classes)
     cls = torch.from_numpy(P.meta["class_of_atom"].astype(np.int32)).to(dev)
     labels, _ = bf.classify(Bt, outbf, cls)
@@ -365,7 +375,8 @@ def learned_comparison(args, pk, torch) -> dict:
                                           "speedup_learned_vs_plain_bf16": res[k]["speedup_learned_vs_plain_bf16"]}
                                  for k in res}
         prop = net.propose(Bt, best)
-        out.update(instrumented(pk, torch, At, P, "bf16", shapes, lambda st: st.solve(Bt, warm=prop), rho=rho))
+        out.update(instrumented(pk, torch, At, P, "bf16", shapes, lambda st: st.solve(Bt, warm=prop), rho=rho,
+                                max_outer=FACE_MAX_OUTER[rho]))
         return out
 
     rec["bf16_learned"] = learned_lines(bf, rec["plain_bf16"]["value"], "rho10", shapes16, P.rho)
@@ -429,6 +440,9 @@ def main():
     ap.add_argument("--learned-signals", type=int, default=16384, help="inference signals of the learned comparison")
     ap.add_argument("--train-signals", type=int, default=200000, help="BMPL-labelled training signals")
     ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--max-outer", type=int, default=16,
+                    help="iteration cap of the cs2048x16384 solves (1..64: each solve is one captured graph with no "
+                         "host read-back; 0: no cap, graph segments with a read-back each)")
     ap.add_argument("--host-loop", action="store_true",
                     help="drive the outer iterations from the host instead of replaying captured graph segments")
     args = ap.parse_args()
@@ -449,7 +463,7 @@ def main():
     Bt = torch.from_numpy(P.Bt).to(dev)
     # Throughput: graph-captured segments, no instrumentation.
     solver = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, graph=not args.host_loop,
-                       screen=args.screen)
+                       screen=args.screen, max_outer=args.max_outer)
     tune = solver.autotune(P.p)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -470,7 +484,8 @@ def main():
 
     # Kernel breakdown and the correlation kernel's roofline: the same steps again with every
     # launch bracketed by HIP events on the solve stream (host-driven loop, same tile shapes).
-    timed = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen=args.screen)
+    timed = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, screen=args.screen,
+                      max_outer=args.max_outer)
     timed.set_tuning(tune["shapes"])
     for _ in range(args.warmup):
         timed.solve(Bt)
@@ -484,7 +499,7 @@ def main():
     tm = timed.timing()
     # master-problem counts (appends, drops, sign-fixed solves, phase ticks): one more instrumented solve
     ph = pk.Solver(At, P.lambda_rel, mode="rel", rho=P.rho, kkt_tol=1e-4, timing=True, phases=True,
-                   screen=args.screen)
+                   screen=args.screen, max_outer=args.max_outer)
     ph.set_tuning(tune["shapes"])
     ph.solve(Bt)
     torch.cuda.synchronize()
@@ -513,7 +528,8 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": P.name, "n": P.n, "m": P.m, "p": P.p, "rho": P.rho,
                    "lambda_rel": P.lambda_rel, "kkt_tol": 1e-4, "screen": args.screen,
-                   "graph": not args.host_loop},
+                   "graph": not args.host_loop, "max_outer": args.max_outer,
+                   "one_graph_per_solve": (not args.host_loop) and 1 <= args.max_outer <= 64},
         "roofline": {
             "bound": "mfma",
             "kernel": "corr_gemm_" + args.screen,

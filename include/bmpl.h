@@ -27,8 +27,13 @@
  *    Concerns").  B is column-major n x p with leading dimension ldb >= n.
  *  - Calls that take a `hip_stream` enqueue their work on that stream
  *    (NULL = the null stream) and may return before it finishes; outputs are
- *    valid once the stream is synchronised.  bmpl_solve synchronises the stream
- *    once per outer iteration to read back how many signals are still running.
+ *    valid once the stream is synchronised.  bmpl_solve reads back how many
+ *    signals are still running (a stream synchronisation) once per outer
+ *    iteration, or once per captured segment of four iterations with
+ *    BMPL_FLAG_GRAPH; with BMPL_FLAG_GRAPH and an iteration cap
+ *    (bmpl_options.max_outer) of at most 64 it captures the whole solve as one
+ *    graph, sizes every signal's slot memory for that cap up front, and does
+ *    not synchronise at all (when that memory fits; see BMPL_FLAG_GRAPH).
  *  - Every call returns a bmpl_status; on failure bmpl_last_error(ctx) describes
  *    it.  A context is not re-entrant: one call in flight per context.
  */
@@ -80,7 +85,13 @@ typedef enum {
 #define BMPL_FLAG_NO_GRAM_TABLE 2   /* do not precompute Q = A^T A; Gram rows by direct dot products */
 #define BMPL_FLAG_GRAPH 4           /* run the outer iterations as captured HIP graphs of 4 iterations each
                                        (2 once fewer than 64 signals run), one launch and one read-back per
-                                       segment (ignored with TIMING) */
+                                       segment (ignored with TIMING).  With max_outer in 1..64 the whole
+                                       solve is one graph of max_outer iterations (passes after the last
+                                       signal's stop run as empty launches) with no read-back: each
+                                       signal's slot memory is then sized for |I| up to the cap
+                                       (p (K^2 + K(K+1)/2 + ...) float64, K = the cap's bound on |I|),
+                                       which must fit in the memory the context already holds for it plus
+                                       half of the free device memory, else the segments are used */
 #define BMPL_FLAG_Q_ROUTE 32        /* Section III's batch correlation, Eq. (12): after the first pass,
                                        g = beta - Q_{:,S} x_S with beta = A^T b (float64, computed once
                                        per solve) and the float64 Gram table, instead of the MFMA product

@@ -148,7 +148,8 @@ struct bmpl_ctx {
     struct GraphKey {
         int p, cur, i0, kl, shapes[3];
         long gen;
-        int variant;  // bit 0: the large tile also covers the middle count bucket; bit 1: a 2-iteration segment
+        int variant;  // bit 0: the large tile also covers the middle count bucket; bit 1: a 2-iteration segment;
+                      // bit 2: the whole solve (i0 = -1 - warm_k, kl = max_outer)
         bool operator==(const GraphKey& o) const
         {
             return p == o.p && cur == o.cur && i0 == o.i0 && kl == o.kl && gen == o.gen &&
@@ -363,6 +364,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int selcap)
 }
 
 constexpr int GRAPH_DEPTH = 4;   // outer iterations per captured segment (even: act buffers return)
+constexpr int FULL_DEPTH_MAX = 64;   // the most iterations captured as one graph for a whole solve
 
 void drop_graphs(bmpl_ctx* c)
 {
@@ -765,11 +767,31 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     const int slack = 2 * rho;   // slot-block growth: room for two more passes past the need
     bmpl_status st = ensure_workspace(c, std::max(p, c->p_cap), std::max(rho, warm ? warm_k : 0));
     if (st != BMPL_OK) return st;
+    // Full depth: with an iteration cap of at most FULL_DEPTH_MAX, graph mode captures every pass of
+    // the solve as one graph and gives each signal, at its first master problem, a slot block for the
+    // largest |I| the cap allows (first_add + (max_outer - 1) rho), so nothing waits for the host: the
+    // solve is enqueued and bmpl_solve returns without synchronising.  Used when those blocks take at
+    // most the arena already held plus half of the free device memory; otherwise the segments below.
+    int kfull = 0;
+    if (graph && c->opt.max_outer > 0 && c->opt.max_outer <= FULL_DEPTH_MAX) {
+        const int bound = std::min(max_active, first_add + (max_outer - 1) * rho);
+        const int k = grow_capacity(0, bound, slack, max_active);
+        const unsigned long long need = (unsigned long long)p * block_doubles(k, c->n);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        if (8.0 * (double)need <= 8.0 * (double)c->arena_total + 0.5 * (double)free_b) kfull = k;
+    }
+    const bool full = kfull > 0;
     // Slot blocks for every signal up to the first host read-back: the first master problem (a
-    // proposal's atoms or rho) and, in graph mode, the iterations of the first segment.
+    // proposal's atoms or rho) and, in graph mode, the iterations of the first segment; in full depth,
+    // the whole solve.
     const int iters0 = (graph && !warm) ? 1 + GRAPH_DEPTH : 1;
     st = arena_ensure(c, 0, (unsigned long long)p *
-                               block_reserve(0, 0, first_add, iters0, rho, slack, max_active, c->n), s);
+                               (full ? (unsigned long long)block_doubles(kfull, c->n)
+                                     : block_reserve(0, 0, first_add, iters0, rho, slack, max_active, c->n)), s);
     if (st != BMPL_OK) return st;
     Workspace& w = c->w;
     w.p = p;
@@ -797,7 +819,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     sa.eps_early = c->opt.eps_early; sa.r_inf_rel = c->opt.r_inf_rel; sa.r2_rel = c->opt.r2_rel;
     sa.rho = c->opt.rho;
     // slot-block reserve for the iterations up to the next read-back (a graph segment at most)
-    sa.reserve_iters = graph ? GRAPH_DEPTH : 1; sa.rho_pass = rho; sa.slack = slack; sa.kcap = max_active;
+    sa.reserve_iters = full ? 0 : (graph ? GRAPH_DEPTH : 1); sa.rho_pass = rho; sa.slack = slack;
+    sa.kcap = max_active;
     sa.clear_cert = c->n_cert32;
     sa.grow_list = c->grow_list; sa.n_grow = c->n_grow;
     hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
@@ -1014,7 +1037,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(kp) <= c->lds_dyn_max) ? 1 : 0;
         if (so.zs_lds) lds += block_scratch_bytes(kp);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
-        GrowArgs ga{w, c->grow_list, c->n_grow, slack, max_active};
+        GrowArgs ga{w, c->grow_list, c->n_grow, slack, max_active, kfull};
         hipLaunchKernelGGL(grow_kernel, dim3(std::min(n_grid, 512)), dim3(256), 0, q, ga);
         HIPC(hipGetLastError());
         if (so.zs_lds)
@@ -1051,10 +1074,32 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         st = enqueue_select_pass(s, 0, n_act, true, false, false);
         if (st != BMPL_OK) return st;
         cur = 1;
-        if (!graph || warm) {
+        if (!graph || (warm && !full)) {
             st = read_count(cur);
             if (st != BMPL_OK) return st;
         }
+    }
+    if (full && n_act > 0) {
+        // every pass of the solve in one graph: max_outer master problems and selection passes (the stop
+        // test stops each signal by then); passes after the last signal's stop are empty launches
+        merge_mid = false;
+        hipGraphExec_t ge = nullptr;
+        st = segment_graph(c, p, cur, -1 - (warm ? warm_k : 0), max_outer, 4, &ge, [&](hipStream_t q) -> bmpl_status {
+            int cc = cur, im = 0;
+            for (int d = 0; d < max_outer; ++d) {
+                const bool wd = warm && d == 0;   // the master problem on a warm start's proposal
+                im = std::min(max_active, im + (wd ? first_add : rho));
+                bmpl_status r = enqueue_master(q, cc, p, wd ? std::min(im, WARM_KL) : im, im, true, !wd);
+                if (r != BMPL_OK) return r;
+                r = enqueue_select_pass(q, cc, p, false, wd, true);
+                if (r != BMPL_OK) return r;
+                cc = 1 - cc;
+            }
+            return BMPL_OK;
+        });
+        if (st != BMPL_OK) return st;
+        HIPC(hipGraphLaunch(ge, s));
+        n_act = 0;
     }
     // Then per iteration: master problem on I_t, next selection pass.
     int imax = 0;

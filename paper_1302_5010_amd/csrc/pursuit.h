@@ -76,6 +76,7 @@ struct GrowArgs {
     Workspace w;
     const int* list; const int* n_list;   // the signals to grow (written by the stop test)
     int slack, kcap;                // grow_capacity's parameters; kcap = max_active
+    int kmin;                       // smallest capacity handed out (a block sized for the whole solve)
 };
 
 struct PackArgs {

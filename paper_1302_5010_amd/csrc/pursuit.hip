@@ -979,7 +979,7 @@ __global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
         const int nI0 = w.nI[sig], nS = w.nS[sig];
         const int nI = nI0 + w.nsel[sig];
         const int K = w.cap[sig];
-        const int K2 = grow_capacity(K, nI, a.slack, a.kcap);
+        const int K2 = max(grow_capacity(K, nI, a.slack, a.kcap), min(a.kmin, a.kcap));
         if (tid == 0) {
             s_blk = arena_alloc(w.arena, (unsigned long long)block_doubles(K2, w.n));
             if (!s_blk) atomicAdd(&w.arena->starved, 1ull);
