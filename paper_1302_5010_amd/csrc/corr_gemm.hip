@@ -238,8 +238,10 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
         }
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int q = 0; q < LR; ++q)
+        for (int q = 0; q < LR; ++q) {
+            staged(gR[q]);   // see gemm_tile.h: keeps the residual load a stage ahead
             *reinterpret_cast<float4*>(&ldsR[cur ^ 1][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gR[q];
+        }
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll

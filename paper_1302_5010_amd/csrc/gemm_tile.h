@@ -54,6 +54,15 @@ struct TileLds {
     char w[2][BN * TILE_LDS_ROW];
 };
 
+// A staged slice held in registers until its LDS store.  Without this the compiler turns the load and
+// the later store of the same 16 bytes into one global-to-LDS copy at the store, i.e. at the end of the
+// stage, and the loads' whole latency is exposed once per stage; the empty asm needs the value in
+// registers, so the load stays where it was issued, a stage ahead.
+__device__ __forceinline__ void staged(float4& v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
 // Thread-to-load mapping: 16-byte column c4 = tid % 8 of the k slice, rows r0 + RSTEP q.
 __device__ __forceinline__ int tile_c4(int tid) { return tid & 7; }
 __device__ __forceinline__ int tile_r0(int tid) { return tid >> 3; }
@@ -91,10 +100,14 @@ __device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const in
     } while (0)
 #define TILE_STORE_SLICE(buf)                                                                               \
     do {                                                                                                    \
-        _Pragma("unroll") for (int q = 0; q < S::LX; ++q)                                                  \
+        _Pragma("unroll") for (int q = 0; q < S::LX; ++q) {                                                \
+            staged(gX[q]);                                                                                  \
             *reinterpret_cast<float4*>(&lds.x[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gX[q];  \
-        _Pragma("unroll") for (int q = 0; q < S::LW; ++q)                                                  \
+        }                                                                                                   \
+        _Pragma("unroll") for (int q = 0; q < S::LW; ++q) {                                                \
+            staged(gW[q]);                                                                                  \
             *reinterpret_cast<float4*>(&lds.w[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gW[q];  \
+        }                                                                                                   \
     } while (0)
 
     TILE_LOAD_SLICE(0);
