@@ -88,6 +88,7 @@ struct bmpl_ctx {
     int* n_cert32 = nullptr;      // their count
     int* grow_list = nullptr;     // [p_cap] signals whose slot block grows before the next master problem
     int* n_grow = nullptr;        // their count
+    unsigned long long* grow_off = nullptr;   // [p_cap] their new blocks' offsets from arena->grow_base
     int* cert_act = nullptr;      // [p_cap] compacted list of those signals
     int* n_cert_dev = nullptr;    // its length
     double band_x = 0.0, band_dx = 0.0;   // bfloat16 band: eps_i = band_x ||xi_i|| + band_dx ||bf16(xi_i) - xi_i||
@@ -227,7 +228,7 @@ void free_signals(bmpl_ctx* c)
     dfree(w.R8); dfree(w.rscale8); dfree(c->cand8); dfree(c->ncand8); dfree(c->vmax8); dfree(c->zeros);
     dfree(c->cert); dfree(c->cert_act); dfree(c->n_cert_dev);
     dfree(c->spill); dfree(c->spill_act); dfree(c->n_spill_dev);
-    dfree(c->cert32); dfree(c->n_cert32); dfree(c->grow_list); dfree(c->n_grow);
+    dfree(c->cert32); dfree(c->n_cert32); dfree(c->grow_list); dfree(c->n_grow); dfree(c->grow_off);
     dfree(c->beta);
     c->p_cap = 0;
 }
@@ -264,12 +265,14 @@ bmpl_status arena_add(bmpl_ctx* c, unsigned long long min_doubles, unsigned long
 }
 
 // Make sure `need` doubles of slot blocks (with a margin for chunk tails) can be handed out after the
-// first `used` doubles of this solve.
+// first `used` doubles of this solve.  `used` may lie past the chunks' end: the stop test places the
+// grow list's blocks before the host adds room, and a block placed past the end lies in the next chunk
+// once it is added (grow_kernel finds it there), so the offset is never moved back.
 bmpl_status arena_ensure(bmpl_ctx* c, unsigned long long used, unsigned long long need, hipStream_t s)
 {
     const unsigned long long want = need + need / 8 + (1ull << 20);
-    if (c->arena_total >= used && c->arena_total - used >= want) return BMPL_OK;
-    const unsigned long long missing = want - (c->arena_total > used ? c->arena_total - used : 0);
+    if (c->arena_total >= used + want) return BMPL_OK;
+    const unsigned long long missing = used + want - c->arena_total;
     return arena_add(c, missing, std::max(missing, c->arena_total / 4), s);
 }
 
@@ -326,6 +329,7 @@ bmpl_status ensure_workspace(bmpl_ctx* c, int p, int selcap)
     HIPC(dalloc(&c->cert32, P));
     HIPC(dalloc(&c->n_cert32, 1));
     HIPC(dalloc(&c->grow_list, P));
+    HIPC(dalloc(&c->grow_off, P));
     HIPC(dalloc(&c->n_grow, 1));
     HIPC(hipMemset(c->n_grow, 0, sizeof(int)));
     HIPC(hipMemset(c->n_cert32, 0, sizeof(int)));
@@ -822,7 +826,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     sa.reserve_iters = full ? 0 : (graph ? GRAPH_DEPTH : 1); sa.rho_pass = rho; sa.slack = slack;
     sa.kcap = max_active;
     sa.clear_cert = c->n_cert32;
-    sa.grow_list = c->grow_list; sa.n_grow = c->n_grow;
+    sa.grow_list = c->grow_list; sa.n_grow = c->n_grow; sa.grow_off = c->grow_off; sa.kmin = kfull;
     hipLaunchKernelGGL(status_compact_kernel, dim3(1), dim3(1024), 0, s, sa);
     HIPC(hipGetLastError());
     // In graph mode the host does not wait for the running count until the first captured segment has
@@ -1037,7 +1041,7 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         so.zs_lds = (c->block_append && !so.rinv_lds && lds + block_scratch_bytes(kp) <= c->lds_dyn_max) ? 1 : 0;
         if (so.zs_lds) lds += block_scratch_bytes(kp);
         so.act = c->act[idx]; so.n_act_dev = c->n_act_dev + idx;
-        GrowArgs ga{w, c->grow_list, c->n_grow, slack, max_active, kfull};
+        GrowArgs ga{w, c->grow_list, c->n_grow, c->grow_off, slack, max_active, kfull};
         hipLaunchKernelGGL(grow_kernel, dim3(std::min(n_grid, 512)), dim3(256), 0, q, ga);
         HIPC(hipGetLastError());
         if (so.zs_lds)
@@ -1057,14 +1061,9 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         const Arena& R = *c->h_arena_rd;
         if (R.starved) HIPC(hipMemsetAsync(&c->arena_dev->starved, 0, sizeof(unsigned long long), s));
         if (n_act == 0) return BMPL_OK;
-        if (R.top > c->arena_total) {
-            // failed requests moved the offset past the last chunk: nothing lies beyond the chunks, so
-            // the offset returns to their end (the stream is idle here)
-            const unsigned long long t = c->arena_total;
-            HIPC(hipMemcpyAsync(&c->arena_dev->top, &t, sizeof t, hipMemcpyHostToDevice, s));
-            HIPC(hipStreamSynchronize(s));
-        }
-        return arena_ensure(c, std::min(R.top, c->arena_total), R.reserve, s);
+        // the offset stays where it is, also past the chunks' end (blocks placed there by the stop test
+        // become valid in the chunk added next)
+        return arena_ensure(c, R.top, R.reserve, s);
     };
 
     // Iteration 0: lambda rule and the first selection (or the warm-start proposal).

@@ -26,12 +26,47 @@ struct Arena {
     unsigned long long top;       // doubles handed out in this solve (offset in the chunk list)
     unsigned long long starved;   // block requests that found no room (the host adds a chunk)
     unsigned long long reserve;   // doubles the running signals may request during the next iterations
+    unsigned long long grow_base; // offset of the blocks the last stop test placed for the grow list
     int nchunks;
     int pad_;
     double* base[ARENA_CHUNKS];
     unsigned long long start[ARENA_CHUNKS];   // offset of each chunk in the list (start[c+1] = start[c] + size[c])
     unsigned long long size[ARENA_CHUNKS];    // doubles
 };
+
+// N chunks of four consecutive correlations of a row per thread (thread t: g[base0 + 1024 q + 4 t ..
+// + 3], q < N) with their bits of the I bitmap (bit set: in I; `absent` for lanes past the vector part
+// of the row, m4, whose values read as zeros).  When every lane's chunks lie inside the row (a test that
+// is the same for the whole workgroup) the loads are unconditional, so all of a thread's loads are in
+// flight at once: a guarded load compiles to a branch that waits for its data at the branch's end.
+template <int N>
+__device__ __forceinline__ void row_chunks(const float* g, const uint32_t* ex, int base0, int m4, uint32_t absent,
+                                           float4 (&f)[N], uint32_t (&w)[N])
+{
+    const int t4 = 4 * (int)threadIdx.x;
+    if (base0 + 1024 * N <= m4) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) f[q] = *reinterpret_cast<const float4*>(g + base0 + 1024 * q + t4);
+        if (ex) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const int j0 = base0 + 1024 * q + t4;
+                w[q] = ex[j0 >> 5] >> (j0 & 31);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < N; ++q) w[q] = 0u;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const int j0 = base0 + 1024 * q + t4;
+        const bool in = j0 < m4;
+        f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        w[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : absent;
+    }
+}
 
 // One signal's slot block for capacity K (slots of I) and signal length n:
 //   G [K][K] float64 (Gram of I, row-major by slot) | Rinv [tri(min(K, n))] float64 (inverse Cholesky

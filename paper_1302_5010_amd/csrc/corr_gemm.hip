@@ -26,7 +26,7 @@
 namespace bmpl {
 namespace {
 
-template <class E, int BM, int BN, int WM, int WN>
+template <class E, int BM, int BN, int WM, int WN, int DEPTH>
 __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gemm_kernel(
     const E* __restrict__ At, int64_t lda, int m, int kpad,
     const E* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
@@ -77,7 +77,7 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     const int l32 = lane & 31;
     const int h = lane >> 5;
     floatx16 acc[S::TI][S::TJ];
-    mfma_tile_loop<E, BM, BN, WM, WN>(Rbuf, oR, At, oA, kpad, lds, ws, wa, acc);
+    mfma_tile_loop<E, BM, BN, WM, WN, DEPTH>(Rbuf, oR, At, oA, kpad, lds, ws, wa, acc);
 
     // D[row][col] of a 32x32 block (both instructions): lane l, register r -> row 8(r/4) + 4(l/32) + r%4,
     // col l%32.
@@ -280,7 +280,7 @@ hipError_t launch_direct(const uint16_t* Apk, int m, int kpad, const uint16_t* R
     return hipGetLastError();
 }
 
-template <class E, int BM, int BN, int WM, int WN>
+template <class E, int BM, int BN, int WM, int WN, int DEPTH = 1>
 hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                         const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                         int n_lo, int n_hi, const float* ascale, const float* rscale, hipStream_t stream)
@@ -289,7 +289,7 @@ hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf
     const int tiles_n = (m + BN - 1) / BN;
     const int64_t nwg = (int64_t)tiles_m * tiles_n;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((corr_gemm_kernel<E, BM, BN, WM, WN>), dim3((unsigned)nwg),
+    hipLaunchKernelGGL((corr_gemm_kernel<E, BM, BN, WM, WN, DEPTH>), dim3((unsigned)nwg),
                        dim3(TileShape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
                        n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi, ascale, rscale);
     return hipGetLastError();
@@ -303,13 +303,16 @@ hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad
 {
     if (p_grid <= 0 || m <= 0) return hipSuccess;
     if (kpad % (TILE_ROW_BYTES / (int)sizeof(E))) return hipErrorInvalidValue;
+    // float32 stages of the shapes with registers to spare load two stages ahead (faster: 604 -> 514 us
+    // for the 256 x 128 tile at 1024 signals); 16- and 8-bit stages measured slower that way
+    constexpr int DEEP = sizeof(E) == 4 ? 2 : 1;
     switch (variant) {
-    case 0: return launch_shape<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 0: return launch_shape<E, 128, 128, 64, 64, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 1: return launch_shape<E, 256, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 2: return launch_shape<E, 256, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 3: return launch_shape<E, 64, 128, 32, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 4: return launch_shape<E, 32, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
-    case 5: return launch_shape<E, 64, 64, 32, 32>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 2: return launch_shape<E, 256, 128, 64, 64, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 3: return launch_shape<E, 64, 128, 32, 64, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 4: return launch_shape<E, 32, 64, 32, 32, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 5: return launch_shape<E, 64, 64, 32, 32, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 6: return launch_shape<E, 256, 256, 128, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 7: return launch_shape<E, 256, 256, 128, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     default: return hipErrorInvalidValue;

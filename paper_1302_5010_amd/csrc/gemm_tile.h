@@ -67,90 +67,42 @@ __device__ __forceinline__ void staged(float4& v)
 __device__ __forceinline__ int tile_c4(int tid) { return tid & 7; }
 __device__ __forceinline__ int tile_r0(int tid) { return tid >> 3; }
 
-// Run the K loop of one tile.  ws / wa: the wave's row offsets within the tile (X / W rows).
+// The matrix work of one LDS stage (both operands' fragments read from the stage's buffers).
 template <class E, int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const int64_t (&oX)[TileShape<BM, BN, WM, WN>::LX],
-                                               const E* __restrict__ W, const int64_t (&oW)[TileShape<BM, BN, WM, WN>::LW],
-                                               int kpad, TileLds<BM, BN>& lds, int ws, int wa,
-                                               floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
+__device__ __forceinline__ void mfma_tile_stage(const char* cX, const char* cW, int ws, int wa, int l32, int h,
+                                                floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
 {
     using S = TileShape<BM, BN, WM, WN>;
-    constexpr int BK = TILE_ROW_BYTES / (int)sizeof(E);   // k per stage
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int c4 = tile_c4(tid);
-    const int r0 = tile_r0(tid);
-    const int l32 = lane & 31;
-    const int h = lane >> 5;
-
+    if constexpr (sizeof(E) == 1) {
+        // e4m3: two v_mfma_scale_f32_32x32x64_f8f6f4 per stage (unit scales); lane half h supplies
+        // the 32 bytes [64 t + 32 h, +32) of k to both operands
 #pragma unroll
-    for (int i = 0; i < S::TI; ++i)
+        for (int t = 0; t < 2; ++t) {
+            intx8 fx[S::TI], fw[S::TJ];
 #pragma unroll
-        for (int j = 0; j < S::TJ; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    float4 gX[S::LX], gW[S::LW];
-#define TILE_LOAD_SLICE(k0)                                                                                 \
-    do {                                                                                                    \
-        _Pragma("unroll") for (int q = 0; q < S::LX; ++q)                                                  \
-            gX[q] = *reinterpret_cast<const float4*>(X + oX[q] + (k0));                                     \
-        _Pragma("unroll") for (int q = 0; q < S::LW; ++q)                                                  \
-            gW[q] = *reinterpret_cast<const float4*>(W + oW[q] + (k0));                                     \
-    } while (0)
-#define TILE_STORE_SLICE(buf)                                                                               \
-    do {                                                                                                    \
-        _Pragma("unroll") for (int q = 0; q < S::LX; ++q) {                                                \
-            staged(gX[q]);                                                                                  \
-            *reinterpret_cast<float4*>(&lds.x[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gX[q];  \
-        }                                                                                                   \
-        _Pragma("unroll") for (int q = 0; q < S::LW; ++q) {                                                \
-            staged(gW[q]);                                                                                  \
-            *reinterpret_cast<float4*>(&lds.w[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gW[q];  \
-        }                                                                                                   \
-    } while (0)
-
-    TILE_LOAD_SLICE(0);
-    TILE_STORE_SLICE(0);
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < kpad; k0 += BK) {
-        // prefetch the next slice (the last iteration re-reads the final slice; its copy is never used)
-        const int kn = k0 + BK < kpad ? k0 + BK : k0;
-        TILE_LOAD_SLICE(kn);
-        asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
-        const char* cX = lds.x[cur];
-        const char* cW = lds.w[cur];
-        if constexpr (sizeof(E) == 1) {
-            // e4m3: two v_mfma_scale_f32_32x32x64_f8f6f4 per stage (unit scales); lane half h supplies
-            // the 32 bytes [64 t + 32 h, +32) of k to both operands
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                intx8 fx[S::TI], fw[S::TJ];
-#pragma unroll
-                for (int i = 0; i < S::TI; ++i) {
-                    const char* pp = &cX[(ws + 32 * i + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
-                    const float4 lo = *reinterpret_cast<const float4*>(pp);
-                    const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
-                    fx[i] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
-                                  __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
-                }
-#pragma unroll
-                for (int j = 0; j < S::TJ; ++j) {
-                    const char* pp = &cW[(wa + 32 * j + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
-                    const float4 lo = *reinterpret_cast<const float4*>(pp);
-                    const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
-                    fw[j] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
-                                  __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
-                }
-#pragma unroll
-                for (int i = 0; i < S::TI; ++i)
-#pragma unroll
-                    for (int j = 0; j < S::TJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fx[i], fw[j], acc[i][j], 0, 0, 0, 127,
-                                                                                   0, 127);
+            for (int i = 0; i < S::TI; ++i) {
+                const char* pp = &cX[(ws + 32 * i + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
+                const float4 lo = *reinterpret_cast<const float4*>(pp);
+                const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
+                fx[i] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                              __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
             }
-        } else {
+#pragma unroll
+            for (int j = 0; j < S::TJ; ++j) {
+                const char* pp = &cW[(wa + 32 * j + l32) * TILE_LDS_ROW + 64 * t + 32 * h];
+                const float4 lo = *reinterpret_cast<const float4*>(pp);
+                const float4 hi = *reinterpret_cast<const float4*>(pp + 16);
+                fw[j] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                              __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
+            }
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fx[i], fw[j], acc[i][j], 0, 0, 0, 127,
+                                                                               0, 127);
+        }
+    } else {
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {       // 4 x 16-byte chunks per lane half per stage
             float4 fx[S::TI], fw[S::TJ];
@@ -191,11 +143,93 @@ __device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const in
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].w, fw[j].w, acc[i][j], 0, 0, 0);
             }
         }
+    }
+}
+
+// Run the K loop of one tile.  ws / wa: the wave's row offsets within the tile (X / W rows).
+// DEPTH = 1: the next slice is loaded into registers at the top of a stage and stored to LDS at its end.
+// DEPTH = 2: two register sets alternate, so a slice's loads are issued two stages before the stage
+// that reads it (twice the latency a stage of matrix work hides; short 16- and 8-bit stages need it).
+template <class E, int BM, int BN, int WM, int WN, int DEPTH = 1>
+__device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const int64_t (&oX)[TileShape<BM, BN, WM, WN>::LX],
+                                               const E* __restrict__ W, const int64_t (&oW)[TileShape<BM, BN, WM, WN>::LW],
+                                               int kpad, TileLds<BM, BN>& lds, int ws, int wa,
+                                               floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    static_assert(DEPTH == 1 || DEPTH == 2, "register prefetch depth");
+    constexpr int BK = TILE_ROW_BYTES / (int)sizeof(E);   // k per stage
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int c4 = tile_c4(tid);
+    const int r0 = tile_r0(tid);
+    const int l32 = lane & 31;
+    const int h = lane >> 5;
+
+#pragma unroll
+    for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < S::TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    float4 gX[DEPTH][S::LX], gW[DEPTH][S::LW];
+    // slices past the last re-read the last one (never used)
+    const int klast = kpad - BK;
+#define TILE_LOAD_SLICE(d, k0)                                                                              \
+    do {                                                                                                    \
+        const int kk_ = (k0) < klast ? (k0) : klast;                                                        \
+        _Pragma("unroll") for (int q = 0; q < S::LX; ++q)                                                  \
+            gX[d][q] = *reinterpret_cast<const float4*>(X + oX[q] + kk_);                                   \
+        _Pragma("unroll") for (int q = 0; q < S::LW; ++q)                                                  \
+            gW[d][q] = *reinterpret_cast<const float4*>(W + oW[q] + kk_);                                   \
+    } while (0)
+#define TILE_STORE_SLICE(d, buf)                                                                            \
+    do {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < S::LX; ++q) {                                                \
+            staged(gX[d][q]);                                                                               \
+            *reinterpret_cast<float4*>(&lds.x[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gX[d][q]; \
+        }                                                                                                   \
+        _Pragma("unroll") for (int q = 0; q < S::LW; ++q) {                                                \
+            staged(gW[d][q]);                                                                               \
+            *reinterpret_cast<float4*>(&lds.w[buf][(r0 + S::RSTEP * q) * TILE_LDS_ROW + 16 * c4]) = gW[d][q]; \
+        }                                                                                                   \
+    } while (0)
+
+    TILE_LOAD_SLICE(0, 0);
+    TILE_STORE_SLICE(0, 0);
+    if constexpr (DEPTH == 2) TILE_LOAD_SLICE(1, BK);   // slice 1, held through stage 0
+    __syncthreads();
+    int cur = 0;
+    if constexpr (DEPTH == 1) {
+        for (int k0 = 0; k0 < kpad; k0 += BK) {
+            TILE_LOAD_SLICE(0, k0 + BK);
+            asm volatile("" ::: "memory");       // issue the prefetch before the matrix work
+            mfma_tile_stage<E, BM, BN, WM, WN>(lds.x[cur], lds.w[cur], ws, wa, l32, h, acc);
+            asm volatile("" ::: "memory");       // and consume it only after
+            TILE_STORE_SLICE(0, cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
         }
-        asm volatile("" ::: "memory");       // and consume it only after
-        TILE_STORE_SLICE(cur ^ 1);
-        __syncthreads();
-        cur ^= 1;
+    } else {
+        // stage s holds slice s + 1 in one register set and loads slice s + 2 into the other
+        for (int k0 = 0; k0 < kpad; k0 += 2 * BK) {
+            TILE_LOAD_SLICE(0, k0 + 2 * BK);
+            asm volatile("" ::: "memory");
+            mfma_tile_stage<E, BM, BN, WM, WN>(lds.x[cur], lds.w[cur], ws, wa, l32, h, acc);
+            asm volatile("" ::: "memory");
+            TILE_STORE_SLICE(1, cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+            if (k0 + BK >= kpad) break;           // an odd number of stages
+            TILE_LOAD_SLICE(1, k0 + 3 * BK);
+            asm volatile("" ::: "memory");
+            mfma_tile_stage<E, BM, BN, WM, WN>(lds.x[cur], lds.w[cur], ws, wa, l32, h, acc);
+            asm volatile("" ::: "memory");
+            TILE_STORE_SLICE(0, cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+        }
     }
 #undef TILE_LOAD_SLICE
 #undef TILE_STORE_SLICE

@@ -31,6 +31,8 @@ struct StatusArgs {
     int reserve_iters; int rho_pass; int slack; int kcap;
     int* clear_cert;    // the selection's certification list count, set to 0 at the end (or null)
     int* grow_list; int* n_grow;   // kept signals whose block must grow for this pass's selection
+    unsigned long long* grow_off;  // their new blocks' offsets from arena->grow_base (one fetch-and-add)
+    int kmin;                      // smallest capacity handed out (as GrowArgs::kmin)
 };
 
 struct WarmArgs {
@@ -75,6 +77,7 @@ struct SolveArgs {
 struct GrowArgs {
     Workspace w;
     const int* list; const int* n_list;   // the signals to grow (written by the stop test)
+    const unsigned long long* off;        // their blocks' offsets from arena->grow_base
     int slack, kcap;                // grow_capacity's parameters; kcap = max_active
     int kmin;                       // smallest capacity handed out (a block sized for the whole solve)
 };

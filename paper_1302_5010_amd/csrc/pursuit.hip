@@ -827,7 +827,8 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
     __shared__ int s_base;
     __shared__ unsigned long long s_res[16];
     __shared__ int s_ng;
-    if (threadIdx.x == 0) { s_base = 0; s_ng = 0; }
+    __shared__ unsigned long long s_goff;   // doubles of the grow list's new blocks
+    if (threadIdx.x == 0) { s_base = 0; s_ng = 0; s_goff = 0; }
     __syncthreads();
     unsigned long long res = 0;   // this thread's share of the slot-block reserve
     for (int r0 = 0; r0 < n_in; r0 += 1024) {
@@ -884,8 +885,15 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                 }
             }
         }
-        if (keep && a.grow_list && w.nI[sig] + w.nsel[sig] > w.cap[sig])
-            a.grow_list[atomicAdd(&s_ng, 1)] = sig;   // its block grows before the master problem
+        if (keep && a.grow_list && w.nI[sig] + w.nsel[sig] > w.cap[sig]) {
+            // its block grows before the master problem; the new blocks of the whole list are placed here
+            // with one fetch-and-add on the arena's offset (below), each at its share of the total
+            const int K2 = max(grow_capacity(w.cap[sig], w.nI[sig] + w.nsel[sig], a.slack, a.kcap),
+                               min(a.kmin, a.kcap));
+            const int e = atomicAdd(&s_ng, 1);
+            a.grow_list[e] = sig;
+            a.grow_off[e] = atomicAdd(&s_goff, (unsigned long long)block_doubles(K2, w.n));
+        }
         if (keep && a.reserve_iters > 0) {
             // the blocks this signal may take while its |I| grows by up to reserve_iters * rho_pass slots
             int Kc = w.cap[sig];
@@ -895,22 +903,27 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                 res += (unsigned long long)block_doubles(Kc, w.n);
             }
         }
-        s_scan[threadIdx.x] = keep;
+        // order-preserving compaction: position = kept signals before this one in the round (a ballot
+        // within the wave, the counts of the earlier waves from LDS), two barriers per round
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) s_scan[wv] = __popcll(bal);
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {           // inclusive Hillis-Steele scan
-            int t = threadIdx.x >= o ? s_scan[threadIdx.x - o] : 0;
-            __syncthreads();
-            s_scan[threadIdx.x] += t;
-            __syncthreads();
+        int before = s_base, total = 0;
+        for (int q = 0; q < 16; ++q) {
+            const int c = s_scan[q];
+            before += q < wv ? c : 0;
+            total += c;
         }
-        if (keep) a.act_out[s_base + s_scan[threadIdx.x] - 1] = sig;
-        __syncthreads();
-        if (threadIdx.x == 1023) s_base += s_scan[1023];
-        __syncthreads();
+        if (keep) a.act_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = sig;
+        __syncthreads();   // every wave has read s_scan and s_base
+        if (threadIdx.x == 0) s_base += total;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         *a.n_out_dev = s_base;
         if (a.n_grow) *a.n_grow = s_ng;
+        if (s_ng > 0) w.arena->grow_base = atomicAdd(&w.arena->top, s_goff);
         if (a.clear_cert) *a.clear_cert = 0;   // this pass's certification list is consumed
     }
     if (a.reserve_iters > 0) {
@@ -966,8 +979,10 @@ __global__ __launch_bounds__(256) void warm_select_kernel(WarmArgs a)
 // the inverse factor and the Gram matrix of I (restrided).  A request that finds no room is counted in
 // the arena's `starved` and leaves the signal as it is (the master-problem kernel then skips it).
 // ---------------------------------------------------------------------------
-// The stop test lists the signals that need it; a grid of at most a few hundred workgroups loops over
-// the list.
+// The stop test lists the signals that need it and places their new blocks with one fetch-and-add
+// (one per listed signal on that single address kept the first master problem of 16 384 signals
+// waiting half a millisecond); a block that would straddle two chunks is requested again on its own.
+// A grid of at most a few hundred workgroups loops over the list.
 __global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
 {
     const int n_list = *a.n_list;
@@ -981,8 +996,16 @@ __global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
         const int K = w.cap[sig];
         const int K2 = max(grow_capacity(K, nI, a.slack, a.kcap), min(a.kmin, a.kcap));
         if (tid == 0) {
-            s_blk = arena_alloc(w.arena, (unsigned long long)block_doubles(K2, w.n));
-            if (!s_blk) atomicAdd(&w.arena->starved, 1ull);
+            const unsigned long long sz = (unsigned long long)block_doubles(K2, w.n);
+            const Arena& A = *w.arena;
+            const unsigned long long off = A.grow_base + a.off[li];
+            int c = 0;
+            while (c < A.nchunks && off >= A.start[c] + A.size[c]) ++c;
+            double* p = nullptr;
+            if (c < A.nchunks && off + sz <= A.start[c] + A.size[c]) p = A.base[c] + (off - A.start[c]);
+            else p = arena_alloc(w.arena, sz);   // straddles a chunk boundary, or past the last chunk
+            if (!p) atomicAdd(&w.arena->starved, 1ull);
+            s_blk = p;
         }
         __syncthreads();
         double* nb = s_blk;

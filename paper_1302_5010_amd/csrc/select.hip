@@ -69,13 +69,16 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
     constexpr int CH = 8;
     float4 f0[CH];
     uint32_t w0[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int j0 = 4 * tid + 1024 * q;
-        const bool in = j0 < m4;
-        f0[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-        w0[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : 0xFu;   // 4 atoms share one word; 0xF: absent
-    }
+    row_chunks<CH>(g, ex, 0, m4, 0xFu, f0, w0);   // 4 atoms share one word; 0xF: absent
+    // The rest of the row streams in chunks of CS float4 per thread, each chunk's loads issued one chunk
+    // ahead (the first before the bound is computed), so a workgroup waits for memory about once.
+    constexpr int CS = 4;
+    float4 fa[CS];
+    uint32_t wa[CS];
+    auto load_chunk = [&](int base0, float4 (&f)[CS], uint32_t (&word)[CS]) {
+        row_chunks<CS>(g, ex, base0, m4, 0xFu, f, word);
+    };
+    load_chunk(1024 * CH, fa, wa);
 
     // Pass 1 (relative lambda rule only): lambda_i = c * max_j |g_j|.
     if (a.lam_rel > 0.0) {
@@ -171,31 +174,29 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
             take(!(w0[q] & 4u) && ok(fabsf(f0[q].z)), j0 + 2, fabsf(f0[q].z));
             take(!(w0[q] & 8u) && ok(fabsf(f0[q].w)), j0 + 3, fabsf(f0[q].w));
         }
-        constexpr int CS = 4;
         // every lane runs the same number of steps (the ballots need the whole wave)
         for (int base0 = 1024 * CH; base0 < m4; base0 += 1024 * CS) {
             const int base = base0 + 4 * tid;
-            float4 f[CS];
-            uint32_t word[CS];
+            float4 fb[CS];
+            uint32_t wb[CS];
+            load_chunk(base0 + 1024 * CS, fb, wb);   // the next chunk (past the row: zeros, no load)
 #pragma unroll
             for (int q = 0; q < CS; ++q) {
                 const int j0 = base + 1024 * q;
-                const bool in = j0 < m4;
-                f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-                word[q] = (ex && in) ? (ex[j0 >> 5] >> (j0 & 31)) : (in ? 0u : 0xFu);
+                const float v0 = fabsf(fa[q].x), v1 = fabsf(fa[q].y), v2 = fabsf(fa[q].z), v3 = fabsf(fa[q].w);
+                if (!(wa[q] & 1u)) vmx = fmaxf(vmx, v0);
+                if (!(wa[q] & 2u)) vmx = fmaxf(vmx, v1);
+                if (!(wa[q] & 4u)) vmx = fmaxf(vmx, v2);
+                if (!(wa[q] & 8u)) vmx = fmaxf(vmx, v3);
+                take(!(wa[q] & 1u) && ok(v0), j0, v0);
+                take(!(wa[q] & 2u) && ok(v1), j0 + 1, v1);
+                take(!(wa[q] & 4u) && ok(v2), j0 + 2, v2);
+                take(!(wa[q] & 8u) && ok(v3), j0 + 3, v3);
             }
 #pragma unroll
             for (int q = 0; q < CS; ++q) {
-                const int j0 = base + 1024 * q;
-                const float v0 = fabsf(f[q].x), v1 = fabsf(f[q].y), v2 = fabsf(f[q].z), v3 = fabsf(f[q].w);
-                if (!(word[q] & 1u)) vmx = fmaxf(vmx, v0);
-                if (!(word[q] & 2u)) vmx = fmaxf(vmx, v1);
-                if (!(word[q] & 4u)) vmx = fmaxf(vmx, v2);
-                if (!(word[q] & 8u)) vmx = fmaxf(vmx, v3);
-                take(!(word[q] & 1u) && ok(v0), j0, v0);
-                take(!(word[q] & 2u) && ok(v1), j0 + 1, v1);
-                take(!(word[q] & 4u) && ok(v2), j0 + 2, v2);
-                take(!(word[q] & 8u) && ok(v3), j0 + 3, v3);
+                fa[q] = fb[q];
+                wa[q] = wb[q];
             }
         }
         for (int j0 = m4; j0 < a.m; j0 += 256) {
