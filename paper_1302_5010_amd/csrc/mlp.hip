@@ -402,17 +402,24 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, 
     int* o = out + (int64_t)row * ldo;
     const int kk = k < L ? k : L;
 
-    // 1. per-thread two largest keys, then their kk-th largest over the workgroup
+    // 1. per-thread two largest keys, then their kk-th largest over the workgroup.  A thread's eight loads
+    //    are unconditional whenever every thread's lie inside the row (a guarded load compiles to a branch
+    //    that waits for its data, so the loads would run one after another).
     uint32_t t1 = 0u, t2 = 0u;
-    for (int j0 = tid; j0 < L; j0 += 256 * 4) {
-        uint32_t key[4];
+    for (int j0 = tid; j0 < L; j0 += 256 * 8) {
+        uint32_t key[8];
+        if (j0 - tid + 256 * 8 <= L) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = j0 + 256 * e;
-            key[e] = j < L ? order_key(s[j]) : 0u;
+            for (int e = 0; e < 8; ++e) key[e] = order_key(s[j0 + 256 * e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = j0 + 256 * e;
+                key[e] = j < L ? order_key(s[j]) : 0u;
+            }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 8; ++e) {
             const uint32_t u = key[e];
             if (u > t1) { t2 = t1; t1 = u; } else if (u > t2) { t2 = u; }
         }
@@ -432,10 +439,15 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, 
     uint64_t* mine = s_c + wave * CW;
     for (int b0 = lo; b0 < hi; b0 += 64 * 4) {
         uint32_t key[4];
+        if (b0 + 64 * 4 <= hi) {   // the whole step inside the quarter (the same for the whole wave)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = b0 + 64 * e + lane;
-            key[e] = j < hi ? order_key(s[j]) : 0u;
+            for (int e = 0; e < 4; ++e) key[e] = order_key(s[b0 + 64 * e + lane]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = b0 + 64 * e + lane;
+                key[e] = j < hi ? order_key(s[j]) : 0u;
+            }
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
