@@ -90,7 +90,27 @@ __global__ __launch_bounds__(256) void q_corr_kernel(QCorrArgs a)
             s_x[k] = b.x[u];
         }
         __syncthreads();
-        for (int k = 0; k < nk; ++k) {
+        int k = 0;
+        if (j0 + QCHUNK <= w.m) {
+            // a chunk inside the row: four rows of Q (sixteen loads per thread) requested together; a
+            // guarded load compiles to a branch that waits for its data, one row after another
+            for (; k + 4 <= nk; k += 4) {
+                double qv[4][QCHUNK / 256];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double* qrow = a.Q + (int64_t)s_atom[k + e] * a.ldq + j0 + tid;
+#pragma unroll
+                    for (int t = 0; t < QCHUNK / 256; ++t) qv[e][t] = qrow[256 * t];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double xk = s_x[k + e];
+#pragma unroll
+                    for (int t = 0; t < QCHUNK / 256; ++t) g[t] -= xk * qv[e][t];
+                }
+            }
+        }
+        for (; k < nk; ++k) {
             const double xk = s_x[k];
             const double* qrow = a.Q + (int64_t)s_atom[k] * a.ldq;
 #pragma unroll
