@@ -1331,11 +1331,20 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
             const int n4 = w.kpad / 4;
             for (int k0 = lane; k0 < n4; k0 += 64 * 4) {
                 float4 fa[4], fb[4];
+                // inside the vectors for the whole wave: no branch, so the eight loads are in flight together
+                if (k0 - lane + 64 * 4 <= n4) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = k0 + 64 * e;
-                    fa[e] = k < n4 ? aj[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    fb[e] = k < n4 ? b4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int e = 0; e < 4; ++e) {
+                        fa[e] = aj[k0 + 64 * e];
+                        fb[e] = b4[k0 + 64 * e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = k0 + 64 * e;
+                        fa[e] = k < n4 ? aj[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                        fb[e] = k < n4 ? b4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e)

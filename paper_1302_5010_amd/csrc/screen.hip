@@ -83,6 +83,17 @@ __device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4
     double acc = 0.0;
     for (int q0 = lane; q0 < n4; q0 += 64 * CH) {
         float4 fx[CH];
+        if (q0 - lane + 64 * CH <= n4) {   // the whole step inside the vectors (the same for the whole wave):
+#pragma unroll                             // no branch, so the loads are all in flight at once
+            for (int e = 0; e < CH; ++e) fx[e] = x[q0 + 64 * e];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const float4 fy = y[q0 + 64 * e];
+                acc += (double)fx[e].x * fy.x + (double)fx[e].y * fy.y + (double)fx[e].z * fy.z +
+                       (double)fx[e].w * fy.w;
+            }
+            continue;
+        }
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = q0 + 64 * e;
