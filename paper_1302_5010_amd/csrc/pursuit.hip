@@ -130,6 +130,12 @@ __device__ double* arena_alloc(Arena* A, unsigned long long sz)
     return nullptr;
 }
 
+// The factor when it is held in LDS, addressed as LDS: the compiler then reads it with LDS
+// instructions instead of generic (flat) ones, which wait on both memory counters.
+typedef __attribute__((address_space(3))) double lds_double;
+__device__ __forceinline__ lds_double* to_lds(double* p) { return (lds_double*)p; }
+__device__ __forceinline__ const lds_double* to_lds(const double* p) { return (const lds_double*)p; }
+
 // Per-signal working view inside the solve kernel.  G is global (row-major,
 // stride K); the rest points into LDS or into the global homes.
 struct Sig {
@@ -171,13 +177,14 @@ __device__ inline int split_lanes(int s) { return s <= NT / 4 ? 4 : (s <= NT / 2
 
 // z[i] = sum_{k <= i} R(i, k) v[k] for i < s (packed lower factor in LDS), split_lanes(s) lanes per
 // row combined by shuffles inside the group.  Returns this lane's share of sum_i z_i^2.
-__device__ inline double rows_matvec_lds(const double* R, const double* v, double* z, int s)
+template <class VP>
+__device__ inline double rows_matvec_lds_t(const lds_double* R, VP v, double* z, int s)
 {
     const int P = split_lanes(s);
     const int sub = threadIdx.x & (P - 1);
     double part = 0.0;
     for (int i = threadIdx.x / P; i < s; i += NT / P) {   // the P lanes of a group share i
-        const double* Ri = R + tri(i);
+        const lds_double* Ri = R + tri(i);
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int k = sub;
         for (; k + 3 * P <= i; k += 4 * P) {
@@ -196,9 +203,18 @@ __device__ inline double rows_matvec_lds(const double* R, const double* v, doubl
     return part;
 }
 
+__device__ inline double rows_matvec_lds(const double* Rg, const double* v, double* z, int s)
+{
+    // the vector too is addressed as LDS when it lives there (the usual case)
+    if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(v)))
+        return rows_matvec_lds_t(to_lds(Rg), to_lds(v), z, s);
+    return rows_matvec_lds_t(to_lds(Rg), v, z, s);
+}
+
 // out[k] = (sum_{i = k}^{s-1} v[i] R(i, k)) / div for k < s (packed lower factor in LDS),
 // split_lanes(s) lanes per column.
-__device__ inline void cols_matvec_lds(const double* R, const double* v, double* out, int s, double div)
+template <class VP, class OP>
+__device__ inline void cols_matvec_lds_t(const lds_double* R, VP v, OP out, int s, double div)
 {
     const int P = split_lanes(s);
     const int sub = threadIdx.x & (P - 1);
@@ -217,23 +233,35 @@ __device__ inline void cols_matvec_lds(const double* R, const double* v, double*
     }
 }
 
+// out[k] = (sum_{i >= k} v[i] R(i, k)) / div for k < s (the factor in LDS), split_lanes(s) lanes per
+// column; the vector and the output are addressed as LDS too when both live there.
+__device__ inline void cols_matvec_lds(const double* R, const double* v, double* out, int s, double div)
+{
+    if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(v)) &&
+        __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(out)))
+        cols_matvec_lds_t(to_lds(R), to_lds(v), to_lds(out), s, div);
+    else
+        cols_matvec_lds_t(to_lds(R), v, out, s, div);
+}
+
 // sum_{i = k}^{s-1} v[i] R(i, k) over column k of a packed lower factor.
 __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
 {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (f.r_lds) {
+        const lds_double* R = to_lds(f.R);
         int i = k;
-        int64_t o = tri(k) + k;              // offset of R(i, k); the next row adds i + 1
+        int o = (int)(tri(k) + k);           // offset of R(i, k); the next row adds i + 1
         for (; i + 4 <= s; i += 4) {
-            const int64_t o1 = o + i + 1, o2 = o1 + i + 2, o3 = o2 + i + 3;
-            a0 += v[i] * f.R[o];
-            a1 += v[i + 1] * f.R[o1];
-            a2 += v[i + 2] * f.R[o2];
-            a3 += v[i + 3] * f.R[o3];
+            const int o1 = o + i + 1, o2 = o1 + i + 2, o3 = o2 + i + 3;
+            a0 += v[i] * R[o];
+            a1 += v[i + 1] * R[o1];
+            a2 += v[i + 2] * R[o2];
+            a3 += v[i + 3] * R[o3];
             o = o3 + i + 4;
         }
         for (; i < s; ++i) {
-            a0 += v[i] * f.R[o];
+            a0 += v[i] * R[o];
             o += i + 1;
         }
     } else {
