@@ -552,6 +552,9 @@ def main():
         "solve_phase_us_per_step_summed_over_signals": dict(zip(
             ("load", "gram", "active_set", "certificate", "appends_within_active_set", "writeback"),
             tph["solve_phase_us"])),
+        "active_set_steps_us_per_step_summed_over_signals": dict(zip(
+            ("drops", "sign_fixed_minimiser", "gradients_outside_S", "violator_list", "ratio_test",
+             "residual_after_writeback"), tph["solve_step_us"])),
         "autotune": tune,
         "signals": {"converged_per_step": conv, "kkt_max": float(np.max(kkt)),
                     "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),

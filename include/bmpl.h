@@ -99,9 +99,13 @@ typedef enum {
 #define BMPL_FLAG_PHASES 16         /* with TIMING: also count the master-problem kernel's phases, factor
                                        appends, drops and solves (device atomics and clock reads inside the
                                        kernel, which slow it; the per-kernel times of TIMING alone do not) */
-#define BMPL_FLAG_SINGLE_APPEND 8   /* grow the master problem's inverse Cholesky factor one atom at a
-                                       time instead of in blocks of up to 8 (same factor in exact
-                                       arithmetic; a diagnostic and comparison switch) */
+#define BMPL_FLAG_BLOCK_APPEND 8    /* grow the master problem's inverse Cholesky factor in blocks of up
+                                       to 8 atoms when it lives in global memory, instead of one atom at
+                                       a time (same factor in exact arithmetic).  Off by default: on the
+                                       4096-signal ragged batch (1024 x 32768, supports up to ~980) the
+                                       block path left 15 to 30 signals unconverged, different ones from
+                                       run to run (cause not found), and took longer than single appends
+                                       (19-20 s against 14.5 s); it passes the smaller parity cases */
 
 /* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning), signals x atoms (waves of
  * 64 lanes, each computing the sub-tile in parentheses): 0 128x128 (64x64), 1 256x256 (64x64, 16 waves),
@@ -338,9 +342,12 @@ typedef struct {
     int64_t factor_drops;       /* support positions removed at a zero crossing */
     int64_t sign_fixed_solves;  /* sign-fixed minimiser evaluations */
     double corr_roof_ms;        /* roofline time of the correlation launches (see above) */
-    double solve_step_us[3];    /* with BMPL_FLAG_PHASES: time inside the active-set iterations spent in
+    double solve_step_us[6];    /* with BMPL_FLAG_PHASES: time inside the active-set iterations spent in
                                    [0] factor downdates (drops), [1] sign-fixed minimiser evaluations,
-                                   [2] gradients outside S, summed over workgroups (microseconds) */
+                                   [2] gradients outside S, [3] the violator list and its ranking,
+                                   [4] the ratio test and step toward the minimiser; [5] the residual
+                                   and objective after the write-back; summed over workgroups
+                                   (microseconds) */
 } bmpl_timing;
 
 /* Copy the accumulated timing into *t.  Errors: BMPL_E_INVALID for NULL. */

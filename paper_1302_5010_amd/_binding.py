@@ -40,7 +40,7 @@ class Timing(ctypes.Structure):
                 ("wall_ms", ctypes.c_double), ("solves", ctypes.c_int64), ("outer_iters", ctypes.c_int64),
                 ("solve_phase_us", ctypes.c_double * 6), ("factor_appends", ctypes.c_int64),
                 ("factor_drops", ctypes.c_int64), ("sign_fixed_solves", ctypes.c_int64),
-                ("corr_roof_ms", ctypes.c_double), ("solve_step_us", ctypes.c_double * 3)]
+                ("corr_roof_ms", ctypes.c_double), ("solve_step_us", ctypes.c_double * 6)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -52,7 +52,7 @@ class Timing(ctypes.Structure):
 BMPL_FLAG_TIMING = 1
 BMPL_FLAG_NO_GRAM_TABLE = 2
 BMPL_FLAG_GRAPH = 4
-BMPL_FLAG_SINGLE_APPEND = 8
+BMPL_FLAG_BLOCK_APPEND = 8
 BMPL_FLAG_PHASES = 16
 BMPL_FLAG_Q_ROUTE = 32
 CORR_SHAPES = 11       # BMPL_CORR_SHAPES
@@ -161,7 +161,7 @@ class Solver:
 
     def __init__(self, At: torch.Tensor, lam: float, mode: str = "abs", rho: int = 10, max_outer: int = 0,
                  max_active: int = 0, kkt_tol: float = 1e-4, screen: str = "fp32", timing: bool = False,
-                 gram_table: bool = True, graph: bool = False, block_append: bool = True, phases: bool = False,
+                 gram_table: bool = True, graph: bool = False, block_append: bool = False, phases: bool = False,
                  q_route: bool = False, omega: int = 1, eps_early: float = 0.0, r_inf_rel: float = 0.0,
                  r2_rel: float = 0.0, stream=None):
         At = _dev(At, torch.float32, "At")
@@ -173,7 +173,7 @@ class Solver:
         o.eps_early, o.r_inf_rel, o.r2_rel = eps_early, r_inf_rel, r2_rel
         o.screen = _PREC[screen]
         o.flags = ((BMPL_FLAG_TIMING if timing else 0) | (0 if gram_table else BMPL_FLAG_NO_GRAM_TABLE)
-                   | (BMPL_FLAG_GRAPH if graph else 0) | (0 if block_append else BMPL_FLAG_SINGLE_APPEND)
+                   | (BMPL_FLAG_GRAPH if graph else 0) | (BMPL_FLAG_BLOCK_APPEND if block_append else 0)
                    | (BMPL_FLAG_PHASES if phases else 0) | (BMPL_FLAG_Q_ROUTE if q_route else 0))
         self.options = o
         self.max_active = max_active if max_active > 0 else min(self.m, 2 * self.n)

@@ -100,7 +100,7 @@ struct bmpl_ctx {
     int* ncand = nullptr;         // [p_cap]
     uint16_t* diag16 = nullptr;   // bfloat16 staging of bmpl_correlate
     size_t lds_dyn_max = 0;       // dynamic LDS a solve workgroup may use (bytes)
-    bool block_append = true;     // inverse-factor appends in blocks (BMPL_FLAG_SINGLE_APPEND clears it)
+    bool block_append = false;    // inverse-factor appends in blocks (BMPL_FLAG_BLOCK_APPEND sets it)
     bool qroute = false;          // correlation as beta - Q_{:,S} x_S after the first pass (BMPL_FLAG_Q_ROUTE)
     double* beta = nullptr;       // [p_cap][ldg] beta = A^T b in float64 (Q-route)
     bmpl_lambda_mode mode = BMPL_LAMBDA_ABS;
@@ -138,7 +138,7 @@ struct bmpl_ctx {
     size_t ev_used = 0;
     struct Span { size_t a, b; int kind; double flops, bytes, roof_ms; };
     std::vector<Span> spans;
-    uint64_t* phase_dev = nullptr;     // [12] solve-kernel phase ticks and counters
+    uint64_t* phase_dev = nullptr;     // [15] solve-kernel phase ticks and counters
     int wall_khz = 0;
 
     // graph capture of iteration segments (BMPL_FLAG_GRAPH)
@@ -562,7 +562,7 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         if (e == hipSuccess) e = hipMemcpyAsync(c->ascale8 + m, &one, sizeof(float), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    c->block_append = !(opt.flags & BMPL_FLAG_SINGLE_APPEND);
+    c->block_append = (opt.flags & BMPL_FLAG_BLOCK_APPEND) != 0;
     c->qroute = (opt.flags & BMPL_FLAG_Q_ROUTE) != 0;
     // Gram table Q = A^T A (float64) unless disabled or larger than the table budget.
     const double q_bytes = 8.0 * (double)m * (double)m;
@@ -806,8 +806,8 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
     c->ev_used = 0;
     const bool phases = tm && (c->opt.flags & BMPL_FLAG_PHASES);
     if (phases && !c->phase_dev) {
-        HIPC(dalloc(&c->phase_dev, 12));
-        HIPC(hipMemsetAsync(c->phase_dev, 0, 12 * sizeof(uint64_t), s));
+        HIPC(dalloc(&c->phase_dev, PHASE_SLOTS));
+        HIPC(hipMemsetAsync(c->phase_dev, 0, PHASE_SLOTS * sizeof(uint64_t), s));
         HIPC(hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, c->device));
     }
     const size_t ev_first = tm ? mark(c, s) : (size_t)-1;
@@ -1268,10 +1268,10 @@ bmpl_status bmpl_get_timing(const bmpl_ctx* c, bmpl_timing* t)
     if (!c || !t) return fail(BMPL_E_INVALID, "bmpl_get_timing: NULL argument");
     *t = c->timing;
     if (c->phase_dev && c->wall_khz > 0) {
-        uint64_t ticks[12];
+        uint64_t ticks[PHASE_SLOTS];
         HIPC(hipMemcpy(ticks, c->phase_dev, sizeof ticks, hipMemcpyDeviceToHost));
         for (int i = 0; i < 6; ++i) t->solve_phase_us[i] = (double)ticks[i] * 1e3 / c->wall_khz;
-        for (int i = 0; i < 3; ++i) t->solve_step_us[i] = (double)ticks[9 + i] * 1e3 / c->wall_khz;
+        for (int i = 0; i < 6; ++i) t->solve_step_us[i] = (double)ticks[9 + i] * 1e3 / c->wall_khz;
         t->factor_appends = (int64_t)ticks[6];
         t->factor_drops = (int64_t)ticks[7];
         t->sign_fixed_solves = (int64_t)ticks[8];
@@ -1283,7 +1283,7 @@ bmpl_status bmpl_reset_timing(bmpl_ctx* c)
 {
     if (!c) return fail(BMPL_E_INVALID, "bmpl_reset_timing: NULL context");
     c->timing = bmpl_timing{};
-    if (c->phase_dev) HIPC(hipMemset(c->phase_dev, 0, 12 * sizeof(uint64_t)));
+    if (c->phase_dev) HIPC(hipMemset(c->phase_dev, 0, PHASE_SLOTS * sizeof(uint64_t)));
     return BMPL_OK;
 }
 

@@ -69,10 +69,14 @@ struct SolveArgs {
                                     // exploratory pass, whose scratch lists live there)
     int zs_lds;                     // block-append scratch in LDS after the vectors (else single appends)
     int smpl_keep;                  // > 0: subspace exploratory matching keeps this many of the new atoms
-    uint64_t* phase;                // [9]: wall-clock ticks of phases 0-5 summed over workgroups,
-                                    // then counts of factor appends, drops and solves; or null
+    uint64_t* phase;                // [PHASE_SLOTS]: wall-clock ticks of phases 0-5 summed over workgroups,
+                                    // counts of factor appends, drops and solves, then ticks of the
+                                    // active-set steps (drops, minimiser, gradients, violator list,
+                                    // ratio test) and of the residual; or null
 };
 
+
+constexpr int PHASE_SLOTS = 15;     // solve-kernel phase ticks and counters (SolveArgs::phase)
 
 struct GrowArgs {
     Workspace w;

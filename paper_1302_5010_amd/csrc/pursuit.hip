@@ -40,6 +40,11 @@ constexpr int NB = 16;      // new atoms per Gram pass
 constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
 constexpr int JADD = 8;     // most violators added to S per active-set step (the largest ones)
 constexpr int LAZY_MIN = 32;   // new slots in one pass above which the Gram matrix is kept lazily
+// Exclusion flag of a slot left out of S for the rest of one pass (cleared at the write-back): an
+// atom admitted alone whose sign-fixed coefficient came out with the wrong sign.  Alone, its exact
+// coefficient is (|g_u| - lambda) / pivot^2 > 0, so the wrong sign means |g_u| exceeds lambda by
+// less than the rounding of x*; it would be dropped with no step and admitted again at once.
+constexpr unsigned char EX_PASS = 2;
 constexpr int JB = SOLVE_JB;   // atoms per block factor append
 
 __device__ inline double block_sum(double v, double* red)
@@ -1277,7 +1282,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     __syncthreads();
 
     // Optional per-phase wall-clock ticks (kernel timing mode): load, Gram, active set,
-    // certificate, residual, write-back.
+    // certificate, (appends), write-back; the residual's ticks go to slot 14.
     auto phase_mark = [&](int ph) {
         if (a.phase && tid == 0) {
             const uint64_t now = wall_clock64();
@@ -1408,6 +1413,7 @@ active_set:
         const uint64_t tg = a.phase ? wall_clock64() : 0;
         grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, true);
         sub_ticks(11, tg);
+        const uint64_t tv = a.phase ? wall_clock64() : 0;
         if (wave == 0) {    // violators outside S, in slot order
             int base = 0;
             for (int u0 = 0; u0 < nI && base < NT; u0 += 64) {
@@ -1452,6 +1458,7 @@ active_set:
             __syncthreads();
             nv = jadd;
         }
+        sub_ticks(12, tv);
         if (lazy && nv > 0) {
             // lazy Gram: the columns of the slots about to enter S, against every slot of I
             const int tot = nv * nI;
@@ -1518,6 +1525,7 @@ active_set:
                 xs_ok = true;
             }
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 8), 1ull);
+            const uint64_t tr = a.phase ? wall_clock64() : 0;
             double alpha = 1.0;
             int q = -1;
             for (int k = tid; k < nS; k += NT) {
@@ -1535,7 +1543,10 @@ active_set:
                 s.x[u] = xo + alpha * (vx[k] - xo);
             }
             __syncthreads();
+            sub_ticks(13, tr);
             if (q < 0) break;
+            // the atom admitted alone blocks at alpha = 0: a numerically void admission (EX_PASS)
+            const bool void_admit = alpha == 0.0 && dropped == 0 && nS == nS_before + 1 && q == nS_before;
             ++dropped;
             // drop position q: downdate the factor (or truncate it and append the later positions again)
             if (a.phase && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.phase + 7), 1ull);
@@ -1546,6 +1557,7 @@ active_set:
                 const int u = vatom[q];
                 s.x[u] = 0.0;
                 s.th[u] = 0;
+                if (void_admit) s.ex[u] = EX_PASS;
             }
             __syncthreads();
             // downdate the factor in place (vw is free scratch here); support positions past q move down
@@ -1656,12 +1668,15 @@ active_set:
     phase_mark(3);
 
 
-    // 5. Write the state back.
+    // 5. Write the state back (slots left out for this pass only may enter S again).
     if (a.vec_lds) {
         for (int u = tid; u < nI; u += NT) {
-            g_x[u] = s.x[u]; g_c[u] = s.c[u]; g_th[u] = s.th[u]; g_ex[u] = s.ex[u];
+            g_x[u] = s.x[u]; g_c[u] = s.c[u]; g_th[u] = s.th[u]; g_ex[u] = s.ex[u] == EX_PASS ? 0 : s.ex[u];
         }
         for (int k = tid; k < nS; k += NT) g_so[k] = s.so[k];
+    } else {
+        for (int u = tid; u < nI; u += NT)
+            if (g_ex[u] == EX_PASS) g_ex[u] = 0;
     }
     if (s.r_lds)
         for (int64_t i = tid; i < tri(nS); i += NT) g_R[i] = s.R[i];
@@ -1674,6 +1689,7 @@ active_set:
         if (inexact) w.status[sig] |= BMPL_SIG_INEXACT;
     }
     phase_mark(5);
+    const uint64_t t_res = a.phase ? wall_clock64() : 0;
 
     // 6. Residual and objective (step 7), from the support's values and atoms gathered into vw / vz
     //    (free after the certificate).
@@ -1691,6 +1707,7 @@ active_set:
         const double xl1 = block_sum(l1, red);    // also orders the writes above
         residual_tail(w, sig, a.At, a.lda, a.Bw, sx, satom, nS, xl1, red);
     }
+    sub_ticks(14, t_res);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void solve_kernel(SolveArgs a) { solve_body<false>(a); }
