@@ -102,10 +102,8 @@ typedef enum {
 #define BMPL_FLAG_BLOCK_APPEND 8    /* grow the master problem's inverse Cholesky factor in blocks of up
                                        to 8 atoms when it lives in global memory, instead of one atom at
                                        a time (same factor in exact arithmetic).  Off by default: on the
-                                       4096-signal ragged batch (1024 x 32768, supports up to ~980) the
-                                       block path left 15 to 30 signals unconverged, different ones from
-                                       run to run (cause not found), and took longer than single appends
-                                       (19-20 s against 14.5 s); it passes the smaller parity cases */
+                                       4096-signal ragged batch (1024 x 32768, supports up to ~980)
+                                       single appends take 14.4 s against 17.0 s */
 
 /* Tile shapes of the correlation kernel (bmpl_autotune, bmpl_set_tuning), signals x atoms (waves of
  * 64 lanes, each computing the sub-tile in parentheses): 0 128x128 (64x64), 1 256x256 (64x64, 16 waves),

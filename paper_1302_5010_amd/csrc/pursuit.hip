@@ -549,6 +549,8 @@ __device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
         double last = v.R[tri(q) + q];
         double b = q + 1 < s ? v.R[tri(q + 1) + q] : 0.0;
         double zcar = (zc && tid == 0) ? zc[q] : 0.0;
+        // every thread has its R(q, q) before the owner of column q rewrites row q in the first rotation
+        __syncthreads();
         for (int j = q; j < s - 1; ++j) {
             // prefetch row j + 2 (the next iteration's row), columns shifted past the moved one
             double nn[DROP_COLS];
