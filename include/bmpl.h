@@ -110,9 +110,11 @@ typedef enum {
  * 2 256x128 (64x64), 3 64x128 (32x64), 4 32x64 (32x32), 5 64x64 (32x32), 6 256x256 (128x128, 4 waves),
  * 7 256x256 (128x64, 8 waves); bfloat16 screening only (the dictionary's fragments read from global
  * memory in the matrix instruction's order, the residual tile through LDS): 8 256x256 (128x64, 8 waves),
- * 9 128x256 (64x64, 8 waves), 10 256x128 (128x64, 4 waves).  A shape a precision lacks is rejected by
- * bmpl_set_tuning and not timed by bmpl_autotune. */
-#define BMPL_CORR_SHAPES 11
+ * 9 128x256 (64x64, 8 waves), 10 256x128 (128x64, 4 waves); both operand tiles copied from global
+ * memory straight into LDS (no staging registers): 11 256x256 (128x64, 8 waves), 12 256x256 (64x64, 16
+ * waves), 13 128x128 (64x64, 4 waves), 14 256x256 (128x128, 4 waves).  A shape a precision lacks is
+ * rejected by bmpl_set_tuning and not timed by bmpl_autotune. */
+#define BMPL_CORR_SHAPES 15
 
 /* bmpl_create precomputes the float64 Gram table Q = A^T A (8 m^2 bytes, the
  * precomputed Q of Section III, Eq. (12)) when it is at most this large. */

@@ -55,7 +55,7 @@ BMPL_FLAG_GRAPH = 4
 BMPL_FLAG_BLOCK_APPEND = 8
 BMPL_FLAG_PHASES = 16
 BMPL_FLAG_Q_ROUTE = 32
-CORR_SHAPES = 11       # BMPL_CORR_SHAPES
+CORR_SHAPES = 15       # BMPL_CORR_SHAPES
 
 
 class _Result(ctypes.Structure):

@@ -1247,9 +1247,9 @@ bmpl_status bmpl_autotune(bmpl_ctx* c, int32_t p, int32_t* shapes, double* ms, v
 bmpl_status bmpl_set_tuning(bmpl_ctx* c, const int32_t* shapes)
 {
     if (!c || !shapes) return fail(BMPL_E_INVALID, "bmpl_set_tuning: NULL argument");
-    const int nvar = (c->A16 && !c->A8) ? CORR_VARIANTS : 8;   // shapes 8.. exist for bfloat16 only
+    const bool bf16_only = c->A16 && !c->A8;   // shapes 8..10 exist for bfloat16 only
     for (int b = 0; b < 3; ++b)
-        if (shapes[b] < 0 || shapes[b] >= nvar)
+        if (shapes[b] < 0 || shapes[b] >= CORR_VARIANTS || (shapes[b] >= 8 && shapes[b] <= 10 && !bf16_only))
             return fail(BMPL_E_INVALID, "bmpl_set_tuning: shape %d out of range for this precision", shapes[b]);
     for (int b = 0; b < 3; ++b) c->corr_shape[b] = shapes[b];
     return BMPL_OK;

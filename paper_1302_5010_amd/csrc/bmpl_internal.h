@@ -160,8 +160,8 @@ struct Workspace {
 // Rbuf: [*][ldr] float32, ldr % 4 == 0, columns zero-padded to kpad; row `zero_row` all zero.
 // act == nullptr means the identity map.  If n_act_dev != nullptr the active count is
 // read on the device and `p_grid` only sizes the grid.
-// `variant` selects the tile shape (0..7, see corr_shape_name).
-constexpr int CORR_VARIANTS = 11;  // == BMPL_CORR_SHAPES (8..10: bfloat16 only)
+// `variant` selects the tile shape (see corr_shape_name; 8..10 exist for bfloat16 only).
+constexpr int CORR_VARIANTS = 15;  // == BMPL_CORR_SHAPES (8..10: bfloat16 only)
 const char* corr_shape_name(int variant);
 hipError_t launch_corr_gemm_f32(int variant, const float* At, int64_t lda, int m, int kpad,
                                 const float* Rbuf, int64_t ldr, const int* act,

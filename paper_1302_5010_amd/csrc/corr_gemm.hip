@@ -26,6 +26,33 @@
 namespace bmpl {
 namespace {
 
+// Store a finished tile: D[row][col] of a 32x32 block (both instructions): lane l, register r -> row
+// 8(r/4) + 4(l/32) + r%4, col l%32.  e4m3 operands carry power-of-two scales: one per atom, one per signal.
+template <class E, int TI, int TJ>
+__device__ __forceinline__ void store_tile(const floatx16 (&acc)[TI][TJ], int sig0, int ws, int atom0, int wa, int l32,
+                                           int h, int m, int n_act, const int* __restrict__ act, float* __restrict__ G,
+                                           int64_t ldg, const float* __restrict__ ascale, const float* __restrict__ rscale)
+{
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int atom = atom0 + wa + 32 * j + l32;
+            if (atom >= m) continue;
+            const float sa = sizeof(E) == 1 ? ascale[atom] : 1.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (a < n_act) {
+                    if constexpr (sizeof(E) == 1)
+                        G[(int64_t)a * ldg + atom] = acc[i][j][r] * sa * rscale[act ? act[a] : a];
+                    else
+                        G[(int64_t)a * ldg + atom] = acc[i][j][r];
+                }
+            }
+        }
+}
+
 template <class E, int BM, int BN, int WM, int WN, int DEPTH>
 __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gemm_kernel(
     const E* __restrict__ At, int64_t lda, int m, int kpad,
@@ -79,37 +106,60 @@ __global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gem
     floatx16 acc[S::TI][S::TJ];
     mfma_tile_loop<E, BM, BN, WM, WN, DEPTH>(Rbuf, oR, At, oA, kpad, lds, ws, wa, acc);
 
-    // D[row][col] of a 32x32 block (both instructions): lane l, register r -> row 8(r/4) + 4(l/32) + r%4,
-    // col l%32.
-    if constexpr (sizeof(E) == 1) {
-        // e4m3 operands carry power-of-two scales: one per atom, one per signal
+    store_tile<E, S::TI, S::TJ>(acc, sig0, ws, atom0, wa, l32, h, m, n_act, act, G, ldg, ascale, rscale);
+}
+
+// The same product with both operand tiles copied straight into swizzled LDS buffers (mfma_tile_loop_dma).
+template <class E, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((TileShape<BM, BN, WM, WN>::THREADS)) void corr_gemm_dma_kernel(
+    const E* __restrict__ At, int64_t lda, int m, int kpad,
+    const E* __restrict__ Rbuf, int64_t ldr, const int* __restrict__ act,
+    const int* __restrict__ n_act_dev, int p_grid, float* __restrict__ G, int64_t ldg, int tiles_n, int zero_row,
+    int n_lo, int n_hi, const float* __restrict__ ascale, const float* __restrict__ rscale)
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    using D = DmaShape<BM, BN, WM, WN>;
+    const int n_act = n_act_dev ? *n_act_dev : p_grid;
+    if (n_act < n_lo || n_act >= n_hi) return;   // another tile shape serves this running count
+    const int tiles_m = ((n_act < p_grid ? n_act : p_grid) + BM - 1) / BM;   // as in corr_gemm_kernel
+    const int nwg = tiles_m * tiles_n;
+    if ((int)blockIdx.x >= nwg) return;
+    const int tile = xcd_tile_index(blockIdx.x, nwg);
+    int tm, tn;
+    grouped_tile<8>(tile, tiles_m, tiles_n, tm, tn);
+    if (tn >= tiles_n) return;
+    const int sig0 = tm * BM;
+    const int atom0 = tn * BN;
+    if (sig0 >= n_act) return;
+
+    __shared__ __attribute__((aligned(1024))) DmaLds<BM, BN> lds;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    constexpr int VE = 16 / (int)sizeof(E);          // k per 16-byte chunk
+    // rows past the end read an all-zero row (row zero_row of the residuals, row m of the dictionary)
+    int64_t oR[D::GX], oA[D::GW];
 #pragma unroll
-        for (int i = 0; i < S::TI; ++i)
-#pragma unroll
-            for (int j = 0; j < S::TJ; ++j) {
-                const int atom = atom0 + wa + 32 * j + l32;
-                if (atom >= m) continue;
-                const float sa = ascale[atom];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r] * sa * rscale[act ? act[a] : a];
-                }
-            }
-    } else {
-#pragma unroll
-        for (int i = 0; i < S::TI; ++i)
-#pragma unroll
-            for (int j = 0; j < S::TJ; ++j) {
-                const int atom = atom0 + wa + 32 * j + l32;
-                if (atom >= m) continue;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int a = sig0 + ws + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (a < n_act) G[(int64_t)a * ldg + atom] = acc[i][j][r];
-                }
-            }
+    for (int i = 0; i < D::GX; ++i) {
+        const int g = wave + S::WAVES * i;
+        const int a = sig0 + dma_row(g, lane);
+        const int sg = a < n_act ? (act ? act[a] : a) : zero_row;
+        oR[i] = (int64_t)sg * ldr + VE * dma_chunk(g, lane);
     }
+#pragma unroll
+    for (int i = 0; i < D::GW; ++i) {
+        const int g = wave + S::WAVES * i;
+        const int j = atom0 + dma_row(g, lane);
+        oA[i] = (int64_t)(j < m ? j : m) * lda + VE * dma_chunk(g, lane);
+    }
+    const int ws = (wave % S::WAVES_M) * WM;
+    const int wa = (wave / S::WAVES_M) * WN;
+    const int l32 = lane & 31;
+    const int h = lane >> 5;
+    floatx16 acc[S::TI][S::TJ];
+    mfma_tile_loop_dma<E, BM, BN, WM, WN>(Rbuf, oR, At, oA, kpad, lds, ws, wa, acc);
+    store_tile<E, S::TI, S::TJ>(acc, sig0, ws, atom0, wa, l32, h, m, n_act, act, G, ldg, ascale, rscale);
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -295,6 +345,21 @@ hipError_t launch_shape(const E* At, int64_t lda, int m, int kpad, const E* Rbuf
     return hipGetLastError();
 }
 
+template <class E, int BM, int BN, int WM, int WN>
+hipError_t launch_dma(const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr, const int* act,
+                      const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row, int n_lo, int n_hi,
+                      const float* ascale, const float* rscale, hipStream_t stream)
+{
+    const int tiles_m = (p_grid + BM - 1) / BM;
+    const int tiles_n = (m + BN - 1) / BN;
+    const int64_t nwg = (int64_t)tiles_m * tiles_n;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((corr_gemm_dma_kernel<E, BM, BN, WM, WN>), dim3((unsigned)nwg),
+                       dim3(TileShape<BM, BN, WM, WN>::THREADS), 0, stream, At, lda, m, kpad, Rbuf, ldr, act,
+                       n_act_dev, p_grid, G, ldg, tiles_n, zero_row, n_lo, n_hi, ascale, rscale);
+    return hipGetLastError();
+}
+
 template <class E>
 hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad, const E* Rbuf, int64_t ldr,
                           const int* act, const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
@@ -315,6 +380,10 @@ hipError_t launch_variant(int variant, const E* At, int64_t lda, int m, int kpad
     case 5: return launch_shape<E, 64, 64, 32, 32, DEEP>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 6: return launch_shape<E, 256, 256, 128, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     case 7: return launch_shape<E, 256, 256, 128, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 11: return launch_dma<E, 256, 256, 128, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 12: return launch_dma<E, 256, 256, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 13: return launch_dma<E, 128, 128, 64, 64>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
+    case 14: return launch_dma<E, 256, 256, 128, 128>(At, lda, m, kpad, Rbuf, ldr, act, n_act_dev, p_grid, G, ldg, zero_row, n_lo, n_hi, ascale, rscale, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -335,6 +404,10 @@ const char* corr_shape_name(int v)
     case 5: return "64x64 (4 waves of 32x32)";
     case 6: return "256x256 (4 waves of 128x128)";
     case 7: return "256x256 (8 waves of 128x64)";
+    case 11: return "256x256 (8 waves of 128x64), operand tiles copied straight into LDS";
+    case 12: return "256x256 (16 waves of 64x64), operand tiles copied straight into LDS";
+    case 13: return "128x128 (4 waves of 64x64), operand tiles copied straight into LDS";
+    case 14: return "256x256 (4 waves of 128x128), operand tiles copied straight into LDS";
     default: return "?";
     }
 }
@@ -379,7 +452,7 @@ hipError_t launch_corr_gemm_bf16(int variant, const uint16_t* At, const uint16_t
                                  const int* n_act_dev, int p_grid, float* G, int64_t ldg, int zero_row,
                                  int n_lo, int n_hi, hipStream_t stream)
 {
-    if (variant >= 8) {
+    if (variant >= 8 && variant <= 10) {
         if (!Apk || p_grid <= 0 || m <= 0) return Apk ? hipSuccess : hipErrorInvalidValue;
         if (kpad % 64) return hipErrorInvalidValue;
         switch (variant) {

@@ -235,6 +235,165 @@ __device__ __forceinline__ void mfma_tile_loop(const E* __restrict__ X, const in
 #undef TILE_STORE_SLICE
 }
 
+// ---------------------------------------------------------------------------------------------------
+// The same contraction with the operand tiles copied from global memory straight into LDS
+// (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's LDS base + 16 lane), so the slices
+// take no registers and no LDS store instructions, and a stage waits for its copies only at its end.
+//
+// LDS rows are 128 bytes with no padding.  Chunk c (16 bytes of k) of tile row r sits at slot
+// c ^ dma_swz(r), dma_swz(r) = (r & 7) ^ ((r >> 3) & 1): the 32 rows of one chunk that a fragment read
+// touches then fall on distinct banks within every 8 consecutive lanes (128 bytes) and every 16 (256
+// bytes).  One copy instruction fills 8 consecutive rows (1 KB): lane l writes slot l & 7 of row
+// 8 g + (l >> 3), so it loads chunk (l & 7) ^ (l >> 3) ^ (g & 1) of that row.  Two LDS buffers: the copy
+// of slice s + 1 is issued at the top of stage s into the buffer stage s - 1 read, and every wave waits
+// for its own copies and then the barrier before stage s + 1 reads them.
+// ---------------------------------------------------------------------------------------------------
+__device__ __forceinline__ int dma_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+template <int BM, int BN>
+struct DmaLds {
+    char x[2][BM * TILE_ROW_BYTES];
+    char w[2][BN * TILE_ROW_BYTES];
+};
+
+template <int BM, int BN, int WM, int WN>
+struct DmaShape {
+    using S = TileShape<BM, BN, WM, WN>;
+    static constexpr int GX = BM / 8 / S::WAVES;   // 1 KB copies per wave and stage, X tile
+    static constexpr int GW = BN / 8 / S::WAVES;   // W tile
+    static_assert(GX * 8 * S::WAVES == BM && GW * 8 * S::WAVES == BN, "copy groups per wave");
+};
+
+// Tile row and chunk of this lane in copy group g (8 rows).
+__device__ __forceinline__ int dma_row(int g, int lane) { return 8 * g + (lane >> 3); }
+__device__ __forceinline__ int dma_chunk(int g, int lane) { return (lane & 7) ^ (lane >> 3) ^ (g & 1); }
+
+// The matrix work of one stage from swizzled buffers (same fragments, same order as mfma_tile_stage).
+template <class E, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_stage_swz(const char* cX, const char* cW, int ws, int wa, int l32, int h,
+                                                    floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    const int sw = dma_swz(l32);                    // ws + 32 i and wa + 32 j are multiples of 16
+    auto at = [&](const char* base, int row, int chunk) {
+        return *reinterpret_cast<const float4*>(base + row * TILE_ROW_BYTES + ((chunk ^ sw) << 4));
+    };
+    if constexpr (sizeof(E) == 1) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            intx8 fx[S::TI], fw[S::TJ];
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i) {
+                const float4 lo = at(cX, ws + 32 * i + l32, 4 * t + 2 * h), hi = at(cX, ws + 32 * i + l32, 4 * t + 2 * h + 1);
+                fx[i] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                              __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
+            }
+#pragma unroll
+            for (int j = 0; j < S::TJ; ++j) {
+                const float4 lo = at(cW, wa + 32 * j + l32, 4 * t + 2 * h), hi = at(cW, wa + 32 * j + l32, 4 * t + 2 * h + 1);
+                fw[j] = intx8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z), __float_as_int(lo.w),
+                              __float_as_int(hi.x), __float_as_int(hi.y), __float_as_int(hi.z), __float_as_int(hi.w)};
+            }
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < S::TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fx[i], fw[j], acc[i][j], 0, 0, 0, 127,
+                                                                               0, 127);
+        }
+    } else {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            float4 fx[S::TI], fw[S::TJ];
+#pragma unroll
+            for (int i = 0; i < S::TI; ++i) fx[i] = at(cX, ws + 32 * i + l32, 2 * kb + h);
+#pragma unroll
+            for (int j = 0; j < S::TJ; ++j) fw[j] = at(cW, wa + 32 * j + l32, 2 * kb + h);
+            if constexpr (sizeof(E) == 2) {
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fx[i]), __builtin_bit_cast(bf16x8, fw[j]), acc[i][j], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].x, fw[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].y, fw[j].y, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].z, fw[j].z, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[i].w, fw[j].w, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+typedef __attribute__((address_space(1))) const void global_cvoid;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wait for this wave's outstanding vector-memory operations (its LDS copies) only.
+__device__ __forceinline__ void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// K loop with direct-to-LDS copies.  oX / oW: per copy group of this wave, the element offset of this
+// lane's row and chunk (dma_row, dma_chunk) in X / W; rows past the end must be readable (zero rows).
+template <class E, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void mfma_tile_loop_dma(const E* __restrict__ X, const int64_t (&oX)[DmaShape<BM, BN, WM, WN>::GX],
+                                                   const E* __restrict__ W, const int64_t (&oW)[DmaShape<BM, BN, WM, WN>::GW],
+                                                   int kpad, DmaLds<BM, BN>& lds, int ws, int wa,
+                                                   floatx16 (&acc)[TileShape<BM, BN, WM, WN>::TI][TileShape<BM, BN, WM, WN>::TJ])
+{
+    using S = TileShape<BM, BN, WM, WN>;
+    using D = DmaShape<BM, BN, WM, WN>;
+    constexpr int BK = TILE_ROW_BYTES / (int)sizeof(E);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int l32 = lane & 31;
+    const int h = lane >> 5;
+    const int nst = kpad / BK;
+#pragma unroll
+    for (int i = 0; i < S::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < S::TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto issue = [&](int st, int buf) {
+        const int k0 = st * BK;
+#pragma unroll
+        for (int i = 0; i < D::GX; ++i)
+            __builtin_amdgcn_global_load_lds((global_cvoid*)(X + oX[i] + k0),
+                                             (lds_void*)(lds.x[buf] + (wave + S::WAVES * i) * 1024), 16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < D::GW; ++i)
+            __builtin_amdgcn_global_load_lds((global_cvoid*)(W + oW[i] + k0),
+                                             (lds_void*)(lds.w[buf] + (wave + S::WAVES * i) * 1024), 16, 0, 0);
+    };
+    issue(0, 0);
+    wait_vm0();
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < nst) issue(st + 1, cur ^ 1);
+        mfma_tile_stage_swz<E, BM, BN, WM, WN>(lds.x[cur], lds.w[cur], ws, wa, l32, h, acc);
+        wait_vm0();
+        __syncthreads();
+    }
+}
+
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
 // contiguous run of tile indices (neighbouring tiles share operand rows in that XCD's L2).
 __device__ __forceinline__ int xcd_tile_index(int wid, int nwg)

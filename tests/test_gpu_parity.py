@@ -61,17 +61,18 @@ def test_correlate_within_float32_bound(n, m, p):
 
 
 @pytest.mark.parametrize("screen", ["fp32", "bf16", "fp8"])
-@pytest.mark.parametrize("shape", range(11))
+@pytest.mark.parametrize("shape", range(15))
 def test_correlate_every_tile_shape(shape, screen):
     """Every tile shape within the precision's bound, entry by entry, and bit-identical to shape 0 (every
     shape feeds each output's accumulator the same k chunks in the same order; shapes 8-10, bfloat16
-    only, read the dictionary from its fragment-ordered copy)."""
+    only, read the dictionary from its fragment-ordered copy; shapes 11-14 copy both operand tiles
+    straight into swizzled LDS buffers)."""
     pk = _lib()
     rng = np.random.default_rng(shape)
     n, m = 160, 1500
     At = rng.standard_normal((m, n)).astype(np.float32)
     s = pk.Solver(to_dev(At), 0.1, screen=screen)
-    if shape >= 8 and screen != "bf16":
+    if 8 <= shape <= 10 and screen != "bf16":
         with pytest.raises(pk.BmplError):
             s.set_tuning([shape, shape, shape])
         return
