@@ -791,18 +791,21 @@ def test_ragged_supports_against_stored_oracle():
 
 
 @pytest.mark.slow
-def test_ragged_full_batch():
+@pytest.mark.parametrize("block_append", [False, True])
+def test_ragged_full_batch(block_append):
     """All 4096 ragged signals in one solve (graph segments; the active sets of the k >= 200 signals grow
     to ~1600 atoms, so each of their float64 Gram matrices of I reaches ~20 MB, while the k <= 150 signals
     stop with a few hundred slots: every signal's slot block follows its own |I|).  Every signal must
-    converge and the stored oracle rows must match."""
+    converge and the stored oracle rows must match, with single appends and with block appends (whose
+    kernel streams factors of up to ~980 positions from global memory through the Givens downdate's
+    register path, where a missing barrier once corrupted a few signals per run)."""
     pk = _lib()
     g, X = _golden_ragged()
     rows = [int(r) for r in g["rows"]]
     P = bi.ragged_gaussian()
     lam = lam_rel(P.At, P.Bt, P.lambda_rel)
     np.testing.assert_allclose(lam[rows], g["lam"], rtol=1e-15)
-    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True)
+    s = pk.Solver(to_dev(P.At), 0.0, rho=P.rho, graph=True, block_append=block_append)
     out = s.solve(to_dev(P.Bt), lam=to_dev(lam))
     torch.cuda.synchronize()
     st = out["status"].cpu().numpy()
