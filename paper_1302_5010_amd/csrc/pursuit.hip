@@ -156,20 +156,25 @@ struct Sig {
 };
 
 // z[i] = sum_{k <= i} R(i, k) w[k] for i < s with the factor in global memory: one row per wave at a
-// time, lanes across the row (coalesced, eight loads in flight), a wave reduction per row.
+// time, lanes across the row (coalesced, eight loads in flight: clamped indices, so no load is guarded
+// by a branch that would wait for it), a wave reduction per row.
 __device__ inline void rows_matvec_global(const double* R, const double* w, double* z, int s)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = wave; i < s; i += NT / 64) {
         const double* Ri = R + tri(i);
         double a0 = 0.0, a1 = 0.0;
-        for (int k0 = lane; k0 <= i; k0 += 512) {   // eight loads in flight per lane
-            double r[8];
+        for (int k0 = lane; k0 <= i; k0 += 512) {
+            double r[8], wv[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) r[e] = k0 + 64 * e <= i ? Ri[k0 + 64 * e] : 0.0;
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + 64 * e <= i ? k0 + 64 * e : i;
+                r[e] = Ri[k];
+                wv[e] = w[k];
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                if (k0 + 64 * e <= i) (e & 1 ? a1 : a0) += r[e] * w[k0 + 64 * e];
+                (e & 1 ? a1 : a0) += k0 + 64 * e <= i ? r[e] * wv[e] : 0.0;
         }
         const double acc = wave_sum(a0 + a1);
         if (lane == 0) z[i] = acc;
@@ -271,12 +276,14 @@ __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
         }
     } else {
         // global factor: rows in lockstep across the wave so loads of one row coalesce; eight rows'
-        // loads in flight
+        // loads in flight (rows above k read row k instead and count zero, so no load is guarded)
         int i = k & ~63;
         for (; i + 8 <= s; i += 8) {
             double r[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) r[e] = i + e >= k ? f.R[tri(i + e) + k] : 0.0;
+            for (int e = 0; e < 8; ++e) r[e] = f.R[tri(i + e >= k ? i + e : k) + k];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r[e] = i + e >= k ? r[e] : 0.0;
             a0 += v[i] * r[0] + v[i + 4] * r[4];
             a1 += v[i + 1] * r[1] + v[i + 5] * r[5];
             a2 += v[i + 2] * r[2] + v[i + 6] * r[6];
@@ -377,7 +384,7 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
             for (int k = lane; k <= i; k += 512) {   // eight loads in flight per lane, the row's tail too
                 double r[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) r[q] = k + 64 * q <= i ? Ri[k + 64 * q] : 0.0;
+                for (int q = 0; q < 8; ++q) r[q] = Ri[k + 64 * q <= i ? k + 64 * q : i];   // clamped, unguarded
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     if (k + 64 * q > i) break;
@@ -454,7 +461,12 @@ __device__ void chol_append_block(Sig& v, int& nS, const int* list, int J, const
         for (; i + 8 <= s0; i += 8) {              // eight rows' loads in flight
             double r[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) r[q] = (i + q >= k) ? v.R[tri(i + q) + k] : 0.0;
+            for (int q = 0; q < 8; ++q) {   // clamped to row >= column and column < s0: always inside the factor
+                const int kk = k < s0 ? k : s0 - 1;
+                r[q] = v.R[tri(i + q >= kk ? i + q : kk) + kk];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = i + q >= k ? r[q] : 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const double* zi = zs + (i + q) * JB;
@@ -539,12 +551,23 @@ __device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
 {
     const int tid = threadIdx.x;
     if (s <= DROP_COLS * NT) {
+        // Loads take clamped, always valid indices and the unused values are zeroed after them: a
+        // guarded load compiles to a branch whose end waits for the data, so a thread's loads would run
+        // one after another.
         double cv[DROP_COLS], nx[DROP_COLS];
+        const bool has_next = q + 1 < s;
 #pragma unroll
         for (int t = 0; t < DROP_COLS; ++t) {
             const int c = tid + NT * t;
-            cv[t] = c < q ? v.R[tri(q) + c] : 0.0;
-            nx[t] = (q + 1 < s && c <= q) ? v.R[tri(q + 1) + (c < q ? c : c + 1)] : 0.0;
+            const int cq = c < q ? c : q;
+            cv[t] = v.R[tri(q) + cq];
+            if (has_next) nx[t] = v.R[tri(q + 1) + (c < q ? c : q + 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < DROP_COLS; ++t) {
+            const int c = tid + NT * t;
+            cv[t] = c < q ? cv[t] : 0.0;
+            nx[t] = (has_next && c <= q) ? nx[t] : 0.0;
         }
         double last = v.R[tri(q) + q];
         double b = q + 1 < s ? v.R[tri(q + 1) + q] : 0.0;
@@ -554,14 +577,23 @@ __device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
         for (int j = q; j < s - 1; ++j) {
             // prefetch row j + 2 (the next iteration's row), columns shifted past the moved one
             double nn[DROP_COLS];
-            const bool more = j + 2 < s;
+            const bool more = j + 2 < s;   // the same for every thread
             const double* r2 = v.R + tri(j + 2);
+            double bn = 0.0;
+            if (more) {
 #pragma unroll
-            for (int t = 0; t < DROP_COLS; ++t) {
-                const int c = tid + NT * t;
-                nn[t] = (more && c <= j + 1) ? r2[c < q ? c : c + 1] : 0.0;
+                for (int t = 0; t < DROP_COLS; ++t) {
+                    const int c = tid + NT * t;
+                    const int cc = c <= j + 1 ? c : j + 1;
+                    nn[t] = r2[cc < q ? cc : cc + 1];
+                }
+                bn = r2[q];
+#pragma unroll
+                for (int t = 0; t < DROP_COLS; ++t) nn[t] = tid + NT * t <= j + 1 ? nn[t] : 0.0;
+            } else {
+#pragma unroll
+                for (int t = 0; t < DROP_COLS; ++t) nn[t] = 0.0;
             }
-            const double bn = more ? r2[q] : 0.0;
             const double r = hypot(last, b);
             const double cs = r > 0.0 ? b / r : 1.0;
             const double sn = r > 0.0 ? -last / r : 0.0;
@@ -695,13 +727,22 @@ __device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outsid
         double a0 = 0.0, a1 = 0.0;
         for (int k0 = sub; k0 < nS; k0 += GL * DEPTH) {
             double g0[DEPTH], g1[DEPTH], xv[DEPTH];
+            // clamped positions: every load is issued (a guarded one would wait at its branch's end);
+            // positions past nS count zero through xv
 #pragma unroll
             for (int e = 0; e < DEPTH; ++e) {
                 const int k = k0 + GL * e;
-                const int sk = k < nS ? v.so[k] : 0;
-                g0[e] = (k < nS && d0) ? G0[sk] : 0.0;
-                g1[e] = (k < nS && d1) ? G1[sk] : 0.0;
-                xv[e] = k < nS ? v.x[sk] : 0.0;
+                const int sk = v.so[k < nS ? k : nS - 1];
+                g0[e] = G0[sk];
+                g1[e] = G1[sk];
+                xv[e] = v.x[sk];
+            }
+#pragma unroll
+            for (int e = 0; e < DEPTH; ++e) {
+                const bool in = k0 + GL * e < nS;
+                g0[e] = in && d0 ? g0[e] : 0.0;
+                g1[e] = in && d1 ? g1[e] : 0.0;
+                xv[e] = in ? xv[e] : 0.0;
             }
 #pragma unroll
             for (int e = 0; e < DEPTH; ++e) {
