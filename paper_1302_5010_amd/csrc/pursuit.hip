@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
             for (int e0 = tid; e0 < tr; e0 += 8 * 256) {   // eight loads in flight per thread
                 double v[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = e0 + q * 256 < tr ? o.Rinv[e0 + q * 256] : 0.0;
+                for (int q = 0; q < 8; ++q) v[q] = o.Rinv[e0 + q * 256 < tr ? e0 + q * 256 : tr - 1];   // clamped
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
                     if (e0 + q * 256 < tr) d.Rinv[e0 + q * 256] = v[q];
@@ -1106,9 +1106,9 @@ __global__ __launch_bounds__(256) void grow_kernel(GrowArgs a)
             for (int e0 = tid; e0 < tot; e0 += 8 * 256) {   // G restrided from K to K2
                 double v[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int e = e0 + q * 256, u = e / nI0;
-                    v[q] = e < tot ? o.G[(int64_t)u * K + (e - u * nI0)] : 0.0;
+                for (int q = 0; q < 8; ++q) {   // clamped, so all eight loads are issued
+                    const int e = e0 + q * 256 < tot ? e0 + q * 256 : tot - 1, u = e / nI0;
+                    v[q] = o.G[(int64_t)u * K + (e - u * nI0)];
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -1305,7 +1305,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         for (int64_t e0 = tid; e0 < T; e0 += 8 * NT) {
             double r[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) r[q] = e0 + q * NT < T ? g_R[e0 + q * NT] : 0.0;
+            for (int q = 0; q < 8; ++q) r[q] = g_R[e0 + q * NT < T ? e0 + q * NT : T - 1];   // clamped
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (e0 + q * NT < T) s.R[e0 + q * NT] = r[q];
