@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void atom_norm_kernel(const float* __restrict_
 // re-score kernel a quarter of its workgroups per CU).
 __device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4* __restrict__ y, int n4, int lane)
 {
-    constexpr int CH = 6;   // six float4 per lane in flight: 122 VGPRs, four workgroups per CU
+    constexpr int CH = 8;   // eight float4 per lane in flight (n = 2048: one step), four workgroups per CU
     double acc = 0.0;
     for (int q0 = lane; q0 < n4; q0 += 64 * CH) {
         float4 fx[CH];
@@ -94,16 +94,20 @@ __device__ inline double wave_dot_f64(const float4* __restrict__ x, const float4
             }
             continue;
         }
+        // the tail: clamped indices, so these loads too are issued together (a guarded load compiles to
+        // a branch whose end waits for it); chunks past the end count zero
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = q0 + 64 * e;
-            fx[e] = q < n4 ? x[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            fx[e] = x[q < n4 ? q : n4 - 1];
         }
 #pragma unroll
         for (int e = 0; e < CH; ++e) {    // y is read as the sums need it (LDS in the re-score)
             const int q = q0 + 64 * e;
-            const float4 fy = q < n4 ? y[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            acc += (double)fx[e].x * fy.x + (double)fx[e].y * fy.y + (double)fx[e].z * fy.z + (double)fx[e].w * fy.w;
+            const float4 fy = y[q < n4 ? q : n4 - 1];
+            const double d = (double)fx[e].x * fy.x + (double)fx[e].y * fy.y + (double)fx[e].z * fy.z +
+                             (double)fx[e].w * fy.w;
+            acc += q < n4 ? d : 0.0;
         }
     }
     return wave_sum(acc);
