@@ -545,7 +545,7 @@ __device__ void append_list(Sig& v, int& nS, const int* list, int nv, const doub
 // loads the next row's entries one iteration ahead, so the global factor's load latency overlaps the
 // barrier; the next row is only read, never written, during an iteration, and the barrier per row keeps
 // every read of a row before the iteration that writes it.  (The kernel capped at 128 registers uses a
-// narrower register window.)
+// narrower register window: four columns, |S| <= 1024.)
 template <int DROP_COLS>
 __device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
 {
@@ -1605,7 +1605,7 @@ active_set:
             __syncthreads();
             // downdate the factor in place (vw is free scratch here); support positions past q move down
             const uint64_t td = a.phase ? wall_clock64() : 0;
-            chol_drop<BLOCK ? 8 : 2>(s, ns_old, q, vw, vzc);
+            chol_drop<BLOCK ? 8 : 4>(s, ns_old, q, vw, vzc);
             // x* on S \ q: with the removed row b (vw) and its z entry zl, x*_new[k] = x*[k'] - b_k zl
             // (k' the position before the shift)
             {
@@ -1652,7 +1652,7 @@ active_set:
             if (u < nI0 || s_keep[u - nI0]) continue;
             for (int q = tid; q < nS; q += NT) vatom[q] = s.so[q];   // vatom is scratch after the Gram phase
             __syncthreads();
-            chol_drop<BLOCK ? 8 : 2>(s, nS, k, vw, nullptr);
+            chol_drop<BLOCK ? 8 : 4>(s, nS, k, vw, nullptr);
             for (int q = k + 1 + tid; q < nS; q += NT) s.so[q - 1] = vatom[q];
             --nS;
             __syncthreads();
