@@ -1353,13 +1353,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
             double val[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int e = e0 + r * NT;
-                if (e < tot) {
-                    const int t = e / span, k = e - t * span;
-                    const int u = k < nS ? s.so[k] : nI0 + t;
-                    val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
-                }
+            for (int r = 0; r < 4; ++r) {   // clamped entry index: all four reads issued together
+                const int e = e0 + r * NT < tot ? e0 + r * NT : tot - 1;
+                const int t = e / span, k = e - t * span;
+                const int u = k < nS ? s.so[k] : nI0 + t;
+                val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -1379,12 +1377,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
             double val[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int e = e0 + r * NT;
-                if (e < tot) {
-                    const int t = e / nI, u = e - t * nI;
-                    val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
-                }
+            for (int r = 0; r < 4; ++r) {   // clamped entry index: all four reads issued together
+                const int e = e0 + r * NT < tot ? e0 + r * NT : tot - 1;
+                const int t = e / nI, u = e - t * nI;
+                val[r] = a.Q[(int64_t)vatom[nI0 + t] * a.ldq + vatom[u]];
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -1508,12 +1504,10 @@ active_set:
             for (int e0 = tid; e0 < tot; e0 += 4 * NT) {
                 double val[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int e = e0 + r * NT;
-                    if (e < tot) {
-                        const int t = e / nI, u2 = e - t * nI;
-                        val[r] = a.Q[(int64_t)g_atom[s_list[t]] * a.ldq + g_atom[u2]];
-                    }
+                for (int r = 0; r < 4; ++r) {   // clamped entry index: all four reads issued together
+                    const int e = e0 + r * NT < tot ? e0 + r * NT : tot - 1;
+                    const int t = e / nI, u2 = e - t * nI;
+                    val[r] = a.Q[(int64_t)g_atom[s_list[t]] * a.ldq + g_atom[u2]];
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
