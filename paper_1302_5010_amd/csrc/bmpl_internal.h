@@ -59,12 +59,28 @@ __device__ __forceinline__ void row_chunks(const float* g, const uint32_t* ex, i
         }
         return;
     }
+    // the row's tail: clamped indices, so the loads are still issued together (a guarded load compiles to
+    // a branch whose end waits for it); lanes past the vector part read as zeros
+    if (m4 == 0 || base0 >= m4) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            f[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            w[q] = absent;
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const int j0 = base0 + 1024 * q + t4;
-        const bool in = j0 < m4;
-        f[q] = in ? *reinterpret_cast<const float4*>(g + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-        w[q] = in ? (ex ? (ex[j0 >> 5] >> (j0 & 31)) : 0u) : absent;
+        const int jl = j0 < m4 ? j0 : m4 - 4;
+        f[q] = *reinterpret_cast<const float4*>(g + jl);
+        w[q] = ex ? (ex[jl >> 5] >> (jl & 31)) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const bool in = base0 + 1024 * q + t4 < m4;
+        f[q] = in ? f[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        w[q] = in ? w[q] : absent;
     }
 }
 
