@@ -588,9 +588,10 @@ bmpl_status bmpl_create(const float* A_dev, int64_t lda, int32_t n, int32_t m, b
         (void)hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
         if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, c->device) != hipSuccess)
             optin = 0;
-        // both solve kernels get the largest dynamic LDS the device allows; the budget is the smaller
+        // the solve kernels get the largest dynamic LDS the device allows; the budget is the smallest
         size_t dyn = SIZE_MAX;
-        for (const void* fn : {reinterpret_cast<const void*>(solve_kernel), reinterpret_cast<const void*>(solve_block_kernel)}) {
+        for (const void* fn : {reinterpret_cast<const void*>(solve_kernel), reinterpret_cast<const void*>(solve_fold_kernel),
+                               reinterpret_cast<const void*>(solve_block_kernel)}) {
             e = hipFuncGetAttributes(&fa, fn);
             if (e != hipSuccess) break;
             size_t total = (size_t)per_block;
@@ -1050,8 +1051,12 @@ bmpl_status bmpl_solve(bmpl_ctx* c, const float* B_dev, int64_t ldb, int32_t p, 
         GrowArgs ga{w, c->grow_list, c->n_grow, c->grow_off, slack, max_active, kfull};
         hipLaunchKernelGGL(grow_kernel, dim3(std::min(n_grid, 512)), dim3(256), 0, q, ga);
         HIPC(hipGetLastError());
+        // factors that start in global memory take the kernel whose appends and solves read them in
+        // one pass (its larger register footprint stays out of the LDS-factor kernel)
         if (so.zs_lds)
             hipLaunchKernelGGL(solve_block_kernel, dim3(n_grid), dim3(256), lds, q, so);
+        else if (!so.rinv_lds)
+            hipLaunchKernelGGL(solve_fold_kernel, dim3(n_grid), dim3(256), lds, q, so);
         else
             hipLaunchKernelGGL(solve_kernel, dim3(n_grid), dim3(256), lds, q, so);
         HIPC(hipGetLastError());

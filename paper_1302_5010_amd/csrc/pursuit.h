@@ -99,6 +99,8 @@ __global__ void prep_kernel(PrepArgs a);
 __global__ void status_compact_kernel(StatusArgs a);
 __global__ void warm_select_kernel(WarmArgs a);
 __global__ void solve_kernel(SolveArgs a);         // single appends only (zs_lds ignored)
+__global__ void solve_fold_kernel(SolveArgs a);    // solve_kernel with one-pass appends and solves on
+                                                   // factors in global memory (launches with rinv_lds = 0)
 __global__ void solve_block_kernel(SolveArgs a);   // block appends when zs_lds
 __global__ void pack_kernel(PackArgs a);
 __global__ void grow_kernel(GrowArgs a);

@@ -19,9 +19,9 @@
 // float64) and kept packed per signal, grown by rows as atoms enter I (atoms
 // never leave I).  G_SS is represented by its inverse Cholesky factor
 // Rinv = L^{-1} (G_SS = L L^T, so G_SS^{-1} = Rinv^T Rinv): adding an atom is a
-// Cholesky row append computed with two matrix-vector products, every solve is
-// two matrix-vector products, and removing position q truncates the factor to
-// q rows and appends the later positions again.
+// Cholesky row append computed from Rinv^T (Rinv g), a solve is Rinv^T (Rinv w)
+// (two matrix-vector products, or one pass over a factor in global memory), and
+// removing position q is a Givens downdate of the rows below it.
 //
 // One 256-thread workgroup per signal; signals are independent.
 #include <float.h>
@@ -140,6 +140,17 @@ __device__ double* arena_alloc(Arena* A, unsigned long long sz)
 typedef __attribute__((address_space(3))) double lds_double;
 __device__ __forceinline__ lds_double* to_lds(double* p) { return (lds_double*)p; }
 __device__ __forceinline__ const lds_double* to_lds(const double* p) { return (const lds_double*)p; }
+// A factor known to be in global memory, addressed as global: loads then take a scalar base and a
+// 32-bit lane offset instead of a 64-bit address per load.  p must be the same in every thread.
+typedef __attribute__((address_space(1))) const double global_cdouble;
+__device__ __forceinline__ global_cdouble* to_global(const double* p)
+{
+    // the same pointer in every thread: read it from the first lane so it stays in scalar registers
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (global_cdouble*)(((uint64_t)hi << 32) | lo);
+}
 
 // Per-signal working view inside the solve kernel.  G is global (row-major,
 // stride K); the rest points into LDS or into the global homes.
@@ -295,9 +306,114 @@ __device__ inline double col_dot(const Sig& f, const double* v, int k, int s)
     return (a0 + a1) + (a2 + a3);
 }
 
+// Rinv^T (Rinv w) in one pass over a factor in global memory with s <= 1024 positions:
+// z_i = sum_{k <= i} R(i, k) w[k] and out_k = sum_i z_i R(i, k) / div.  The columns are split over
+// the waves (wave v owns the 64-column chunks v, v + 4, v + 8, v + 12, lane l column l of each), the
+// rows taken in batches: a wave loads its chunks of the batch's rows (chunks past a row's diagonal
+// are skipped by a test on the row index, a scalar branch that leaves the loads in flight; the chunk
+// that holds the diagonal is read whole and masked, so every load of the wave shares one lane
+// offset: it reads at most 63 entries past the factor's last one, which lie inside the signal's slot
+// block, where the per-slot vectors follow the factor), forms its partial dot products, and the four
+// waves' partials meet in LDS (double-buffered, one barrier per batch, added in wave order) to give
+// z_i, which each lane folds into its columns' sums while the rows are still in registers.  A row
+// below 512 has at most two chunks per wave, so batches there take 8 rows (4 beyond): up to sixteen
+// loads per lane in flight in every batch.  One read of the factor, instead of a row pass
+// and a column pass that waits for its loads row by row.  Every thread ends with the same sum of
+// z_i^2; z_i goes to z[i] when z is not null.
+//   append (gjj > 0): returns the pivot gjj - sum_i z_i^2; when it exceeds 1e-11 gjj, out receives
+//     the new factor row (div = -sqrt(pivot)), else out is left alone.
+//   solve (gjj = 0): div = 1; returns 0.
+// Ends with a barrier when it writes out.
+constexpr int FOLD_MAX = 1024;
+
+// Rows [i_begin, i_end) of the one-pass product, RB at a time, each lane's chunks j < NJ.
+template <int RB, int NJ>
+__device__ inline void fold_rows(global_cdouble* R, int i_begin, int i_end, const double (&g)[4], double (&acc)[4],
+                                 double& zz, int& buf, double* z, double (*part)[NT / 64][8])
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i0 = i_begin; i0 < i_end; i0 += RB) {
+        double r[RB][NJ];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int i = i0 + q < i_end ? i0 + q : i_end - 1;   // the same on every lane
+            global_cdouble* Ri = R + tri(i);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int c0 = 64 * (wave + 4 * j);
+                r[q][j] = c0 <= i ? Ri[c0 + lane] : 0.0;       // whole chunk, masked below
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < (RB + 7) / 8; ++h) {
+            double pq[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 8 * h; q < RB && q < 8 * h + 8; ++q) {
+                double a = 0.0;
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const int k = 64 * (wave + 4 * j) + lane;
+                    r[q][j] = k <= i0 + q && i0 + q < i_end ? r[q][j] : 0.0;
+                    a += r[q][j] * g[j];
+                }
+                pq[q - 8 * h] = a;
+            }
+            const double mine = wave_sum8(pq);   // lane l holds the wave's sum for row wave_sum8_index(l)
+            if (lane < 8 && 8 * h + wave_sum8_index(lane) < RB) part[buf][wave][8 * h + wave_sum8_index(lane)] = mine;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const double zi = ((part[buf][0][q] + part[buf][1][q]) + part[buf][2][q]) + part[buf][3][q];
+            zz += zi * zi;                       // zero past i_end
+            if (z && threadIdx.x == 0 && i0 + q < i_end) z[i0 + q] = zi;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[j] += zi * r[q][j];
+        }
+        buf ^= 1;
+    }
+}
+
+__device__ inline double fold_pass_global(const double* R, const double* w, int s, double* out, double* z,
+                                          double gjj)
+{
+    __shared__ double part_lds[2][NT / 64][8];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    s = __builtin_amdgcn_readfirstlane(s);      // the same in every thread: row indices stay scalar
+    const int last = s > 0 ? s - 1 : 0;
+    double g[4], acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 64 * (wave + 4 * j) + lane;
+        g[j] = w[k < s ? k : last];
+        acc[j] = 0.0;
+    }
+    double zz = 0.0;
+    int buf = 0;
+    global_cdouble* Rg = to_global(R);
+    fold_rows<8, 2>(Rg, 0, s < 512 ? s : 512, g, acc, zz, buf, z, part_lds);
+    fold_rows<4, 4>(Rg, 512, s, g, acc, zz, buf, z, part_lds);
+    double div = 1.0, pivot = 0.0;
+    if (gjj > 0.0) {
+        pivot = gjj - zz;
+        if (!(pivot > 1e-11 * gjj)) return pivot;
+        div = -sqrt(pivot);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 64 * (wave + 4 * j) + lane;
+        if (k < s) out[k] = acc[j] / div;
+    }
+    __syncthreads();
+    return pivot;
+}
+
 // Append slot j with sign th at support position s = nS (a Cholesky row append
 // held as the inverse factor).  Returns false and excludes j if its Schur
 // complement pivot vanishes, i.e. a_j is numerically in the span of A_S.
+template <bool FOLD>
 __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, double* vz, double* red,
                             uint64_t* cnt)
 {
@@ -310,17 +426,23 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     for (int k = tid; k < s; k += NT) vw[k] = Gj[v.so[k]];
     if (tid == 0) s_gjj = Gj[j];
     __syncthreads();
-    double part = 0.0;
-    if (v.r_lds) {
-        part = rows_matvec_lds(v.R, vw, vz, s);    // z = Rinv w
-    } else {
-        rows_matvec_global(v.R, vw, vz, s);
-        __syncthreads();
-        for (int i = tid; i < s; i += NT) part += vz[i] * vz[i];
-    }
-    const double zz = block_sum_fenced(part, red);   // the barrier after the gather fences red
+    double* Rs = v.R + tri(s);
     const double gjj = s_gjj;
-    const double dd = gjj - zz;
+    const bool fold = FOLD && !v.r_lds && s <= FOLD_MAX;   // one pass over a global factor
+    double dd;
+    if (fold) {
+        dd = fold_pass_global(v.R, vw, s, Rs, nullptr, gjj);   // writes the new row if dd is a pivot
+    } else {
+        double part = 0.0;
+        if (v.r_lds) {
+            part = rows_matvec_lds(v.R, vw, vz, s);    // z = Rinv w
+        } else {
+            rows_matvec_global(v.R, vw, vz, s);
+            __syncthreads();
+            for (int i = tid; i < s; i += NT) part += vz[i] * vz[i];
+        }
+        dd = gjj - block_sum_fenced(part, red);   // the barrier after the gather fences red
+    }
     if (!(dd > 1e-11 * gjj)) {
         if (tid == 0) { v.ex[j] = 1; v.th[j] = 0; v.x[j] = 0.0; }
         __syncthreads();
@@ -329,10 +451,9 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
         return false;
     }
     const double d = sqrt(dd);
-    double* Rs = v.R + tri(s);
     if (v.r_lds)                             // new row: -(z^T Rinv)_k / d
         cols_matvec_lds(v.R, vz, Rs, s, -d);
-    else
+    else if (!fold)
         for (int k = tid; k < s; k += NT) Rs[k] = -col_dot(v, vz, k, s) / d;
     if (tid == 0) {
         Rs[s] = 1.0 / d;
@@ -685,6 +806,7 @@ __device__ void xstar_after_append(const Sig& v, int s0, int s1, double lam, dou
 }
 
 // x_S = Rinv^T Rinv (c_S - lambda theta_S) into vx[0..nS).
+template <bool FOLD>
 __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, double* vz, double* vx)
 {
     const int tid = threadIdx.x;
@@ -693,6 +815,10 @@ __device__ void sign_fixed_solve(const Sig& v, int nS, double lam, double* vw, d
         vw[k] = v.c[u] - lam * (double)v.th[u];
     }
     __syncthreads();
+    if (FOLD && !v.r_lds && nS <= FOLD_MAX) {   // one pass over a global factor
+        fold_pass_global(v.R, vw, nS, vx, vz, 0.0);
+        return;
+    }
     if (v.r_lds) {
         rows_matvec_lds(v.R, vw, vz, nS);
     } else {
@@ -1206,7 +1332,7 @@ __device__ void residual_tail(const Workspace& w, int sig, const float* At, int6
     if (w.R8) write_residual_fp8(w, sig, red);
 }
 
-template <bool BLOCK>
+template <bool BLOCK, bool FOLD>
 __device__ __forceinline__ void solve_body(const SolveArgs& a)
 {
     extern __shared__ double s_dyn[];
@@ -1543,7 +1669,7 @@ active_set:
                     __syncthreads();
                     continue;
                 }
-                chol_append(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
+                chol_append<FOLD>(s, nS, u, th, vw, vz, red, a.phase ? a.phase + 6 : nullptr);
             }
         }
         if (xs_ok && nS > nS_before) {
@@ -1557,7 +1683,7 @@ active_set:
             if (++steps > max_steps) { inexact = true; break; }
             if (!xs_ok) {
                 const uint64_t tsf = a.phase ? wall_clock64() : 0;
-                sign_fixed_solve(s, nS, lam, vw, vzc, vx);
+                sign_fixed_solve<FOLD>(s, nS, lam, vw, vzc, vx);
                 sub_ticks(10, tsf);
                 xs_ok = true;
             }
@@ -1747,8 +1873,9 @@ active_set:
     sub_ticks(14, t_res);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void solve_kernel(SolveArgs a) { solve_body<false>(a); }
-__global__ __launch_bounds__(256) void solve_block_kernel(SolveArgs a) { solve_body<true>(a); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void solve_kernel(SolveArgs a) { solve_body<false, false>(a); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void solve_fold_kernel(SolveArgs a) { solve_body<false, true>(a); }
+__global__ __launch_bounds__(256) void solve_block_kernel(SolveArgs a) { solve_body<true, false>(a); }
 
 // ---------------------------------------------------------------------------
 // Results: support sorted by atom index, float32 values, per-signal scalars.
