@@ -143,6 +143,7 @@ __device__ __forceinline__ const lds_double* to_lds(const double* p) { return (c
 // A factor known to be in global memory, addressed as global: loads then take a scalar base and a
 // 32-bit lane offset instead of a 64-bit address per load.  p must be the same in every thread.
 typedef __attribute__((address_space(1))) const double global_cdouble;
+typedef __attribute__((address_space(1))) double global_double;
 __device__ __forceinline__ global_cdouble* to_global(const double* p)
 {
     // the same pointer in every thread: read it from the first lane so it stays in scalar registers
@@ -150,6 +151,10 @@ __device__ __forceinline__ global_cdouble* to_global(const double* p)
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
     return (global_cdouble*)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ global_double* to_global(double* p)
+{
+    return (global_double*)const_cast<global_cdouble*>(to_global(static_cast<const double*>(p)));
 }
 
 // Per-signal working view inside the solve kernel.  G is global (row-major,
@@ -773,6 +778,118 @@ __device__ void chol_drop(Sig& v, int s, int q, double* cbuf, double* zc)
     }
     if (zc && tid == 0) zc[s - 1] = zcar;
     __syncthreads();
+}
+
+// chol_drop's register path for a factor in global memory (s <= 4 NT): the same rotations in the same
+// order.  Every access names its memory (the factor as global from a scalar base, zc as LDS or global
+// by ZK: 0 none, 1 LDS, 2 global): the generic accesses of chol_drop count against the LDS counter
+// as well, so its barrier after each step waited for that step's global loads and stores to
+// complete.  Here the barrier only orders the workgroup (its waves share one vector L1, which keeps
+// their global accesses in order), and the next step's row and zc entry are in flight meanwhile:
+// their loads take clamped indices and are not masked (a masked load, or one behind a branch, makes
+// the wave wait for it at once), into two buffers that take turns.  Entries past a row's end are
+// never used: step j uses row j + 1 in columns c <= j only, and rows past s - 1 (read as row s - 1)
+// are never used.  Row r is read two steps before step r rewrites it, with a barrier after every step.
+template <int ZK>
+__device__ void chol_drop_global_t(Sig& v, int s, int q, double* cbuf, double* zc)
+{
+    constexpr int DC = 4;
+    const int tid = threadIdx.x;
+    s = __builtin_amdgcn_readfirstlane(s);
+    q = __builtin_amdgcn_readfirstlane(q);
+    global_double* R = to_global(v.R);
+    // row r >= q + 1 with column q moved out (entry c from column c if c < q, else c + 1; clamped
+    // into the row), and bq = R(r, q)
+    auto load_row = [&](int r, double (&o)[DC], double& bq) {
+        r = r < s ? r : s - 1;
+        global_double* Rr = R + tri(r);
+#pragma unroll
+        for (int t = 0; t < DC; ++t) {
+            const int c = tid + NT * t;
+            const int cc = c <= r - 1 ? c : r - 1;
+            o[t] = Rr[cc < q ? cc : cc + 1];
+        }
+        bq = Rr[q];
+    };
+    auto load_z = [&](int r) -> double {
+        r = r < s ? r : s - 1;
+        if (ZK == 1) return to_lds(zc)[r];
+        if (ZK == 2) return to_global(zc)[r];
+        return 0.0;
+    };
+    double cv[DC], ra[DC], rb[DC];
+    {
+        global_double* Rq = R + tri(q);
+#pragma unroll
+        for (int t = 0; t < DC; ++t) {
+            const int c = tid + NT * t;
+            cv[t] = Rq[c < q ? c : q];
+        }
+#pragma unroll
+        for (int t = 0; t < DC; ++t) cv[t] = tid + NT * t < q ? cv[t] : 0.0;
+    }
+    double ba = 0.0, bb = 0.0;
+    if (q + 1 < s) load_row(q + 1, ra, ba);
+    double za = load_z(q + 1), zb = 0.0;
+    double last = R[tri(q) + q];
+    double zcar = load_z(q);
+    // every thread has its R(q, q) before the owner of column q rewrites row q in the first rotation
+    __syncthreads();
+    // Step j rotates with row j + 1 (in X) and loads row j + 2 into Z, the buffer step j - 1 used; the
+    // two buffers take turns by name (a copy of a register that a load is still filling would wait
+    // for the load).
+    auto step = [&](int j, const double (&X)[DC], double bX, double zX, double (&Z)[DC], double& bZ, double& zZ) {
+        load_row(j + 2, Z, bZ);
+        zZ = load_z(j + 2);
+        const double r = hypot(last, bX);
+        const double cs = r > 0.0 ? bX / r : 1.0;
+        const double sn = r > 0.0 ? -last / r : 0.0;
+        global_double* out = R + tri(j);
+#pragma unroll
+        for (int t = 0; t < DC; ++t) {
+            const int c = tid + NT * t;
+            if (c <= j) {                    // columns past j stay zero in the moved column
+                out[c] = cs * cv[t] + sn * X[t];
+                cv[t] = -sn * cv[t] + cs * X[t];
+            }
+        }
+        if (ZK != 0) {
+            const double zj = cs * zcar + sn * zX;
+            zcar = -sn * zcar + cs * zX;
+            if (tid == 0) {
+                if (ZK == 1) to_lds(zc)[j] = zj;
+                else to_global(zc)[j] = zj;
+            }
+        }
+        last = r;
+        __syncthreads();
+    };
+    for (int j = q; j < s - 1; j += 2) {
+        step(j, ra, ba, za, rb, bb, zb);
+        if (j + 1 >= s - 1) break;
+        step(j + 1, rb, bb, zb, ra, ba, za);
+    }
+#pragma unroll
+    for (int t = 0; t < DC; ++t) {
+        const int c = tid + NT * t;
+        if (c < s) cbuf[c] = cv[t];
+    }
+    if (ZK != 0 && tid == 0) {
+        if (ZK == 1) to_lds(zc)[s - 1] = zcar;
+        else to_global(zc)[s - 1] = zcar;
+    }
+    __syncthreads();
+}
+
+__device__ inline bool is_lds(const double* p)
+{
+    return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(p));
+}
+
+// chol_drop_global_t for a zc in global memory (the fold kernel's large supports)
+__device__ inline void chol_drop_global(Sig& v, int s, int q, double* cbuf, double* zc)
+{
+    chol_drop_global_t<2>(v, s, q, cbuf, zc);
 }
 
 // The sign-fixed minimiser after support positions s0..s1-1 were appended to the factor, from the cached
@@ -1725,7 +1842,10 @@ active_set:
             __syncthreads();
             // downdate the factor in place (vw is free scratch here); support positions past q move down
             const uint64_t td = a.phase ? wall_clock64() : 0;
-            chol_drop<BLOCK ? 8 : 4>(s, ns_old, q, vw, vzc);
+            // the fold kernel's factors are in global memory; with its vectors there too (large supports)
+            // the downdate keeps rows in flight across its barriers
+            if (FOLD && ns_old <= 4 * NT && !is_lds(vzc)) chol_drop_global(s, ns_old, q, vw, vzc);
+            else chol_drop<BLOCK ? 8 : 4>(s, ns_old, q, vw, vzc);
             // x* on S \ q: with the removed row b (vw) and its z entry zl, x*_new[k] = x*[k'] - b_k zl
             // (k' the position before the shift)
             {
