@@ -1003,6 +1003,140 @@ __device__ void grad_slots(const Sig& v, int nI, int nS, double* vg, bool outsid
     __syncthreads();
 }
 
+// Element i of a global array that a generic pointer (the same in every thread) points into.
+template <class T>
+__device__ __forceinline__ T gld(const T* p, int64_t i)
+{
+    typedef __attribute__((address_space(1))) const T gT;
+    return reinterpret_cast<gT*>(const_cast<gT*>(reinterpret_cast<gT*>(to_global(reinterpret_cast<const double*>(p)))))[i];
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, int64_t i, T x)
+{
+    typedef __attribute__((address_space(1))) T gT;
+    reinterpret_cast<gT*>(to_global(reinterpret_cast<double*>(p)))[i] = x;
+}
+
+// grad_slots for the fold kernel with the per-slot vectors in global memory (|S| <= GF_MS NT,
+// |I| <= GF_MU NT): the same gradients, organised around the dependent gather G(u, so[k]).  Every
+// thread reads the slot and coefficient of its support positions (tid + NT m) once; the slots that
+// need a gradient are listed in slot order (list: nI ints of global scratch, written through wave
+// ballots); the list is taken GF_B slots at a time: one round trip gathers every thread's entries of
+// those rows (the next batch's slot numbers already in flight), the partial sums meet in LDS
+// (double-buffered, added in wave order) and thread i writes slot i's gradient.  grad_slots takes a
+// slot's support entries 16 lanes at a time, a slot-number load and then the gathers for every 64
+// entries, so its round trips grow with |S|.  Ends with a barrier.
+constexpr int GF_MS = 4, GF_MU = 8, GF_B = 4;
+
+__device__ void grad_fold(const Sig& v, int nI, int nS, double* vg, bool outside_only, int* list)
+{
+    __shared__ double part[2][NT / 64][GF_B];
+    __shared__ int wcnt[NT / 64][GF_MU];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    nI = __builtin_amdgcn_readfirstlane(nI);
+    nS = __builtin_amdgcn_readfirstlane(nS);
+    if (nI == 0) {
+        __syncthreads();
+        return;
+    }
+    global_cdouble* G = to_global(v.G);
+    const int64_t K = v.K;
+    // this thread's support positions: slot and coefficient (zero past nS)
+    int sk[GF_MS];
+    double xs[GF_MS];
+#pragma unroll
+    for (int m = 0; m < GF_MS; ++m) {
+        const int k = tid + NT * m;
+        sk[m] = nS > 0 ? gld(v.so, k < nS ? k : nS - 1) : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < GF_MS; ++m) xs[m] = gld(v.x, sk[m]);
+#pragma unroll
+    for (int m = 0; m < GF_MS; ++m) xs[m] = tid + NT * m < nS ? xs[m] : 0.0;
+    // the slots that need a gradient, listed in the order (m, wave, lane) = slot order
+    unsigned need = 0;
+#pragma unroll
+    for (int m = 0; m < GF_MU; ++m) {
+        const int u = tid + NT * m;
+        const int uc = u < nI ? u : nI - 1;
+        const signed char th = gld(v.th, uc);
+        const unsigned char ex = gld(v.ex, uc);
+        need |= (u < nI && (!outside_only || (th == 0 && !ex))) ? 1u << m : 0u;
+    }
+    unsigned long long bal[GF_MU];
+#pragma unroll
+    for (int m = 0; m < GF_MU; ++m) bal[m] = __ballot((need >> m) & 1);
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < GF_MU; ++m) wcnt[wave][m] = __popcll(bal[m]);
+    }
+    __syncthreads();
+    int ncand = 0;
+#pragma unroll
+    for (int m = 0; m < GF_MU; ++m) {
+        int off = ncand;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            off += w < wave ? wcnt[w][m] : 0;
+            ncand += wcnt[w][m];
+        }
+        if ((need >> m) & 1) {
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(bal[m] >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal[m], 0));
+            gst(list, off + rank, tid + NT * m);
+        }
+    }
+    ncand = __builtin_amdgcn_readfirstlane(ncand);
+    __syncthreads();
+    int nx[GF_B];
+#pragma unroll
+    for (int i = 0; i < GF_B; ++i) nx[i] = gld(list, i < ncand ? i : ncand - 1);
+    int buf = 0;
+    for (int b = 0; b < ncand; b += GF_B) {
+        int us[GF_B];
+#pragma unroll
+        for (int i = 0; i < GF_B; ++i) us[i] = __builtin_amdgcn_readfirstlane(nx[i]);
+#pragma unroll
+        for (int i = 0; i < GF_B; ++i) {
+            const int e = b + GF_B + i;
+            nx[i] = gld(list, e < ncand ? e : ncand - 1);
+        }
+        double cu[GF_B], gv[GF_B][GF_MS];
+#pragma unroll
+        for (int i = 0; i < GF_B; ++i) {
+            cu[i] = gld(v.c, us[i]);
+            global_cdouble* Gu = G + us[i] * K;
+#pragma unroll
+            for (int m = 0; m < GF_MS; ++m) gv[i][m] = Gu[sk[m]];
+        }
+        double pq[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < GF_B; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < GF_MS; ++m) acc += gv[i][m] * xs[m];
+            pq[i] = acc;
+        }
+        const double mine = wave_sum8(pq);       // lane l holds the wave's sum for slot wave_sum8_index(l)
+        if (lane < 8 && wave_sum8_index(lane) < GF_B) part[buf][wave][wave_sum8_index(lane)] = mine;
+        __syncthreads();
+        if (tid < GF_B && b + tid < ncand) {
+            int u = us[0];
+            double c = cu[0];
+#pragma unroll
+            for (int i = 1; i < GF_B; ++i) {
+                u = tid == i ? us[i] : u;
+                c = tid == i ? cu[i] : c;
+            }
+            const double sum = ((part[buf][0][tid] + part[buf][1][tid]) + part[buf][2][tid]) + part[buf][3][tid];
+            gst(vg, u, c - sum);
+        }
+        buf ^= 1;
+    }
+    __syncthreads();
+}
+
 // Gram rows G(q, u) of the new slots q against every slot u, and c_q = a_q^T b,
 // as n-long float64 dot products (used when no Gram table is available).  The
 // new atoms are staged through LDS in chunks (s_new: CH x NB doubles of the launch's dynamic
@@ -1529,6 +1663,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
         vatom = reinterpret_cast<int*>(d + 4 * K);
         vzc = d + 5 * K;
     }
+    // the gradients' slot list (grad_fold), in the unused end of the global vector scratch
+    int* glist = a.vec_lds ? nullptr : reinterpret_cast<int*>(hb.vs + 6 * (int64_t)K);
     // block-append scratch after the vectors (K rows of JB doubles), when the launch provided it
     double* zs = (BLOCK && a.zs_lds) ? reinterpret_cast<double*>(lp + (a.vec_lds ? vec_area_bytes(KV, KP) : 0)) : nullptr;
     // direct Gram staging (no table) after the vectors and the block scratch
@@ -1693,7 +1829,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
 active_set:
     for (;;) {
         const uint64_t tg = a.phase ? wall_clock64() : 0;
-        grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, true);
+        if (FOLD && glist && nI <= GF_MU * NT && nS <= GF_MS * NT) grad_fold(s, nI, nS, vg, true, glist);
+        else grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, true);
         sub_ticks(11, tg);
         const uint64_t tv = a.phase ? wall_clock64() : 0;
         if (wave == 0) {    // violators outside S, in slot order
