@@ -156,6 +156,10 @@ __device__ __forceinline__ global_double* to_global(double* p)
 {
     return (global_double*)const_cast<global_cdouble*>(to_global(static_cast<const double*>(p)));
 }
+__device__ __forceinline__ bool is_lds(const double* p)
+{
+    return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(p));
+}
 
 // Per-signal working view inside the solve kernel.  G is global (row-major,
 // stride K); the rest points into LDS or into the global homes.
@@ -406,10 +410,19 @@ __device__ inline double fold_pass_global(const double* R, const double* w, int 
         if (!(pivot > 1e-11 * gjj)) return pivot;
         div = -sqrt(pivot);
     }
+    // (out's own memory: a generic store would hold up the barrier until it reaches global memory)
+    if (is_lds(out)) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = 64 * (wave + 4 * j) + lane;
-        if (k < s) out[k] = acc[j] / div;
+        for (int j = 0; j < 4; ++j) {
+            const int k = 64 * (wave + 4 * j) + lane;
+            if (k < s) to_lds(out)[k] = acc[j] / div;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 64 * (wave + 4 * j) + lane;
+            if (k < s) to_global(out)[k] = acc[j] / div;
+        }
     }
     __syncthreads();
     return pivot;
@@ -428,7 +441,22 @@ __device__ bool chol_append(Sig& v, int& nS, int j, signed char th, double* vw, 
     if (cnt && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
     const double* Gj = v.G + (int64_t)j * v.K;
     __shared__ double s_gjj;
-    for (int k = tid; k < s; k += NT) vw[k] = Gj[v.so[k]];
+    // w = G(S, j): four positions per thread at once, slot numbers first and then the gathers (clamped
+    // indices: a load behind a per-thread test would be waited for before the next one is issued)
+    for (int k0 = tid; k0 < s; k0 += 4 * NT) {
+        int sk[4];
+        double gv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = k0 + NT * e;
+            sk[e] = v.so[k < s ? k : s - 1];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gv[e] = Gj[sk[e]];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (k0 + NT * e < s) vw[k0 + NT * e] = gv[e];
+    }
     if (tid == 0) s_gjj = Gj[j];
     __syncthreads();
     double* Rs = v.R + tri(s);
@@ -879,11 +907,6 @@ __device__ void chol_drop_global_t(Sig& v, int s, int q, double* cbuf, double* z
         else to_global(zc)[s - 1] = zcar;
     }
     __syncthreads();
-}
-
-__device__ inline bool is_lds(const double* p)
-{
-    return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(p));
 }
 
 // chol_drop_global_t for a zc in global memory (the fold kernel's large supports)
