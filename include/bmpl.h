@@ -335,7 +335,8 @@ typedef struct {
     int64_t outer_iters;
     /* master-problem kernel, summed over its workgroups (wall-clock counter, microseconds; these and
      * the three counts below need BMPL_FLAG_PHASES):
-     * [0] state load, [1] Gram rows, [2] active-set iterations, [3] certificate on I,
+     * [0] state load, [1] Gram rows, [2] active-set iterations (with the gradient on all of I that
+     * the certificate uses), [3] certificate on I,
      * [4] of which inside factor appends, [5] state write-back */
     double solve_phase_us[6];
     int64_t factor_appends;     /* Cholesky row appends (including re-appends after drops) */
@@ -344,7 +345,8 @@ typedef struct {
     double corr_roof_ms;        /* roofline time of the correlation launches (see above) */
     double solve_step_us[6];    /* with BMPL_FLAG_PHASES: time inside the active-set iterations spent in
                                    [0] factor downdates (drops), [1] sign-fixed minimiser evaluations,
-                                   [2] gradients outside S, [3] the violator list and its ranking,
+                                   [2] gradients outside S (and on all of I for the certificate),
+                                   [3] the violator list and its ranking,
                                    [4] the ratio test and step toward the minimiser; [5] the residual
                                    and objective after the write-back; summed over workgroups
                                    (microseconds) */

@@ -1849,12 +1849,16 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     // the sign-fixed minimiser x* (vx) and z = Rinv w (vzc) are computed in full once, then kept current
     // through appends (xstar_after_append) and drops (rotated z, and x* from the removed row)
     bool xs_ok = false;
+    // the last pass of the loop computes the gradient on all of I for the certificate (one call site of
+    // the gradient routine: each inlined copy costs the kernel registers)
+    bool cert = false;
 active_set:
     for (;;) {
         const uint64_t tg = a.phase ? wall_clock64() : 0;
-        if (FOLD && glist && nI <= GF_MU * NT && nS <= GF_MS * NT) grad_fold(s, nI, nS, vg, true, glist);
-        else grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, true);
+        if (FOLD && glist && nI <= GF_MU * NT && nS <= GF_MS * NT) grad_fold(s, nI, nS, vg, !cert, glist);
+        else grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, !cert);
         sub_ticks(11, tg);
+        if (cert) break;
         const uint64_t tv = a.phase ? wall_clock64() : 0;
         if (wave == 0) {    // violators outside S, in slot order
             int base = 0;
@@ -1872,7 +1876,10 @@ active_set:
         }
         __syncthreads();
         int nv = s_cnt;
-        if (nv == 0 && !resolve) break;
+        if (nv == 0 && !resolve) {
+            cert = true;
+            continue;
+        }
         resolve = false;
         if (nv > jadd) {
             // keep the jadd largest violations (ties to the lower slot), in slot order: adding a few at a
@@ -2018,7 +2025,10 @@ active_set:
             nS = ns_old - 1;
             __syncthreads();
         }
-        if (inexact) break;
+        if (inexact) {
+            cert = true;
+            continue;
+        }
         jadd = dropped > 0 ? (jadd > 1 ? jadd / 2 : 1) : (jadd < JADD ? jadd * 2 : JADD);
     }
     if (a.smpl_keep > 0 && !explored && !inexact && nnew > a.smpl_keep && nnew <= NT && a.Q) {
@@ -2092,14 +2102,14 @@ active_set:
             __syncthreads();
             resolve = true;
             xs_ok = false;
+            cert = false;
             goto active_set;
         }
     }
 
     phase_mark(2);
 
-    // 4. Certificate on I (float64).
-    grad_slots<BLOCK ? 8 : 4>(s, nI, nS, vg, false);
+    // 4. Certificate on I (float64), from the gradient on all of I the loop's last pass left in vg.
     double e = 0.0;
     for (int u = tid; u < nI; u += NT) {
         const double gu = vg[u];
