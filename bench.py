@@ -256,7 +256,7 @@ def ragged_measurement(args, pk, torch) -> dict:
     lam = P.lambda_rel * np.abs(P.At.astype(np.float64) @ P.Bt.astype(np.float64).T).max(axis=0)
     lam[rows] = [float.fromhex(v) for v in g["lam"]]
     At, Bt, lam_d = (torch.from_numpy(P.At).to(dev), torch.from_numpy(P.Bt).to(dev), torch.from_numpy(lam).to(dev))
-    s = pk.Solver(At, 0.0, rho=P.rho, kkt_tol=1e-4, graph=True)
+    s = pk.Solver(At, 0.0, rho=P.rho, kkt_tol=1e-4, graph=not args.host_loop)
     tune = s.autotune(P.p)
     outs, dt = timed_steps(args, torch, lambda: s.solve(Bt, lam=lam_d), steps=1, warmup=1)
     out = outs[-1]

@@ -155,7 +155,7 @@ struct Workspace {
     float* g0max;       // [p] ||A^T b_i||_inf from the first correlation pass (Eq. (10))
     double* kkt;        // [p] final certificate (relative to lambda_i)
     uint32_t* inI;      // [p][words] membership bitmap of I
-    int* jadd;          // [p] violators the next active-set step admits (adapted per signal, 1..8)
+    int* jadd;          // [p] violators the next active-set step admits (adapted per signal, 1..32)
     int* glazy;         // [p] 1: G holds only the entries against S members (and the diagonal); a slot's
                         //     column is gathered when it enters S (set once a pass adds many slots)
     int* cap;           // [p] slot capacity of the signal's block (0: none yet)

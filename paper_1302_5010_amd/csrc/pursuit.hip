@@ -38,7 +38,8 @@ namespace {
 constexpr int NT = 256;
 constexpr int NB = 16;      // new atoms per Gram pass
 constexpr int CH = 64;      // k per Gram staging chunk (direct Gram rows)
-constexpr int JADD = 8;     // most violators added to S per active-set step (the largest ones)
+constexpr int JADD = 32;    // most violators added to S per active-set step (the largest ones)
+constexpr int JADD0 = 8;    // the width a signal starts with
 constexpr int LAZY_MIN = 32;   // new slots in one pass above which the Gram matrix is kept lazily
 // Exclusion flag of a slot left out of S for the rest of one pass (cleared at the write-back): an
 // atom admitted alone whose sign-fixed coefficient came out with the wrong sign.  Alone, its exact
@@ -1268,7 +1269,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a)
         w.nS[sig] = 0;
         w.nsel[sig] = 0;
         w.glazy[sig] = 0;
-        w.jadd[sig] = JADD;
+        w.jadd[sig] = JADD0;
         w.vmax[sig] = 0.f;
         w.kkt_on[sig] = 0.0;
         w.kkt[sig] = 0.0;
@@ -1841,11 +1842,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     bool inexact = false;
     bool explored = false;
     bool resolve = false;   // after the pruning: solve on I_t even if no slot outside S violates
-    // Violators admitted per step, adapted to the dictionary: halved after a step whose move to the
-    // sign-fixed minimiser dropped atoms (correlated atoms enter and leave), doubled (up to JADD) after a
-    // clean one; carried from one outer iteration to the next.
+    // Violators admitted per step, adapted to the dictionary and carried from one outer iteration to
+    // the next: doubled (up to JADD) after a step whose move to the sign-fixed minimiser dropped nothing;
+    // halved after one that dropped at least a quarter as many atoms as it admitted (correlated atoms
+    // that enter and leave together); otherwise trimmed by an eighth (by one below 8), since a drop or
+    // two among many admissions is what a nearly saturated support sees at every step.
     int jadd = w.jadd[sig];
-    jadd = jadd >= 1 && jadd <= JADD ? jadd : JADD;
+    jadd = jadd >= 1 && jadd <= JADD ? jadd : JADD0;
     // the sign-fixed minimiser x* (vx) and z = Rinv w (vzc) are computed in full once, then kept current
     // through appends (xstar_after_append) and drops (rotated z, and x* from the removed row)
     bool xs_ok = false;
@@ -1961,6 +1964,7 @@ active_set:
             xstar_after_append(s, nS_before, nS, lam, vw, vzc, vx, red);
             sub_ticks(10, tsf);
         }
+        const int added = nS - nS_before;
         // move toward the sign-fixed minimiser, dropping at zero crossings
         int dropped = 0;
         for (;;) {
@@ -2029,7 +2033,9 @@ active_set:
             cert = true;
             continue;
         }
-        jadd = dropped > 0 ? (jadd > 1 ? jadd / 2 : 1) : (jadd < JADD ? jadd * 2 : JADD);
+        if (dropped == 0) jadd = jadd < JADD / 2 ? 2 * jadd : JADD;
+        else if (4 * dropped >= added) jadd = jadd > 1 ? jadd / 2 : 1;
+        else jadd = jadd > 8 ? jadd * 7 / 8 : (jadd > 1 ? jadd - 1 : 1);
     }
     if (a.smpl_keep > 0 && !explored && !inexact && nnew > a.smpl_keep && nnew <= NT && a.Q) {
         // Subspace exploratory matching (Algorithm 2): keep the smpl_keep new atoms with the largest |u_j|
