@@ -1844,9 +1844,10 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a)
     bool resolve = false;   // after the pruning: solve on I_t even if no slot outside S violates
     // Violators admitted per step, adapted to the dictionary and carried from one outer iteration to
     // the next: doubled (up to JADD) after a step whose move to the sign-fixed minimiser dropped nothing;
-    // halved after one that dropped at least a quarter as many atoms as it admitted (correlated atoms
-    // that enter and leave together); otherwise trimmed by an eighth (by one below 8), since a drop or
-    // two among many admissions is what a nearly saturated support sees at every step.
+    // on a small support (|S| < 128) halved after one that dropped at least a quarter as many atoms as it
+    // admitted (correlated atoms that enter and leave together); otherwise trimmed by an eighth (by one
+    // below 8): a large, nearly saturated support sees drops at almost every step, and each admission
+    // saved there is a pass over a factor of hundreds of rows.
     int jadd = w.jadd[sig];
     jadd = jadd >= 1 && jadd <= JADD ? jadd : JADD0;
     // the sign-fixed minimiser x* (vx) and z = Rinv w (vzc) are computed in full once, then kept current
@@ -2034,7 +2035,7 @@ active_set:
             continue;
         }
         if (dropped == 0) jadd = jadd < JADD / 2 ? 2 * jadd : JADD;
-        else if (4 * dropped >= added) jadd = jadd > 1 ? jadd / 2 : 1;
+        else if (nS < 128 && 4 * dropped >= added) jadd = jadd > 1 ? jadd / 2 : 1;
         else jadd = jadd > 8 ? jadd * 7 / 8 : (jadd > 1 ? jadd - 1 : 1);
     }
     if (a.smpl_keep > 0 && !explored && !inexact && nnew > a.smpl_keep && nnew <= NT && a.Q) {
