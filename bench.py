@@ -45,22 +45,26 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1302_5010_amd/csrc/corr_gemm.hip", "paper_1302_5010_amd/csrc/gemm_tile.h")
 
 
-def kernel_source_hash() -> str:
-    """First 16 hex digits of the sha256 of the correlation kernel's sources, concatenated."""
+SOLVE_SOURCES = ("paper_1302_5010_amd/csrc/pursuit.hip", "paper_1302_5010_amd/csrc/pursuit.h",
+                 "paper_1302_5010_amd/csrc/bmpl_internal.h", "paper_1302_5010_amd/csrc/wave_ops.h")
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
+    """First 16 hex digits of the sha256 of a kernel's sources (default: the correlation's), concatenated."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(path: str):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was taken on these kernel sources."""
+def load_traffic(path: str, sources=KERNEL_SOURCES):
+    """HBM bytes from a committed rocprofv3 --pmc summary, if it was taken on these kernel sources."""
     try:
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("kernel_sha256_16") != kernel_source_hash():
+        if rec.get("kernel_sha256_16") != kernel_source_hash(sources):
             return None
         return rec
     except (OSError, ValueError):
@@ -261,6 +265,22 @@ def ragged_measurement(args, pk, torch) -> dict:
     outs, dt = timed_steps(args, torch, lambda: s.solve(Bt, lam=lam_d), steps=1, warmup=1)
     out = outs[-1]
     s.close()
+    # The master problem's roofline: its kernels' time in one instrumented solve (host loop, HIP events
+    # around every solve launch) against the HBM bytes rocprofv3 counted for them on these sources.
+    st = pk.Solver(At, 0.0, rho=P.rho, kkt_tol=1e-4, timing=True)
+    st.set_tuning(tune["shapes"])
+    st.solve(Bt, lam=lam_d)
+    torch.cuda.synchronize()
+    tb = st.timing()
+    st.close()
+    traffic = load_traffic(os.path.join(ROOT, "profiles", "solve_ragged1024x32768_pmc.json"), SOLVE_SOURCES)
+    hbm = traffic["hbm_bytes_per_solve"] if traffic else None
+    ach = hbm / (tb["solve_ms"] * 1e-3) / 1e9 if hbm and tb["solve_ms"] > 0 else None
+    master = {"bound": "hbm", "kernel": "solve_fold_kernel + solve_kernel (master problem)",
+              "solve_kernel_ms": tb["solve_ms"], "solve_launches": tb["solve_launches"],
+              "traffic": hbm, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+              "frac": ach / PEAK_HBM_GBS if ach else None,
+              "corr_ms": tb["corr_ms"], "select_ms": tb["select_ms"], "other_ms": tb["other_ms"]}
     X = np.zeros((len(rows), P.m))
     val = [float.fromhex(v) for v in g["val"]]
     off = 0
@@ -277,6 +297,7 @@ def ragged_measurement(args, pk, torch) -> dict:
             "support_mean_k_le_150": float(supp[k <= 150].mean()), "support_mean_k_ge_200": float(supp[k >= 200].mean()),
             "parity_on_stored_subset": parity_stats(P.At, P.Bt[rows], lam[rows], sparse_rows(out, rows, P.m), X),
             "iters_equal_to_oracle_on_subset": float(np.mean(it[rows] == np.array(g["iters"]))),
+            "master_problem_roofline": master,
             "cpu_baseline": {"value": len(rows) / g["seconds"], "unit": "signals/s", "cores": g["threads"],
                              "kind": "oracle", "sample": "the stored 64-signal stratified subset (32 with k >= 200, "
                              "32 with k <= 150), FP64 C oracle, one signal per thread; time recorded when the "
