@@ -1305,9 +1305,11 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
     __shared__ unsigned long long s_res[16];
     __shared__ int s_ng;
     __shared__ unsigned long long s_goff;   // doubles of the grow list's new blocks
-    if (threadIdx.x == 0) { s_base = 0; s_ng = 0; s_goff = 0; }
+    __shared__ int s_maxb;                  // largest support bucket (256 positions each) among kept signals
+    if (threadIdx.x == 0) { s_base = 0; s_ng = 0; s_goff = 0; s_maxb = 0; }
     __syncthreads();
     unsigned long long res = 0;   // this thread's share of the slot-block reserve
+    int mbk = 0;                  // largest support bucket among this thread's kept signals
     for (int r0 = 0; r0 < n_in; r0 += 1024) {
         const int r = r0 + threadIdx.x;
         int keep = 0, sig = -1;
@@ -1362,6 +1364,7 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
                 }
             }
         }
+        if (keep) mbk = max(mbk, min(3, w.nS[sig] / 256));
         if (keep && a.grow_list && w.nI[sig] + w.nsel[sig] > w.cap[sig]) {
             // its block grows before the master problem; the new blocks of the whole list are placed here
             // with one fetch-and-add on the arena's offset (below), each at its share of the total
@@ -1396,7 +1399,48 @@ __global__ __launch_bounds__(1024) void status_compact_kernel(StatusArgs a)
         __syncthreads();   // every wave has read s_scan and s_base
         if (threadIdx.x == 0) s_base += total;
     }
+    if (mbk > 0) atomicMax(&s_maxb, mbk);
     __syncthreads();
+    {
+        // The running list, largest supports first (buckets of 256 support positions, kept in signal
+        // order within a bucket): the master problem's workgroups start with the longest problems and
+        // the short ones fill the end of the launch.  Only when some support has 256 positions or more,
+        // and for lists of at most 16 entries per thread (longer lists keep their order).
+        constexpr int RMAX = 16;
+        const int n = s_base;
+        const bool reorder = !a.initial && s_maxb > 0 && n <= RMAX * 1024;   // the same in every thread
+        int v[RMAX], bk[RMAX];
+        if (reorder) {
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) {
+                const int r = threadIdx.x + 1024 * j;
+                v[j] = r < n ? a.act_out[r] : -1;
+                bk[j] = v[j] >= 0 ? min(3, w.nS[v[j]] / 256) : -1;
+            }
+            __syncthreads();                  // every entry is read before any is rewritten
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            int base = 0;
+            for (int b = 3; b >= 0; --b) {
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) {
+                    if (1024 * j >= n) break;  // the same in every thread
+                    const bool in = bk[j] == b;
+                    const unsigned long long bal = __ballot(in);
+                    if (lane == 0) s_scan[wv] = __popcll(bal);
+                    __syncthreads();
+                    int before = base, total = 0;
+                    for (int q = 0; q < 16; ++q) {
+                        const int c = s_scan[q];
+                        before += q < wv ? c : 0;
+                        total += c;
+                    }
+                    if (in) a.act_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = v[j];
+                    __syncthreads();           // every wave has read s_scan
+                    base += total;
+                }
+            }
+        }
+    }
     if (threadIdx.x == 0) {
         *a.n_out_dev = s_base;
         if (a.n_grow) *a.n_grow = s_ng;
